@@ -1,0 +1,191 @@
+"""Seeded synthetic inputs shared by the tests, the smoke check and the benchmark.
+
+This module only builds input arrays (charts, wall displacements, initial
+velocities, population perturbations) and names the workloads.  It holds none
+of the method's arithmetic: the solver and the oracle each turn these arrays
+into geometry and populations on their own.
+
+All arrays are float64 numpy arrays in the layouts of ``include/lbm.h``:
+chart [3, nz, ny, nx], displacement [nz, nx], wall velocity [nz, nx, 3],
+fluid fields [c, nz, ny-2, nx].
+"""
+from dataclasses import dataclass, field
+from typing import Callable, Optional
+
+import numpy as np
+
+
+# ----------------------------------------------------------------- charts
+def identity_chart(nx: int, ny: int, nz: int) -> np.ndarray:
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    return np.stack([i, j, k]).astype(np.float64)
+
+
+def shear_chart(nx: int, ny: int, nz: int, eps: float) -> np.ndarray:
+    """Tangential shear of flat space that keeps both walls in place:
+    x_c = xi_x + eps*H*sin(pi*eta/H), eta = xi_y - 1/2."""
+    H = ny - 2
+    ch = identity_chart(nx, ny, nz)
+    eta = ch[1] - 0.5
+    ch[0] += eps * H * np.sin(np.pi * eta / H)
+    return ch
+
+
+def bump_chart(nx: int, ny: int, nz: int, eps: float) -> np.ndarray:
+    """Interior bump of flat space, walls fixed:
+    y_c = xi_y + eps*H*sin(2 pi xi_x/nx)*sin(pi*eta/H)."""
+    H = ny - 2
+    ch = identity_chart(nx, ny, nz)
+    eta = ch[1] - 0.5
+    ch[1] += eps * H * np.sin(2 * np.pi * ch[0] / nx) * np.sin(np.pi * eta / H)
+    return ch
+
+
+def bump3_chart(nx: int, ny: int, nz: int, eps: float) -> np.ndarray:
+    """Interior bump varying in x and z (all nine Jacobian entries of the
+    x-y-z coupling exercised), walls fixed."""
+    H = ny - 2
+    xi = identity_chart(nx, ny, nz)
+    ch = xi.copy()
+    s = np.sin(np.pi * (xi[1] - 0.5) / H)
+    sx, cz = np.sin(2 * np.pi * xi[0] / nx), np.cos(2 * np.pi * xi[2] / nz)
+    ch[0] += 0.5 * eps * H * cz * s
+    ch[1] += eps * H * sx * cz * s
+    ch[2] += 0.5 * eps * H * sx * s
+    return ch
+
+
+def diagonal_metric_chart(nx: int, ny: int, nz: int, eps: float, n_quad: int = 64) -> np.ndarray:
+    """Chart whose metric is diag(1, 1 + d^2/dy^2 h'(y), 1) with
+    h'(y) = eps cos(pi y / L), L = H, y = eta (Sec. V.A, Poiseuille test):
+    y_c(y) = integral_0^y sqrt(g_yy) dy' by Gauss-Legendre quadrature.
+    The walls stay at y_c(0) = 0 and y_c(H) (shifted by a constant)."""
+    H = ny - 2
+    ch = identity_chart(nx, ny, nz)
+    xg, wg = np.polynomial.legendre.leggauss(n_quad)
+
+    def gyy(y):
+        return 1.0 - eps * (np.pi / H) ** 2 * np.cos(np.pi * y / H)
+
+    def yc(y):
+        a = 0.5 * y * (xg + 1.0)
+        return 0.5 * y * np.sum(wg * np.sqrt(gyy(a)))
+
+    etas = np.arange(ny) - 0.5
+    ycs = np.array([np.sign(e) * yc(abs(e)) if e >= 0 else -yc(-e) for e in etas])
+    ch[1] = (ycs + 0.5)[None, :, None] * np.ones((nz, 1, nx))
+    return ch
+
+
+def chart_from_displacement(nx: int, ny: int, nz: int, d_top: np.ndarray, d_bot: Optional[np.ndarray] = None):
+    """Explicit chart of the linearly blended wall displacement family.
+
+    Used only by tests that need the same chart as a plain array (for example
+    to drive the generic chart entry point with it)."""
+    H = ny - 2
+    ch = identity_chart(nx, ny, nz)
+    eta = ch[1] - 0.5
+    db = np.zeros((nz, nx)) if d_bot is None else d_bot
+    ch[1] = ch[1] + (1.0 - eta / H) * db[:, None, :] + (eta / H) * d_top[:, None, :]
+    return ch
+
+
+# ------------------------------------------------------- wall displacements
+def c1_displacement(nx=32, ny=16, nz=16, frac=0.03):
+    """Static sinusoidal shear of the top wall, 0.03 H sin(2 pi x / 32)."""
+    H = ny - 2
+    x = np.arange(nx)
+    return np.tile(frac * H * np.sin(2 * np.pi * x / 32.0), (nz, 1))
+
+
+def gaussian_bump(nx=256, nz=128, A=0.08 * 128, x0=128.0, z0=64.0, sigma=16.0):
+    """Inward (-y) Gaussian bump of the top wall."""
+    x = np.arange(nx)[None, :]
+    z = np.arange(nz)[:, None]
+    return -A * np.exp(-((x - x0) ** 2 + (z - z0) ** 2) / (2 * sigma**2))
+
+
+def oscillating_wall(nx=256, nz=128, A=0.06 * 128, T=2000.0, t=0.0):
+    """d(x,z,t) = A sin(2 pi x / nx) sin(2 pi t / T) and its time derivative."""
+    x = np.arange(nx)[None, :] * np.ones((nz, 1))
+    d = A * np.sin(2 * np.pi * x / nx) * np.sin(2 * np.pi * t / T)
+    v = A * np.sin(2 * np.pi * x / nx) * np.cos(2 * np.pi * t / T) * (2 * np.pi / T)
+    return d, v
+
+
+def gaussian_random_field(nx=128, nz=64, corr=8.0, max_abs=0.05 * 64, seed=4):
+    """Periodic Gaussian random field with covariance exp(-r^2/(2 l^2)),
+    synthesised in Fourier space and scaled to the given maximum |d|."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    w = rng.standard_normal((nz, nx))
+    kx = 2 * np.pi * np.fft.fftfreq(nx)[None, :]
+    kz = 2 * np.pi * np.fft.fftfreq(nz)[:, None]
+    filt = np.exp(-0.25 * (kx**2 + kz**2) * corr**2)
+    d = np.real(np.fft.ifft2(np.fft.fft2(w) * filt))
+    return d * (max_abs / np.abs(d).max())
+
+
+def patch_wave(nx=512, nz=256, A=0.08 * 256, t=0.0, x0=192, z0=64, L=128, lam=128.0, T=1500.0):
+    """Travelling wave A sin(2 pi (x/lam - t/T)) under a sin^4 window on the
+    L x L patch [x0, x0+L) x [z0, z0+L); zero elsewhere.  Returns d and dd/dt."""
+    x = np.arange(nx)[None, :] * np.ones((nz, 1))
+    z = np.arange(nz)[:, None] * np.ones((1, nx))
+    sx = np.clip((x - x0) / L, 0.0, 1.0)
+    sz = np.clip((z - z0) / L, 0.0, 1.0)
+    win = np.sin(np.pi * sx) ** 4 * np.sin(np.pi * sz) ** 4
+    ph = 2 * np.pi * (x / lam - t / T)
+    return A * np.sin(ph) * win, -A * np.cos(ph) * win * (2 * np.pi / T)
+
+
+# --------------------------------------------------------- initial fields
+def uniform_noise_velocity(nx, ny, nz, amp=1e-4, seed=2):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.uniform(-amp, amp, size=(3, nz, ny - 2, nx))
+
+
+def random_perturbation(shape, amp, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return amp * rng.standard_normal(shape)
+
+
+def random_unit(shape, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    v = rng.standard_normal(shape)
+    return v / np.linalg.norm(v)
+
+
+# -------------------------------------------------------------- workloads
+@dataclass
+class Workload:
+    name: str
+    nx: int
+    ny: int
+    nz: int
+    tau: float
+    force: tuple = (1e-6, 0.0, 0.0)
+    steps: int = 0
+    disp: Optional[Callable] = None
+    notes: str = ""
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def fluid_nodes(self) -> int:
+        return self.nx * (self.ny - 2) * self.nz
+
+
+def workload(name: str) -> Workload:
+    """The five channel workloads (sizes, relaxation time, drive, wall motion)."""
+    if name == "c1_shear_32x16x16":
+        return Workload(name, 32, 16, 16, 0.8, steps=2000, disp=lambda: c1_displacement())
+    if name == "c2_bump_256x128x128":
+        return Workload(name, 256, 128, 128, 0.6, steps=1000, disp=lambda: gaussian_bump())
+    if name == "c3_oscillating_256x128x128":
+        return Workload(name, 256, 128, 128, 0.6, steps=4000, extra={"update_every": 10})
+    if name == "c4_adjoint_128x64x64":
+        return Workload(name, 128, 64, 64, 0.7, steps=200, disp=lambda: gaussian_random_field(),
+                        extra={"ckpt_every": 20})
+    if name == "c5_patch_wave_512x256x256":
+        # Re = u_max * 128 / nu = 100 with u_max = F H^2 / (8 nu), H = 254
+        nu = float(np.sqrt(1e-6 * 254**2 * 128.0 / 800.0))
+        return Workload(name, 512, 256, 256, 0.5 + 3 * nu, steps=3000, extra={"K": 100, "ckpt_every": 10})
+    raise KeyError(name)

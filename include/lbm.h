@@ -1,0 +1,188 @@
+/*
+ * lbm.h -- C-ABI of the curved-space D3Q19 lattice Boltzmann library (liblbm.so)
+ *
+ * Method: the second-order curved-space lattice Boltzmann scheme of Flouris et
+ * al., "Fluid structure interaction with curved space lattice Boltzmann"
+ * (arXiv 1803.07822): Eq. (CE-LB) split into collision Eq. (collision) and
+ * streaming Eq. (streaming), with the metric-dependent Hermite equilibrium
+ * (Eq. expansion-equilibrium, App. B), the forcing of Eqs. (forcing2),
+ * (forcing-A), (forcing-B), (forcing-C), the geometry of App. A computed with
+ * the fourth-order lattice derivative of App. D, the re-projection of the
+ * populations on a chart change (Sec. IV.B) and the node-exact wall force
+ * (Sec. IV.A.2).
+ *
+ * Units and lattice: dx = dt = 1, c_s^2 = theta = 1/3.  D3Q19, population
+ * order: 0 rest; 1..6 = +x,-x,+y,-y,+z,-z; 7..18 = (+x+y,-x-y), (+x-y,-x+y),
+ * (+x+z,-x-z), (+x-z,-x+z), (+y+z,-y-z), (+y-z,-y+z).
+ *
+ * Grid: nodes (i,j,k), x fastest.  Layers j = 0 and j = ny-1 are solid walls;
+ * fluid layers are j = 1..ny-2 (H = ny-2 of them); x and z are periodic.  The
+ * halfway walls sit half a cell outside the first and last fluid layer.
+ *
+ * Array layouts (all C order; "fluid" = [nz][H][nx]):
+ *   chart          double [3][nz][ny][nx]  Cartesian node positions h(xi)
+ *   displacement   double [nz][nx]         y-displacement of one wall
+ *   wall velocity  double [nz][nx][3]      Cartesian
+ *   populations    double [19][fluid]      f_l(x,t), Eq. (streaming)
+ *   history        double [10][fluid]      A, B^x, B^y, B^z, C^xx, C^xy,
+ *                                          C^xz, C^yy, C^yz, C^zz of F(x,t-1)
+ *   geometry       double [28][fluid]      sqrt g, g^xx, g^xy, g^xz, g^yy,
+ *                                          g^yz, g^zz, Gamma^i_jk (i = x,y,z;
+ *                                          jk = xx,xy,xz,yy,yz,zz), F^x,F^y,F^z
+ *   jacobian       double [9][fluid]       J[a][i] = d h^a / d xi^i
+ *   rho            double [fluid];  u double [3][fluid]
+ *
+ * Ownership: every d_* pointer is device memory owned by the caller; it must
+ * stay valid until the stream has passed the call.  The workspace (sized by
+ * lbm_workspace_bytes) is caller-owned device memory that must outlive the
+ * context.  The library never allocates device memory; it allocates only the
+ * small host-side context.  Host pointers are marked h_*.
+ *
+ * Streams: all device work is enqueued on the hip stream given to lbm_create
+ * (NULL = the null stream).  Calls return once the work is enqueued, except
+ * the sync points (lbm_sync, lbm_wall_force with a host result, lbm_backward)
+ * and calls documented as synchronising.
+ *
+ * Errors: every call returns LBM_OK or a negative code; lbm_last_error gives a
+ * message.  LBM_EHIP and LBM_EUNSTABLE are sticky: once raised, every later
+ * call on the context returns them.  The instability guard (a non-finite
+ * population, density <= 0 or |u|^2 > 0.1 at any node) is raised by the
+ * kernels and reported at the next sync point.  A context is not thread safe.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ctx lbm_ctx;
+
+typedef struct {
+  int nx, ny, nz; /* ny includes the two solid wall layers */
+} lbm_grid;
+
+enum { LBM_D3Q19 = 19 };
+/* LBM_FP64: populations, history and geometry stored and computed in FP64.
+ * LBM_FP32_DEV: populations stored as deviations f - w_l, history and
+ * geometry as FP32 deviations (sqrt g - 1, g^ij - delta^ij, Gamma, F^i),
+ * arithmetic in FP32; the geometry itself is computed in FP64. */
+enum { LBM_FP64 = 0, LBM_FP32_DEV = 1 };
+enum { LBM_WALL_YMIN = 0, LBM_WALL_YMAX = 1 };
+enum { LBM_FORCE_STRESS = 0 };
+enum {
+  LBM_OK = 0,
+  LBM_EINVAL = -1,      /* bad argument */
+  LBM_ENOMEM = -2,      /* workspace too small */
+  LBM_EHIP = -3,        /* a HIP call failed (sticky) */
+  LBM_ESTATE = -4,      /* call out of order */
+  LBM_EUNSTABLE = -5,   /* instability guard tripped (sticky) */
+  LBM_EUNSUPPORTED = -6 /* option not provided */
+};
+
+/* Bytes of device workspace a context needs.  adjoint_K > 0 reserves the
+ * trajectory storage of lbm_forward_record/lbm_backward for K steps with a
+ * checkpoint every ckpt_every steps (ckpt_every in 1..K).  Returns 0 for an
+ * invalid grid (nx, nz >= 1, ny >= 4) or lattice. */
+size_t lbm_workspace_bytes(const lbm_grid* h_grid, int lattice, int precision, int adjoint_K,
+                           int ckpt_every);
+
+/* Create a context.  tau > 1/2 is the BGK relaxation time (kinematic
+ * viscosity (tau - 1/2)/3, App. C).  d_workspace: bytes >= lbm_workspace_bytes
+ * of the same arguments (adjoint sizes from the last two of them are taken as
+ * adjoint_K = ckpt_every = 0 unless set with lbm_reserve_adjoint).  The body
+ * force is zero and the walls are at rest until set. */
+int lbm_create(lbm_ctx** out, const lbm_grid* h_grid, int lattice, double tau, int precision,
+               void* d_workspace, size_t bytes, void* hip_stream);
+
+/* Declare the adjoint trajectory sizes the workspace was sized for (before
+ * the first metric is set). */
+int lbm_reserve_adjoint(lbm_ctx* ctx, int adjoint_K, int ckpt_every);
+
+int lbm_destroy(lbm_ctx* ctx);
+
+/* Cartesian body-force density F_ext (force per physical volume).  It enters
+ * B^i of Eq. (forcing-B) as F^i = (J^{-1} F)^i.  Takes effect at the next
+ * step (the history of the current state is not rewritten). */
+int lbm_set_body_force(lbm_ctx* ctx, const double h_F_cart[3]);
+
+/* Set the chart (node positions, wall layers included) and precompute the
+ * geometry of App. A with the fourth-order derivative of App. D (FP64).  The
+ * chart is continued three layers beyond each wall layer by the cubic through
+ * the four nearest layers.  reproject != 0 carries the current state onto the
+ * new chart (Sec. IV.B); it needs a state.  Synchronising. */
+int lbm_set_metric(lbm_ctx* ctx, const double* d_chart, int reproject);
+
+/* Set the y-displacement d of one wall and rebuild the chart by the linear
+ * blending of Sec. IV.A.1 (i):
+ *   h = (xi_x, xi_y + (1 - eta/H) d_bot + (eta/H) d_top, xi_z), eta = xi_y - 1/2.
+ * The other wall keeps its last displacement (initially 0).  Otherwise as
+ * lbm_set_metric. */
+int lbm_set_wall_displacement(lbm_ctx* ctx, int wall, const double* d_disp, int reproject);
+
+/* Cartesian velocity of a wall ([nz][nx][3], NULL = at rest).  It enters the
+ * halfway bounce-back as the moving-wall term and the momentum ghost of the
+ * lattice gradient, in chart components J^{-1} v at the adjacent fluid node. */
+int lbm_set_wall_velocity(lbm_ctx* ctx, int wall, const double* d_vcart);
+
+/* Initial state f = f_eq(rho, u) with u = J^{-1} u_cart (rho NULL = 1, u NULL
+ * = 0); the forcing history is set to the forcing of this state. */
+int lbm_init_equilibrium(lbm_ctx* ctx, const double* d_rho, const double* d_ucart);
+
+/* Set / read the populations f_l(x,t) (FP64, full values).  Setting recomputes
+ * the forcing history from the given state, as lbm_init_equilibrium does. */
+int lbm_set_populations(lbm_ctx* ctx, const double* d_f);
+int lbm_get_populations(lbm_ctx* ctx, double* d_f);
+
+/* Read the forcing history (coefficients of F(x,t-1)) and the precomputed
+ * geometry (d_jac9 may be NULL). */
+int lbm_get_history(lbm_ctx* ctx, double* d_coef);
+int lbm_get_geometry(lbm_ctx* ctx, double* d_geo28, double* d_jac9);
+
+/* Advance n >= 0 steps (collision, streaming, bounce-back, history update). */
+int lbm_step(lbm_ctx* ctx, int n);
+
+/* rho = sqrt g sum f, u = (sqrt g sum f c)/rho (Eqs. fields1-2); u in chart
+ * components, or Cartesian (J u) if cartesian != 0.  Either output may be
+ * NULL.  Checks the instability guard (synchronising). */
+int lbm_moments(lbm_ctx* ctx, double* d_rho, double* d_u, int cartesian);
+
+/* Node-exact force of the fluid on a wall at the current state: per column,
+ * the traction sqrt g T^{i y} e_i at the fluid layer next to the wall (sign
+ * flipped for the bottom wall), T from Eq. (fields3), e_i = J[.][i].
+ * d_total3: the sum over columns (3 doubles, device).  d_per_node ([nz][nx][3]
+ * or NULL).  Only LBM_FORCE_STRESS is provided. */
+int lbm_wall_force(lbm_ctx* ctx, int wall, int method, double* d_total3, double* d_per_node);
+
+/* Run K steps from the current state and record the force on `wall` at
+ * states 1..K into d_forces [K][3]; the initial state and a checkpoint every
+ * ckpt_every steps are kept for lbm_backward.  K and ckpt_every must match
+ * lbm_reserve_adjoint.  Needs the FP64 form. */
+int lbm_forward_record(lbm_ctx* ctx, int K, int ckpt_every, int wall, int method, double* d_forces);
+
+/* Reverse sweep of the last lbm_forward_record: given dL/dF [K][3], write
+ * dL/d(top-wall displacement) [nz][nx], dL/d(chart) [3][nz][ny][nx] and dL/d
+ * f0 [19][fluid] (each may be NULL).  The initial populations f0 are an
+ * independent input (the history F(x,-1) is recomputed from f0 and the chart).
+ * Synchronising. */
+int lbm_backward(lbm_ctx* ctx, const double* d_dL_dF, double* d_grad_disp, double* d_grad_chart,
+                 double* d_grad_f0);
+
+/* lbm_step with each kernel of the step bracketed by HIP events on the
+ * context's stream: h_ms[k] receives the average duration (ms) of kernel k
+ * of the step over the n steps (nslots >= the number of kernels per step,
+ * currently 2: the moment pass and the collision pass).  Synchronising. */
+int lbm_step_profiled(lbm_ctx* ctx, int n, double* h_ms, int nslots);
+
+/* Wait for the stream and check the instability guard. */
+int lbm_sync(lbm_ctx* ctx);
+
+const char* lbm_last_error(const lbm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

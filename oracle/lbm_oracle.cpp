@@ -31,6 +31,9 @@
 #include <cstdio>
 #include <cstring>
 #include <vector>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 namespace orc {
 
@@ -888,6 +891,15 @@ using orc::Dual;
 using orc::Sim;
 
 extern "C" {
+
+// Threads the node loops use (OpenMP over z-planes).
+int orc_threads() {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
 
 void* orc_create(int nx, int ny, int nz, double tau) {
   if (nx < 1 || nz < 1 || ny < 4 || !(tau > 0.5)) return nullptr;

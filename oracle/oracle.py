@@ -36,6 +36,8 @@ def _lib():
         L.orc_create.restype = ctypes.c_void_p
         L.orc_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double]
         L.orc_destroy.argtypes = [ctypes.c_void_p]
+        L.orc_threads.restype = ctypes.c_int
+        L.orc_threads.argtypes = []
         L.orc_fluid_nodes.restype = ctypes.c_long
         L.orc_fluid_nodes.argtypes = [ctypes.c_void_p]
         for name, extra in [
@@ -64,6 +66,11 @@ def _lib():
         L.orc_dual_forces.restype = None
         _LIB = L
     return _LIB
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's node loops use."""
+    return int(_lib().orc_threads())
 
 
 def _p(a):

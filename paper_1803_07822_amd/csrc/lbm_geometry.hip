@@ -1,0 +1,278 @@
+// Geometry precompute (FP64): chart -> J, g, g^{-1}, sqrt g, Christoffel
+// symbols and the contravariant body force at every fluid node (App. A), with
+// the fourth-order isotropic lattice derivative of App. D,
+//   D_i f = G_i[f - (c_s^2/2) L f],
+//   G_i f = (1/c_s^2) sum_l w_l c_l^i f(x + c_l),
+//   L f   = (2/c_s^2) sum_l w_l (f(x + c_l) - f(x)).
+// The chart is split into the identity and a displacement u that is periodic
+// in x and z (the stencils are exact on the identity, so J = I + D u).  In y,
+// u is continued three layers past each wall layer by the cubic through the
+// four nearest layers.  Each stage is a separate, embarrassingly parallel
+// pass over the y-extended grid (memory bound; runs once per metric update).
+#include "lbm_internal.h"
+
+namespace lbm {
+
+namespace {
+
+__device__ __forceinline__ int wrap(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
+
+// extended-grid index, layer j in [-3, ny+2]
+__device__ __forceinline__ long long eidx(const Grid& g, int i, int j, int k) {
+  return ((long long)k * (g.ny + 6) + (j + 3)) * g.nx + i;
+}
+
+__device__ __forceinline__ void inv3(const double m[3][3], double r[3][3], double& det) {
+  det = m[0][0] * (m[1][1] * m[2][2] - m[1][2] * m[2][1]) - m[0][1] * (m[1][0] * m[2][2] - m[1][2] * m[2][0]) +
+        m[0][2] * (m[1][0] * m[2][1] - m[1][1] * m[2][0]);
+  const double id = 1.0 / det;
+  r[0][0] = (m[1][1] * m[2][2] - m[1][2] * m[2][1]) * id;
+  r[0][1] = (m[0][2] * m[2][1] - m[0][1] * m[2][2]) * id;
+  r[0][2] = (m[0][1] * m[1][2] - m[0][2] * m[1][1]) * id;
+  r[1][0] = (m[1][2] * m[2][0] - m[1][0] * m[2][2]) * id;
+  r[1][1] = (m[0][0] * m[2][2] - m[0][2] * m[2][0]) * id;
+  r[1][2] = (m[0][2] * m[1][0] - m[0][0] * m[1][2]) * id;
+  r[2][0] = (m[1][0] * m[2][1] - m[1][1] * m[2][0]) * id;
+  r[2][1] = (m[0][1] * m[2][0] - m[0][0] * m[2][1]) * id;
+  r[2][2] = (m[0][0] * m[1][1] - m[0][1] * m[1][0]) * id;
+}
+
+__global__ void k_chart_from_disp(Grid g, const double* __restrict__ disp, double* __restrict__ chart) {
+  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  if (i >= g.nx || j >= g.ny) return;
+  const long long NC = (long long)g.nz * g.ny * g.nx;
+  const long long p = ((long long)k * g.ny + j) * g.nx + i;
+  const long long q = (long long)k * g.nx + i;
+  const double eta = j - 0.5, s = eta / g.H;
+  chart[p] = (double)i;
+  chart[NC + p] = (double)j + (1.0 - s) * disp[q] + s * disp[(long long)g.nz * g.nx + q];
+  chart[2 * NC + p] = (double)k;
+}
+
+// u = chart - xi on layers 0..ny-1, cubic continuation on -3..-1 and ny..ny+2.
+__global__ void k_uext(Grid g, const double* __restrict__ chart, double* __restrict__ u) {
+  const int i = blockIdx.x * BX + threadIdx.x, je = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  if (i >= g.nx || je >= g.ny + 6) return;
+  const int j = je - 3;
+  const long long NC = (long long)g.nz * g.ny * g.nx, NE = (long long)g.nz * (g.ny + 6) * g.nx;
+  auto uat = [&](int a, int jj) {
+    const double xi = a == 0 ? (double)i : (a == 1 ? (double)jj : (double)k);
+    return chart[a * NC + ((long long)k * g.ny + jj) * g.nx + i] - xi;
+  };
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    double v;
+    if (j >= 0 && j < g.ny) {
+      v = uat(a, j);
+    } else {
+      // Lagrange cubic through the four nearest layers, evaluated 1..3 layers out
+      const int d = j < 0 ? -j : j - (g.ny - 1);  // 1, 2, 3
+      const int b0 = j < 0 ? 0 : g.ny - 1, s = j < 0 ? 1 : -1;
+      const double u0 = uat(a, b0), u1 = uat(a, b0 + s), u2 = uat(a, b0 + 2 * s), u3 = uat(a, b0 + 3 * s);
+      if (d == 1)
+        v = 4.0 * u0 - 6.0 * u1 + 4.0 * u2 - u3;
+      else if (d == 2)
+        v = 10.0 * u0 - 20.0 * u1 + 15.0 * u2 - 4.0 * u3;
+      else
+        v = 20.0 * u0 - 45.0 * u1 + 36.0 * u2 - 10.0 * u3;
+    }
+    u[a * NE + eidx(g, i, j, k)] = v;
+  }
+}
+
+// out = in - (c_s^2/2) L in = in - sum_l w_l (in(x+c_l) - in(x)) on layers [jlo, jhi]
+__global__ void k_smooth(Grid g, int ncomp, int jlo, int jhi, const double* __restrict__ in, double* __restrict__ out) {
+  const int i = blockIdx.x * BX + threadIdx.x, je = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  const int j = je - 3;
+  if (i >= g.nx || j < jlo || j > jhi) return;
+  const long long NE = (long long)g.nz * (g.ny + 6) * g.nx;
+  const long long e = eidx(g, i, j, k);
+  for (int c = 0; c < ncomp; ++c) {
+    const double* f = in + c * NE;
+    const double f0 = f[e];
+    double s = 0.0;
+    for_q([&](auto L) {
+      constexpr int l = decltype(L)::value;
+      if (l == 0) return;
+      s += wgt(l) * (f[eidx(g, wrap(i + cx(l), g.nx), j + cy(l), wrap(k + cz(l), g.nz))] - f0);
+    });
+    out[c * NE + e] = f0 - s;
+  }
+}
+
+// J = I + G v and g = J^T J on layers [-1, ny]; J also stored at fluid nodes.
+__global__ void k_jac_metric(Grid g, const double* __restrict__ v, double* __restrict__ gext, double* __restrict__ jac) {
+  const int i = blockIdx.x * BX + threadIdx.x, je = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  const int j = je - 3;
+  if (i >= g.nx || j < -1 || j > g.ny) return;
+  const long long NE = (long long)g.nz * (g.ny + 6) * g.nx;
+  double J[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    double s0 = 0, s1 = 0, s2 = 0;
+    for_q([&](auto L) {
+      constexpr int l = decltype(L)::value;
+      if (l == 0) return;
+      const double fv = v[a * NE + eidx(g, wrap(i + cx(l), g.nx), j + cy(l), wrap(k + cz(l), g.nz))];
+      if (cx(l)) s0 += wgt(l) * cx(l) * fv;
+      if (cy(l)) s1 += wgt(l) * cy(l) * fv;
+      if (cz(l)) s2 += wgt(l) * cz(l) * fv;
+    });
+    J[a][0] = (a == 0 ? 1.0 : 0.0) + 3.0 * s0;
+    J[a][1] = (a == 1 ? 1.0 : 0.0) + 3.0 * s1;
+    J[a][2] = (a == 2 ? 1.0 : 0.0) + 3.0 * s2;
+  }
+  const long long e = eidx(g, i, j, k);
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = a; b < 3; ++b)
+      gext[sym(a, b) * NE + e] = J[0][a] * J[0][b] + J[1][a] * J[1][b] + J[2][a] * J[2][b];
+  if (j >= 1 && j <= g.ny - 2) {
+    const long long n = ((long long)k * g.H + (j - 1)) * g.nx + i;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) jac[(a * 3 + b) * g.N + n] = J[a][b];
+  }
+}
+
+// Fluid-node geometry: g^{-1}, sqrt g = det J, Gamma^i_jk = 1/2 g^il (D_j g_kl
+// + D_k g_jl - D_l g_jk) with D_l g = G_l w, and F^i = (J^{-1} F_cart)^i.
+template <class T>
+__global__ void k_geo(Grid g, const double* __restrict__ w, const double* __restrict__ gext,
+                      const double* __restrict__ jac, double F0, double F1, double F2, T* __restrict__ geo) {
+  const int i = blockIdx.x * BX + threadIdx.x, jf = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  if (i >= g.nx || jf >= g.H) return;
+  const int j = jf + 1;
+  const long long NE = (long long)g.nz * (g.ny + 6) * g.nx;
+  const long long n = ((long long)k * g.H + jf) * g.nx + i;
+  const long long e = eidx(g, i, j, k);
+  double gm[3][3], gi[3][3], J[3][3], Ji[3][3], det, detJ;
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      gm[a][b] = gext[sym(a, b) * NE + e];
+      J[a][b] = jac[(a * 3 + b) * g.N + n];
+    }
+  inv3(gm, gi, det);
+  inv3(J, Ji, detJ);
+  // dg[l][q] = D_l g_q
+  double dg[3][6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    double s0 = 0, s1 = 0, s2 = 0;
+    const double* f = w + q * NE;
+    for_q([&](auto L) {
+      constexpr int l = decltype(L)::value;
+      if (l == 0) return;
+      const double fv = f[eidx(g, wrap(i + cx(l), g.nx), j + cy(l), wrap(k + cz(l), g.nz))];
+      if (cx(l)) s0 += wgt(l) * cx(l) * fv;
+      if (cy(l)) s1 += wgt(l) * cy(l) * fv;
+      if (cz(l)) s2 += wgt(l) * cz(l) * fv;
+    });
+    dg[0][q] = 3.0 * s0;
+    dg[1][q] = 3.0 * s1;
+    dg[2][q] = 3.0 * s2;
+  }
+  geo[G_SG * g.N + n] = (T)(detJ - 1.0);
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = a; b < 3; ++b) geo[(G_GI + sym(a, b)) * g.N + n] = (T)(gi[a][b] - (a == b ? 1.0 : 0.0));
+#pragma unroll
+  for (int ii = 0; ii < 3; ++ii)
+#pragma unroll
+    for (int jj = 0; jj < 3; ++jj)
+#pragma unroll
+      for (int kk = jj; kk < 3; ++kk) {
+        double s = 0.0;
+#pragma unroll
+        for (int l = 0; l < 3; ++l)
+          s += gi[ii][l] * (dg[jj][sym(kk, l)] + dg[kk][sym(jj, l)] - dg[l][sym(jj, kk)]);
+        geo[(G_GAM + ii * 6 + sym(jj, kk)) * g.N + n] = (T)(0.5 * s);
+      }
+  const double Fc[3] = {F0, F1, F2};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) geo[(G_F + a) * g.N + n] = (T)(Ji[a][0] * Fc[0] + Ji[a][1] * Fc[1] + Ji[a][2] * Fc[2]);
+}
+
+template <class T>
+__global__ void k_body_force(Grid g, const double* __restrict__ jac, double F0, double F1, double F2, T* __restrict__ geo) {
+  const int i = blockIdx.x * BX + threadIdx.x, jf = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  if (i >= g.nx || jf >= g.H) return;
+  const long long n = ((long long)k * g.H + jf) * g.nx + i;
+  double J[3][3], Ji[3][3], det;
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) J[a][b] = jac[(a * 3 + b) * g.N + n];
+  inv3(J, Ji, det);
+  const double Fc[3] = {F0, F1, F2};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) geo[(G_F + a) * g.N + n] = (T)(Ji[a][0] * Fc[0] + Ji[a][1] * Fc[1] + Ji[a][2] * Fc[2]);
+}
+
+// Chart components J^{-1} v of the Cartesian wall velocity at the fluid node
+// next to each wall.
+template <class T>
+__global__ void k_wall_velocity(Grid g, const double* __restrict__ jac, const double* __restrict__ vwall, T* __restrict__ uw) {
+  const int i = blockIdx.x * BX + threadIdx.x, k = blockIdx.y * BY + threadIdx.y;
+  if (i >= g.nx || k >= g.nz) return;
+  for (int w = 0; w < 2; ++w) {
+    const int jf = w == 0 ? 0 : g.H - 1;
+    const long long n = ((long long)k * g.H + jf) * g.nx + i;
+    double J[3][3], Ji[3][3], det;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) J[a][b] = jac[(a * 3 + b) * g.N + n];
+    inv3(J, Ji, det);
+    const long long c = (((long long)w * g.nz + k) * g.nx + i) * 3;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+      uw[c + a] = (T)(Ji[a][0] * vwall[c] + Ji[a][1] * vwall[c + 1] + Ji[a][2] * vwall[c + 2]);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_chart_from_disp(Fields& F, hipStream_t s) {
+  dim3 b(BX, BY), gr((F.g.nx + BX - 1) / BX, (F.g.ny + BY - 1) / BY, F.g.nz);
+  hipLaunchKernelGGL(k_chart_from_disp, gr, b, 0, s, F.g, F.disp, F.chart);
+  return hipGetLastError();
+}
+
+template <class T> hipError_t launch_geometry(Fields& F, hipStream_t s, const double Fc[3]) {
+  const Grid g = F.g;
+  dim3 b(BX, BY);
+  double* u = F.uext[F.uext_cur];
+  hipLaunchKernelGGL(k_uext, ext_grid(g), b, 0, s, g, F.chart, u);
+  hipLaunchKernelGGL(k_smooth, ext_grid(g), b, 0, s, g, 3, -2, g.ny + 1, u, F.vtmp);
+  hipLaunchKernelGGL(k_jac_metric, ext_grid(g), b, 0, s, g, F.vtmp, F.gext, F.jac);
+  hipLaunchKernelGGL(k_smooth, ext_grid(g), b, 0, s, g, 6, 0, g.ny - 1, F.gext, F.wext);
+  hipLaunchKernelGGL(k_geo<T>, fluid_grid(g), b, 0, s, g, F.wext, F.gext, F.jac, Fc[0], Fc[1], Fc[2], (T*)F.geo);
+  return hipGetLastError();
+}
+
+template <class T> hipError_t launch_body_force(Fields& F, hipStream_t s, const double Fc[3]) {
+  dim3 b(BX, BY);
+  hipLaunchKernelGGL(k_body_force<T>, fluid_grid(F.g), b, 0, s, F.g, F.jac, Fc[0], Fc[1], Fc[2], (T*)F.geo);
+  return hipGetLastError();
+}
+
+template <class T> hipError_t launch_wall_velocity(Fields& F, hipStream_t s) {
+  dim3 b(BX, BY);
+  hipLaunchKernelGGL(k_wall_velocity<T>, col_grid(F.g), b, 0, s, F.g, F.jac, F.vwall, (T*)F.uw);
+  return hipGetLastError();
+}
+
+template hipError_t launch_geometry<double>(Fields&, hipStream_t, const double*);
+template hipError_t launch_geometry<float>(Fields&, hipStream_t, const double*);
+template hipError_t launch_body_force<double>(Fields&, hipStream_t, const double*);
+template hipError_t launch_body_force<float>(Fields&, hipStream_t, const double*);
+template hipError_t launch_wall_velocity<double>(Fields&, hipStream_t);
+template hipError_t launch_wall_velocity<float>(Fields&, hipStream_t);
+
+}  // namespace lbm

@@ -1,0 +1,79 @@
+// Host-side launchers shared between the kernel translation units and the
+// C-ABI implementation.  Every launcher enqueues on the given stream and
+// returns the launch status.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "lbm_device.h"
+
+namespace lbm {
+
+// Device buffers of one context, carved from the caller's workspace.
+struct Fields {
+  Grid g;
+  long long NE;   // nodes of the y-extended grid, nz * (ny + 6) * nx
+  long long NC;   // nodes of the full grid, nz * ny * nx
+  double* chart;  // [3][NC] current chart
+  double* uext[2];// [3][NE] chart displacement on the extended grid (current / previous)
+  double* vtmp;   // [3][NE]
+  double* gext;   // [6][NE]
+  double* wext;   // [6][NE]
+  double* jac;    // [9][N] J = dh/dxi at fluid nodes
+  void* geo;      // [28][N] T
+  void* pop[2];   // [19][N] T
+  void* hist;     // [10][N] T
+  void* mom;      // [4][N] T
+  void* uw;       // [2][nz][nx][3] T
+  double* disp;   // [2][nz][nx]
+  double* vwall;  // [2][nz][nx][3] Cartesian wall velocity
+  double* full;   // [19][N] FP64 scratch
+  double* mf;     // [20][NC] Cartesian moment fields for re-projection
+  double* part;   // reduction partials
+  int* flag;      // instability guard
+  int cur;        // index of the current population buffer
+  int uext_cur;   // index of the current extended displacement
+  int moving[2];
+};
+
+constexpr int BX = 64, BY = 4;
+constexpr size_t ALIGN = 256;
+
+// Carves the caller's workspace into aligned buffers; with base == nullptr it
+// only counts bytes (used by lbm_workspace_bytes).
+struct Carver {
+  char* base;
+  size_t off = 0;
+  explicit Carver(char* b) : base(b) {}
+  void* take(size_t n) {
+    off = (off + ALIGN - 1) / ALIGN * ALIGN;
+    void* p = base ? base + off : nullptr;
+    off += n;
+    return p;
+  }
+};
+
+inline dim3 fluid_grid(const Grid& g) { return dim3((g.nx + BX - 1) / BX, (g.H + BY - 1) / BY, g.nz); }
+inline dim3 ext_grid(const Grid& g) { return dim3((g.nx + BX - 1) / BX, (g.ny + 6 + BY - 1) / BY, g.nz); }
+inline dim3 col_grid(const Grid& g) { return dim3((g.nx + BX - 1) / BX, (g.nz + BY - 1) / BY, 1); }
+
+// geometry (FP64 precompute; writes geo in precision T)
+template <class T> hipError_t launch_geometry(Fields& F, hipStream_t s, const double Fc[3]);
+template <class T> hipError_t launch_body_force(Fields& F, hipStream_t s, const double Fc[3]);
+template <class T> hipError_t launch_wall_velocity(Fields& F, hipStream_t s);
+hipError_t launch_chart_from_disp(Fields& F, hipStream_t s);
+
+// state
+template <class T> hipError_t launch_feq_full(Fields& F, hipStream_t s, const double* rho, const double* uc);
+template <class T> hipError_t launch_set_state(Fields& F, hipStream_t s, const double* f, T tau);
+template <class T> hipError_t launch_get_pops(Fields& F, hipStream_t s, double* out);
+template <class T> hipError_t launch_get_hist(Fields& F, hipStream_t s, double* out);
+template <class T> hipError_t launch_get_geo(Fields& F, hipStream_t s, double* out);
+constexpr int STEP_KERNELS = 2;  // kernels per step (timed separately by lbm_step_profiled)
+template <class T> hipError_t launch_step(Fields& F, hipStream_t s, T tau, hipEvent_t* ev = nullptr);
+template <class T> hipError_t launch_moments_out(Fields& F, hipStream_t s, double* rho, double* u, int cart);
+template <class T> hipError_t launch_wall_force(Fields& F, hipStream_t s, int wall, T tau, double* total,
+                                                double* per_node);
+template <class T> hipError_t launch_reproject(Fields& F, hipStream_t s, const double Fc[3], T tau);
+
+}  // namespace lbm

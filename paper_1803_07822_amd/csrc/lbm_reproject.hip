@@ -1,0 +1,333 @@
+// Re-projection of the state onto a new chart (Sec. IV.B).
+//
+// The populations depend on space only through their Hermite moments, so the
+// state is carried by its moments: rho, rho u and the momentum flux
+// Pi = sqrt g sum f c c at the old nodes, and the forcing history (A, B, C).
+// They are pushed to Cartesian components with the old J (tensor rule,
+// Eq. vector_transform), interpolated trilinearly at psi(x~) = h^{-1}(h~(x~))
+// (found by Newton on the trilinear interpolant of the old chart), pulled
+// back with the new J^{-1}, and recomposed to second order in the new chart
+// (a2 = Pi~ - c_s^2 rho I).  The layers outside the walls carry ghosts: rho u
+// by the mirror rule about rho v_wall, the other moments by linear
+// extrapolation.  Moments and geometry are handled in FP64; populations end in
+// the storage precision.
+#include "lbm_internal.h"
+
+namespace lbm {
+
+namespace {
+
+__device__ __forceinline__ int wrapr(int a, int n) {
+  a %= n;
+  return a < 0 ? a + n : a;
+}
+
+constexpr int NMF = 20;  // 0 rho, 1-3 j, 4-9 Pi, 10 A, 11-13 B, 14-19 C (Cartesian)
+
+__device__ __forceinline__ void inv3d(const double m[3][3], double r[3][3]) {
+  const double det = m[0][0] * (m[1][1] * m[2][2] - m[1][2] * m[2][1]) -
+                     m[0][1] * (m[1][0] * m[2][2] - m[1][2] * m[2][0]) +
+                     m[0][2] * (m[1][0] * m[2][1] - m[1][1] * m[2][0]);
+  r[0][0] = (m[1][1] * m[2][2] - m[1][2] * m[2][1]) / det;
+  r[0][1] = (m[0][2] * m[2][1] - m[0][1] * m[2][2]) / det;
+  r[0][2] = (m[0][1] * m[1][2] - m[0][2] * m[1][1]) / det;
+  r[1][0] = (m[1][2] * m[2][0] - m[1][0] * m[2][2]) / det;
+  r[1][1] = (m[0][0] * m[2][2] - m[0][2] * m[2][0]) / det;
+  r[1][2] = (m[0][2] * m[1][0] - m[0][0] * m[1][2]) / det;
+  r[2][0] = (m[1][0] * m[2][1] - m[1][1] * m[2][0]) / det;
+  r[2][1] = (m[0][1] * m[2][0] - m[0][0] * m[2][1]) / det;
+  r[2][2] = (m[0][0] * m[1][1] - m[0][1] * m[1][0]) / det;
+}
+
+template <class T, int l>
+__device__ __forceinline__ T pull_rp(const T* __restrict__ pop, const Grid& g, int i, int jf, int k, long long n) {
+  constexpr int x = cx(l), y = cy(l), z = cz(l);
+  if ((y > 0 && jf == 0) || (y < 0 && jf == g.H - 1)) return pop[(long long)opp(l) * g.N + n];
+  const int is = x ? wrapr(i - x, g.nx) : i;
+  const int ks = z ? wrapr(k - z, g.nz) : k;
+  return pop[(long long)l * g.N + ((long long)ks * g.H + (jf - y)) * g.nx + is];
+}
+
+// Cartesian moment fields at the old fluid nodes.
+template <class T>
+__global__ void k_rp_moments(Grid g, const T* __restrict__ pop, const T* __restrict__ hist, const T* __restrict__ geo,
+                             const double* __restrict__ jac, double* __restrict__ mf) {
+  const int i = blockIdx.x * BX + threadIdx.x, jf = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  if (i >= g.nx || jf >= g.H) return;
+  const long long n = ((long long)k * g.H + jf) * g.nx + i;
+  const long long NC = (long long)g.nz * g.ny * g.nx;
+  const long long e = ((long long)k * g.ny + (jf + 1)) * g.nx + i;
+  Coef<T> c;
+  c.A = hist[H_A * g.N + n];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) c.B[a] = hist[(H_B + a) * g.N + n];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) c.C[q] = hist[(H_C + q) * g.N + n];
+  const T sgd = geo[G_SG * g.N + n];
+  const T isg = T(1) / (T(1) + sgd);
+  T Fp[Q];
+  forcing_pops(c, isg, Fp);
+  double s = 0, jv[3] = {0, 0, 0}, P[6] = {0, 0, 0, 0, 0, 0};
+  for_q([&](auto L) {
+    constexpr int l = decltype(L)::value;
+    const double v = (double)pull_rp<T, l>(pop, g, i, jf, k, n) + 0.5 * (double)Fp[l];
+    constexpr int x = cx(l), y = cy(l), z = cz(l);
+    s += v;
+    if (x) jv[0] += x * v;
+    if (y) jv[1] += y * v;
+    if (z) jv[2] += z * v;
+    if (x) P[0] += v;
+    if (y) P[3] += v;
+    if (z) P[5] += v;
+    if (x && y) P[1] += x * y * v;
+    if (x && z) P[2] += x * z * v;
+    if (y && z) P[4] += y * z * v;
+  });
+  const double sg = 1.0 + (double)sgd;
+  double J[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) J[a][b] = jac[(a * 3 + b) * g.N + n];
+  // f = w + f~: sum w = 1, sum w c c = I/3
+  const double rho = sg * (1.0 + s);
+  double j[3], Pm[3][3], Bv[3], Cm[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    j[a] = sg * jv[a];
+    Bv[a] = (double)c.B[a];
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      Pm[a][b] = sg * ((a == b ? 1.0 / 3.0 : 0.0) + P[sym(a, b)]);
+      Cm[a][b] = (double)c.C[sym(a, b)];
+    }
+  mf[0 * NC + e] = rho;
+  mf[10 * NC + e] = (double)c.A;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    mf[(1 + a) * NC + e] = J[a][0] * j[0] + J[a][1] * j[1] + J[a][2] * j[2];
+    mf[(11 + a) * NC + e] = J[a][0] * Bv[0] + J[a][1] * Bv[1] + J[a][2] * Bv[2];
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = a; b < 3; ++b) {
+      double sp = 0.0, sc = 0.0;
+#pragma unroll
+      for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+          sp += J[a][p] * Pm[p][r] * J[b][r];
+          sc += J[a][p] * Cm[p][r] * J[b][r];
+        }
+      mf[(4 + sym(a, b)) * NC + e] = sp;
+      mf[(14 + sym(a, b)) * NC + e] = sc;
+    }
+}
+
+__global__ void k_rp_ghost(Grid g, const double* __restrict__ vwall, double* __restrict__ mf) {
+  const int i = blockIdx.x * BX + threadIdx.x, k = blockIdx.y * BY + threadIdx.y;
+  if (i >= g.nx || k >= g.nz) return;
+  const long long NC = (long long)g.nz * g.ny * g.nx;
+  for (int w = 0; w < 2; ++w) {
+    const int jg = w == 0 ? 0 : g.ny - 1, jm = w == 0 ? 1 : g.ny - 2, jm2 = w == 0 ? 2 : g.ny - 3;
+    const long long eg = ((long long)k * g.ny + jg) * g.nx + i;
+    const long long em = ((long long)k * g.ny + jm) * g.nx + i;
+    const long long em2 = ((long long)k * g.ny + jm2) * g.nx + i;
+    for (int q = 0; q < NMF; ++q) mf[q * NC + eg] = 2.0 * mf[q * NC + em] - mf[q * NC + em2];
+    const long long c = (((long long)w * g.nz + k) * g.nx + i) * 3;
+    for (int a = 0; a < 3; ++a) mf[(1 + a) * NC + eg] = 2.0 * mf[em] * vwall[c + a] - mf[(1 + a) * NC + em];
+  }
+}
+
+// Trilinear value and gradient of an extended-grid field (layers -3..ny+2).
+__device__ __forceinline__ double trilin_ext(const Grid& g, const double* __restrict__ F, const double p[3],
+                                             double grad[3]) {
+  const int bx = (int)floor(p[0]), bz = (int)floor(p[2]);
+  int by = (int)floor(p[1]);
+  if (by < -3) by = -3;
+  if (by > g.ny + 1) by = g.ny + 1;
+  const double fr[3] = {p[0] - bx, p[1] - by, p[2] - bz};
+  double v = 0.0;
+  grad[0] = grad[1] = grad[2] = 0.0;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int ox = c & 1, oy = (c >> 1) & 1, oz = (c >> 2) & 1;
+    const double wx = ox ? fr[0] : 1.0 - fr[0];
+    const double wy = oy ? fr[1] : 1.0 - fr[1];
+    const double wz = oz ? fr[2] : 1.0 - fr[2];
+    const double fv =
+        F[((long long)wrapr(bz + oz, g.nz) * (g.ny + 6) + (by + oy + 3)) * g.nx + wrapr(bx + ox, g.nx)];
+    v += wx * wy * wz * fv;
+    grad[0] += (ox ? 1.0 : -1.0) * wy * wz * fv;
+    grad[1] += wx * (oy ? 1.0 : -1.0) * wz * fv;
+    grad[2] += wx * wy * (oz ? 1.0 : -1.0) * fv;
+  }
+  return v;
+}
+
+// New state at the new fluid nodes; writes the streamed deviations g~ (FP64)
+// and the new history.
+template <class T>
+__global__ void k_rp_new(Grid g, const double* __restrict__ chart, const double* __restrict__ uold,
+                         const double* __restrict__ mf, const double* __restrict__ jac, const T* __restrict__ geo,
+                         double* __restrict__ gs, T* __restrict__ hist) {
+  const int i = blockIdx.x * BX + threadIdx.x, jf = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  if (i >= g.nx || jf >= g.H) return;
+  const long long n = ((long long)k * g.H + jf) * g.nx + i;
+  const long long NC = (long long)g.nz * g.ny * g.nx, NE = (long long)g.nz * (g.ny + 6) * g.nx;
+  const long long pc = ((long long)k * g.ny + (jf + 1)) * g.nx + i;
+  const double p[3] = {chart[pc], chart[NC + pc], chart[2 * NC + pc]};
+  // psi: xi + u_old(xi) = p
+  double xi[3] = {(double)i, (double)(jf + 1), (double)k};
+  for (int it = 0; it < 50; ++it) {
+    double r[3], Jm[3][3], Ji[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      double gr[3];
+      r[a] = xi[a] + trilin_ext(g, uold + a * NE, xi, gr) - p[a];
+#pragma unroll
+      for (int b = 0; b < 3; ++b) Jm[a][b] = (a == b ? 1.0 : 0.0) + gr[b];
+    }
+    inv3d(Jm, Ji);
+    double dmax = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const double d = Ji[a][0] * r[0] + Ji[a][1] * r[1] + Ji[a][2] * r[2];
+      xi[a] -= d;
+      dmax = fmax(dmax, fabs(d));
+    }
+    if (dmax <= 1e-13 * (1.0 + fabs(xi[0]) + fabs(xi[1]) + fabs(xi[2]))) break;
+  }
+  // trilinear interpolation of the moment fields, y inside layers 0..ny-1
+  double q1 = xi[1];
+  if (q1 < 0.0) q1 = 0.0;
+  if (q1 > g.ny - 1.0) q1 = g.ny - 1.0;
+  const int bx = (int)floor(xi[0]), bz = (int)floor(xi[2]);
+  int by = (int)floor(q1);
+  if (by > g.ny - 2) by = g.ny - 2;
+  if (by < 0) by = 0;
+  const double fx = xi[0] - bx, fy = q1 - by, fz = xi[2] - bz;
+  double m[NMF];
+#pragma unroll
+  for (int q = 0; q < NMF; ++q) m[q] = 0.0;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int ox = c & 1, oy = (c >> 1) & 1, oz = (c >> 2) & 1;
+    const double w = (ox ? fx : 1.0 - fx) * (oy ? fy : 1.0 - fy) * (oz ? fz : 1.0 - fz);
+    const long long e = ((long long)wrapr(bz + oz, g.nz) * g.ny + (by + oy)) * g.nx + wrapr(bx + ox, g.nx);
+#pragma unroll
+    for (int q = 0; q < NMF; ++q) m[q] += w * mf[q * NC + e];
+  }
+  // pull back with the new J^{-1}
+  double J[3][3], Ji[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) J[a][b] = jac[(a * 3 + b) * g.N + n];
+  inv3d(J, Ji);
+  double Pc[3][3], Cc[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      Pc[a][b] = m[4 + sym(a, b)];
+      Cc[a][b] = m[14 + sym(a, b)];
+    }
+  double jt[3], Bt[3], a2[6], Ct[6];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    jt[a] = Ji[a][0] * m[1] + Ji[a][1] * m[2] + Ji[a][2] * m[3];
+    Bt[a] = Ji[a][0] * m[11] + Ji[a][1] * m[12] + Ji[a][2] * m[13];
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = a; b < 3; ++b) {
+      double sp = 0.0, sc = 0.0;
+#pragma unroll
+      for (int p1 = 0; p1 < 3; ++p1)
+#pragma unroll
+        for (int r1 = 0; r1 < 3; ++r1) {
+          sp += Ji[a][p1] * Pc[p1][r1] * Ji[b][r1];
+          sc += Ji[a][p1] * Cc[p1][r1] * Ji[b][r1];
+        }
+      a2[sym(a, b)] = sp - (a == b ? m[0] / 3.0 : 0.0);
+      Ct[sym(a, b)] = sc;
+    }
+  // new history (in storage precision) and the F(t-1)/2 it implies
+  Coef<T> c;
+  c.A = (T)m[10];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) c.B[a] = (T)Bt[a];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) c.C[q] = (T)Ct[q];
+  hist[H_A * g.N + n] = c.A;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) hist[(H_B + a) * g.N + n] = c.B[a];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) hist[(H_C + q) * g.N + n] = c.C[q];
+  const T sgd = geo[G_SG * g.N + n];
+  const T isg = T(1) / (T(1) + sgd);
+  T Fp[Q];
+  forcing_pops(c, isg, Fp);
+  // f~ - w = (w/sqrt g)[rho + 3 j.c + 4.5 a2:cc - 1.5 tr a2] - w
+  const double sg = 1.0 + (double)sgd;
+  const double a0 = m[0] - sg;  // (rho/sqrt g - 1) sqrt g
+  for_q([&](auto L) {
+    constexpr int l = decltype(L)::value;
+    const double fdev = wgt(l) / sg * hermite_term<double, l>(a0, jt, a2);
+    gs[(long long)l * g.N + n] = fdev - 0.5 * (double)Fp[l];
+  });
+}
+
+// pop[l][y] = g~_l(y + c_l) if fluid, else g~_opp(l)(y)
+template <class T>
+__global__ void k_rp_unpull(Grid g, const double* __restrict__ gs, T* __restrict__ pop) {
+  const int i = blockIdx.x * BX + threadIdx.x, jf = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  if (i >= g.nx || jf >= g.H) return;
+  const long long n = ((long long)k * g.H + jf) * g.nx + i;
+  for_q([&](auto L) {
+    constexpr int l = decltype(L)::value;
+    constexpr int x = cx(l), y = cy(l), z = cz(l);
+    const int jd = jf + y;
+    double v;
+    if (jd < 0 || jd >= g.H) {
+      v = gs[(long long)opp(l) * g.N + n];
+    } else {
+      const int id = x ? wrapr(i + x, g.nx) : i;
+      const int kd = z ? wrapr(k + z, g.nz) : k;
+      v = gs[(long long)l * g.N + ((long long)kd * g.H + jd) * g.nx + id];
+    }
+    pop[(long long)l * g.N + n] = (T)v;
+  });
+}
+
+}  // namespace
+
+// Precondition: F.chart holds the new chart; uext/jac/geo still describe the
+// old one.  Computes the new geometry on the way.
+template <class T> hipError_t launch_reproject(Fields& F, hipStream_t s, const double Fc[3], T tau) {
+  (void)tau;
+  const Grid g = F.g;
+  dim3 b(BX, BY);
+  hipLaunchKernelGGL(k_rp_moments<T>, fluid_grid(g), b, 0, s, g, (const T*)F.pop[F.cur], (const T*)F.hist,
+                     (const T*)F.geo, (const double*)F.jac, F.mf);
+  hipLaunchKernelGGL(k_rp_ghost, col_grid(g), b, 0, s, g, (const double*)F.vwall, F.mf);
+  const int old = F.uext_cur;
+  F.uext_cur ^= 1;
+  hipError_t e = launch_geometry<T>(F, s, Fc);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_rp_new<T>, fluid_grid(g), b, 0, s, g, (const double*)F.chart, (const double*)F.uext[old],
+                     (const double*)F.mf, (const double*)F.jac, (const T*)F.geo, F.full, (T*)F.hist);
+  hipLaunchKernelGGL(k_rp_unpull<T>, fluid_grid(g), b, 0, s, g, (const double*)F.full, (T*)F.pop[F.cur]);
+  return hipGetLastError();
+}
+
+template hipError_t launch_reproject<double>(Fields&, hipStream_t, const double*, double);
+template hipError_t launch_reproject<float>(Fields&, hipStream_t, const double*, float);
+
+}  // namespace lbm

@@ -1,0 +1,570 @@
+// One time step of the curved-space D3Q19 scheme, and the kernels that move
+// state in and out.
+//
+// Storage ("pull" layout): pop[l][x] holds the post-collision deviation
+// f*_l(x) - w_l of node x, except on links that leave the fluid through a
+// wall, where it holds the bounced value f*_l - 2 (w_l/sqrt g) rho (c_l.u_w)/c_s^2
+// destined to come back to x as direction opp(l).  The streamed value of
+// Eq. (streaming) at node x is therefore
+//   g_l(x) = pop[l][x - c_l]   if x - c_l is a fluid node,
+//          = pop[opp(l)][x]    otherwise (halfway bounce-back),
+// and f_l(x, t) = g_l(x) + F_l(x, t-1)/2, with F(x, t-1) rebuilt from the ten
+// history coefficients of x.  Reads are shifted by at most one node in each
+// direction; all writes are aligned and coalesced.
+//
+// A step is two passes.  The lattice gradient d_k(rho u^i) (App. D, radius 1)
+// needs the momentum of all 18 neighbours before any collision, so pass 1
+// forms rho and rho u at every node, and pass 2 does the rest of the step
+// node-locally: equilibrium, stress, forcing A/B/C, collision, bounce-back
+// term, history update.
+#include "lbm_internal.h"
+
+namespace lbm {
+
+namespace {
+
+__device__ __forceinline__ int wrapd(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
+
+struct Pos {
+  int i, jf, k;
+  long long n;
+};
+
+__device__ __forceinline__ bool node_pos(const Grid& g, Pos& p) {
+  p.i = blockIdx.x * BX + threadIdx.x;
+  p.jf = blockIdx.y * BY + threadIdx.y;
+  p.k = blockIdx.z;
+  if (p.i >= g.nx || p.jf >= g.H) return false;
+  p.n = ((long long)p.k * g.H + p.jf) * g.nx + p.i;
+  return true;
+}
+
+template <class T, int l>
+__device__ __forceinline__ T pull(const T* __restrict__ pop, const Grid& g, const Pos& p) {
+  constexpr int x = cx(l), y = cy(l), z = cz(l);
+  if ((y > 0 && p.jf == 0) || (y < 0 && p.jf == g.H - 1)) return pop[(long long)opp(l) * g.N + p.n];
+  const int is = x ? wrapd(p.i - x, g.nx) : p.i;
+  const int ks = z ? wrapd(p.k - z, g.nz) : p.k;
+  const int js = p.jf - y;
+  return pop[(long long)l * g.N + ((long long)ks * g.H + js) * g.nx + is];
+}
+
+template <class T>
+__device__ __forceinline__ void load_coef(const T* __restrict__ hist, long long N, long long n, Coef<T>& c) {
+  c.A = hist[H_A * N + n];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) c.B[a] = hist[(H_B + a) * N + n];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) c.C[q] = hist[(H_C + q) * N + n];
+}
+
+template <class T>
+__device__ __forceinline__ void store_coef(T* __restrict__ hist, long long N, long long n, const Coef<T>& c) {
+  hist[H_A * N + n] = c.A;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) hist[(H_B + a) * N + n] = c.B[a];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) hist[(H_C + q) * N + n] = c.C[q];
+}
+
+// rho - 1 and rho u of the streamed state at p: rho = sqrt g sum_l g_l + A/2,
+// rho u = sqrt g sum_l g_l c_l + B/2 (the half history term summed in closed
+// form: sum_l F_l sqrt g = A, sum_l F_l c_l sqrt g = B).
+template <class T>
+__device__ __forceinline__ void streamed_moments(const T* __restrict__ pop, const T* __restrict__ hist, T sgd,
+                                                 const Grid& g, const Pos& p, T& dr, T j[3]) {
+  T s = 0, j0 = 0, j1 = 0, j2 = 0;
+  for_q([&](auto L) {
+    constexpr int l = decltype(L)::value;
+    const T v = pull<T, l>(pop, g, p);
+    s += v;
+    if (cx(l)) j0 += T(cx(l)) * v;
+    if (cy(l)) j1 += T(cy(l)) * v;
+    if (cz(l)) j2 += T(cz(l)) * v;
+  });
+  const T sg = T(1) + sgd;
+  dr = sgd + sg * s + T(0.5) * hist[H_A * g.N + p.n];
+  j[0] = sg * j0 + T(0.5) * hist[(H_B + 0) * g.N + p.n];
+  j[1] = sg * j1 + T(0.5) * hist[(H_B + 1) * g.N + p.n];
+  j[2] = sg * j2 + T(0.5) * hist[(H_B + 2) * g.N + p.n];
+}
+
+// Second-order isotropic lattice gradient dj[k][i] = (1/c_s^2) sum_l w_l c_l^k
+// j^i(x + c_l) (App. D).  Neighbours in a wall layer carry the mirror ghost
+// j = 2 rho_m u_w - j_m of the fluid node m in the same column next to the wall.
+template <class T>
+__device__ __forceinline__ void lattice_gradient(const T* __restrict__ mom, const T* __restrict__ uw, const int mv0,
+                                                 const int mv1, const Grid& g, const Pos& p, T dj[3][3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) dj[a][b] = T(0);
+  for_q([&](auto L) {
+    constexpr int l = decltype(L)::value;
+    if (l == 0) return;
+    constexpr int x = cx(l), y = cy(l), z = cz(l);
+    const int in = x ? wrapd(p.i + x, g.nx) : p.i;
+    const int kn = z ? wrapd(p.k + z, g.nz) : p.k;
+    const int jn = p.jf + y;
+    T jb[3];
+    if (jn >= 0 && jn < g.H) {
+      const long long m = ((long long)kn * g.H + jn) * g.nx + in;
+      jb[0] = mom[1 * g.N + m];
+      jb[1] = mom[2 * g.N + m];
+      jb[2] = mom[3 * g.N + m];
+    } else {
+      const int w = jn < 0 ? 0 : 1;
+      const long long m = ((long long)kn * g.H + p.jf) * g.nx + in;
+      jb[0] = -mom[1 * g.N + m];
+      jb[1] = -mom[2 * g.N + m];
+      jb[2] = -mom[3 * g.N + m];
+      if (w == 0 ? mv0 : mv1) {
+        const T r2 = T(2) * (T(1) + mom[m]);
+        const long long c = (((long long)w * g.nz + kn) * g.nx + in) * 3;
+        jb[0] += r2 * uw[c];
+        jb[1] += r2 * uw[c + 1];
+        jb[2] += r2 * uw[c + 2];
+      }
+    }
+    constexpr T f = T(3.0 * wgt(l));
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      if (x) dj[0][b] += T(x) * f * jb[b];
+      if (y) dj[1][b] += T(y) * f * jb[b];
+      if (z) dj[2][b] += T(z) * f * jb[b];
+    }
+  });
+}
+
+// ---------------------------------------------------------------- pass 1
+template <class T>
+__global__ __launch_bounds__(BX* BY) void k_moments(Grid g, const T* __restrict__ pop, const T* __restrict__ hist,
+                                                   const T* __restrict__ geo, T* __restrict__ mom) {
+  Pos p;
+  if (!node_pos(g, p)) return;
+  T dr, j[3];
+  streamed_moments(pop, hist, geo[G_SG * g.N + p.n], g, p, dr, j);
+  mom[p.n] = dr;
+  mom[g.N + p.n] = j[0];
+  mom[2 * g.N + p.n] = j[1];
+  mom[3 * g.N + p.n] = j[2];
+}
+
+// ---------------------------------------------------------------- pass 2
+// Collision f* = f - (f - feq)/tau + F(t) - F(t-1)/2 (Eq. collision with the
+// leading f restored) and the bounce-back term of Eq. (streaming) at walls.
+template <class T>
+__global__ __launch_bounds__(BX* BY) void k_collide(Grid g, const T* __restrict__ pin, T* __restrict__ pout,
+                                                   T* __restrict__ hist, const T* __restrict__ geo,
+                                                   const T* __restrict__ mom, const T* __restrict__ uw, int mv0,
+                                                   int mv1, T tau, int* __restrict__ flag) {
+  Pos p;
+  if (!node_pos(g, p)) return;
+  NodeGeo<T> G;
+  load_geo(geo, g.N, p.n, G);
+  Coef<T> cp;
+  load_coef(hist, g.N, p.n, cp);
+  const T sg = T(1) + G.sgd, isg = T(1) / sg;
+  T Fp[Q], ft[Q];
+  forcing_pops(cp, isg, Fp);
+  for_q([&](auto L) {
+    constexpr int l = decltype(L)::value;
+    ft[l] = pull<T, l>(pin, g, p) + T(0.5) * Fp[l];
+  });
+  const T dr = mom[p.n];
+  const T j[3] = {mom[g.N + p.n], mom[2 * g.N + p.n], mom[3 * g.N + p.n]};
+  T dj[3][3];
+  lattice_gradient(mom, uw, mv0, mv1, g, p, dj);
+  T ne[Q], Tm[6];
+  node_stress(G, ft, dr, j, tau, ne, Tm);
+  Coef<T> c;
+  forcing_coef(G, j, Tm, dj, c);
+  T F[Q];
+  forcing_pops(c, isg, F);
+  const T rho = T(1) + dr;
+  const T itau = T(1) / tau;
+  const long long col0 = ((long long)p.k * g.nx + p.i) * 3;
+  T chk = T(0);
+  for_q([&](auto L) {
+    constexpr int l = decltype(L)::value;
+    T v = ft[l] - ne[l] * itau + F[l] - T(0.5) * Fp[l];
+    constexpr int y = cy(l);
+    if ((y > 0 && p.jf == g.H - 1) || (y < 0 && p.jf == 0)) {
+      const int w = y > 0 ? 1 : 0;
+      if (w == 0 ? mv0 : mv1) {
+        const T* u = uw + (long long)w * g.nz * g.nx * 3 + col0;
+        T cu = T(0);
+        if (cx(l)) cu += T(cx(l)) * u[0];
+        cu += T(y) * u[1];
+        if (cz(l)) cu += T(cz(l)) * u[2];
+        v -= T(6.0 * wgt(l)) * isg * rho * cu;
+      }
+    }
+    chk += v;
+    pout[(long long)l * g.N + p.n] = v;
+  });
+  store_coef(hist, g.N, p.n, c);
+  const T uu = j[0] * j[0] + j[1] * j[1] + j[2] * j[2];
+  if (!(rho > T(0)) || !(uu < T(0.1) * rho * rho) || !isfinite(chk)) atomicOr(flag, 1);
+}
+
+// ------------------------------------------------------- state in / out
+// Equilibrium state in FP64: f = w + feq deviations of (rho, J^{-1} u_cart).
+template <class T>
+__global__ void k_feq_full(Grid g, const double* __restrict__ rho_in, const double* __restrict__ uc,
+                           const double* __restrict__ jac, const T* __restrict__ geo, double* __restrict__ full) {
+  Pos p;
+  if (!node_pos(g, p)) return;
+  NodeGeo<double> G;
+  G.sgd = (double)geo[G_SG * g.N + p.n];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) G.gid[q] = (double)geo[(G_GI + q) * g.N + p.n];
+  double J[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) J[a][b] = jac[(a * 3 + b) * g.N + p.n];
+  const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                     J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                     J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+  const double Ji[3][3] = {
+      {(J[1][1] * J[2][2] - J[1][2] * J[2][1]) / det, (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det,
+       (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det},
+      {(J[1][2] * J[2][0] - J[1][0] * J[2][2]) / det, (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det,
+       (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det},
+      {(J[1][0] * J[2][1] - J[1][1] * J[2][0]) / det, (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det,
+       (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det}};
+  const double r = rho_in ? rho_in[p.n] : 1.0;
+  double u[3] = {0, 0, 0};
+  if (uc) {
+    const double v[3] = {uc[p.n], uc[g.N + p.n], uc[2 * g.N + p.n]};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) u[a] = Ji[a][0] * v[0] + Ji[a][1] * v[1] + Ji[a][2] * v[2];
+  }
+  const double j[3] = {r * u[0], r * u[1], r * u[2]};
+  double fe[Q];
+  equilibrium_dev(G, r - 1.0, j, fe);
+  for_q([&](auto L) {
+    constexpr int l = decltype(L)::value;
+    full[(long long)l * g.N + p.n] = wgt(l) + fe[l];
+  });
+}
+
+// Moments of a full FP64 state f (rho = sqrt g sum f, j = sqrt g sum f c).
+template <class T>
+__global__ void k_moments_full(Grid g, const double* __restrict__ f, const T* __restrict__ geo, T* __restrict__ mom) {
+  Pos p;
+  if (!node_pos(g, p)) return;
+  double s = 0, j0 = 0, j1 = 0, j2 = 0;
+  for_q([&](auto L) {
+    constexpr int l = decltype(L)::value;
+    const double v = f[(long long)l * g.N + p.n] - wgt(l);
+    s += v;
+    if (cx(l)) j0 += cx(l) * v;
+    if (cy(l)) j1 += cy(l) * v;
+    if (cz(l)) j2 += cz(l) * v;
+  });
+  const double sgd = (double)geo[G_SG * g.N + p.n], sg = 1.0 + sgd;
+  mom[p.n] = (T)(sgd + sg * s);
+  mom[g.N + p.n] = (T)(sg * j0);
+  mom[2 * g.N + p.n] = (T)(sg * j1);
+  mom[3 * g.N + p.n] = (T)(sg * j2);
+}
+
+// Forcing history of a full state (the forcing F(x, 0) that stands in for
+// F(x, -1) at the first step).
+template <class T>
+__global__ void k_hist_full(Grid g, const double* __restrict__ f, const T* __restrict__ geo, const T* __restrict__ mom,
+                            const T* __restrict__ uw, int mv0, int mv1, T tau, T* __restrict__ hist) {
+  Pos p;
+  if (!node_pos(g, p)) return;
+  NodeGeo<T> G;
+  load_geo(geo, g.N, p.n, G);
+  T ft[Q];
+  for_q([&](auto L) {
+    constexpr int l = decltype(L)::value;
+    ft[l] = (T)(f[(long long)l * g.N + p.n] - wgt(l));
+  });
+  const T dr = mom[p.n];
+  const T j[3] = {mom[g.N + p.n], mom[2 * g.N + p.n], mom[3 * g.N + p.n]};
+  T dj[3][3];
+  lattice_gradient(mom, uw, mv0, mv1, g, p, dj);
+  T ne[Q], Tm[6];
+  node_stress(G, ft, dr, j, tau, ne, Tm);
+  Coef<T> c;
+  forcing_coef(G, j, Tm, dj, c);
+  store_coef(hist, g.N, p.n, c);
+}
+
+// In place: full[l] = f_l - w_l - F_l(history)/2, the streamed deviation g~.
+template <class T>
+__global__ void k_full_to_streamed(Grid g, double* __restrict__ full, const T* __restrict__ hist,
+                                   const T* __restrict__ geo) {
+  Pos p;
+  if (!node_pos(g, p)) return;
+  Coef<T> c;
+  load_coef(hist, g.N, p.n, c);
+  const T isg = T(1) / (T(1) + geo[G_SG * g.N + p.n]);
+  T Fp[Q];
+  forcing_pops(c, isg, Fp);
+  for_q([&](auto L) {
+    constexpr int l = decltype(L)::value;
+    const long long q = (long long)l * g.N + p.n;
+    full[q] = full[q] - wgt(l) - 0.5 * (double)Fp[l];
+  });
+}
+
+// Inverse of the pull: pop[l][y] = g~_l(y + c_l) if y + c_l is fluid, else
+// g~_opp(l)(y).
+template <class T>
+__global__ void k_unpull(Grid g, const double* __restrict__ gs, T* __restrict__ pop) {
+  Pos p;
+  if (!node_pos(g, p)) return;
+  for_q([&](auto L) {
+    constexpr int l = decltype(L)::value;
+    constexpr int x = cx(l), y = cy(l), z = cz(l);
+    const int jd = p.jf + y;
+    double v;
+    if (jd < 0 || jd >= g.H) {
+      v = gs[(long long)opp(l) * g.N + p.n];
+    } else {
+      const int id = x ? wrapd(p.i + x, g.nx) : p.i;
+      const int kd = z ? wrapd(p.k + z, g.nz) : p.k;
+      v = gs[(long long)l * g.N + ((long long)kd * g.H + jd) * g.nx + id];
+    }
+    pop[(long long)l * g.N + p.n] = (T)v;
+  });
+}
+
+template <class T>
+__global__ void k_get_pops(Grid g, const T* __restrict__ pop, const T* __restrict__ hist, const T* __restrict__ geo,
+                           double* __restrict__ out) {
+  Pos p;
+  if (!node_pos(g, p)) return;
+  Coef<T> c;
+  load_coef(hist, g.N, p.n, c);
+  const T isg = T(1) / (T(1) + geo[G_SG * g.N + p.n]);
+  T Fp[Q];
+  forcing_pops(c, isg, Fp);
+  for_q([&](auto L) {
+    constexpr int l = decltype(L)::value;
+    out[(long long)l * g.N + p.n] = wgt(l) + ((double)pull<T, l>(pop, g, p) + 0.5 * (double)Fp[l]);
+  });
+}
+
+template <class T>
+__global__ void k_get_hist(Grid g, const T* __restrict__ hist, double* __restrict__ out) {
+  Pos p;
+  if (!node_pos(g, p)) return;
+  for (int q = 0; q < H_N; ++q) out[q * g.N + p.n] = (double)hist[q * g.N + p.n];
+}
+
+template <class T>
+__global__ void k_get_geo(Grid g, const T* __restrict__ geo, double* __restrict__ out) {
+  Pos p;
+  if (!node_pos(g, p)) return;
+  for (int q = 0; q < G_N; ++q) {
+    double v = (double)geo[q * g.N + p.n];
+    if (q == G_SG || q == G_GI + 0 || q == G_GI + 3 || q == G_GI + 5) v += 1.0;
+    out[q * g.N + p.n] = v;
+  }
+}
+
+template <class T>
+__global__ void k_moments_out(Grid g, const T* __restrict__ pop, const T* __restrict__ hist, const T* __restrict__ geo,
+                              const double* __restrict__ jac, double* __restrict__ rho, double* __restrict__ u,
+                              int cart) {
+  Pos p;
+  if (!node_pos(g, p)) return;
+  T dr, j[3];
+  streamed_moments(pop, hist, geo[G_SG * g.N + p.n], g, p, dr, j);
+  const double r = 1.0 + (double)dr;
+  if (rho) rho[p.n] = r;
+  if (u) {
+    const double v[3] = {(double)j[0] / r, (double)j[1] / r, (double)j[2] / r};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      double s = v[a];
+      if (cart)
+        s = jac[(a * 3 + 0) * g.N + p.n] * v[0] + jac[(a * 3 + 1) * g.N + p.n] * v[1] +
+            jac[(a * 3 + 2) * g.N + p.n] * v[2];
+      u[a * g.N + p.n] = s;
+    }
+  }
+}
+
+// Node-exact wall traction per column: sqrt g T^{i y} e_i at the fluid layer
+// next to the wall (outward normal sign), summed per block.
+template <class T>
+__global__ __launch_bounds__(BX* BY) void k_wall_force(Grid g, int wall, const T* __restrict__ pop,
+                                                      const T* __restrict__ hist, const T* __restrict__ geo,
+                                                      const double* __restrict__ jac, T tau,
+                                                      double* __restrict__ per_node, double* __restrict__ part) {
+  __shared__ double red[3][BX * BY];
+  const int tid = threadIdx.y * BX + threadIdx.x;
+  Pos p;
+  p.i = blockIdx.x * BX + threadIdx.x;
+  p.k = blockIdx.y * BY + threadIdx.y;
+  p.jf = wall == 0 ? 0 : g.H - 1;
+  double t[3] = {0, 0, 0};
+  if (p.i < g.nx && p.k < g.nz) {
+    p.n = ((long long)p.k * g.H + p.jf) * g.nx + p.i;
+    NodeGeo<T> G;
+    load_geo(geo, g.N, p.n, G);
+    Coef<T> cp;
+    load_coef(hist, g.N, p.n, cp);
+    const T isg = T(1) / (T(1) + G.sgd);
+    T Fp[Q], ft[Q];
+    forcing_pops(cp, isg, Fp);
+    for_q([&](auto L) {
+      constexpr int l = decltype(L)::value;
+      ft[l] = pull<T, l>(pop, g, p) + T(0.5) * Fp[l];
+    });
+    T dr, j[3];
+    streamed_moments(pop, hist, G.sgd, g, p, dr, j);
+    T ne[Q], Tm[6];
+    node_stress(G, ft, dr, j, tau, ne, Tm);
+    const double sg = 1.0 + (double)G.sgd, sgn = wall == 0 ? -1.0 : 1.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      double s = 0.0;
+#pragma unroll
+      for (int i2 = 0; i2 < 3; ++i2) s += (double)Tm[sym(i2, 1)] * jac[(a * 3 + i2) * g.N + p.n];
+      t[a] = sgn * sg * s;
+    }
+    if (per_node) {
+      const long long c = ((long long)p.k * g.nx + p.i) * 3;
+      per_node[c] = t[0];
+      per_node[c + 1] = t[1];
+      per_node[c + 2] = t[2];
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) red[a][tid] = t[a];
+  __syncthreads();
+  for (int s = BX * BY / 2; s > 0; s >>= 1) {
+    if (tid < s) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) red[a][tid] += red[a][tid + s];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const long long b = (long long)blockIdx.y * gridDim.x + blockIdx.x;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) part[b * 3 + a] = red[a][0];
+  }
+}
+
+// Fixed-order sum of the block partials (deterministic).
+__global__ void k_sum_partials(int nb, const double* __restrict__ part, double* __restrict__ out) {
+  __shared__ double red[3][256];
+  const int tid = threadIdx.x;
+  double s[3] = {0, 0, 0};
+  for (int b = tid; b < nb; b += 256)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) s[a] += part[b * 3 + a];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) red[a][tid] = s[a];
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (tid < st)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) red[a][tid] += red[a][tid + st];
+    __syncthreads();
+  }
+  if (tid == 0)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) out[a] = red[a][0];
+}
+
+}  // namespace
+
+// One step; with ev != nullptr, events ev[0..2] bracket the two passes.
+template <class T> hipError_t launch_step(Fields& F, hipStream_t s, T tau, hipEvent_t* ev) {
+  const Grid g = F.g;
+  dim3 b(BX, BY);
+  const T* pin = (const T*)F.pop[F.cur];
+  T* pout = (T*)F.pop[F.cur ^ 1];
+  if (ev) hipEventRecord(ev[0], s);
+  hipLaunchKernelGGL(k_moments<T>, fluid_grid(g), b, 0, s, g, pin, (const T*)F.hist, (const T*)F.geo, (T*)F.mom);
+  if (ev) hipEventRecord(ev[1], s);
+  hipLaunchKernelGGL(k_collide<T>, fluid_grid(g), b, 0, s, g, pin, pout, (T*)F.hist, (const T*)F.geo,
+                     (const T*)F.mom, (const T*)F.uw, F.moving[0], F.moving[1], tau, F.flag);
+  if (ev) hipEventRecord(ev[2], s);
+  F.cur ^= 1;
+  return hipGetLastError();
+}
+
+template <class T> hipError_t launch_feq_full(Fields& F, hipStream_t s, const double* rho, const double* uc) {
+  dim3 b(BX, BY);
+  hipLaunchKernelGGL(k_feq_full<T>, fluid_grid(F.g), b, 0, s, F.g, rho, uc, F.jac, (const T*)F.geo, F.full);
+  return hipGetLastError();
+}
+
+// F.full holds a full FP64 state f; build history and the pull layout.
+template <class T> hipError_t launch_set_state(Fields& F, hipStream_t s, const double* f, T tau) {
+  const Grid g = F.g;
+  dim3 b(BX, BY);
+  if (f != F.full) {
+    hipError_t e = hipMemcpyAsync(F.full, f, sizeof(double) * 19 * g.N, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_moments_full<T>, fluid_grid(g), b, 0, s, g, F.full, (const T*)F.geo, (T*)F.mom);
+  hipLaunchKernelGGL(k_hist_full<T>, fluid_grid(g), b, 0, s, g, F.full, (const T*)F.geo, (const T*)F.mom,
+                     (const T*)F.uw, F.moving[0], F.moving[1], tau, (T*)F.hist);
+  hipLaunchKernelGGL(k_full_to_streamed<T>, fluid_grid(g), b, 0, s, g, F.full, (const T*)F.hist, (const T*)F.geo);
+  hipLaunchKernelGGL(k_unpull<T>, fluid_grid(g), b, 0, s, g, (const double*)F.full, (T*)F.pop[F.cur]);
+  return hipGetLastError();
+}
+
+template <class T> hipError_t launch_get_pops(Fields& F, hipStream_t s, double* out) {
+  dim3 b(BX, BY);
+  hipLaunchKernelGGL(k_get_pops<T>, fluid_grid(F.g), b, 0, s, F.g, (const T*)F.pop[F.cur], (const T*)F.hist,
+                     (const T*)F.geo, out);
+  return hipGetLastError();
+}
+
+template <class T> hipError_t launch_get_hist(Fields& F, hipStream_t s, double* out) {
+  dim3 b(BX, BY);
+  hipLaunchKernelGGL(k_get_hist<T>, fluid_grid(F.g), b, 0, s, F.g, (const T*)F.hist, out);
+  return hipGetLastError();
+}
+
+template <class T> hipError_t launch_get_geo(Fields& F, hipStream_t s, double* out) {
+  dim3 b(BX, BY);
+  hipLaunchKernelGGL(k_get_geo<T>, fluid_grid(F.g), b, 0, s, F.g, (const T*)F.geo, out);
+  return hipGetLastError();
+}
+
+template <class T> hipError_t launch_moments_out(Fields& F, hipStream_t s, double* rho, double* u, int cart) {
+  dim3 b(BX, BY);
+  hipLaunchKernelGGL(k_moments_out<T>, fluid_grid(F.g), b, 0, s, F.g, (const T*)F.pop[F.cur], (const T*)F.hist,
+                     (const T*)F.geo, F.jac, rho, u, cart);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_wall_force(Fields& F, hipStream_t s, int wall, T tau, double* total, double* per_node) {
+  dim3 b(BX, BY), gr = col_grid(F.g);
+  hipLaunchKernelGGL(k_wall_force<T>, gr, b, 0, s, F.g, wall, (const T*)F.pop[F.cur], (const T*)F.hist,
+                     (const T*)F.geo, F.jac, tau, per_node, F.part);
+  const int nb = (int)(gr.x * gr.y);
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, nb, (const double*)F.part, total);
+  return hipGetLastError();
+}
+
+#define LBM_INST(T)                                                                                     \
+  template hipError_t launch_step<T>(Fields&, hipStream_t, T, hipEvent_t*);                            \
+  template hipError_t launch_feq_full<T>(Fields&, hipStream_t, const double*, const double*);          \
+  template hipError_t launch_set_state<T>(Fields&, hipStream_t, const double*, T);                     \
+  template hipError_t launch_get_pops<T>(Fields&, hipStream_t, double*);                               \
+  template hipError_t launch_get_hist<T>(Fields&, hipStream_t, double*);                               \
+  template hipError_t launch_get_geo<T>(Fields&, hipStream_t, double*);                                \
+  template hipError_t launch_moments_out<T>(Fields&, hipStream_t, double*, double*, int);              \
+  template hipError_t launch_wall_force<T>(Fields&, hipStream_t, int, T, double*, double*);
+LBM_INST(double)
+LBM_INST(float)
+#undef LBM_INST
+
+}  // namespace lbm

@@ -1,0 +1,296 @@
+"""ctypes binding of ``liblbm.so`` (C-ABI in ``include/lbm.h``).
+
+Argument marshalling only: every step of the method runs in the HIP library.
+PyTorch supplies device memory (the workspace and all arrays) and the stream.
+Importing this module fails if the library has not been built.
+
+Low-level functions carry the C names (``lbm_create``, ``lbm_set_metric``,
+``lbm_step``, ...) and take a context handle plus torch tensors; ``Solver``
+wraps one context with its workspace.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbm.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build the HIP library first (python -c 'import __graft_entry__ as g; g.build()')"
+    )
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+LBM_D3Q19 = 19
+LBM_FP64, LBM_FP32_DEV = 0, 1
+LBM_WALL_YMIN, LBM_WALL_YMAX = 0, 1
+LBM_FORCE_STRESS = 0
+ERRORS = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EHIP", -4: "LBM_ESTATE",
+          -5: "LBM_EUNSTABLE", -6: "LBM_EUNSUPPORTED"}
+
+SYMBOLS = [
+    "lbm_workspace_bytes", "lbm_create", "lbm_reserve_adjoint", "lbm_destroy", "lbm_set_body_force",
+    "lbm_set_metric", "lbm_set_wall_displacement", "lbm_set_wall_velocity", "lbm_init_equilibrium",
+    "lbm_set_populations", "lbm_get_populations", "lbm_get_history", "lbm_get_geometry", "lbm_step",
+    "lbm_step_profiled", "lbm_moments", "lbm_wall_force", "lbm_forward_record", "lbm_backward", "lbm_sync", "lbm_last_error",
+]
+
+
+class lbm_grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int)]
+
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_lib.lbm_workspace_bytes.restype = ctypes.c_size_t
+_lib.lbm_workspace_bytes.argtypes = [ctypes.POINTER(lbm_grid), _I, _I, _I, _I]
+_lib.lbm_create.argtypes = [ctypes.POINTER(_P), ctypes.POINTER(lbm_grid), _I, ctypes.c_double, _I, _P,
+                            ctypes.c_size_t, _P]
+_lib.lbm_reserve_adjoint.argtypes = [_P, _I, _I]
+_lib.lbm_destroy.argtypes = [_P]
+_lib.lbm_set_body_force.argtypes = [_P, ctypes.POINTER(ctypes.c_double)]
+_lib.lbm_set_metric.argtypes = [_P, _P, _I]
+_lib.lbm_set_wall_displacement.argtypes = [_P, _I, _P, _I]
+_lib.lbm_set_wall_velocity.argtypes = [_P, _I, _P]
+_lib.lbm_init_equilibrium.argtypes = [_P, _P, _P]
+_lib.lbm_set_populations.argtypes = [_P, _P]
+_lib.lbm_get_populations.argtypes = [_P, _P]
+_lib.lbm_get_history.argtypes = [_P, _P]
+_lib.lbm_get_geometry.argtypes = [_P, _P, _P]
+_lib.lbm_step.argtypes = [_P, _I]
+_lib.lbm_step_profiled.argtypes = [_P, _I, ctypes.POINTER(ctypes.c_double), _I]
+_lib.lbm_moments.argtypes = [_P, _P, _P, _I]
+_lib.lbm_wall_force.argtypes = [_P, _I, _I, _P, _P]
+_lib.lbm_forward_record.argtypes = [_P, _I, _I, _I, _I, _P]
+_lib.lbm_backward.argtypes = [_P, _P, _P, _P, _P]
+_lib.lbm_sync.argtypes = [_P]
+_lib.lbm_last_error.restype = ctypes.c_char_p
+_lib.lbm_last_error.argtypes = [_P]
+for _n in SYMBOLS:
+    if _n not in ("lbm_workspace_bytes", "lbm_last_error"):
+        getattr(_lib, _n).restype = _I
+
+
+class LBMError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("device arrays must be torch tensors")
+    if t.device.type != "cuda" or t.dtype != torch.float64 or not t.is_contiguous():
+        raise ValueError("device arrays must be contiguous float64 tensors on the GPU")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _check(ctx, code):
+    if code != 0:
+        raise LBMError(code, lbm_last_error(ctx))
+    return code
+
+
+# ------------------------------------------------------- C names, thin wrappers
+def lbm_workspace_bytes(nx, ny, nz, precision=LBM_FP64, adjoint_K=0, ckpt_every=0, lattice=LBM_D3Q19):
+    g = lbm_grid(nx, ny, nz)
+    return int(_lib.lbm_workspace_bytes(ctypes.byref(g), lattice, precision, adjoint_K, ckpt_every))
+
+
+def lbm_create(nx, ny, nz, tau, precision, workspace: torch.Tensor, stream=None, lattice=LBM_D3Q19):
+    g = lbm_grid(nx, ny, nz)
+    h = _P()
+    st = ctypes.c_void_p(stream if stream is not None else torch.cuda.current_stream().cuda_stream)
+    code = _lib.lbm_create(ctypes.byref(h), ctypes.byref(g), lattice, float(tau), precision,
+                           ctypes.c_void_p(workspace.data_ptr()), workspace.numel() * workspace.element_size(), st)
+    if code != 0:
+        raise LBMError(code, "lbm_create failed")
+    return h
+
+
+def lbm_last_error(ctx):
+    m = _lib.lbm_last_error(ctx)
+    return m.decode() if m else ""
+
+
+def lbm_reserve_adjoint(ctx, K, ckpt_every):
+    return _check(ctx, _lib.lbm_reserve_adjoint(ctx, int(K), int(ckpt_every)))
+
+
+def lbm_destroy(ctx):
+    return _lib.lbm_destroy(ctx)
+
+
+def lbm_set_body_force(ctx, F):
+    arr = (ctypes.c_double * 3)(*[float(v) for v in F])
+    return _check(ctx, _lib.lbm_set_body_force(ctx, arr))
+
+
+def lbm_set_metric(ctx, chart, reproject=False):
+    return _check(ctx, _lib.lbm_set_metric(ctx, _ptr(chart), int(bool(reproject))))
+
+
+def lbm_set_wall_displacement(ctx, wall, d, reproject=False):
+    return _check(ctx, _lib.lbm_set_wall_displacement(ctx, int(wall), _ptr(d), int(bool(reproject))))
+
+
+def lbm_set_wall_velocity(ctx, wall, v):
+    return _check(ctx, _lib.lbm_set_wall_velocity(ctx, int(wall), _ptr(v)))
+
+
+def lbm_init_equilibrium(ctx, rho=None, ucart=None):
+    return _check(ctx, _lib.lbm_init_equilibrium(ctx, _ptr(rho), _ptr(ucart)))
+
+
+def lbm_set_populations(ctx, f):
+    return _check(ctx, _lib.lbm_set_populations(ctx, _ptr(f)))
+
+
+def lbm_get_populations(ctx, out):
+    return _check(ctx, _lib.lbm_get_populations(ctx, _ptr(out)))
+
+
+def lbm_get_history(ctx, out):
+    return _check(ctx, _lib.lbm_get_history(ctx, _ptr(out)))
+
+
+def lbm_get_geometry(ctx, geo, jac=None):
+    return _check(ctx, _lib.lbm_get_geometry(ctx, _ptr(geo), _ptr(jac)))
+
+
+def lbm_step(ctx, n=1):
+    return _check(ctx, _lib.lbm_step(ctx, int(n)))
+
+
+def lbm_step_profiled(ctx, n, nslots=4):
+    """Run n steps; returns the average duration (ms) of each kernel of the step."""
+    arr = (ctypes.c_double * nslots)()
+    _check(ctx, _lib.lbm_step_profiled(ctx, int(n), arr, nslots))
+    return list(arr)
+
+
+def lbm_moments(ctx, rho, u, cartesian=False):
+    return _check(ctx, _lib.lbm_moments(ctx, _ptr(rho), _ptr(u), int(bool(cartesian))))
+
+
+def lbm_wall_force(ctx, wall, total, per_node=None, method=LBM_FORCE_STRESS):
+    return _check(ctx, _lib.lbm_wall_force(ctx, int(wall), int(method), _ptr(total), _ptr(per_node)))
+
+
+def lbm_forward_record(ctx, K, ckpt_every, wall, forces, method=LBM_FORCE_STRESS):
+    return _check(ctx, _lib.lbm_forward_record(ctx, int(K), int(ckpt_every), int(wall), int(method), _ptr(forces)))
+
+
+def lbm_backward(ctx, dLdF, grad_disp=None, grad_chart=None, grad_f0=None):
+    return _check(ctx, _lib.lbm_backward(ctx, _ptr(dLdF), _ptr(grad_disp), _ptr(grad_chart), _ptr(grad_f0)))
+
+
+def lbm_sync(ctx):
+    return _check(ctx, _lib.lbm_sync(ctx))
+
+
+# ------------------------------------------------------------------ Solver
+class Solver:
+    """One context with its workspace on ``device`` (a CUDA/HIP torch device)."""
+
+    def __init__(self, nx, ny, nz, tau, precision="fp64", adjoint_K=0, ckpt_every=0, device="cuda:0"):
+        self.nx, self.ny, self.nz, self.tau = nx, ny, nz, tau
+        self.H = ny - 2
+        self.device = torch.device(device)
+        self.precision = {"fp64": LBM_FP64, "fp32": LBM_FP32_DEV}[precision]
+        nbytes = lbm_workspace_bytes(nx, ny, nz, self.precision, adjoint_K, ckpt_every)
+        if nbytes == 0:
+            raise ValueError("invalid grid or adjoint sizes")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        with torch.cuda.device(self.device):
+            self.stream = torch.cuda.current_stream(self.device)
+            self.ctx = lbm_create(nx, ny, nz, tau, self.precision, self.workspace, self.stream.cuda_stream)
+        if adjoint_K:
+            lbm_reserve_adjoint(self.ctx, adjoint_K, ckpt_every)
+        self.adjoint_K, self.ckpt_every = adjoint_K, ckpt_every
+
+    def __del__(self):
+        ctx = getattr(self, "ctx", None)
+        if ctx:
+            lbm_destroy(ctx)
+            self.ctx = None
+
+    @property
+    def fluid_shape(self):
+        return (self.nz, self.H, self.nx)
+
+    @property
+    def fluid_nodes(self):
+        return self.nz * self.H * self.nx
+
+    def _dev(self, a, shape=None):
+        if a is None:
+            return None
+        t = torch.as_tensor(a, dtype=torch.float64).to(self.device).contiguous()
+        if shape is not None:
+            t = t.reshape(shape)
+        return t
+
+    def set_body_force(self, F):
+        lbm_set_body_force(self.ctx, F)
+
+    def set_metric(self, chart, reproject=False):
+        self._keep = self._dev(chart, (3, self.nz, self.ny, self.nx))
+        lbm_set_metric(self.ctx, self._keep, reproject)
+
+    def set_wall_displacement(self, wall, d, reproject=False):
+        self._keep = self._dev(d, (self.nz, self.nx))
+        lbm_set_wall_displacement(self.ctx, wall, self._keep, reproject)
+
+    def set_wall_velocity(self, wall, v):
+        self._keep_v = self._dev(v, (self.nz, self.nx, 3))
+        lbm_set_wall_velocity(self.ctx, wall, self._keep_v)
+
+    def init_equilibrium(self, rho=None, ucart=None):
+        r = self._dev(rho, self.fluid_shape)
+        u = self._dev(ucart, (3,) + self.fluid_shape)
+        lbm_init_equilibrium(self.ctx, r, u)
+        self.stream.synchronize()
+
+    def set_populations(self, f):
+        t = self._dev(f, (19,) + self.fluid_shape)
+        lbm_set_populations(self.ctx, t)
+        self.stream.synchronize()
+
+    def populations(self):
+        out = torch.empty((19,) + self.fluid_shape, dtype=torch.float64, device=self.device)
+        lbm_get_populations(self.ctx, out)
+        return out
+
+    def history(self):
+        out = torch.empty((10,) + self.fluid_shape, dtype=torch.float64, device=self.device)
+        lbm_get_history(self.ctx, out)
+        return out
+
+    def geometry(self):
+        geo = torch.empty((28,) + self.fluid_shape, dtype=torch.float64, device=self.device)
+        jac = torch.empty((9,) + self.fluid_shape, dtype=torch.float64, device=self.device)
+        lbm_get_geometry(self.ctx, geo, jac)
+        return geo, jac
+
+    def step(self, n=1):
+        lbm_step(self.ctx, n)
+
+    def moments(self, cartesian=False):
+        rho = torch.empty(self.fluid_shape, dtype=torch.float64, device=self.device)
+        u = torch.empty((3,) + self.fluid_shape, dtype=torch.float64, device=self.device)
+        lbm_moments(self.ctx, rho, u, cartesian)
+        return rho, u
+
+    def wall_force(self, wall, per_node=False):
+        tot = torch.empty(3, dtype=torch.float64, device=self.device)
+        pn = torch.empty((self.nz, self.nx, 3), dtype=torch.float64, device=self.device) if per_node else None
+        lbm_wall_force(self.ctx, wall, tot, pn)
+        return (tot, pn) if per_node else tot
+
+    def sync(self):
+        lbm_sync(self.ctx)

@@ -1,0 +1,252 @@
+"""GPU parity: the HIP library (through its C-ABI) against the FP64 oracle on
+the same seeded inputs.
+
+FP64 form: element-wise agreement to rounding (the two differ only in the
+order of floating-point operations).  FP32 deviation form: agreement within a
+bound derived from FP32 rounding of the deviation variables.
+"""
+import numpy as np
+import pytest
+
+from oracle import Oracle
+from paper_1803_07822_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+W = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
+
+
+def _lbm():
+    from paper_1803_07822_amd import lbm
+
+    return lbm
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def dev_err(a, b, ref):
+    """max |a - b| relative to the largest deviation of ref from the weights."""
+    scale = np.abs(ref - W.reshape((19,) + (1,) * (ref.ndim - 1))).max()
+    return np.abs(a - b).max() / scale
+
+
+def make_pair(nx, ny, nz, tau, precision="fp64", chart=None, disp=None, F=(0, 0, 0), vwall=None):
+    lbm = _lbm()
+    S = lbm.Solver(nx, ny, nz, tau, precision)
+    O = Oracle(nx, ny, nz, tau)
+    S.set_body_force(F)
+    O.set_body_force(F)
+    if vwall is not None:
+        for w in (0, 1):
+            if vwall[w] is not None:
+                S.set_wall_velocity(w, vwall[w])
+                O.set_wall_velocity(w, vwall[w])
+    if chart is not None:
+        S.set_metric(chart)
+        O.set_metric(chart)
+    else:
+        S.set_wall_displacement(1, disp)
+        O.set_wall_displacement(1, disp)
+    return S, O
+
+
+GEO_CASES = {
+    "bump3_70x12x9": lambda: (70, 12, 9, synth.bump3_chart(70, 12, 9, 0.08), None),
+    "disp_gauss_33x10x17": lambda: (33, 10, 17, None, synth.gaussian_bump(33, 17, A=1.5, x0=16, z0=8, sigma=3)),
+    "identity_5x4x3": lambda: (5, 4, 3, synth.identity_chart(5, 4, 3), None),
+}
+
+
+@pytest.mark.parametrize("case", sorted(GEO_CASES))
+def test_geometry_parity_fp64(case):
+    nx, ny, nz, chart, disp = GEO_CASES[case]()
+    S, O = make_pair(nx, ny, nz, 0.8, chart=chart, disp=disp, F=(1e-5, -3e-6, 2e-6))
+    geo, jac = S.geometry()
+    og, oj = O.geometry(), O.jacobian()
+    assert np.abs(_np(jac) - oj).max() < 1e-13
+    g = _np(geo)
+    # sqrt g and g^ij are O(1): absolute agreement to rounding
+    assert np.abs(g[:7] - og[:7]).max() < 1e-13
+    # Christoffel symbols and F^i: relative to the largest entry of the field group
+    gam_scale = np.abs(og[7:25]).max()
+    assert np.abs(g[7:25] - og[7:25]).max() <= 1e-11 * gam_scale + 1e-16
+    f_scale = np.abs(og[25:]).max()
+    assert np.abs(g[25:] - og[25:]).max() <= 1e-13 * f_scale
+
+
+def _random_state(O, nz, H, nx, seed):
+    O.init_equilibrium(1 + synth.random_perturbation((nz, H, nx), 2e-3, seed),
+                       synth.random_perturbation((3, nz, H, nx), 1e-2, seed + 1))
+    f = O.populations() + synth.random_perturbation((19, nz, H, nx), 1e-4, seed + 2) * W[:, None, None, None]
+    return f
+
+
+@pytest.mark.parametrize("shape", [(70, 12, 9), (64, 8, 4), (7, 5, 3)])
+def test_step_parity_fp64(shape):
+    """Curved chart, body force, moving walls, non-equilibrium start: the GPU
+    state matches the oracle population by population after 1 and 12 steps;
+    history, moments and wall forces too.  Shapes span several 64x4 tiles with
+    ragged edges in x and y."""
+    nx, ny, nz = shape
+    H = ny - 2
+    vt = np.zeros((nz, nx, 3))
+    vt[..., 0], vt[..., 2] = 0.01, -0.003
+    vb = np.zeros((nz, nx, 3))
+    vb[..., 1] = 0.0  # normal velocity stays zero at a wall at rest in y
+    vb[..., 2] = 0.004
+    S, O = make_pair(nx, ny, nz, 0.7, chart=synth.bump3_chart(nx, ny, nz, 0.06), F=(2e-5, 0, 1e-5), vwall=(vb, vt))
+    f0 = _random_state(O, nz, H, nx, 21)
+    O.set_populations(f0)
+    S.set_populations(f0)
+    assert dev_err(_np(S.populations()), O.populations(), f0) < 1e-13
+    assert np.abs(_np(S.history()) - O.history()).max() < 1e-14
+    for n in (1, 11):
+        O.step(n)
+        S.step(n)
+        fo = O.populations()
+        assert dev_err(_np(S.populations()), fo, fo) < 1e-12, n
+        assert np.abs(_np(S.history()) - O.history()).max() < 1e-13
+        r, u = S.moments(cartesian=True)
+        ro, uo = O.moments(cartesian=True)
+        assert np.abs(_np(r) - ro).max() < 1e-13
+        assert np.abs(_np(u) - uo).max() < 1e-13
+        for wall in (0, 1):
+            t, pn = S.wall_force(wall, per_node=True)
+            to, pno = O.wall_force(wall, per_node=True)
+            assert np.abs(_np(pn) - pno).max() < 1e-13
+            assert np.abs(_np(t) - to).max() < 1e-12 * max(1.0, np.abs(to).max())
+
+
+def test_init_equilibrium_parity_fp64():
+    nx, ny, nz = 40, 9, 6
+    d = synth.gaussian_bump(nx, nz, A=1.0, x0=20, z0=3, sigma=3)
+    S, O = make_pair(nx, ny, nz, 0.9, disp=d, F=(1e-5, 0, 0))
+    rho = 1 + synth.random_perturbation((nz, ny - 2, nx), 1e-3, 5)
+    uc = synth.random_perturbation((3, nz, ny - 2, nx), 1e-2, 6)
+    S.init_equilibrium(rho, uc)
+    O.init_equilibrium(rho, uc)
+    fo = O.populations()
+    assert dev_err(_np(S.populations()), fo, fo) < 1e-13
+    assert np.abs(_np(S.history()) - O.history()).max() < 1e-14
+
+
+def test_reprojection_parity_fp64():
+    nx, ny, nz = 48, 10, 12
+    H = ny - 2
+    d1 = synth.gaussian_bump(nx, nz, A=1.2, x0=24, z0=6, sigma=4)
+    d2 = 0.7 * d1 + 0.3 * np.sin(2 * np.pi * np.arange(nx) / nx)[None, :]
+    v = np.zeros((nz, nx, 3))
+    v[..., 1] = 0.002 * np.cos(2 * np.pi * np.arange(nx) / nx)[None, :]
+    S, O = make_pair(nx, ny, nz, 0.75, disp=d1, F=(1e-5, 0, 0), vwall=(None, v))
+    f0 = _random_state(O, nz, H, nx, 31)
+    O.set_populations(f0)
+    S.set_populations(f0)
+    O.step(3)
+    S.step(3)
+    O.set_wall_displacement(1, d2, reproject=True)
+    S.set_wall_displacement(1, d2, reproject=True)
+    fo = O.populations()
+    assert dev_err(_np(S.populations()), fo, fo) < 1e-12
+    assert np.abs(_np(S.history()) - O.history()).max() < 1e-13
+    O.step(4)
+    S.step(4)
+    fo = O.populations()
+    assert dev_err(_np(S.populations()), fo, fo) < 1e-12
+    # generic chart entry point with re-projection
+    ch = synth.bump3_chart(nx, ny, nz, 0.05)
+    O.set_metric(ch, reproject=True)
+    S.set_metric(ch, reproject=True)
+    fo = O.populations()
+    assert dev_err(_np(S.populations()), fo, fo) < 1e-12
+
+
+def test_config1_channel_parity_fp64():
+    """The 32x16x16 sheared channel, tau 0.8, F 1e-6, 2000 steps."""
+    w = synth.workload("c1_shear_32x16x16")
+    S, O = make_pair(w.nx, w.ny, w.nz, w.tau, disp=w.disp(), F=w.force)
+    S.init_equilibrium()
+    O.init_equilibrium()
+    S.step(w.steps)
+    O.step(w.steps)
+    r, u = S.moments(cartesian=True)
+    ro, uo = O.moments(cartesian=True)
+    eu = np.abs(_np(u) - uo).max() / np.abs(uo).max()
+    # rho carries the rounding of 2000 mass updates (~1e-16 each, same sign on
+    # all nodes): bound 2000 * 2.5e-16
+    er = np.abs(_np(r) - ro).max()
+    fo = O.populations()
+    ef = dev_err(_np(S.populations()), fo, fo)
+    assert eu < 1e-10, eu
+    assert er < 5e-13, er
+    assert ef < 1e-10, ef
+
+
+@pytest.mark.parametrize("shape", [(70, 12, 9), (32, 16, 16)])
+def test_step_parity_fp32(shape):
+    """FP32 deviation storage and arithmetic against the FP64 oracle: errors in
+    rho, u and wall force stay at the FP32 rounding level of the deviation
+    variables."""
+    nx, ny, nz = shape
+    H = ny - 2
+    S, O = make_pair(nx, ny, nz, 0.7, precision="fp32", chart=synth.bump3_chart(nx, ny, nz, 0.06), F=(1e-5, 0, 0))
+    f0 = _random_state(O, nz, H, nx, 41)
+    O.set_populations(f0)
+    S.set_populations(f0)
+    O.step(50)
+    S.step(50)
+    r, u = S.moments(cartesian=True)
+    ro, uo = O.moments(cartesian=True)
+    er = np.abs(_np(r) - ro).max()
+    eu = np.abs(_np(u) - uo).max() / np.abs(uo).max()
+    t = _np(S.wall_force(1))
+    to = O.wall_force(1)
+    ef = np.abs(t - to).max() / np.abs(to).max()
+    print(f"fp32 {shape}: max|drho| {er:.2e}, max|du|/max|u| {eu:.2e}, wall force rel {ef:.2e}")
+    assert er < 2e-6
+    assert eu < 1e-4
+    assert ef < 1e-5
+
+
+def test_instability_guard_reports_nonfinite_state():
+    lbm = _lbm()
+    nx, ny, nz = 16, 8, 4
+    S = lbm.Solver(nx, ny, nz, 0.8)
+    S.set_wall_displacement(1, np.zeros((nz, nx)))
+    f = np.tile(W[:, None, None, None], (1, nz, ny - 2, nx))
+    f[3, 1, 2, 5] = np.nan
+    S.set_populations(f)
+    S.step(2)
+    with pytest.raises(lbm.LBMError) as e:
+        S.sync()
+    assert e.value.code == -5
+    with pytest.raises(lbm.LBMError) as e:  # sticky
+        S.step(1)
+    assert e.value.code == -5
+
+
+def test_call_order_and_argument_errors():
+    lbm = _lbm()
+    S = lbm.Solver(8, 6, 4, 0.8)
+    with pytest.raises(lbm.LBMError) as e:
+        S.step(1)
+    assert e.value.code == -4
+    with pytest.raises(lbm.LBMError) as e:
+        S.init_equilibrium()
+    assert e.value.code == -4
+    S.set_wall_displacement(1, np.zeros((4, 8)))
+    with pytest.raises(lbm.LBMError) as e:
+        S.set_wall_displacement(1, np.zeros((4, 8)), reproject=True)
+    assert e.value.code == -4
+    with pytest.raises(lbm.LBMError) as e:
+        lbm.lbm_wall_force(S.ctx, 2, torch.zeros(3, dtype=torch.float64, device=S.device))
+    assert e.value.code == -1
+    S.init_equilibrium()
+    with pytest.raises(lbm.LBMError) as e:
+        lbm.lbm_step(S.ctx, -1)
+    assert e.value.code == -1
+    S.step(3)
+    S.sync()

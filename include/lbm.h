@@ -176,6 +176,13 @@ int lbm_backward(lbm_ctx* ctx, const double* d_dL_dF, double* d_grad_disp, doubl
  * currently 2: the moment pass and the collision pass).  Synchronising. */
 int lbm_step_profiled(lbm_ctx* ctx, int n, double* h_ms, int nslots);
 
+/* Launch shape of the step: zchunk = planes marched per block by the fused
+ * step kernel (0 = chosen from the grid size); variant 0 = fused single-kernel
+ * step on 64x4 tiles, 1 = two kernels (moment pass, collision pass), 2 =
+ * fused on 64x2 tiles, 3 = fused on 64x1 tiles.  Results agree to rounding;
+ * only the speed differs. */
+int lbm_set_tuning(lbm_ctx* ctx, int zchunk, int variant);
+
 /* Wait for the stream and check the instability guard. */
 int lbm_sync(lbm_ctx* ctx);
 

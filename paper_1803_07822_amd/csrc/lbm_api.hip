@@ -63,7 +63,8 @@ void carve_core(Carver& c, const Grid& g, int precision, Fields& F) {
   F.geo = c.take(sz * lbm::G_N * N);
   F.pop[0] = c.take(sz * 19 * N);
   F.pop[1] = c.take(sz * 19 * N);
-  F.hist = c.take(sz * lbm::H_N * N);
+  F.hist[0] = c.take(sz * lbm::H_N * N);
+  F.hist[1] = c.take(sz * lbm::H_N * N);
   F.mom = c.take(sz * 4 * N);
   F.uw = c.take(sz * 2 * 3 * (size_t)g.nz * g.nx);
   F.disp = (double*)c.take(sizeof(double) * 2 * (size_t)g.nz * g.nx);
@@ -351,6 +352,15 @@ int lbm_step_profiled(lbm_ctx* c, int n, double* h_ms, int nslots) {
   for (auto& e : ev) hipEventDestroy(e);
   if (n > 0) c->recorded = 0;
   return rc;
+}
+
+int lbm_set_tuning(lbm_ctx* c, int zchunk, int variant) {
+  LBM_GUARD(c);
+  if (zchunk < 0 || variant < 0 || variant > 3) return fail(c, LBM_EINVAL, "bad tuning arguments");
+  c->F.zc = zchunk;
+  c->F.variant = variant == 1 ? 1 : 0;
+  c->F.ty = variant == 2 ? 2 : (variant == 3 ? 1 : 4);
+  return LBM_OK;
 }
 
 int lbm_sync(lbm_ctx* c) {

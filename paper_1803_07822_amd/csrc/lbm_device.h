@@ -36,7 +36,7 @@ __host__ __device__ constexpr int opp(int l) { return l == 0 ? 0 : ((l & 1) ? l 
 
 // Symmetric 3x3 packing: xx, xy, xz, yy, yz, zz.
 __host__ __device__ constexpr int sym(int a, int b) {
-  return a > b ? sym(b, a) : (a == 0 ? b : (a == 1 ? 2 + b : 5));
+  return (a < b ? a : b) == 0 ? (a < b ? b : a) : ((a < b ? a : b) == 1 ? 2 + (a < b ? b : a) : 5);
 }
 
 // ------------------------------------------------------------- grid / layout

@@ -22,7 +22,7 @@ struct Fields {
   double* jac;    // [9][N] J = dh/dxi at fluid nodes
   void* geo;      // [28][N] T
   void* pop[2];   // [19][N] T
-  void* hist;     // [10][N] T
+  void* hist[2];  // [10][N] T forcing history, flips with the populations
   void* mom;      // [4][N] T
   void* uw;       // [2][nz][nx][3] T
   double* disp;   // [2][nz][nx]
@@ -31,9 +31,12 @@ struct Fields {
   double* mf;     // [20][NC] Cartesian moment fields for re-projection
   double* part;   // reduction partials
   int* flag;      // instability guard
-  int cur;        // index of the current population buffer
+  int cur;        // index of the current population and history buffers
   int uext_cur;   // index of the current extended displacement
   int moving[2];
+  int zc = 0;        // planes per block of the fused step (0 = automatic)
+  int variant = 0;   // 0: fused step; 1: two-pass step (moments pass + collision pass)
+  int ty = 4;        // rows of 64 nodes per block of the fused step (1, 2, 4)
 };
 
 constexpr int BX = 64, BY = 4;
@@ -69,8 +72,9 @@ template <class T> hipError_t launch_set_state(Fields& F, hipStream_t s, const d
 template <class T> hipError_t launch_get_pops(Fields& F, hipStream_t s, double* out);
 template <class T> hipError_t launch_get_hist(Fields& F, hipStream_t s, double* out);
 template <class T> hipError_t launch_get_geo(Fields& F, hipStream_t s, double* out);
-constexpr int STEP_KERNELS = 2;  // kernels per step (timed separately by lbm_step_profiled)
+constexpr int STEP_KERNELS = 2;  // at most this many kernels per step (timed separately by lbm_step_profiled)
 template <class T> hipError_t launch_step(Fields& F, hipStream_t s, T tau, hipEvent_t* ev = nullptr);
+template <class T> hipError_t launch_step_fused(Fields& F, hipStream_t s, T tau, int zc, int ty);
 template <class T> hipError_t launch_moments_out(Fields& F, hipStream_t s, double* rho, double* u, int cart);
 template <class T> hipError_t launch_wall_force(Fields& F, hipStream_t s, int wall, T tau, double* total,
                                                 double* per_node);

@@ -314,7 +314,7 @@ template <class T> hipError_t launch_reproject(Fields& F, hipStream_t s, const d
   (void)tau;
   const Grid g = F.g;
   dim3 b(BX, BY);
-  hipLaunchKernelGGL(k_rp_moments<T>, fluid_grid(g), b, 0, s, g, (const T*)F.pop[F.cur], (const T*)F.hist,
+  hipLaunchKernelGGL(k_rp_moments<T>, fluid_grid(g), b, 0, s, g, (const T*)F.pop[F.cur], (const T*)F.hist[F.cur],
                      (const T*)F.geo, (const double*)F.jac, F.mf);
   hipLaunchKernelGGL(k_rp_ghost, col_grid(g), b, 0, s, g, (const double*)F.vwall, F.mf);
   const int old = F.uext_cur;
@@ -322,7 +322,7 @@ template <class T> hipError_t launch_reproject(Fields& F, hipStream_t s, const d
   hipError_t e = launch_geometry<T>(F, s, Fc);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_rp_new<T>, fluid_grid(g), b, 0, s, g, (const double*)F.chart, (const double*)F.uext[old],
-                     (const double*)F.mf, (const double*)F.jac, (const T*)F.geo, F.full, (T*)F.hist);
+                     (const double*)F.mf, (const double*)F.jac, (const T*)F.geo, F.full, (T*)F.hist[F.cur]);
   hipLaunchKernelGGL(k_rp_unpull<T>, fluid_grid(g), b, 0, s, g, (const double*)F.full, (T*)F.pop[F.cur]);
   return hipGetLastError();
 }

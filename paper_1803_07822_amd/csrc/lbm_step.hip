@@ -155,7 +155,8 @@ __global__ __launch_bounds__(BX* BY) void k_moments(Grid g, const T* __restrict_
 // leading f restored) and the bounce-back term of Eq. (streaming) at walls.
 template <class T>
 __global__ __launch_bounds__(BX* BY) void k_collide(Grid g, const T* __restrict__ pin, T* __restrict__ pout,
-                                                   T* __restrict__ hist, const T* __restrict__ geo,
+                                                   const T* __restrict__ hist, T* __restrict__ hout,
+                                                   const T* __restrict__ geo,
                                                    const T* __restrict__ mom, const T* __restrict__ uw, int mv0,
                                                    int mv1, T tau, int* __restrict__ flag) {
   Pos p;
@@ -203,7 +204,7 @@ __global__ __launch_bounds__(BX* BY) void k_collide(Grid g, const T* __restrict_
     chk += v;
     pout[(long long)l * g.N + p.n] = v;
   });
-  store_coef(hist, g.N, p.n, c);
+  store_coef(hout, g.N, p.n, c);
   const T uu = j[0] * j[0] + j[1] * j[1] + j[2] * j[2];
   if (!(rho > T(0)) || !(uu < T(0.1) * rho * rho) || !isfinite(chk)) atomicOr(flag, 1);
 }
@@ -480,16 +481,28 @@ __global__ void k_sum_partials(int nb, const double* __restrict__ part, double* 
 
 }  // namespace
 
-// One step; with ev != nullptr, events ev[0..2] bracket the two passes.
+// One step; with ev != nullptr, events ev[0..2] bracket the kernels of the
+// step (the fused step is one kernel: ev[1] and ev[2] then coincide).
 template <class T> hipError_t launch_step(Fields& F, hipStream_t s, T tau, hipEvent_t* ev) {
   const Grid g = F.g;
+  if (F.variant == 0) {
+    if (ev) hipEventRecord(ev[0], s);
+    hipError_t e = launch_step_fused<T>(F, s, tau, F.zc, F.ty);
+    if (ev) {
+      hipEventRecord(ev[1], s);
+      hipEventRecord(ev[2], s);
+    }
+    return e;
+  }
   dim3 b(BX, BY);
   const T* pin = (const T*)F.pop[F.cur];
   T* pout = (T*)F.pop[F.cur ^ 1];
   if (ev) hipEventRecord(ev[0], s);
-  hipLaunchKernelGGL(k_moments<T>, fluid_grid(g), b, 0, s, g, pin, (const T*)F.hist, (const T*)F.geo, (T*)F.mom);
+  hipLaunchKernelGGL(k_moments<T>, fluid_grid(g), b, 0, s, g, pin, (const T*)F.hist[F.cur], (const T*)F.geo,
+                     (T*)F.mom);
   if (ev) hipEventRecord(ev[1], s);
-  hipLaunchKernelGGL(k_collide<T>, fluid_grid(g), b, 0, s, g, pin, pout, (T*)F.hist, (const T*)F.geo,
+  hipLaunchKernelGGL(k_collide<T>, fluid_grid(g), b, 0, s, g, pin, pout, (const T*)F.hist[F.cur],
+                     (T*)F.hist[F.cur ^ 1], (const T*)F.geo,
                      (const T*)F.mom, (const T*)F.uw, F.moving[0], F.moving[1], tau, F.flag);
   if (ev) hipEventRecord(ev[2], s);
   F.cur ^= 1;
@@ -512,22 +525,23 @@ template <class T> hipError_t launch_set_state(Fields& F, hipStream_t s, const d
   }
   hipLaunchKernelGGL(k_moments_full<T>, fluid_grid(g), b, 0, s, g, F.full, (const T*)F.geo, (T*)F.mom);
   hipLaunchKernelGGL(k_hist_full<T>, fluid_grid(g), b, 0, s, g, F.full, (const T*)F.geo, (const T*)F.mom,
-                     (const T*)F.uw, F.moving[0], F.moving[1], tau, (T*)F.hist);
-  hipLaunchKernelGGL(k_full_to_streamed<T>, fluid_grid(g), b, 0, s, g, F.full, (const T*)F.hist, (const T*)F.geo);
+                     (const T*)F.uw, F.moving[0], F.moving[1], tau, (T*)F.hist[F.cur]);
+  hipLaunchKernelGGL(k_full_to_streamed<T>, fluid_grid(g), b, 0, s, g, F.full, (const T*)F.hist[F.cur],
+                     (const T*)F.geo);
   hipLaunchKernelGGL(k_unpull<T>, fluid_grid(g), b, 0, s, g, (const double*)F.full, (T*)F.pop[F.cur]);
   return hipGetLastError();
 }
 
 template <class T> hipError_t launch_get_pops(Fields& F, hipStream_t s, double* out) {
   dim3 b(BX, BY);
-  hipLaunchKernelGGL(k_get_pops<T>, fluid_grid(F.g), b, 0, s, F.g, (const T*)F.pop[F.cur], (const T*)F.hist,
+  hipLaunchKernelGGL(k_get_pops<T>, fluid_grid(F.g), b, 0, s, F.g, (const T*)F.pop[F.cur], (const T*)F.hist[F.cur],
                      (const T*)F.geo, out);
   return hipGetLastError();
 }
 
 template <class T> hipError_t launch_get_hist(Fields& F, hipStream_t s, double* out) {
   dim3 b(BX, BY);
-  hipLaunchKernelGGL(k_get_hist<T>, fluid_grid(F.g), b, 0, s, F.g, (const T*)F.hist, out);
+  hipLaunchKernelGGL(k_get_hist<T>, fluid_grid(F.g), b, 0, s, F.g, (const T*)F.hist[F.cur], out);
   return hipGetLastError();
 }
 
@@ -539,7 +553,7 @@ template <class T> hipError_t launch_get_geo(Fields& F, hipStream_t s, double* o
 
 template <class T> hipError_t launch_moments_out(Fields& F, hipStream_t s, double* rho, double* u, int cart) {
   dim3 b(BX, BY);
-  hipLaunchKernelGGL(k_moments_out<T>, fluid_grid(F.g), b, 0, s, F.g, (const T*)F.pop[F.cur], (const T*)F.hist,
+  hipLaunchKernelGGL(k_moments_out<T>, fluid_grid(F.g), b, 0, s, F.g, (const T*)F.pop[F.cur], (const T*)F.hist[F.cur],
                      (const T*)F.geo, F.jac, rho, u, cart);
   return hipGetLastError();
 }
@@ -547,7 +561,7 @@ template <class T> hipError_t launch_moments_out(Fields& F, hipStream_t s, doubl
 template <class T>
 hipError_t launch_wall_force(Fields& F, hipStream_t s, int wall, T tau, double* total, double* per_node) {
   dim3 b(BX, BY), gr = col_grid(F.g);
-  hipLaunchKernelGGL(k_wall_force<T>, gr, b, 0, s, F.g, wall, (const T*)F.pop[F.cur], (const T*)F.hist,
+  hipLaunchKernelGGL(k_wall_force<T>, gr, b, 0, s, F.g, wall, (const T*)F.pop[F.cur], (const T*)F.hist[F.cur],
                      (const T*)F.geo, F.jac, tau, per_node, F.part);
   const int nb = (int)(gr.x * gr.y);
   hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, nb, (const double*)F.part, total);

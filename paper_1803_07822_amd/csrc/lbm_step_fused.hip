@@ -1,0 +1,335 @@
+// Fused single-kernel time step (plane marching).
+//
+// A block owns a TX x TY tile of the (x, y) plane and marches along a chunk of
+// ZC planes in z.  The lattice gradient d_k(rho u^i) needs the momentum of all
+// 18 neighbours before any collision, so the block keeps the moments
+// (rho - 1, rho u) of three consecutive planes of its tile plus a one-node
+// halo in an LDS ring: at plane z it forms the moments of plane z+1, then
+// collides plane z.  Populations are read from HBM once per step (the second
+// read of a plane, one iteration later, and the halo reads hit the caches).
+// Blocks are numbered so that each XCD gets a contiguous range of tiles,
+// which keeps the halo reads of neighbouring tiles in one L2.
+//
+// The population layout, the streamed value g_l and the collision are those
+// of the two-pass form (pull layout with bounce-back slots, deviation
+// variables); see the state kernels for the layout.
+#include "lbm_internal.h"
+
+namespace lbm {
+
+namespace {
+
+constexpr int TX = 64;
+constexpr int HX = TX + 2;
+template <int TY> struct Tile {
+  static constexpr int NT = TX * TY;
+  static constexpr int HY = TY + 2;
+  static constexpr int HN = HX * HY;  // haloed tile
+};
+
+__device__ __forceinline__ int wrapf(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
+
+// Neighbour offsets of one fluid node in 32-bit element units: the source of
+// a pull in direction l is n + ox[x] + oz[z] - y*nx (periodic wraps folded in),
+// and every plane l is addressed as a uniform base plus that offset.
+struct NodeIdx {
+  unsigned n;         // fluid index
+  int oxm, oxp;       // offset to i-1 and to i+1 (wrapped)
+  int ozm, ozp;       // offset to k-1 and to k+1 (wrapped), in whole planes
+  int jf;
+};
+
+__device__ __forceinline__ NodeIdx node_idx(const Grid& g, int i, int jf, int k) {
+  NodeIdx r;
+  const int plane = g.H * g.nx;
+  r.n = (unsigned)(k * plane + jf * g.nx + i);
+  r.oxm = i == 0 ? g.nx - 1 : -1;
+  r.oxp = i == g.nx - 1 ? 1 - g.nx : 1;
+  r.ozm = k == 0 ? (g.nz - 1) * plane : -plane;
+  r.ozp = k == g.nz - 1 ? (1 - g.nz) * plane : plane;
+  r.jf = jf;
+  return r;
+}
+
+// Element e of a plane given by a uniform base pointer: the byte offset is
+// formed in 32 bits so that loads and stores use a scalar base register plus
+// one 32-bit vector offset.
+template <class T> __device__ __forceinline__ const T& at(const T* __restrict__ base, unsigned e) {
+  return *(const T*)((const char*)base + (e * (unsigned)sizeof(T)));
+}
+template <class T> __device__ __forceinline__ T& atw(T* __restrict__ base, unsigned e) {
+  return *(T*)((char*)base + (e * (unsigned)sizeof(T)));
+}
+
+// Pulled deviation g~_l: the population that left x - c_l in direction l,
+// or the bounce-back slot opp(l) of this node when x - c_l is a wall node.
+template <class T, int l>
+__device__ __forceinline__ T pullf(const T* __restrict__ pop, const Grid& g, const NodeIdx& p) {
+  constexpr int x = cx(l), y = cy(l), z = cz(l);
+  if ((y > 0 && p.jf == 0) || (y < 0 && p.jf == g.H - 1)) return at(pop + (size_t)opp(l) * g.N, p.n);
+  int off = -y * g.nx;
+  if (x > 0) off += p.oxm;
+  if (x < 0) off += p.oxp;
+  if (z > 0) off += p.ozm;
+  if (z < 0) off += p.ozp;
+  return at(pop + (size_t)l * g.N, (unsigned)((int)p.n + off));
+}
+
+template <class T> __device__ __forceinline__ T fld(const T* __restrict__ a, int q, const Grid& g, unsigned n) {
+  return at(a + (size_t)q * g.N, n);
+}
+
+// rho - 1 and rho u of the streamed state at a fluid node.
+template <class T>
+__device__ __forceinline__ void node_moments(const T* __restrict__ pop, const T* __restrict__ hist,
+                                             const T* __restrict__ geo, const Grid& g, int i, int jf, int k, T m[4]) {
+  const NodeIdx p = node_idx(g, i, jf, k);
+  T s = 0, j0 = 0, j1 = 0, j2 = 0;
+  for_q([&](auto L) {
+    constexpr int l = decltype(L)::value;
+    const T v = pullf<T, l>(pop, g, p);
+    s += v;
+    if (cx(l)) j0 += T(cx(l)) * v;
+    if (cy(l)) j1 += T(cy(l)) * v;
+    if (cz(l)) j2 += T(cz(l)) * v;
+  });
+  const T sgd = fld(geo, G_SG, g, p.n);
+  const T sg = T(1) + sgd;
+  m[0] = sgd + sg * s + T(0.5) * fld(hist, H_A, g, p.n);
+  m[1] = sg * j0 + T(0.5) * fld(hist, H_B + 0, g, p.n);
+  m[2] = sg * j1 + T(0.5) * fld(hist, H_B + 1, g, p.n);
+  m[3] = sg * j2 + T(0.5) * fld(hist, H_B + 2, g, p.n);
+}
+
+// Fill one ring slot with the moments of plane k over the haloed tile.  Wall
+// layers (jf = -1, H) get the mirror ghost of the adjacent fluid node.
+template <class T, int TY>
+__device__ __forceinline__ void fill_plane(T (*ring)[Tile<TY>::HN], const T* __restrict__ pop, const T* __restrict__ hist,
+                                           const T* __restrict__ geo, const T* __restrict__ uw, int mv0, int mv1,
+                                           const Grid& g, int i0, int j0, int k) {
+  k = wrapf(k, g.nz);
+  for (int e = threadIdx.x; e < Tile<TY>::HN; e += Tile<TY>::NT) {
+    const int hx = e % HX, hy = e / HX;
+    const int i = i0 - 1 + hx, jf = j0 - 1 + hy;
+    if (i > g.nx || jf > g.H) continue;  // beyond a ragged tile edge: never read
+    const int iw = wrapf(i, g.nx);
+    T m[4];
+    if (jf >= 0 && jf < g.H) {
+      node_moments(pop, hist, geo, g, iw, jf, k, m);
+    } else {
+      const int w = jf < 0 ? 0 : 1;
+      T mm[4];
+      node_moments(pop, hist, geo, g, iw, w == 0 ? 0 : g.H - 1, k, mm);
+      m[0] = mm[0];
+      m[1] = -mm[1];
+      m[2] = -mm[2];
+      m[3] = -mm[3];
+      if (w == 0 ? mv0 : mv1) {
+        const T r2 = T(2) * (T(1) + mm[0]);
+        const long long c = (((long long)w * g.nz + k) * g.nx + iw) * 3;
+        m[1] += r2 * uw[c];
+        m[2] += r2 * uw[c + 1];
+        m[3] += r2 * uw[c + 2];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) ring[q][e] = m[q];
+  }
+}
+
+template <class T, int TY>
+__global__ __launch_bounds__(Tile<TY>::NT) void k_step_fused(Grid g, int ntx, int nty, int nzc, int zc,
+                                                   const T* __restrict__ pin, T* __restrict__ pout,
+                                                   const T* __restrict__ hist, T* __restrict__ hout,
+                                                   const T* __restrict__ geo,
+                                                   const T* __restrict__ uw, int mv0, int mv1, T tau,
+                                                   int* __restrict__ flag) {
+  constexpr int HN = Tile<TY>::HN;
+  __shared__ T ring[3][4][HN];
+  // XCD-aware tile order: hardware deals blocks round-robin over 8 XCDs;
+  // give each XCD a contiguous range of tiles.
+  const int nb = ntx * nty * nzc;
+  const int b = blockIdx.x;
+  const int per = (nb + 7) / 8;
+  const int xcd = b % 8, slot = b / 8;
+  const int tile = xcd * per + slot;
+  if (tile >= nb) return;  // whole block exits together (no barrier skipped)
+  const int tzc = tile / (ntx * nty);
+  const int rem = tile % (ntx * nty);
+  const int ty0 = rem / ntx, tx0 = rem % ntx;
+  const int i0 = tx0 * TX, j0 = ty0 * TY;
+  const int z0 = tzc * zc;
+  const int z1 = min(z0 + zc, g.nz);
+  const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+  const int i = i0 + tx, jf = j0 + ty;
+  const bool active = i < g.nx && jf < g.H;
+
+  fill_plane<T, TY>(ring[(z0 + 2) % 3], pin, hist, geo, uw, mv0, mv1, g, i0, j0, z0 - 1);
+  fill_plane<T, TY>(ring[z0 % 3], pin, hist, geo, uw, mv0, mv1, g, i0, j0, z0);
+  const T itau = T(1) / tau;
+  for (int k = z0; k < z1; ++k) {
+    fill_plane<T, TY>(ring[(k + 1) % 3], pin, hist, geo, uw, mv0, mv1, g, i0, j0, k + 1);
+    __syncthreads();
+    if (active) {
+      const NodeIdx p = node_idx(g, i, jf, k);
+      const unsigned n = p.n;
+      const int c0 = (ty + 1) * HX + (tx + 1);
+      const T(*rc)[HN] = ring[k % 3];
+      const T dr = rc[0][c0];
+      const T j[3] = {rc[1][c0], rc[2][c0], rc[3][c0]};
+      // lattice gradient from the ring
+      T dj[3][3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int bb = 0; bb < 3; ++bb) dj[a][bb] = T(0);
+      for_q([&](auto L) {
+        constexpr int l = decltype(L)::value;
+        if (l == 0) return;
+        constexpr int x = cx(l), y = cy(l), z = cz(l);
+        const T(*rs)[HN] = ring[(k + 3 + z) % 3];
+        const int e = (ty + 1 + y) * HX + (tx + 1 + x);
+        constexpr T f = T(3.0 * wgt(l));
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          const T v = rs[1 + q][e];
+          if (x) dj[0][q] += T(x) * f * v;
+          if (y) dj[1][q] += T(y) * f * v;
+          if (z) dj[2][q] += T(z) * f * v;
+        }
+      });
+      // Streamed deviations g~_l and their second moment.
+      T gv[Q];
+      T sgc[6] = {0, 0, 0, 0, 0, 0};
+      for_q([&](auto L) {
+        constexpr int l = decltype(L)::value;
+        const T v = pullf<T, l>(pin, g, p);
+        gv[l] = v;
+        constexpr int x = cx(l), y = cy(l), z = cz(l);
+        if (x) sgc[0] += v;
+        if (y) sgc[3] += v;
+        if (z) sgc[5] += v;
+        if (x && y) sgc[1] += T(x * y) * v;
+        if (x && z) sgc[2] += T(x * z) * v;
+        if (y && z) sgc[4] += T(y * z) * v;
+      });
+      NodeGeo<T> G;
+      G.sgd = fld(geo, G_SG, g, n);
+#pragma unroll
+      for (int q = 0; q < 6; ++q) G.gid[q] = fld(geo, G_GI + q, g, n);
+#pragma unroll
+      for (int q = 0; q < 18; ++q) G.gam[q] = fld(geo, G_GAM + q, g, n);
+#pragma unroll
+      for (int q = 0; q < 3; ++q) G.F[q] = fld(geo, G_F + q, g, n);
+      Coef<T> cp;
+      cp.A = fld(hist, H_A, g, n);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) cp.B[a] = fld(hist, H_B + a, g, n);
+#pragma unroll
+      for (int q = 0; q < 6; ++q) cp.C[q] = fld(hist, H_C + q, g, n);
+      const T sg = T(1) + G.sgd, isg = T(1) / sg;
+      const T rho = T(1) + dr, irho = T(1) / rho;
+      // equilibrium coefficients (deviation form): a0 = rho - sqrt g,
+      // a1 = rho u, a2 = rho theta (g^ij - delta) + rho u u
+      const T a0e = dr - G.sgd;
+      T ae[6];
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int bb = a; bb < 3; ++bb) ae[sym(a, bb)] = rho * T(1.0 / 3.0) * G.gid[sym(a, bb)] + j[a] * j[bb] * irho;
+      // sum_l (f - feq) c c, with sum_l F_l c c = C/sqrt g and
+      // sum_l feq~_l c c = (a0 delta/3 + a2)/sqrt g (D3Q19 quadrature)
+      const T kneq = (T(1) - T(0.5) * itau) * sg;
+      T Tm[6];
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int bb = a; bb < 3; ++bb) {
+          const int q = sym(a, bb);
+          const T pn = sgc[q] + isg * (T(0.5) * cp.C[q] - ae[q] - (a == bb ? a0e * T(1.0 / 3.0) : T(0)));
+          Tm[q] = rho * T(1.0 / 3.0) * ((a == bb ? T(1) : T(0)) + G.gid[q]) + j[a] * j[bb] * irho + kneq * pn;
+        }
+      Coef<T> c;
+      forcing_coef(G, j, Tm, dj, c);
+      // f*_l - w_l = (1 - 1/tau) g~_l + (w_l/sqrt g) h_l(a_eq/tau + a_F - a_Fprev/(2 tau))
+      const T hf = T(0.5) * itau;
+      const T A0 = a0e * itau + c.A - hf * cp.A;
+      T A1[3], A2[6];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) A1[a] = j[a] * itau + c.B[a] - hf * cp.B[a];
+#pragma unroll
+      for (int q = 0; q < 6; ++q) A2[q] = ae[q] * itau + c.C[q] - hf * cp.C[q];
+      {
+        const T dA = T(1.0 / 3.0) * (c.A - hf * cp.A);  // b2 = C - c_s^2 A delta
+        A2[0] -= dA;
+        A2[3] -= dA;
+        A2[5] -= dA;
+      }
+      const T keep = T(1) - itau;
+      const T* u = uw + ((unsigned)((jf == 0 ? 0 : g.nz) + k) * g.nx + i) * 3;
+      const bool mv = (jf == 0 && mv0) || (jf == g.H - 1 && mv1);
+      T chk = T(0);
+      for_q([&](auto L) {
+        constexpr int l = decltype(L)::value;
+        const T wl = T(wgt(l)) * isg;
+        T v = keep * gv[l] + wl * hermite_term<T, l>(A0, A1, A2);
+        constexpr int y = cy(l);
+        if ((y > 0 && jf == g.H - 1) || (y < 0 && jf == 0)) {
+          if (mv) {
+            T cu = T(y) * u[1];
+            if (cx(l)) cu += T(cx(l)) * u[0];
+            if (cz(l)) cu += T(cz(l)) * u[2];
+            v -= T(6) * wl * rho * cu;
+          }
+        }
+        chk += v;
+        atw(pout + (size_t)l * g.N, n) = v;
+      });
+      atw(hout + (size_t)H_A * g.N, n) = c.A;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) atw(hout + (size_t)(H_B + a) * g.N, n) = c.B[a];
+#pragma unroll
+      for (int q = 0; q < 6; ++q) atw(hout + (size_t)(H_C + q) * g.N, n) = c.C[q];
+      const T uu = j[0] * j[0] + j[1] * j[1] + j[2] * j[2];
+      if (!(rho > T(0)) || !(uu < T(0.1) * rho * rho) || !isfinite(chk)) atomicOr(flag, 1);
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+// Planes per block: enough blocks to fill 256 CUs several times over.
+template <int TY> inline int fused_zc(const Grid& g) {
+  const int ntx = (g.nx + TX - 1) / TX, nty = (g.H + TY - 1) / TY;
+  const long long tiles = (long long)ntx * nty;
+  int zc = (int)((tiles * g.nz + 2047) / 2048);
+  if (zc < 4) zc = 4;
+  if (zc > g.nz) zc = g.nz;
+  return zc;
+}
+
+template <class T, int TY> hipError_t launch_fused_ty(Fields& F, hipStream_t s, T tau, int zc) {
+  const Grid g = F.g;
+  if (zc <= 0) zc = fused_zc<TY>(g);
+  const int ntx = (g.nx + TX - 1) / TX, nty = (g.H + TY - 1) / TY, nzc = (g.nz + zc - 1) / zc;
+  const int nb = ntx * nty * nzc;
+  const int per = (nb + 7) / 8;
+  hipLaunchKernelGGL((k_step_fused<T, TY>), dim3(per * 8), dim3(Tile<TY>::NT), 0, s, g, ntx, nty, nzc, zc,
+                     (const T*)F.pop[F.cur], (T*)F.pop[F.cur ^ 1], (const T*)F.hist[F.cur],
+                     (T*)F.hist[F.cur ^ 1], (const T*)F.geo, (const T*)F.uw, F.moving[0], F.moving[1], tau, F.flag);
+  F.cur ^= 1;
+  return hipGetLastError();
+}
+
+// ty: tile height in y (1, 2 or 4 rows of 64 nodes per block).
+template <class T> hipError_t launch_step_fused(Fields& F, hipStream_t s, T tau, int zc, int ty) {
+  if (ty == 1) return launch_fused_ty<T, 1>(F, s, tau, zc);
+  if (ty == 2) return launch_fused_ty<T, 2>(F, s, tau, zc);
+  return launch_fused_ty<T, 4>(F, s, tau, zc);
+}
+
+template hipError_t launch_step_fused<double>(Fields&, hipStream_t, double, int, int);
+template hipError_t launch_step_fused<float>(Fields&, hipStream_t, float, int, int);
+
+}  // namespace lbm

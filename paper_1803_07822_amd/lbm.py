@@ -34,7 +34,7 @@ SYMBOLS = [
     "lbm_workspace_bytes", "lbm_create", "lbm_reserve_adjoint", "lbm_destroy", "lbm_set_body_force",
     "lbm_set_metric", "lbm_set_wall_displacement", "lbm_set_wall_velocity", "lbm_init_equilibrium",
     "lbm_set_populations", "lbm_get_populations", "lbm_get_history", "lbm_get_geometry", "lbm_step",
-    "lbm_step_profiled", "lbm_moments", "lbm_wall_force", "lbm_forward_record", "lbm_backward", "lbm_sync", "lbm_last_error",
+    "lbm_step_profiled", "lbm_set_tuning", "lbm_moments", "lbm_wall_force", "lbm_forward_record", "lbm_backward", "lbm_sync", "lbm_last_error",
 ]
 
 
@@ -61,6 +61,7 @@ _lib.lbm_get_history.argtypes = [_P, _P]
 _lib.lbm_get_geometry.argtypes = [_P, _P, _P]
 _lib.lbm_step.argtypes = [_P, _I]
 _lib.lbm_step_profiled.argtypes = [_P, _I, ctypes.POINTER(ctypes.c_double), _I]
+_lib.lbm_set_tuning.argtypes = [_P, _I, _I]
 _lib.lbm_moments.argtypes = [_P, _P, _P, _I]
 _lib.lbm_wall_force.argtypes = [_P, _I, _I, _P, _P]
 _lib.lbm_forward_record.argtypes = [_P, _I, _I, _I, _I, _P]
@@ -171,6 +172,10 @@ def lbm_step_profiled(ctx, n, nslots=4):
     arr = (ctypes.c_double * nslots)()
     _check(ctx, _lib.lbm_step_profiled(ctx, int(n), arr, nslots))
     return list(arr)
+
+
+def lbm_set_tuning(ctx, zchunk=0, variant=0):
+    return _check(ctx, _lib.lbm_set_tuning(ctx, int(zchunk), int(variant)))
 
 
 def lbm_moments(ctx, rho, u, cartesian=False):

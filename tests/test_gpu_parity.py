@@ -85,8 +85,10 @@ def _random_state(O, nz, H, nx, seed):
     return f
 
 
-@pytest.mark.parametrize("shape", [(70, 12, 9), (64, 8, 4), (7, 5, 3)])
-def test_step_parity_fp64(shape):
+@pytest.mark.parametrize("shape,variant,zc", [((70, 12, 9), 0, 0), ((64, 8, 4), 0, 0), ((7, 5, 3), 0, 0),
+                                              ((70, 12, 9), 1, 0), ((70, 12, 9), 2, 3), ((70, 12, 9), 3, 4),
+                                              ((33, 9, 11), 0, 5)])
+def test_step_parity_fp64(shape, variant, zc):
     """Curved chart, body force, moving walls, non-equilibrium start: the GPU
     state matches the oracle population by population after 1 and 12 steps;
     history, moments and wall forces too.  Shapes span several 64x4 tiles with
@@ -99,6 +101,7 @@ def test_step_parity_fp64(shape):
     vb[..., 1] = 0.0  # normal velocity stays zero at a wall at rest in y
     vb[..., 2] = 0.004
     S, O = make_pair(nx, ny, nz, 0.7, chart=synth.bump3_chart(nx, ny, nz, 0.06), F=(2e-5, 0, 1e-5), vwall=(vb, vt))
+    _lbm().lbm_set_tuning(S.ctx, zc, variant)
     f0 = _random_state(O, nz, H, nx, 21)
     O.set_populations(f0)
     S.set_populations(f0)

@@ -1,14 +1,631 @@
-// Adjoint of K steps: not provided yet in this build.
+// Adjoint of K steps of the FP64 scheme with checkpoint-every-N recomputation.
+//
+// Forward record: the initial state, a checkpoint at every N-th step and the
+// final state are kept; the wall force of states 1..K is written out.
+// Backward: for each segment, newest first, the segment's states are rebuilt
+// from its checkpoint and the steps are reversed one at a time.  A reversed
+// step is three passes: moments of the stored state (the forward stencil
+// input), the per-node vector-Jacobian product (transposed streaming and
+// bounce-back gathered from the destinations, then the collision, forcing and
+// equilibrium in reverse), and a gather that applies the transposed lattice
+// gradient (with its wall ghosts) and the moment VJP.  The wall-force VJP is
+// added at every recorded state.  The history of the initial state (forcing
+// of f0) is reversed last.  Geometry adjoints are accumulated per node and
+// finally carried through the reverse of the metric precompute (Christoffel
+// symbols, inverse metric, determinant, metric products, both lattice
+// stencils and the cubic continuation) to the chart and the wall displacement.
+//
+// Walls at rest and a static metric (no re-projection inside the K steps).
 #include "lbm_adjoint.h"
+#include "lbm_adjoint_node.h"
 
 namespace lbm {
 
-hipError_t adjoint_forward(Fields&, AdjointBuffers&, hipStream_t, int, int, int, double, double*) {
-  return hipErrorNotSupported;
+namespace {
+
+__device__ __forceinline__ int wrapa(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
+
+struct Node {
+  int i, jf, k;
+  long long n;
+};
+
+__device__ __forceinline__ bool fluid_node(const Grid& g, Node& p) {
+  p.i = blockIdx.x * BX + threadIdx.x;
+  p.jf = blockIdx.y * BY + threadIdx.y;
+  p.k = blockIdx.z;
+  if (p.i >= g.nx || p.jf >= g.H) return false;
+  p.n = ((long long)p.k * g.H + p.jf) * g.nx + p.i;
+  return true;
 }
-hipError_t adjoint_backward(Fields&, AdjointBuffers&, hipStream_t, int, int, int, double, const double*,
-                            const double*, double*, double*, double*) {
-  return hipErrorNotSupported;
+
+__device__ __forceinline__ long long nidx(const Grid& g, int i, int jf, int k) {
+  return ((long long)k * g.H + jf) * g.nx + i;
+}
+
+// Full populations f(t) = w + pulled deviation + F(t-1)/2 of a stored state.
+__device__ inline void load_state(const Grid& g, const double* __restrict__ pop, const double* __restrict__ hist,
+                                  const AGeo& G, const Node& p, double f[Q], double Fp[10]) {
+  for (int q = 0; q < 10; ++q) Fp[q] = hist[q * g.N + p.n];
+  double bp[6];
+  for (int q = 0; q < 6; ++q) bp[q] = Fp[4 + q];
+  bp[0] -= Fp[0] / 3.0;
+  bp[3] -= Fp[0] / 3.0;
+  bp[5] -= Fp[0] / 3.0;
+  const double isg = 1.0 / G.sg;
+  for (int l = 0; l < Q; ++l) {
+    const int x = cx(l), y = cy(l), z = cz(l);
+    double v;
+    if ((y > 0 && p.jf == 0) || (y < 0 && p.jf == g.H - 1))
+      v = pop[opp(l) * g.N + p.n];
+    else
+      v = pop[l * g.N + nidx(g, wrapa(p.i - x, g.nx), p.jf - y, wrapa(p.k - z, g.nz))];
+    f[l] = wgt(l) + v + 0.5 * hermite_eval(l, isg, Fp[0], Fp + 1, bp);
+  }
+}
+
+__device__ inline void load_geo_full(const Grid& g, const double* __restrict__ geo, long long n, AGeo& G) {
+  G.sg = 1.0 + geo[G_SG * g.N + n];
+  for (int q = 0; q < 6; ++q) G.gi[q] = geo[(G_GI + q) * g.N + n] + ((q == 0 || q == 3 || q == 5) ? 1.0 : 0.0);
+  for (int q = 0; q < 18; ++q) G.gam[q] = geo[(G_GAM + q) * g.N + n];
+  for (int q = 0; q < 3; ++q) G.F[q] = geo[(G_F + q) * g.N + n];
+}
+
+// Lattice gradient of the stored moments (walls at rest: ghost j = -j_m).
+__device__ inline void gradient_at(const Grid& g, const double* __restrict__ mom, const Node& p, double dj[3][3]) {
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) dj[a][b] = 0.0;
+  for (int l = 1; l < Q; ++l) {
+    const int x = cx(l), y = cy(l), z = cz(l);
+    const int in = wrapa(p.i + x, g.nx), kn = wrapa(p.k + z, g.nz), jn = p.jf + y;
+    double jb[3];
+    if (jn >= 0 && jn < g.H) {
+      const long long m = nidx(g, in, jn, kn);
+      for (int b = 0; b < 3; ++b) jb[b] = mom[(1 + b) * g.N + m];
+    } else {
+      const long long m = nidx(g, in, p.jf, kn);
+      for (int b = 0; b < 3; ++b) jb[b] = -mom[(1 + b) * g.N + m];
+    }
+    const double fct = 3.0 * wgt(l);
+    for (int b = 0; b < 3; ++b) {
+      dj[0][b] += x * fct * jb[b];
+      dj[1][b] += y * fct * jb[b];
+      dj[2][b] += z * fct * jb[b];
+    }
+  }
+}
+
+__device__ inline void add_geo_bar(const Grid& g, double* __restrict__ lg, long long n, const AGeoBar& gb) {
+  lg[G_SG * g.N + n] += gb.sg;
+  for (int q = 0; q < 6; ++q) lg[(G_GI + q) * g.N + n] += gb.gi[q];
+  for (int q = 0; q < 18; ++q) lg[(G_GAM + q) * g.N + n] += gb.gam[q];
+  for (int q = 0; q < 3; ++q) lg[(G_F + q) * g.N + n] += gb.F[q];
+}
+
+__device__ inline void zero_bar(AGeoBar& gb) {
+  gb.sg = 0;
+  for (int q = 0; q < 6; ++q) gb.gi[q] = 0;
+  for (int q = 0; q < 18; ++q) gb.gam[q] = 0;
+  for (int q = 0; q < 3; ++q) gb.F[q] = 0;
+}
+
+// Moments rho, j of a stored state at every node.
+__global__ void k_adj_moments(Grid g, const double* __restrict__ pop, const double* __restrict__ hist,
+                              const double* __restrict__ geo, double* __restrict__ mom) {
+  Node p;
+  if (!fluid_node(g, p)) return;
+  AGeo G;
+  load_geo_full(g, geo, p.n, G);
+  double f[Q], Fp[10];
+  load_state(g, pop, hist, G, p, f, Fp);
+  double s = 0, j[3] = {0, 0, 0};
+  for (int l = 0; l < Q; ++l) {
+    s += f[l];
+    j[0] += cx(l) * f[l];
+    j[1] += cy(l) * f[l];
+    j[2] += cz(l) * f[l];
+  }
+  mom[p.n] = G.sg * s;
+  for (int a = 0; a < 3; ++a) mom[(1 + a) * g.N + p.n] = G.sg * j[a];
+}
+
+// Reverse of one step at each node (mode 0), or of the history of an initial
+// state (mode 1: only the new coefficients carry an adjoint).
+__global__ void k_adj_node(Grid g, int mode, const double* __restrict__ pop, const double* __restrict__ hist,
+                           const double* __restrict__ geo, const double* __restrict__ mom, double tau,
+                           const double* __restrict__ lfn, const double* __restrict__ lpn, double* __restrict__ lfd,
+                           double* __restrict__ lml, double* __restrict__ ldj, double* __restrict__ lpo,
+                           double* __restrict__ lg) {
+  Node p;
+  if (!fluid_node(g, p)) return;
+  AGeo G;
+  load_geo_full(g, geo, p.n, G);
+  double f[Q], Fp[10], dj[3][3];
+  load_state(g, pop, hist, G, p, f, Fp);
+  gradient_at(g, mom, p, dj);
+  const bool with_old = mode == 0;
+  NodeFwd o;
+  node_fwd(f, Fp, G, dj, tau, with_old, o);
+  double fsb[Q], Fb[Q], cb[10];
+  for (int l = 0; l < Q; ++l) {
+    fsb[l] = 0;
+    Fb[l] = 0;
+  }
+  if (with_old) {
+    // transposed streaming: f*_l(x) went to x + c_l (or bounced back into
+    // direction opp(l) at x); F_l(x)/2 was added to f_l(x, t+1).
+    for (int l = 0; l < Q; ++l) {
+      const int x = cx(l), y = cy(l), z = cz(l);
+      const int jd = p.jf + y;
+      if (jd >= 0 && jd < g.H)
+        fsb[l] = lfn[l * g.N + nidx(g, wrapa(p.i + x, g.nx), jd, wrapa(p.k + z, g.nz))];
+      else
+        fsb[l] = lfn[opp(l) * g.N + p.n];
+      Fb[l] = 0.5 * lfn[l * g.N + p.n];
+    }
+  }
+  for (int q = 0; q < 10; ++q) cb[q] = lpn[q * g.N + p.n];
+  double fb[Q], rb = 0, jb[3] = {0, 0, 0}, djb[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, Fpb[10];
+  for (int l = 0; l < Q; ++l) fb[l] = 0;
+  for (int q = 0; q < 10; ++q) Fpb[q] = 0;
+  AGeoBar gb;
+  zero_bar(gb);
+  node_vjp(f, Fp, G, dj, tau, with_old, o, fsb, Fb, cb, nullptr, fb, rb, jb, djb, Fpb, gb);
+  for (int l = 0; l < Q; ++l) lfd[l * g.N + p.n] = fb[l];
+  lml[p.n] = rb;
+  for (int a = 0; a < 3; ++a) lml[(1 + a) * g.N + p.n] = jb[a];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) ldj[(a * 3 + b) * g.N + p.n] = djb[a][b];
+  if (lpo)
+    for (int q = 0; q < 10; ++q) lpo[q * g.N + p.n] = Fpb[q];
+  add_geo_bar(g, lg, p.n, gb);
+}
+
+// Transposed lattice gradient and the moment VJP:
+// lf_out = lfd + sqrt g (rho_bar + j_bar . c) (+ lf_add), with
+// j_bar = local + sum over the stencil of the neighbours' dj adjoints.
+__global__ void k_adj_gather(Grid g, const double* __restrict__ geo, const double* __restrict__ mom,
+                             const double* __restrict__ lfd, const double* __restrict__ lml,
+                             const double* __restrict__ ldj, const double* __restrict__ lf_add,
+                             double* __restrict__ lf_out, double* __restrict__ lg) {
+  Node p;
+  if (!fluid_node(g, p)) return;
+  double rb = lml[p.n], jb[3] = {lml[g.N + p.n], lml[2 * g.N + p.n], lml[3 * g.N + p.n]};
+  for (int l = 1; l < Q; ++l) {
+    const int x = cx(l), y = cy(l), z = cz(l);
+    const double fct = 3.0 * wgt(l);
+    // x_src = p - c_l used this node as its neighbour in direction l
+    const int js = p.jf - y;
+    if (js >= 0 && js < g.H) {
+      const long long m = nidx(g, wrapa(p.i - x, g.nx), js, wrapa(p.k - z, g.nz));
+      for (int b = 0; b < 3; ++b)
+        jb[b] += fct * (x * ldj[(0 * 3 + b) * g.N + m] + y * ldj[(1 * 3 + b) * g.N + m] + z * ldj[(2 * 3 + b) * g.N + m]);
+    }
+    // wall ghost: node m' = p - (c_x, 0, c_z) in this layer, whose neighbour in
+    // direction l is solid, used -j(p)
+    if ((y < 0 && p.jf == 0) || (y > 0 && p.jf == g.H - 1)) {
+      const long long m = nidx(g, wrapa(p.i - x, g.nx), p.jf, wrapa(p.k - z, g.nz));
+      for (int b = 0; b < 3; ++b)
+        jb[b] -= fct * (x * ldj[(0 * 3 + b) * g.N + m] + y * ldj[(1 * 3 + b) * g.N + m] + z * ldj[(2 * 3 + b) * g.N + m]);
+    }
+  }
+  const double sg = 1.0 + geo[G_SG * g.N + p.n];
+  const double rho = mom[p.n];
+  const double S0 = rho / sg, S1[3] = {mom[g.N + p.n] / sg, mom[2 * g.N + p.n] / sg, mom[3 * g.N + p.n] / sg};
+  double fb[Q];
+  for (int l = 0; l < Q; ++l) fb[l] = lfd[l * g.N + p.n] + (lf_add ? lf_add[l * g.N + p.n] : 0.0);
+  double sgb = 0;
+  moments_vjp(sg, S0, S1, rb, jb, fb, sgb);
+  for (int l = 0; l < Q; ++l) lf_out[l * g.N + p.n] = fb[l];
+  lg[G_SG * g.N + p.n] += sgb;
+}
+
+// Wall-force VJP at one state: L += sum_a W_a F^a, F^a = sgn sum sqrt g
+// T^{i y} J^a_i at the fluid layer next to `wall`.  Adds into lf (adjoint of
+// f at this state), lg and lj.
+__global__ void k_adj_force(Grid g, int wall, const double* __restrict__ pop, const double* __restrict__ hist,
+                            const double* __restrict__ geo, const double* __restrict__ jac, double tau,
+                            const double* __restrict__ W, double* __restrict__ lf, double* __restrict__ lg,
+                            double* __restrict__ lj) {
+  Node p;
+  p.i = blockIdx.x * BX + threadIdx.x;
+  p.k = blockIdx.y * BY + threadIdx.y;
+  if (p.i >= g.nx || p.k >= g.nz) return;
+  p.jf = wall == 0 ? 0 : g.H - 1;
+  p.n = nidx(g, p.i, p.jf, p.k);
+  AGeo G;
+  load_geo_full(g, geo, p.n, G);
+  double f[Q], Fp[10];
+  load_state(g, pop, hist, G, p, f, Fp);
+  const double dj0[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  NodeFwd o;
+  node_fwd(f, Fp, G, dj0, tau, false, o);
+  const double sgn = wall == 0 ? -1.0 : 1.0;
+  double J[3][3];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) J[a][b] = jac[(a * 3 + b) * g.N + p.n];
+  // T^{i y} with y = 1: packed indices sym(i, 1)
+  double Tb[6] = {0, 0, 0, 0, 0, 0};
+  double sgb = 0;
+  for (int i = 0; i < 3; ++i) {
+    double wj = 0;
+    for (int a = 0; a < 3; ++a) wj += W[a] * J[a][i];
+    Tb[sym(i, 1)] += sgn * G.sg * wj;
+    sgb += sgn * wj * o.T[sym(i, 1)];
+    for (int a = 0; a < 3; ++a) lj[(a * 3 + i) * g.N + p.n] += sgn * G.sg * W[a] * o.T[sym(i, 1)];
+  }
+  double fsb[Q], Fb[Q], cb[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int l = 0; l < Q; ++l) fsb[l] = Fb[l] = 0;
+  double fb[Q], rb = 0, jb[3] = {0, 0, 0}, djb[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, Fpb[10];
+  for (int l = 0; l < Q; ++l) fb[l] = 0;
+  AGeoBar gb;
+  zero_bar(gb);
+  gb.sg = sgb;
+  node_vjp(f, Fp, G, dj0, tau, false, o, fsb, Fb, cb, Tb, fb, rb, jb, djb, Fpb, gb);
+  moments_vjp(G.sg, o.S0, o.S1, rb, jb, fb, gb.sg);
+  for (int l = 0; l < Q; ++l) lf[l * g.N + p.n] += fb[l];
+  add_geo_bar(g, lg, p.n, gb);
+}
+
+// ---------------------------------------------------- geometry adjoint
+__device__ __forceinline__ long long eix(const Grid& g, int i, int j, int k) {
+  return ((long long)k * (g.ny + 6) + (j + 3)) * g.nx + i;
+}
+
+__device__ inline void inv3a(const double m[3][3], double r[3][3], double& det) {
+  det = m[0][0] * (m[1][1] * m[2][2] - m[1][2] * m[2][1]) - m[0][1] * (m[1][0] * m[2][2] - m[1][2] * m[2][0]) +
+        m[0][2] * (m[1][0] * m[2][1] - m[1][1] * m[2][0]);
+  const double id = 1.0 / det;
+  r[0][0] = (m[1][1] * m[2][2] - m[1][2] * m[2][1]) * id;
+  r[0][1] = (m[0][2] * m[2][1] - m[0][1] * m[2][2]) * id;
+  r[0][2] = (m[0][1] * m[1][2] - m[0][2] * m[1][1]) * id;
+  r[1][0] = (m[1][2] * m[2][0] - m[1][0] * m[2][2]) * id;
+  r[1][1] = (m[0][0] * m[2][2] - m[0][2] * m[2][0]) * id;
+  r[1][2] = (m[0][2] * m[1][0] - m[0][0] * m[1][2]) * id;
+  r[2][0] = (m[1][0] * m[2][1] - m[1][1] * m[2][0]) * id;
+  r[2][1] = (m[0][1] * m[2][0] - m[0][0] * m[2][1]) * id;
+  r[2][2] = (m[0][0] * m[1][1] - m[0][1] * m[1][0]) * id;
+}
+
+// Fluid-node part: adjoints of Gamma, g^{-1}, det J and J^{-1} F back to
+// D_l g (ldg), g (lge, packed) and J (lJe) on the extended grid.
+__global__ void k_adjg_fluid(Grid g, const double* __restrict__ wext, const double* __restrict__ gext,
+                             const double* __restrict__ jac, double F0, double F1, double F2,
+                             const double* __restrict__ lgv, const double* __restrict__ lj, double* __restrict__ ldg,
+                             double* __restrict__ lge, double* __restrict__ lJe) {
+  Node p;
+  if (!fluid_node(g, p)) return;
+  const int j = p.jf + 1;
+  const long long NE = (long long)g.nz * (g.ny + 6) * g.nx;
+  const long long e = eix(g, p.i, j, p.k);
+  double gm[3][3], gi[3][3], J[3][3], Ji[3][3], det, detJ;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      gm[a][b] = gext[sym(a, b) * NE + e];
+      J[a][b] = jac[(a * 3 + b) * g.N + p.n];
+    }
+  inv3a(gm, gi, det);
+  inv3a(J, Ji, detJ);
+  double dg[3][6];
+  for (int q = 0; q < 6; ++q) {
+    double s0 = 0, s1 = 0, s2 = 0;
+    for (int l = 1; l < Q; ++l) {
+      const double fv = wext[q * NE + eix(g, wrapa(p.i + cx(l), g.nx), j + cy(l), wrapa(p.k + cz(l), g.nz))];
+      s0 += wgt(l) * cx(l) * fv;
+      s1 += wgt(l) * cy(l) * fv;
+      s2 += wgt(l) * cz(l) * fv;
+    }
+    dg[0][q] = 3.0 * s0;
+    dg[1][q] = 3.0 * s1;
+    dg[2][q] = 3.0 * s2;
+  }
+  // Gamma^i_{jk} (packed jk) = 1/2 sum_l gi[i][l] (dg[j][kl] + dg[k][jl] - dg[l][jk])
+  double gib[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};  // adjoint of the full matrix entries
+  double dgb[3][6] = {{0, 0, 0, 0, 0, 0}, {0, 0, 0, 0, 0, 0}, {0, 0, 0, 0, 0, 0}};
+  for (int ii = 0; ii < 3; ++ii)
+    for (int jj = 0; jj < 3; ++jj)
+      for (int kk = jj; kk < 3; ++kk) {
+        const double lb = 0.5 * lgv[(G_GAM + ii * 6 + sym(jj, kk)) * g.N + p.n];
+        for (int l = 0; l < 3; ++l) {
+          gib[ii][l] += lb * (dg[jj][sym(kk, l)] + dg[kk][sym(jj, l)] - dg[l][sym(jj, kk)]);
+          dgb[jj][sym(kk, l)] += lb * gi[ii][l];
+          dgb[kk][sym(jj, l)] += lb * gi[ii][l];
+          dgb[l][sym(jj, kk)] -= lb * gi[ii][l];
+        }
+      }
+  // stored g^ij (packed, a <= b) used gi[a][b]
+  for (int a = 0; a < 3; ++a)
+    for (int b = a; b < 3; ++b) {
+      const double v = lgv[(G_GI + sym(a, b)) * g.N + p.n];
+      if (a == b)
+        gib[a][a] += v;
+      else {
+        gib[a][b] += 0.5 * v;
+        gib[b][a] += 0.5 * v;
+      }
+    }
+  // gi = g^{-1}: gbar = -gi^T gib gi^T, then packed (off-diagonal counted twice)
+  double t[3][3], gbf[3][3];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      double s = 0;
+      for (int c = 0; c < 3; ++c) s += gib[a][c] * gi[c][b];
+      t[a][b] = s;
+    }
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      double s = 0;
+      for (int c = 0; c < 3; ++c) s += gi[c][a] * t[c][b];
+      gbf[a][b] = -s;
+    }
+  for (int a = 0; a < 3; ++a)
+    for (int b = a; b < 3; ++b) lge[sym(a, b) * NE + e] = a == b ? gbf[a][a] : gbf[a][b] + gbf[b][a];
+  for (int l = 0; l < 3; ++l)
+    for (int q = 0; q < 6; ++q) ldg[(l * 6 + q) * g.N + p.n] = dgb[l][q];
+  // sqrt g = det J: d det / dJ = det J^{-T}
+  double Jb[3][3];
+  const double sgb = lgv[G_SG * g.N + p.n];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) Jb[a][b] = sgb * detJ * Ji[b][a] + lj[(a * 3 + b) * g.N + p.n];
+  // F = J^{-1} Fc: Jib[i][a] = Fb[i] Fc[a]; Jb -= J^{-T} Jib J^{-T}
+  const double Fc[3] = {F0, F1, F2};
+  double Fb[3];
+  for (int i = 0; i < 3; ++i) Fb[i] = lgv[(G_F + i) * g.N + p.n];
+  for (int pp = 0; pp < 3; ++pp)
+    for (int q = 0; q < 3; ++q) {
+      double s = 0;
+      for (int i = 0; i < 3; ++i)
+        for (int a = 0; a < 3; ++a) s += Ji[i][pp] * Fb[i] * Fc[a] * Ji[q][a];
+      Jb[pp][q] -= s;
+    }
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) lJe[(a * 3 + b) * NE + e] = Jb[a][b];
+}
+
+// lwe(y) on layers [0, ny-1] = transposed D (the G stencil) of ldg.
+__global__ void k_adjg_w(Grid g, const double* __restrict__ ldg, double* __restrict__ lwe) {
+  const int i = blockIdx.x * BX + threadIdx.x, je = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  const int j = je - 3;
+  if (i >= g.nx || j < 0 || j > g.ny - 1) return;
+  const long long NE = (long long)g.nz * (g.ny + 6) * g.nx;
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  for (int l = 1; l < Q; ++l) {
+    const int jx = j - cy(l);  // source node x = y - c_l (fluid layers 1..ny-2)
+    if (jx < 1 || jx > g.ny - 2) continue;
+    const long long m = nidx(g, wrapa(i - cx(l), g.nx), jx - 1, wrapa(k - cz(l), g.nz));
+    const double fct = 3.0 * wgt(l);
+    for (int q = 0; q < 6; ++q)
+      acc[q] += fct * (cx(l) * ldg[(0 * 6 + q) * g.N + m] + cy(l) * ldg[(1 * 6 + q) * g.N + m] +
+                       cz(l) * ldg[(2 * 6 + q) * g.N + m]);
+  }
+  const long long e = eix(g, i, j, k);
+  for (int q = 0; q < 6; ++q) lwe[q * NE + e] = acc[q];
+}
+
+// Transpose of out(x) = (1 + s) in(x) - sum_l w_l in(x + c_l), out on layers
+// [olo, ohi]:  inb(y) += (1 + s) outb(y) [y in range] - sum_l w_l outb(y - c_l)
+// [y - c_l in range], for y on layers [olo - 1, ohi + 1].  Adds into inb.
+__global__ void k_adjg_smooth(Grid g, int ncomp, int olo, int ohi, const double* __restrict__ outb,
+                              double* __restrict__ inb) {
+  const int i = blockIdx.x * BX + threadIdx.x, je = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  const int j = je - 3;
+  if (i >= g.nx || j < olo - 1 || j > ohi + 1) return;
+  const long long NE = (long long)g.nz * (g.ny + 6) * g.nx;
+  const long long e = eix(g, i, j, k);
+  double s_all = 0;
+  for (int l = 1; l < Q; ++l) s_all += wgt(l);
+  for (int c = 0; c < ncomp; ++c) {
+    double acc = 0;
+    if (j >= olo && j <= ohi) acc += (1.0 + s_all) * outb[c * NE + e];
+    for (int l = 1; l < Q; ++l) {
+      const int jx = j - cy(l);
+      if (jx < olo || jx > ohi) continue;
+      acc -= wgt(l) * outb[c * NE + eix(g, wrapa(i - cx(l), g.nx), jx, wrapa(k - cz(l), g.nz))];
+    }
+    inb[c * NE + e] += acc;
+  }
+}
+
+// g = J^T J on layers [-1, ny]: lJe += from lge (J recomputed from v).
+__global__ void k_adjg_J(Grid g, const double* __restrict__ v, const double* __restrict__ lge,
+                         double* __restrict__ lJe) {
+  const int i = blockIdx.x * BX + threadIdx.x, je = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  const int j = je - 3;
+  if (i >= g.nx || j < -1 || j > g.ny) return;
+  const long long NE = (long long)g.nz * (g.ny + 6) * g.nx;
+  const long long e = eix(g, i, j, k);
+  double J[3][3];
+  for (int a = 0; a < 3; ++a) {
+    double s[3] = {0, 0, 0};
+    for (int l = 1; l < Q; ++l) {
+      const double fv = v[a * NE + eix(g, wrapa(i + cx(l), g.nx), j + cy(l), wrapa(k + cz(l), g.nz))];
+      s[0] += wgt(l) * cx(l) * fv;
+      s[1] += wgt(l) * cy(l) * fv;
+      s[2] += wgt(l) * cz(l) * fv;
+    }
+    for (int b = 0; b < 3; ++b) J[a][b] = (a == b ? 1.0 : 0.0) + 3.0 * s[b];
+  }
+  const bool fluid = j >= 1 && j <= g.ny - 2;
+  double Jb[3][3];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) Jb[a][b] = fluid ? lJe[(a * 3 + b) * NE + e] : 0.0;
+  for (int a = 0; a < 3; ++a)
+    for (int b = a; b < 3; ++b) {
+      const double lb = lge[sym(a, b) * NE + e];
+      for (int c = 0; c < 3; ++c) {
+        Jb[c][a] += lb * J[c][b];
+        Jb[c][b] += lb * J[c][a];
+      }
+    }
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) lJe[(a * 3 + b) * NE + e] = Jb[a][b];
+}
+
+// J = I + G v on layers [-1, ny]: lve(y) for y on [-2, ny+1].
+__global__ void k_adjg_v(Grid g, const double* __restrict__ lJe, double* __restrict__ lve) {
+  const int i = blockIdx.x * BX + threadIdx.x, je = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  const int j = je - 3;
+  if (i >= g.nx || j < -2 || j > g.ny + 1) return;
+  const long long NE = (long long)g.nz * (g.ny + 6) * g.nx;
+  double acc[3] = {0, 0, 0};
+  for (int l = 1; l < Q; ++l) {
+    const int jx = j - cy(l);
+    if (jx < -1 || jx > g.ny) continue;
+    const long long m = eix(g, wrapa(i - cx(l), g.nx), jx, wrapa(k - cz(l), g.nz));
+    const double fct = 3.0 * wgt(l);
+    for (int a = 0; a < 3; ++a)
+      acc[a] += fct * (cx(l) * lJe[(a * 3 + 0) * NE + m] + cy(l) * lJe[(a * 3 + 1) * NE + m] +
+                       cz(l) * lJe[(a * 3 + 2) * NE + m]);
+  }
+  const long long e = eix(g, i, j, k);
+  for (int a = 0; a < 3; ++a) lve[a * NE + e] = acc[a];
+}
+
+// Chart adjoint from the displacement adjoint on the extended grid: layers
+// 0..ny-1 directly, plus the transposed cubic continuation.
+__global__ void k_adjg_chart(Grid g, const double* __restrict__ lue, double* __restrict__ gc) {
+  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  if (i >= g.nx || j >= g.ny) return;
+  const long long NE = (long long)g.nz * (g.ny + 6) * g.nx, NC = (long long)g.nz * g.ny * g.nx;
+  // u(-d) = sum_m C[d][m] u(m); u(ny-1+d) = sum_m C[d][m] u(ny-1-m)
+  const double C[3][4] = {{4, -6, 4, -1}, {10, -20, 15, -4}, {20, -45, 36, -10}};
+  for (int a = 0; a < 3; ++a) {
+    double acc = lue[a * NE + eix(g, i, j, k)];
+    if (j <= 3)
+      for (int d = 0; d < 3; ++d) acc += C[d][j] * lue[a * NE + eix(g, i, -1 - d, k)];
+    if (j >= g.ny - 4)
+      for (int d = 0; d < 3; ++d) acc += C[d][g.ny - 1 - j] * lue[a * NE + eix(g, i, g.ny + d, k)];
+    gc[a * NC + ((long long)k * g.ny + j) * g.nx + i] = acc;
+  }
+}
+
+// Top-wall displacement adjoint: chart_y = xi_y + (eta/H) d_top + ...
+__global__ void k_adjg_disp(Grid g, const double* __restrict__ gc, double* __restrict__ gd) {
+  const int i = blockIdx.x * BX + threadIdx.x, k = blockIdx.y * BY + threadIdx.y;
+  if (i >= g.nx || k >= g.nz) return;
+  const long long NC = (long long)g.nz * g.ny * g.nx;
+  double acc = 0;
+  for (int j = 0; j < g.ny; ++j) acc += ((j - 0.5) / g.H) * gc[NC + ((long long)k * g.ny + j) * g.nx + i];
+  gd[(long long)k * g.nx + i] = acc;
+}
+
+hipError_t copy_state(const Fields& F, double* dst, bool save, hipStream_t s) {
+  const size_t np = sizeof(double) * 19 * (size_t)F.g.N, nh = sizeof(double) * H_N * (size_t)F.g.N;
+  double* pop = (double*)F.pop[F.cur];
+  double* hist = (double*)F.hist[F.cur];
+  hipError_t e;
+  if (save) {
+    e = hipMemcpyAsync(dst, pop, np, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(dst + 19 * F.g.N, hist, nh, hipMemcpyDeviceToDevice, s);
+  } else {
+    e = hipMemcpyAsync(pop, dst, np, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(hist, dst + 19 * F.g.N, nh, hipMemcpyDeviceToDevice, s);
+  }
+  return e;
+}
+
+}  // namespace
+
+#define HCHK(x)                        \
+  do {                                 \
+    hipError_t _e = (x);               \
+    if (_e != hipSuccess) return _e;   \
+  } while (0)
+
+hipError_t adjoint_forward(Fields& F, AdjointBuffers& A, hipStream_t s, int K, int N, int wall, double tau,
+                           double* forces) {
+  const size_t state = (size_t)(19 + H_N) * F.g.N;
+  HCHK(copy_state(F, A.ckpt, true, s));
+  for (int t = 0; t < K; ++t) {
+    HCHK(launch_step<double>(F, s, tau));
+    HCHK(launch_wall_force<double>(F, s, wall, tau, forces + 3 * t, nullptr));
+    if ((t + 1) % N == 0 && t + 1 < K) HCHK(copy_state(F, A.ckpt + state * ((t + 1) / N), true, s));
+  }
+  HCHK(copy_state(F, A.ckpt + state * (A.nckpt - 1), true, s));
+  return hipGetLastError();
+}
+
+hipError_t adjoint_backward(Fields& F, AdjointBuffers& A, hipStream_t s, int K, int N, int wall, double tau,
+                            const double Fc[3], const double* dLdF, double* grad_disp, double* grad_chart,
+                            double* grad_f0) {
+  if (F.moving[0] || F.moving[1]) return hipErrorNotSupported;
+  const Grid g = F.g;
+  const size_t Nn = (size_t)g.N;
+  const size_t state = (size_t)(19 + H_N) * Nn;
+  const size_t NE = (size_t)g.nz * (g.ny + 6) * g.nx, NC = (size_t)g.nz * g.ny * g.nx;
+  const dim3 b(BX, BY), fg = fluid_grid(g), cg = col_grid(g), eg = ext_grid(g);
+  double* mom = (double*)F.mom;
+  const double* geo = (const double*)F.geo;
+  int cur = 0;
+  HCHK(hipMemsetAsync(A.lf[cur], 0, sizeof(double) * 19 * Nn, s));
+  HCHK(hipMemsetAsync(A.lp[cur], 0, sizeof(double) * H_N * Nn, s));
+  HCHK(hipMemsetAsync(A.lg, 0, sizeof(double) * G_N * Nn, s));
+  HCHK(hipMemsetAsync(A.lj, 0, sizeof(double) * 9 * Nn, s));
+  // force at the final state K
+  {
+    const double* fin = A.ckpt + state * (A.nckpt - 1);
+    hipLaunchKernelGGL(k_adj_force, cg, b, 0, s, g, wall, fin, fin + 19 * Nn, geo, (const double*)F.jac, tau,
+                       dLdF + 3 * (K - 1), A.lf[cur], A.lg, A.lj);
+  }
+  const int nseg = (K + N - 1) / N;
+  for (int sgm = nseg - 1; sgm >= 0; --sgm) {
+    const int t0 = sgm * N, t1 = (t0 + N < K) ? t0 + N : K;
+    HCHK(copy_state(F, A.ckpt + state * sgm, false, s));
+    for (int t = t0; t < t1; ++t) {
+      HCHK(copy_state(F, A.traj + state * (t - t0), true, s));
+      if (t + 1 < t1) HCHK(launch_step<double>(F, s, tau));
+    }
+    for (int t = t1 - 1; t >= t0; --t) {
+      const double* st = A.traj + state * (t - t0);
+      const double* pop = st;
+      const double* hist = st + 19 * Nn;
+      hipLaunchKernelGGL(k_adj_moments, fg, b, 0, s, g, pop, hist, geo, mom);
+      hipLaunchKernelGGL(k_adj_node, fg, b, 0, s, g, 0, pop, hist, geo, (const double*)mom, tau,
+                         (const double*)A.lf[cur], (const double*)A.lp[cur], A.lfd, A.lml, A.ldj, A.lp[cur ^ 1],
+                         A.lg);
+      hipLaunchKernelGGL(k_adj_gather, fg, b, 0, s, g, geo, (const double*)mom, (const double*)A.lfd,
+                         (const double*)A.lml, (const double*)A.ldj, (const double*)nullptr, A.lf[cur ^ 1], A.lg);
+      cur ^= 1;
+      if (t >= 1)
+        hipLaunchKernelGGL(k_adj_force, cg, b, 0, s, g, wall, pop, hist, geo, (const double*)F.jac, tau,
+                           dLdF + 3 * (t - 1), A.lf[cur], A.lg, A.lj);
+    }
+  }
+  // history of the initial state: F(x,-1) := F(state 0)
+  {
+    const double* pop = A.ckpt;
+    const double* hist = A.ckpt + 19 * Nn;
+    hipLaunchKernelGGL(k_adj_moments, fg, b, 0, s, g, pop, hist, geo, mom);
+    hipLaunchKernelGGL(k_adj_node, fg, b, 0, s, g, 1, pop, hist, geo, (const double*)mom, tau,
+                       (const double*)A.lf[cur], (const double*)A.lp[cur], A.lfd, A.lml, A.ldj, (double*)nullptr,
+                       A.lg);
+    hipLaunchKernelGGL(k_adj_gather, fg, b, 0, s, g, geo, (const double*)mom, (const double*)A.lfd,
+                       (const double*)A.lml, (const double*)A.ldj, (const double*)A.lf[cur], A.lf[cur ^ 1], A.lg);
+    cur ^= 1;
+  }
+  if (grad_f0) HCHK(hipMemcpyAsync(grad_f0, A.lf[cur], sizeof(double) * 19 * Nn, hipMemcpyDeviceToDevice, s));
+  // geometry
+  if (grad_disp || grad_chart) {
+    HCHK(hipMemsetAsync(A.lge, 0, sizeof(double) * 6 * NE, s));
+    HCHK(hipMemsetAsync(A.lJe, 0, sizeof(double) * 9 * NE, s));
+    HCHK(hipMemsetAsync(A.lve, 0, sizeof(double) * 3 * NE, s));
+    HCHK(hipMemsetAsync(A.lue, 0, sizeof(double) * 3 * NE, s));
+    hipLaunchKernelGGL(k_adjg_fluid, fg, b, 0, s, g, (const double*)F.wext, (const double*)F.gext,
+                       (const double*)F.jac, Fc[0], Fc[1], Fc[2], (const double*)A.lg, (const double*)A.lj, A.ldg,
+                       A.lge, A.lJe);
+    hipLaunchKernelGGL(k_adjg_w, eg, b, 0, s, g, (const double*)A.ldg, A.lwe);
+    hipLaunchKernelGGL(k_adjg_smooth, eg, b, 0, s, g, 6, 0, g.ny - 1, (const double*)A.lwe, A.lge);
+    hipLaunchKernelGGL(k_adjg_J, eg, b, 0, s, g, (const double*)F.vtmp, (const double*)A.lge, A.lJe);
+    hipLaunchKernelGGL(k_adjg_v, eg, b, 0, s, g, (const double*)A.lJe, A.lve);
+    hipLaunchKernelGGL(k_adjg_smooth, eg, b, 0, s, g, 3, -2, g.ny + 1, (const double*)A.lve, A.lue);
+    hipLaunchKernelGGL(k_adjg_chart, dim3((g.nx + BX - 1) / BX, (g.ny + BY - 1) / BY, g.nz), b, 0, s, g,
+                       (const double*)A.lue, A.gc);
+    if (grad_chart) HCHK(hipMemcpyAsync(grad_chart, A.gc, sizeof(double) * 3 * NC, hipMemcpyDeviceToDevice, s));
+    if (grad_disp) hipLaunchKernelGGL(k_adjg_disp, cg, b, 0, s, g, (const double*)A.gc, grad_disp);
+  }
+  // leave the context at the recorded final state
+  HCHK(copy_state(F, A.ckpt + state * (A.nckpt - 1), false, s));
+  return hipGetLastError();
 }
 
 }  // namespace lbm

@@ -299,3 +299,41 @@ class Solver:
 
     def sync(self):
         lbm_sync(self.ctx)
+
+    def forward_record(self, K, wall=LBM_WALL_YMAX):
+        """Run K steps from the current state, keeping checkpoints for
+        backward(); returns the wall forces of states 1..K, [K, 3]."""
+        forces = torch.empty((K, 3), dtype=torch.float64, device=self.device)
+        lbm_forward_record(self.ctx, K, self.ckpt_every, wall, forces)
+        return forces
+
+    def backward(self, dLdF, need_disp=True, need_chart=False, need_f0=True):
+        """Adjoint of the last forward_record for dL/dF [K, 3]: returns
+        (dL/d top-wall displacement [nz, nx], dL/d chart [3, nz, ny, nx],
+        dL/d f0 [19, nz, H, nx]); entries not asked for are None."""
+        g = self._dev(dLdF)
+        gd = torch.empty((self.nz, self.nx), dtype=torch.float64, device=self.device) if need_disp else None
+        gc = torch.empty((3, self.nz, self.ny, self.nx), dtype=torch.float64, device=self.device) if need_chart else None
+        gf = torch.empty((19,) + self.fluid_shape, dtype=torch.float64, device=self.device) if need_f0 else None
+        lbm_backward(self.ctx, g, gd, gc, gf)
+        return gd, gc, gf
+
+
+class WallForceFn(torch.autograd.Function):
+    """forces[K, 3] = wall forces of states 1..K after setting the top-wall
+    displacement d [nz, nx] and the initial populations f0 [19, nz, H, nx] on
+    `solver` (FP64, walls at rest).  backward returns (dL/dd, dL/df0); f0 is an
+    independent input (its forcing history is recomputed from it)."""
+
+    @staticmethod
+    def forward(ctx, d, f0, solver, K, wall=LBM_WALL_YMAX):
+        solver.set_wall_displacement(LBM_WALL_YMAX, d.detach())
+        solver.set_populations(f0.detach())
+        forces = solver.forward_record(K, wall)
+        ctx.solver = solver
+        return forces
+
+    @staticmethod
+    def backward(ctx, gF):
+        gd, _, gf = ctx.solver.backward(gF.contiguous(), need_disp=True, need_chart=False, need_f0=True)
+        return gd, gf, None, None, None

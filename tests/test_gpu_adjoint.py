@@ -1,0 +1,120 @@
+"""Adjoint of K FP64 steps (lbm_forward_record / lbm_backward) against the
+oracle's exact forward-mode derivatives, and its own consistency checks."""
+import numpy as np
+import pytest
+
+from oracle import Oracle, dual_forces, run_forces
+from paper_1803_07822_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _lbm():
+    from paper_1803_07822_amd import lbm
+
+    return lbm
+
+
+def _case(nx=10, ny=7, nz=6, tau=0.7, seed=3):
+    d = synth.gaussian_random_field(nx, nz, corr=2.5, max_abs=0.4, seed=seed)
+    o = Oracle(nx, ny, nz, tau)
+    o.set_wall_displacement(1, d)
+    o.init_equilibrium(1 + synth.random_perturbation((nz, ny - 2, nx), 1e-3, seed + 1),
+                       synth.random_perturbation((3, nz, ny - 2, nx), 1e-2, seed + 2))
+    f0 = o.populations()
+    return d, f0
+
+
+def _gpu_grads(nx, ny, nz, tau, F, d, f0, K, N, W):
+    lbm = _lbm()
+    S = lbm.Solver(nx, ny, nz, tau, "fp64", adjoint_K=K, ckpt_every=N)
+    S.set_body_force(F)
+    S.set_wall_displacement(1, d)
+    S.set_populations(f0)
+    forces = S.forward_record(K).cpu().numpy()
+    gd, gc, gf = S.backward(W, need_disp=True, need_chart=True, need_f0=True)
+    return S, forces, gd.cpu().numpy(), gc.cpu().numpy(), gf.cpu().numpy()
+
+
+def test_adjoint_matches_forward_mode_derivatives():
+    nx, ny, nz, tau, K, N = 10, 7, 6, 0.7, 6, 2
+    F = (1e-4, 0.0, 2e-5)
+    d, f0 = _case(nx, ny, nz, tau)
+    W = synth.random_perturbation((K, 3), 1.0, 17)
+    S, forces, gd, gc, gf = _gpu_grads(nx, ny, nz, tau, F, d, f0, K, N, W)
+    fo = run_forces(nx, ny, nz, tau, F, d, f0, K)
+    assert np.abs(forces - fo).max() < 1e-12 * np.abs(fo).max()
+    errs = []
+    for r in range(4):
+        dd = synth.random_unit(d.shape, 100 + r) if r != 1 else np.zeros(d.shape)
+        df = synth.random_unit(f0.shape, 200 + r) * 1e-2 if r != 0 else np.zeros(f0.shape)
+        _, dforces = dual_forces(nx, ny, nz, tau, F, d, dd, f0, df, K)
+        exact = float((W * dforces).sum())
+        adj = float((gd * dd).sum() + (gf * df).sum())
+        errs.append(abs(adj - exact) / max(abs(exact), 1e-30))
+        assert abs(exact) > 1e-12
+    print("adjoint vs forward mode, relative errors:", errs)
+    assert max(errs) < 1e-9, errs
+
+
+def test_adjoint_chart_and_displacement_agree():
+    """d enters only through chart_y = xi_y + (eta/H) d: <dL/dchart, dchart> = <dL/dd, dd>."""
+    nx, ny, nz, tau, K, N = 10, 7, 6, 0.7, 4, 2
+    d, f0 = _case(nx, ny, nz, tau, seed=5)
+    W = synth.random_perturbation((K, 3), 1.0, 9)
+    _, _, gd, gc, _ = _gpu_grads(nx, ny, nz, tau, (1e-4, 0, 0), d, f0, K, N, W)
+    dd = synth.random_unit(d.shape, 31)
+    dchart = synth.chart_from_displacement(nx, ny, nz, dd) - synth.identity_chart(nx, ny, nz)
+    a = float((gc * dchart).sum())
+    b = float((gd * dd).sum())
+    assert abs(a - b) < 1e-12 * max(abs(a), abs(b))
+
+
+@pytest.mark.parametrize("N", [1, 3, 6])
+def test_adjoint_independent_of_checkpoint_interval(N):
+    nx, ny, nz, tau, K = 10, 7, 6, 0.7, 6
+    d, f0 = _case(nx, ny, nz, tau, seed=7)
+    W = synth.random_perturbation((K, 3), 1.0, 23)
+    _, _, gd_ref, _, gf_ref = _gpu_grads(nx, ny, nz, tau, (1e-4, 0, 0), d, f0, K, 2, W)
+    _, _, gd, _, gf = _gpu_grads(nx, ny, nz, tau, (1e-4, 0, 0), d, f0, K, N, W)
+    assert np.abs(gd - gd_ref).max() <= 1e-13 * np.abs(gd_ref).max()
+    assert np.abs(gf - gf_ref).max() <= 1e-13 * np.abs(gf_ref).max()
+
+
+def test_autograd_function():
+    lbm = _lbm()
+    nx, ny, nz, tau, K, N = 10, 7, 6, 0.7, 5, 2
+    d, f0 = _case(nx, ny, nz, tau, seed=11)
+    S = lbm.Solver(nx, ny, nz, tau, "fp64", adjoint_K=K, ckpt_every=N)
+    S.set_body_force((1e-4, 0, 0))
+    dt = torch.tensor(d, dtype=torch.float64, device=S.device, requires_grad=True)
+    ft = torch.tensor(f0, dtype=torch.float64, device=S.device, requires_grad=True)
+    forces = lbm.WallForceFn.apply(dt, ft, S, K)
+    loss = forces[:, 0].sum()
+    loss.backward()
+    dd = synth.random_unit(d.shape, 41)
+    _, dforces = dual_forces(nx, ny, nz, tau, (1e-4, 0, 0), d, dd, f0, np.zeros_like(f0), K)
+    exact = dforces[:, 0].sum()
+    adj = float((dt.grad.cpu().numpy() * dd).sum())
+    assert abs(adj - exact) < 1e-9 * abs(exact)
+    assert ft.grad is not None and torch.isfinite(ft.grad).all()
+
+
+def test_adjoint_rejects_fp32_and_moving_walls():
+    lbm = _lbm()
+    S = lbm.Solver(8, 6, 4, 0.8, "fp32")
+    with pytest.raises(lbm.LBMError) as e:
+        lbm.lbm_reserve_adjoint(S.ctx, 4, 2)
+    assert e.value.code == -6
+    S = lbm.Solver(8, 6, 4, 0.8, "fp64", adjoint_K=4, ckpt_every=2)
+    S.set_wall_displacement(1, np.zeros((4, 8)))
+    v = np.zeros((4, 8, 3))
+    v[..., 0] = 1e-3
+    S.set_wall_velocity(1, v)
+    S.init_equilibrium()
+    S.forward_record(4)
+    with pytest.raises(lbm.LBMError) as e:
+        S.backward(np.ones((4, 3)))
+    assert e.value.code == -6

@@ -220,8 +220,11 @@ class Solver:
 
     def __del__(self):
         ctx = getattr(self, "ctx", None)
-        if ctx:
-            lbm_destroy(ctx)
+        if ctx and _lib is not None:
+            try:
+                _lib.lbm_destroy(ctx)
+            except Exception:  # interpreter shutdown: the library may be gone
+                pass
             self.ctx = None
 
     @property

@@ -118,3 +118,54 @@ def test_adjoint_rejects_fp32_and_moving_walls():
     with pytest.raises(lbm.LBMError) as e:
         S.backward(np.ones((4, 3)))
     assert e.value.code == -6
+
+
+def c4_setup():
+    """The 128x64x64 adjoint workload: tau 0.7, body force 1e-6, top-wall
+    displacement from a Gaussian random field (l = 8, max |d| = 0.05*64,
+    seed 4) stored in FP32, initial state at rest."""
+    w = synth.workload("c4_adjoint_128x64x64")
+    d = w.disp().astype(np.float32).astype(np.float64)
+    o = Oracle(w.nx, w.ny, w.nz, w.tau)  # the oracle only builds f0 here (no stepping)
+    o.set_wall_displacement(1, d)
+    o.init_equilibrium()
+    return w, d, o.populations()
+
+
+def test_c4_adjoint_against_central_differences():
+    """Gradient of L = sum_{t=1..200} F_x(t) against FP64 central differences
+    of the GPU forward (step 1e-6) on 16 seeded directions in d and 16 in f0."""
+    lbm = _lbm()
+    w, d, f0 = c4_setup()
+    K, N = w.steps, w.extra["ckpt_every"]
+    S = lbm.Solver(w.nx, w.ny, w.nz, w.tau, "fp64", adjoint_K=K, ckpt_every=N)
+    S.set_body_force(w.force)
+
+    def loss(dv, fv):
+        S.set_wall_displacement(1, dv)
+        S.set_populations(fv)
+        return float(S.forward_record(K)[:, 0].sum().item())
+
+    S.set_wall_displacement(1, d)
+    S.set_populations(f0)
+    S.forward_record(K)
+    W = np.zeros((K, 3))
+    W[:, 0] = 1.0
+    gd, _, gf = S.backward(W)
+    gd, gf = gd.cpu().numpy(), gf.cpu().numpy()
+    # Directions have i.i.d. standard-normal entries (f0: scaled by the lattice
+    # weights), so the step 1e-6 moves every entry by about 1e-6.
+    eps = 1e-6
+    wl = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)[:, None, None, None]
+    errs_d, errs_f = [], []
+    rng = np.random.Generator(np.random.PCG64(44))
+    for r in range(16):
+        v = rng.standard_normal(d.shape)
+        fd = (loss(d + eps * v, f0) - loss(d - eps * v, f0)) / (2 * eps)
+        errs_d.append(abs(fd - float((gd * v).sum())) / abs(fd))
+        u = rng.standard_normal(f0.shape) * wl
+        fdu = (loss(d, f0 + eps * u) - loss(d, f0 - eps * u)) / (2 * eps)
+        errs_f.append(abs(fdu - float((gf * u).sum())) / abs(fdu))
+    print(f"C4 FD check: max rel err d {max(errs_d):.2e}, f0 {max(errs_f):.2e}")
+    assert max(errs_d) < 1e-3, errs_d
+    assert max(errs_f) < 1e-3, errs_f

@@ -179,9 +179,13 @@ int lbm_step_profiled(lbm_ctx* ctx, int n, double* h_ms, int nslots);
 /* Launch shape of the step: zchunk = planes marched per block by the fused
  * step kernel (0 = chosen from the grid size); variant 0 = fused single-kernel
  * step on 64x4 tiles, 1 = two kernels (moment pass, collision pass), 2 =
- * fused on 64x2 tiles, 3 = fused on 64x1 tiles.  Results agree to rounding;
- * only the speed differs. */
-int lbm_set_tuning(lbm_ctx* ctx, int zchunk, int variant);
+ * fused on 64x2 tiles, 3 = fused on 64x1 tiles.  stage = where the fused step
+ * keeps a plane's pulled populations between its moment pass and its
+ * collision: 0 = nowhere (pulled again, from the caches), 1 = registers (FP32
+ * only; FP64 runs 0), -1 = the default of the precision (1 in FP32, 0 in
+ * FP64).  Results agree to rounding; only the speed differs.  EINVAL for
+ * zchunk < 0, a variant outside 0..3 or a stage outside -1..1. */
+int lbm_set_tuning(lbm_ctx* ctx, int zchunk, int variant, int stage);
 
 /* Wait for the stream and check the instability guard. */
 int lbm_sync(lbm_ctx* ctx);

@@ -47,6 +47,11 @@ Grid make_grid(const lbm_grid* h) {
   return g;
 }
 
+// Staging of pulled populations in the fused step that measured fastest:
+// registers in FP32; in FP64 the collision leaves no registers for a second
+// plane.
+int default_stage(int precision) { return precision == LBM_FP64 ? 0 : 1; }
+
 void carve_core(Carver& c, const Grid& g, int precision, Fields& F) {
   const size_t sz = precision == LBM_FP64 ? sizeof(double) : sizeof(float);
   const long long NE = (long long)g.nz * (g.ny + 6) * g.nx, NC = (long long)g.nz * g.ny * g.nx, N = g.N;
@@ -150,6 +155,7 @@ int lbm_create(lbm_ctx** out, const lbm_grid* h_grid, int lattice, double tau, i
   if (bytes < need) return LBM_ENOMEM;
   lbm_ctx* c = new lbm_ctx();
   c->precision = precision;
+  c->F.stage = default_stage(precision);
   c->tau = tau;
   c->stream = (hipStream_t)hip_stream;
   c->ws = (char*)d_workspace;
@@ -331,9 +337,10 @@ int lbm_step_profiled(lbm_ctx* c, int n, double* h_ms, int nslots) {
   if (n < 1 || !h_ms || nslots < lbm::STEP_KERNELS) return fail(c, LBM_EINVAL, "bad profiling arguments");
   if (!c->have_state) return fail(c, LBM_ESTATE, "no state");
   const int NK = lbm::STEP_KERNELS;
-  std::vector<hipEvent_t> ev((size_t)n * (NK + 1));
-  for (auto& e : ev) LBM_HIP(c, hipEventCreate(&e));
+  std::vector<hipEvent_t> ev((size_t)n * (NK + 1), nullptr);
   int rc = LBM_OK;
+  for (auto& e : ev)
+    if (rc == LBM_OK) rc = hip_check(c, hipEventCreate(&e), "hipEventCreate");
   for (int t = 0; t < n && rc == LBM_OK; ++t) {
     hipError_t e = c->precision == LBM_FP64
                        ? lbm::launch_step<double>(c->F, c->stream, c->tau, &ev[(size_t)t * (NK + 1)])
@@ -342,24 +349,30 @@ int lbm_step_profiled(lbm_ctx* c, int n, double* h_ms, int nslots) {
   }
   if (rc == LBM_OK) rc = hip_check(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
   for (int k = 0; k < nslots; ++k) h_ms[k] = 0.0;
-  if (rc == LBM_OK)
-    for (int t = 0; t < n; ++t)
-      for (int k = 0; k < NK; ++k) {
-        float ms = 0.f;
-        hipEventElapsedTime(&ms, ev[(size_t)t * (NK + 1) + k], ev[(size_t)t * (NK + 1) + k + 1]);
-        h_ms[k] += ms / n;
-      }
-  for (auto& e : ev) hipEventDestroy(e);
+  for (int t = 0; t < n && rc == LBM_OK; ++t)
+    for (int k = 0; k < NK && rc == LBM_OK; ++k) {
+      float ms = 0.f;
+      rc = hip_check(c, hipEventElapsedTime(&ms, ev[(size_t)t * (NK + 1) + k], ev[(size_t)t * (NK + 1) + k + 1]),
+                     "hipEventElapsedTime");
+      h_ms[k] += ms / n;
+    }
+  for (auto& e : ev) {
+    if (!e) continue;
+    const hipError_t d = hipEventDestroy(e);
+    if (rc == LBM_OK) rc = hip_check(c, d, "hipEventDestroy");
+  }
   if (n > 0) c->recorded = 0;
   return rc;
 }
 
-int lbm_set_tuning(lbm_ctx* c, int zchunk, int variant) {
+int lbm_set_tuning(lbm_ctx* c, int zchunk, int variant, int stage) {
   LBM_GUARD(c);
-  if (zchunk < 0 || variant < 0 || variant > 3) return fail(c, LBM_EINVAL, "bad tuning arguments");
+  if (zchunk < 0 || variant < 0 || variant > 3 || stage < -1 || stage > 1)
+    return fail(c, LBM_EINVAL, "bad tuning arguments");
   c->F.zc = zchunk;
   c->F.variant = variant == 1 ? 1 : 0;
   c->F.ty = variant == 2 ? 2 : (variant == 3 ? 1 : 4);
+  c->F.stage = stage >= 0 ? stage : default_stage(c->precision);
   return LBM_OK;
 }
 

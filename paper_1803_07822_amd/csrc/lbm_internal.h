@@ -37,6 +37,7 @@ struct Fields {
   int zc = 0;        // planes per block of the fused step (0 = automatic)
   int variant = 0;   // 0: fused step; 1: two-pass step (moments pass + collision pass)
   int ty = 4;        // rows of 64 nodes per block of the fused step (1, 2, 4)
+  int stage = 1;     // FP32 fused step keeps pulled populations in registers
 };
 
 constexpr int BX = 64, BY = 4;

@@ -485,28 +485,31 @@ __global__ void k_sum_partials(int nb, const double* __restrict__ part, double* 
 // step (the fused step is one kernel: ev[1] and ev[2] then coincide).
 template <class T> hipError_t launch_step(Fields& F, hipStream_t s, T tau, hipEvent_t* ev) {
   const Grid g = F.g;
+  hipError_t e = hipSuccess;
+  auto mark = [&](int k) {
+    if (ev && e == hipSuccess) e = hipEventRecord(ev[k], s);
+  };
   if (F.variant == 0) {
-    if (ev) hipEventRecord(ev[0], s);
-    hipError_t e = launch_step_fused<T>(F, s, tau, F.zc, F.ty);
-    if (ev) {
-      hipEventRecord(ev[1], s);
-      hipEventRecord(ev[2], s);
-    }
+    mark(0);
+    if (e == hipSuccess) e = launch_step_fused<T>(F, s, tau, F.zc, F.ty);
+    mark(1);
+    mark(2);
     return e;
   }
   dim3 b(BX, BY);
   const T* pin = (const T*)F.pop[F.cur];
   T* pout = (T*)F.pop[F.cur ^ 1];
-  if (ev) hipEventRecord(ev[0], s);
+  mark(0);
   hipLaunchKernelGGL(k_moments<T>, fluid_grid(g), b, 0, s, g, pin, (const T*)F.hist[F.cur], (const T*)F.geo,
                      (T*)F.mom);
-  if (ev) hipEventRecord(ev[1], s);
+  mark(1);
   hipLaunchKernelGGL(k_collide<T>, fluid_grid(g), b, 0, s, g, pin, pout, (const T*)F.hist[F.cur],
                      (T*)F.hist[F.cur ^ 1], (const T*)F.geo,
                      (const T*)F.mom, (const T*)F.uw, F.moving[0], F.moving[1], tau, F.flag);
-  if (ev) hipEventRecord(ev[2], s);
+  mark(2);
   F.cur ^= 1;
-  return hipGetLastError();
+  const hipError_t l = hipGetLastError();
+  return e != hipSuccess ? e : l;
 }
 
 template <class T> hipError_t launch_feq_full(Fields& F, hipStream_t s, const double* rho, const double* uc) {

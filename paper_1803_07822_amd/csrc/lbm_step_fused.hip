@@ -5,8 +5,11 @@
 // 18 neighbours before any collision, so the block keeps the moments
 // (rho - 1, rho u) of three consecutive planes of its tile plus a one-node
 // halo in an LDS ring: at plane z it forms the moments of plane z+1, then
-// collides plane z.  Populations are read from HBM once per step (the second
-// read of a plane, one iteration later, and the halo reads hit the caches).
+// collides plane z.  In FP32 each thread keeps the 19 pulled populations of
+// its own node in registers from the moment pass to the collision one
+// iteration later; in FP64 (no register room) the collision pulls them again,
+// from the caches.  The halo entries are pulled by the block as well, and
+// those reads mostly hit L2.
 // Blocks are numbered so that each XCD gets a contiguous range of tiles,
 // which keeps the halo reads of neighbouring tiles in one L2.
 //
@@ -79,15 +82,23 @@ template <class T> __device__ __forceinline__ T fld(const T* __restrict__ a, int
   return at(a + (size_t)q * g.N, n);
 }
 
-// rho - 1 and rho u of the streamed state at a fluid node.
-template <class T>
+// Discards the pulled deviations of a node.
+struct NoKeep {
+  template <class L, class T> __device__ void operator()(L, T) const {}
+};
+
+// rho - 1 and rho u of the streamed state at a fluid node; each pulled
+// deviation g~_l is also handed to keep(l, g~_l).
+template <class T, class Keep = NoKeep>
 __device__ __forceinline__ void node_moments(const T* __restrict__ pop, const T* __restrict__ hist,
-                                             const T* __restrict__ geo, const Grid& g, int i, int jf, int k, T m[4]) {
+                                             const T* __restrict__ geo, const Grid& g, int i, int jf, int k, T m[4],
+                                             const Keep& keep = Keep()) {
   const NodeIdx p = node_idx(g, i, jf, k);
   T s = 0, j0 = 0, j1 = 0, j2 = 0;
   for_q([&](auto L) {
     constexpr int l = decltype(L)::value;
     const T v = pullf<T, l>(pop, g, p);
+    keep(L, v);
     s += v;
     if (cx(l)) j0 += T(cx(l)) * v;
     if (cy(l)) j1 += T(cy(l)) * v;
@@ -101,43 +112,84 @@ __device__ __forceinline__ void node_moments(const T* __restrict__ pop, const T*
   m[3] = sg * j2 + T(0.5) * fld(hist, H_B + 2, g, p.n);
 }
 
-// Fill one ring slot with the moments of plane k over the haloed tile.  Wall
-// layers (jf = -1, H) get the mirror ghost of the adjacent fluid node.
+// Moments of entry e of the haloed tile at plane k into the ring slot.  Wall
+// layers (jf = -1, H) get the mirror ghost of the adjacent fluid node.  A
+// fluid entry hands its pulled deviations to `keep`.
+template <class T, int TY, class Keep = NoKeep>
+__device__ __forceinline__ void fill_entry(T (*ring)[Tile<TY>::HN], const T* __restrict__ pop,
+                                           const T* __restrict__ hist, const T* __restrict__ geo,
+                                           const T* __restrict__ uw, int mv0, int mv1, const Grid& g, int i0,
+                                           int j0, int k, int e, const Keep& keep = Keep()) {
+  const int hx = e % HX, hy = e / HX;
+  const int i = i0 - 1 + hx, jf = j0 - 1 + hy;
+  if (i > g.nx || jf > g.H) return;  // beyond a ragged tile edge: never read
+  const int iw = wrapf(i, g.nx);
+  T m[4];
+  if (jf >= 0 && jf < g.H) {
+    node_moments(pop, hist, geo, g, iw, jf, k, m, keep);
+  } else {
+    const int w = jf < 0 ? 0 : 1;
+    T mm[4];
+    node_moments(pop, hist, geo, g, iw, w == 0 ? 0 : g.H - 1, k, mm);
+    m[0] = mm[0];
+    m[1] = -mm[1];
+    m[2] = -mm[2];
+    m[3] = -mm[3];
+    if (w == 0 ? mv0 : mv1) {
+      const T r2 = T(2) * (T(1) + mm[0]);
+      const long long c = (((long long)w * g.nz + k) * g.nx + iw) * 3;
+      m[1] += r2 * uw[c];
+      m[2] += r2 * uw[c + 1];
+      m[3] += r2 * uw[c + 2];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) ring[q][e] = m[q];
+}
+
+// Fill one ring slot with the moments of plane k over the haloed tile.
 template <class T, int TY>
 __device__ __forceinline__ void fill_plane(T (*ring)[Tile<TY>::HN], const T* __restrict__ pop, const T* __restrict__ hist,
                                            const T* __restrict__ geo, const T* __restrict__ uw, int mv0, int mv1,
                                            const Grid& g, int i0, int j0, int k) {
   k = wrapf(k, g.nz);
-  for (int e = threadIdx.x; e < Tile<TY>::HN; e += Tile<TY>::NT) {
-    const int hx = e % HX, hy = e / HX;
-    const int i = i0 - 1 + hx, jf = j0 - 1 + hy;
-    if (i > g.nx || jf > g.H) continue;  // beyond a ragged tile edge: never read
-    const int iw = wrapf(i, g.nx);
-    T m[4];
-    if (jf >= 0 && jf < g.H) {
-      node_moments(pop, hist, geo, g, iw, jf, k, m);
-    } else {
-      const int w = jf < 0 ? 0 : 1;
-      T mm[4];
-      node_moments(pop, hist, geo, g, iw, w == 0 ? 0 : g.H - 1, k, mm);
-      m[0] = mm[0];
-      m[1] = -mm[1];
-      m[2] = -mm[2];
-      m[3] = -mm[3];
-      if (w == 0 ? mv0 : mv1) {
-        const T r2 = T(2) * (T(1) + mm[0]);
-        const long long c = (((long long)w * g.nz + k) * g.nx + iw) * 3;
-        m[1] += r2 * uw[c];
-        m[2] += r2 * uw[c + 1];
-        m[3] += r2 * uw[c + 2];
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) ring[q][e] = m[q];
+  for (int e = threadIdx.x; e < Tile<TY>::HN; e += Tile<TY>::NT)
+    fill_entry<T, TY>(ring, pop, hist, geo, uw, mv0, mv1, g, i0, j0, k, e);
+}
+
+// Staged fill: each thread fills the entry of its own node (handing that
+// node's pulled deviations to `keep`, for the collision one iteration later);
+// the 2*(TX+2) + 2*TY halo entries are shared out over the block.
+template <class T, int TY, class Keep>
+__device__ __forceinline__ void fill_plane_staged(T (*ring)[Tile<TY>::HN], const T* __restrict__ pop,
+                                                  const T* __restrict__ hist, const T* __restrict__ geo,
+                                                  const T* __restrict__ uw, int mv0, int mv1, const Grid& g, int i0,
+                                                  int j0, int k, int tx, int ty, const Keep& keep) {
+  k = wrapf(k, g.nz);
+  fill_entry<T, TY>(ring, pop, hist, geo, uw, mv0, mv1, g, i0, j0, k, (ty + 1) * HX + (tx + 1), keep);
+  constexpr int NH = 2 * HX + 2 * TY;
+  for (int h = threadIdx.x; h < NH; h += Tile<TY>::NT) {
+    int e;
+    if (h < HX)
+      e = h;
+    else if (h < 2 * HX)
+      e = (TY + 1) * HX + (h - HX);
+    else if (h < 2 * HX + TY)
+      e = (1 + h - 2 * HX) * HX;
+    else
+      e = (1 + h - 2 * HX - TY) * HX + (HX - 1);
+    fill_entry<T, TY>(ring, pop, hist, geo, uw, mv0, mv1, g, i0, j0, k, e);
   }
 }
 
-template <class T, int TY>
+// Where the pulled deviations of a plane wait between its moment pass and its
+// collision one iteration later.
+enum Stage {
+  STAGE_NONE = 0,  // nowhere: the collision pulls them again (cache hits)
+  STAGE_REG = 1,   // registers (two planes live across the collision)
+};
+
+template <class T, int TY, int STAGE>
 __global__ __launch_bounds__(Tile<TY>::NT) void k_step_fused(Grid g, int ntx, int nty, int nzc, int zc,
                                                    const T* __restrict__ pin, T* __restrict__ pout,
                                                    const T* __restrict__ hist, T* __restrict__ hout,
@@ -164,11 +216,26 @@ __global__ __launch_bounds__(Tile<TY>::NT) void k_step_fused(Grid g, int ntx, in
   const int i = i0 + tx, jf = j0 + ty;
   const bool active = i < g.nx && jf < g.H;
 
+  T cur[Q], nxt[Q];
+  bool own = active;  // this thread's node is collided later in the chunk
+  auto to_cur = [&](auto L, T v) {
+    if (own) cur[decltype(L)::value] = v;
+  };
+  auto to_next = [&](auto L, T v) {
+    if (own) nxt[decltype(L)::value] = v;
+  };
   fill_plane<T, TY>(ring[(z0 + 2) % 3], pin, hist, geo, uw, mv0, mv1, g, i0, j0, z0 - 1);
-  fill_plane<T, TY>(ring[z0 % 3], pin, hist, geo, uw, mv0, mv1, g, i0, j0, z0);
+  if constexpr (STAGE == STAGE_NONE)
+    fill_plane<T, TY>(ring[z0 % 3], pin, hist, geo, uw, mv0, mv1, g, i0, j0, z0);
+  else
+    fill_plane_staged<T, TY>(ring[z0 % 3], pin, hist, geo, uw, mv0, mv1, g, i0, j0, z0, tx, ty, to_cur);
   const T itau = T(1) / tau;
   for (int k = z0; k < z1; ++k) {
-    fill_plane<T, TY>(ring[(k + 1) % 3], pin, hist, geo, uw, mv0, mv1, g, i0, j0, k + 1);
+    own = active && k + 1 < z1;
+    if constexpr (STAGE == STAGE_NONE)
+      fill_plane<T, TY>(ring[(k + 1) % 3], pin, hist, geo, uw, mv0, mv1, g, i0, j0, k + 1);
+    else
+      fill_plane_staged<T, TY>(ring[(k + 1) % 3], pin, hist, geo, uw, mv0, mv1, g, i0, j0, k + 1, tx, ty, to_next);
     __syncthreads();
     if (active) {
       const NodeIdx p = node_idx(g, i, jf, k);
@@ -203,7 +270,7 @@ __global__ __launch_bounds__(Tile<TY>::NT) void k_step_fused(Grid g, int ntx, in
       T sgc[6] = {0, 0, 0, 0, 0, 0};
       for_q([&](auto L) {
         constexpr int l = decltype(L)::value;
-        const T v = pullf<T, l>(pin, g, p);
+        const T v = STAGE == STAGE_NONE ? pullf<T, l>(pin, g, p) : cur[l];
         gv[l] = v;
         constexpr int x = cx(l), y = cy(l), z = cz(l);
         if (x) sgc[0] += v;
@@ -294,6 +361,12 @@ __global__ __launch_bounds__(Tile<TY>::NT) void k_step_fused(Grid g, int ntx, in
       if (!(rho > T(0)) || !(uu < T(0.1) * rho * rho) || !isfinite(chk)) atomicOr(flag, 1);
     }
     __syncthreads();
+    if constexpr (STAGE == STAGE_REG)
+      if (own)
+        for_q([&](auto L) {
+          constexpr int l = decltype(L)::value;
+          cur[l] = nxt[l];
+        });
   }
 }
 
@@ -309,15 +382,26 @@ template <int TY> inline int fused_zc(const Grid& g) {
   return zc;
 }
 
+// Register staging for FP32 only: FP64 has no register room for a second
+// plane of pulled populations.
+template <class T> constexpr int reg_stage() { return sizeof(T) == 4 ? STAGE_REG : STAGE_NONE; }
+
+template <class T, int TY, int ST>
+void fused_launch(Fields& F, hipStream_t s, T tau, int ntx, int nty, int nzc, int zc) {
+  const int per = (ntx * nty * nzc + 7) / 8;
+  hipLaunchKernelGGL((k_step_fused<T, TY, ST>), dim3(per * 8), dim3(Tile<TY>::NT), 0, s, F.g, ntx, nty, nzc, zc,
+                     (const T*)F.pop[F.cur], (T*)F.pop[F.cur ^ 1], (const T*)F.hist[F.cur], (T*)F.hist[F.cur ^ 1],
+                     (const T*)F.geo, (const T*)F.uw, F.moving[0], F.moving[1], tau, F.flag);
+}
+
 template <class T, int TY> hipError_t launch_fused_ty(Fields& F, hipStream_t s, T tau, int zc) {
   const Grid g = F.g;
   if (zc <= 0) zc = fused_zc<TY>(g);
   const int ntx = (g.nx + TX - 1) / TX, nty = (g.H + TY - 1) / TY, nzc = (g.nz + zc - 1) / zc;
-  const int nb = ntx * nty * nzc;
-  const int per = (nb + 7) / 8;
-  hipLaunchKernelGGL((k_step_fused<T, TY>), dim3(per * 8), dim3(Tile<TY>::NT), 0, s, g, ntx, nty, nzc, zc,
-                     (const T*)F.pop[F.cur], (T*)F.pop[F.cur ^ 1], (const T*)F.hist[F.cur],
-                     (T*)F.hist[F.cur ^ 1], (const T*)F.geo, (const T*)F.uw, F.moving[0], F.moving[1], tau, F.flag);
+  if (F.stage == STAGE_REG)
+    fused_launch<T, TY, reg_stage<T>()>(F, s, tau, ntx, nty, nzc, zc);
+  else
+    fused_launch<T, TY, STAGE_NONE>(F, s, tau, ntx, nty, nzc, zc);
   F.cur ^= 1;
   return hipGetLastError();
 }

@@ -61,7 +61,7 @@ _lib.lbm_get_history.argtypes = [_P, _P]
 _lib.lbm_get_geometry.argtypes = [_P, _P, _P]
 _lib.lbm_step.argtypes = [_P, _I]
 _lib.lbm_step_profiled.argtypes = [_P, _I, ctypes.POINTER(ctypes.c_double), _I]
-_lib.lbm_set_tuning.argtypes = [_P, _I, _I]
+_lib.lbm_set_tuning.argtypes = [_P, _I, _I, _I]
 _lib.lbm_moments.argtypes = [_P, _P, _P, _I]
 _lib.lbm_wall_force.argtypes = [_P, _I, _I, _P, _P]
 _lib.lbm_forward_record.argtypes = [_P, _I, _I, _I, _I, _P]
@@ -174,8 +174,8 @@ def lbm_step_profiled(ctx, n, nslots=4):
     return list(arr)
 
 
-def lbm_set_tuning(ctx, zchunk=0, variant=0):
-    return _check(ctx, _lib.lbm_set_tuning(ctx, int(zchunk), int(variant)))
+def lbm_set_tuning(ctx, zchunk=0, variant=0, stage=-1):
+    return _check(ctx, _lib.lbm_set_tuning(ctx, int(zchunk), int(variant), int(stage)))
 
 
 def lbm_moments(ctx, rho, u, cartesian=False):

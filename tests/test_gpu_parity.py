@@ -85,10 +85,11 @@ def _random_state(O, nz, H, nx, seed):
     return f
 
 
-@pytest.mark.parametrize("shape,variant,zc", [((70, 12, 9), 0, 0), ((64, 8, 4), 0, 0), ((7, 5, 3), 0, 0),
-                                              ((70, 12, 9), 1, 0), ((70, 12, 9), 2, 3), ((70, 12, 9), 3, 4),
-                                              ((33, 9, 11), 0, 5)])
-def test_step_parity_fp64(shape, variant, zc):
+@pytest.mark.parametrize("shape,variant,zc,stage", [((70, 12, 9), 0, 0, -1), ((64, 8, 4), 0, 0, -1),
+                                                    ((7, 5, 3), 0, 0, -1), ((70, 12, 9), 1, 0, -1),
+                                                    ((70, 12, 9), 2, 3, -1), ((70, 12, 9), 3, 4, -1),
+                                                    ((33, 9, 11), 0, 5, -1), ((70, 12, 9), 0, 4, 1)])
+def test_step_parity_fp64(shape, variant, zc, stage):
     """Curved chart, body force, moving walls, non-equilibrium start: the GPU
     state matches the oracle population by population after 1 and 12 steps;
     history, moments and wall forces too.  Shapes span several 64x4 tiles with
@@ -101,7 +102,7 @@ def test_step_parity_fp64(shape, variant, zc):
     vb[..., 1] = 0.0  # normal velocity stays zero at a wall at rest in y
     vb[..., 2] = 0.004
     S, O = make_pair(nx, ny, nz, 0.7, chart=synth.bump3_chart(nx, ny, nz, 0.06), F=(2e-5, 0, 1e-5), vwall=(vb, vt))
-    _lbm().lbm_set_tuning(S.ctx, zc, variant)
+    _lbm().lbm_set_tuning(S.ctx, zc, variant, stage)
     f0 = _random_state(O, nz, H, nx, 21)
     O.set_populations(f0)
     S.set_populations(f0)
@@ -188,14 +189,25 @@ def test_config1_channel_parity_fp64():
     assert ef < 1e-10, ef
 
 
-@pytest.mark.parametrize("shape", [(70, 12, 9), (32, 16, 16)])
-def test_step_parity_fp32(shape):
+@pytest.mark.parametrize("shape,variant,zc,stage", [((70, 12, 9), 0, 0, -1), ((32, 16, 16), 0, 0, -1),
+                                                    ((33, 9, 11), 0, 5, 1), ((70, 12, 9), 2, 4, 1),
+                                                    ((70, 12, 9), 3, 5, 1), ((70, 12, 9), 1, 0, -1),
+                                                    ((70, 12, 9), 0, 0, 0), ((70, 12, 9), 2, 3, 0),
+                                                    ((33, 9, 11), 3, 4, 0), ((7, 5, 3), 3, 0, 1),
+                                                    ((7, 5, 3), 0, 0, 0)])
+def test_step_parity_fp32(shape, variant, zc, stage):
     """FP32 deviation storage and arithmetic against the FP64 oracle: errors in
     rho, u and wall force stay at the FP32 rounding level of the deviation
-    variables."""
+    variables.  Covers every tile shape with both stagings of the pulled
+    populations (re-read, registers), ragged tiles and z chunks, and a moving
+    top wall."""
     nx, ny, nz = shape
     H = ny - 2
-    S, O = make_pair(nx, ny, nz, 0.7, precision="fp32", chart=synth.bump3_chart(nx, ny, nz, 0.06), F=(1e-5, 0, 0))
+    vt = np.zeros((nz, nx, 3))
+    vt[..., 0] = 0.01
+    S, O = make_pair(nx, ny, nz, 0.7, precision="fp32", chart=synth.bump3_chart(nx, ny, nz, 0.06), F=(1e-5, 0, 0),
+                     vwall=(None, vt))
+    _lbm().lbm_set_tuning(S.ctx, zc, variant, stage)
     f0 = _random_state(O, nz, H, nx, 41)
     O.set_populations(f0)
     S.set_populations(f0)

@@ -23,6 +23,11 @@ sys.path.insert(0, ROOT)
 # written (10 each), geometry read (28).
 BYTES_PER_LUP = {"fp32": 4 * (19 + 19 + 10 + 10 + 28), "fp64": 8 * (19 + 19 + 10 + 10 + 28)}
 HBM_PEAK_GBPS = 8000.0
+# The committed rocprofv3 summary of the step kernel's HBM counters, and the
+# sources it was taken from: traffic is reported only while they are unchanged.
+COUNTER_PROFILE = os.path.join(ROOT, "profiles", "step_fused_c2_256x128x128.md")
+STEP_SOURCES = ["paper_1803_07822_amd/csrc/lbm_step_fused.hip", "paper_1803_07822_amd/csrc/lbm_device.h",
+                "paper_1803_07822_amd/csrc/lbm_internal.h", "paper_1803_07822_amd/build.py"]
 METRIC = "MLUPS + HBM GB/s (% peak) FP32 vs FP64 step; adjoint/forward time ratio"
 
 
@@ -36,6 +41,8 @@ def parse():
     p.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward timing")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--fp64-steps", type=int, default=None)
+    p.add_argument("--counters", action="store_true",
+                   help="no timing: a 256 MiB calibration copy, then --steps FP32 steps, for rocprofv3 --pmc runs")
     return p.parse_args()
 
 
@@ -155,6 +162,80 @@ def cpu_baseline(w, budget_s):
             "sample": f"{n} FP64 steps of the full {w.nx}x{w.ny}x{w.nz} workload after 1 warm-up step ({t:.1f} s)"}
 
 
+def step_source_hash():
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in STEP_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(workload):
+    """HBM bytes per launch of the FP32 step kernel from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE, calibrated), or None if the summary is
+    for another workload or the kernel sources changed since it was taken."""
+    try:
+        with open(COUNTER_PROFILE) as fh:
+            lines = [ln for ln in fh if ln.startswith("counters:")]
+    except OSError:
+        return None
+    if not lines:
+        return None
+    kv = dict(item.split("=", 1) for item in lines[-1][len("counters:"):].split())
+    if kv.get("workload") != workload or kv.get("source_sha256") != step_source_hash():
+        return None
+    return int(kv["fetch_bytes"]) + int(kv["write_bytes"])
+
+
+def copy_rate():
+    """Device-to-device copy of 1 GiB (the runtime's copy kernel), as a
+    practical bandwidth reference beside the 8 TB/s peak: GB/s counting the
+    bytes read plus the bytes written."""
+    import torch
+
+    a = torch.ones(256 * 1024 * 1024, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) * 1e-3 / 10
+    r = 2 * a.numel() * 4 / t / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return round(r, 1)
+
+
+def counter_run(w, steps):
+    """What the HBM counters are read over: a device-to-device copy of
+    256 MiB into a fresh buffer (calibrates FETCH_SIZE and WRITE_SIZE against
+    known bytes), then `steps` FP32 steps of the workload with the default
+    launch shape."""
+    import torch
+
+    a = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+    a.fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+    torch.cuda.empty_cache()
+    S, uc = setup(w, "fp32")
+    S.step(steps)
+    S.sync()
+    from paper_1803_07822_amd import lbm
+
+    z, v, st = lbm.lbm_get_tuning(S.ctx)
+    print(json.dumps({"counter_run": w.name, "steps": steps, "zchunk": z, "variant": v, "stage": st}), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -167,6 +248,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     w = synth.workload(a.workload)
+    if a.counters:
+        counter_run(w, a.steps)
+        return
     N = w.fluid_nodes
     res = {}
     for prec, steps in (("fp32", a.steps), ("fp64", a.fp64_steps or max(10, a.steps // 2))):
@@ -197,12 +281,13 @@ def main():
                    "form": "fp32 deviation storage, fp64 metric precompute"},
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_step_fused<float> (whole step, one launch)",
+            "kernel": "k_step_fused<float, 4, 1> (whole step, one launch)",
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBPS, 4),
-            "traffic": None,
+            "traffic": recorded_traffic(w.name),
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
             "bytes_per_lup": BYTES_PER_LUP["fp32"],
             "kernel_ms": [round(x, 5) for x in f32["kernel_ms"]],
         },
@@ -216,6 +301,7 @@ def main():
             "steps": res["fp64"]["steps"],
         },
         "fp32_effective_GBps": round(f32["eff_gbps"], 1),
+        "device_copy_GBps": copy_rate(),
         "adjoint_forward_ratio": None,
     }
     if not a.no_adjoint:

@@ -187,6 +187,12 @@ int lbm_step_profiled(lbm_ctx* ctx, int n, double* h_ms, int nslots);
  * zchunk < 0, a variant outside 0..3 or a stage outside -1..1. */
 int lbm_set_tuning(lbm_ctx* ctx, int zchunk, int variant, int stage);
 
+/* The launch shape the next step will use: *zchunk = planes per block of the
+ * fused step (the automatic choice resolved for this device; 0 for the
+ * two-kernel variant), *variant as in lbm_set_tuning, *stage = the staging
+ * that actually runs (0 in FP64).  EINVAL for a null pointer. */
+int lbm_get_tuning(lbm_ctx* ctx, int* zchunk, int* variant, int* stage);
+
 /* Wait for the stream and check the instability guard. */
 int lbm_sync(lbm_ctx* ctx);
 

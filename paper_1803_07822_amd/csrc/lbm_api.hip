@@ -376,6 +376,19 @@ int lbm_set_tuning(lbm_ctx* c, int zchunk, int variant, int stage) {
   return LBM_OK;
 }
 
+int lbm_get_tuning(lbm_ctx* c, int* zchunk, int* variant, int* stage) {
+  LBM_GUARD(c);
+  if (!zchunk || !variant || !stage) return fail(c, LBM_EINVAL, "null output pointer");
+  int zc = 0;
+  if (c->F.variant == 0)
+    LBM_HIP(c, c->precision == LBM_FP64 ? lbm::fused_step_chunk<double>(c->F, &zc)
+                                        : lbm::fused_step_chunk<float>(c->F, &zc));
+  *zchunk = zc;
+  *variant = c->F.variant == 1 ? 1 : (c->F.ty == 2 ? 2 : (c->F.ty == 1 ? 3 : 0));
+  *stage = c->precision == LBM_FP64 ? 0 : c->F.stage;
+  return LBM_OK;
+}
+
 int lbm_sync(lbm_ctx* c) {
   LBM_GUARD(c);
   LBM_HIP(c, hipStreamSynchronize(c->stream));

@@ -38,6 +38,8 @@ struct Fields {
   int variant = 0;   // 0: fused step; 1: two-pass step (moments pass + collision pass)
   int ty = 4;        // rows of 64 nodes per block of the fused step (1, 2, 4)
   int stage = 1;     // FP32 fused step keeps pulled populations in registers
+  int slots_key = -1;     // fused kernel whose resident-block count is cached
+  long long slots = 0;    // resident blocks of that kernel on the device
 };
 
 constexpr int BX = 64, BY = 4;
@@ -76,6 +78,8 @@ template <class T> hipError_t launch_get_geo(Fields& F, hipStream_t s, double* o
 constexpr int STEP_KERNELS = 2;  // at most this many kernels per step (timed separately by lbm_step_profiled)
 template <class T> hipError_t launch_step(Fields& F, hipStream_t s, T tau, hipEvent_t* ev = nullptr);
 template <class T> hipError_t launch_step_fused(Fields& F, hipStream_t s, T tau, int zc, int ty);
+// Planes per block the fused step runs with (F.zc, or the automatic choice).
+template <class T> hipError_t fused_step_chunk(Fields& F, int* zc);
 template <class T> hipError_t launch_moments_out(Fields& F, hipStream_t s, double* rho, double* u, int cart);
 template <class T> hipError_t launch_wall_force(Fields& F, hipStream_t s, int wall, T tau, double* total,
                                                 double* per_node);

@@ -60,8 +60,9 @@ __device__ __forceinline__ NodeIdx node_idx(const Grid& g, int i, int jf, int k)
 template <class T> __device__ __forceinline__ const T& at(const T* __restrict__ base, unsigned e) {
   return *(const T*)((const char*)base + (e * (unsigned)sizeof(T)));
 }
-template <class T> __device__ __forceinline__ T& atw(T* __restrict__ base, unsigned e) {
-  return *(T*)((char*)base + (e * (unsigned)sizeof(T)));
+// Streaming store: the step's outputs are not read again within the step.
+template <class T> __device__ __forceinline__ void stw(T* __restrict__ base, unsigned e, T v) {
+  __builtin_nontemporal_store(v, (T*)((char*)base + (e * (unsigned)sizeof(T))));
 }
 
 // Pulled deviation g~_l: the population that left x - c_l in direction l,
@@ -80,6 +81,10 @@ __device__ __forceinline__ T pullf(const T* __restrict__ pop, const Grid& g, con
 
 template <class T> __device__ __forceinline__ T fld(const T* __restrict__ a, int q, const Grid& g, unsigned n) {
   return at(a + (size_t)q * g.N, n);
+}
+// Streaming load of a field read once per step.
+template <class T> __device__ __forceinline__ T fldnt(const T* __restrict__ a, int q, const Grid& g, unsigned n) {
+  return __builtin_nontemporal_load((const T*)((const char*)(a + (size_t)q * g.N) + n * (unsigned)sizeof(T)));
 }
 
 // Discards the pulled deviations of a node.
@@ -283,17 +288,17 @@ __global__ __launch_bounds__(Tile<TY>::NT) void k_step_fused(Grid g, int ntx, in
       NodeGeo<T> G;
       G.sgd = fld(geo, G_SG, g, n);
 #pragma unroll
-      for (int q = 0; q < 6; ++q) G.gid[q] = fld(geo, G_GI + q, g, n);
+      for (int q = 0; q < 6; ++q) G.gid[q] = fldnt(geo, G_GI + q, g, n);
 #pragma unroll
-      for (int q = 0; q < 18; ++q) G.gam[q] = fld(geo, G_GAM + q, g, n);
+      for (int q = 0; q < 18; ++q) G.gam[q] = fldnt(geo, G_GAM + q, g, n);
 #pragma unroll
-      for (int q = 0; q < 3; ++q) G.F[q] = fld(geo, G_F + q, g, n);
+      for (int q = 0; q < 3; ++q) G.F[q] = fldnt(geo, G_F + q, g, n);
       Coef<T> cp;
       cp.A = fld(hist, H_A, g, n);
 #pragma unroll
       for (int a = 0; a < 3; ++a) cp.B[a] = fld(hist, H_B + a, g, n);
 #pragma unroll
-      for (int q = 0; q < 6; ++q) cp.C[q] = fld(hist, H_C + q, g, n);
+      for (int q = 0; q < 6; ++q) cp.C[q] = fldnt(hist, H_C + q, g, n);
       const T sg = T(1) + G.sgd, isg = T(1) / sg;
       const T rho = T(1) + dr, irho = T(1) / rho;
       // equilibrium coefficients (deviation form): a0 = rho - sqrt g,
@@ -350,13 +355,13 @@ __global__ __launch_bounds__(Tile<TY>::NT) void k_step_fused(Grid g, int ntx, in
           }
         }
         chk += v;
-        atw(pout + (size_t)l * g.N, n) = v;
+        stw(pout + (size_t)l * g.N, n, v);
       });
-      atw(hout + (size_t)H_A * g.N, n) = c.A;
+      stw(hout + (size_t)H_A * g.N, n, c.A);
 #pragma unroll
-      for (int a = 0; a < 3; ++a) atw(hout + (size_t)(H_B + a) * g.N, n) = c.B[a];
+      for (int a = 0; a < 3; ++a) stw(hout + (size_t)(H_B + a) * g.N, n, c.B[a]);
 #pragma unroll
-      for (int q = 0; q < 6; ++q) atw(hout + (size_t)(H_C + q) * g.N, n) = c.C[q];
+      for (int q = 0; q < 6; ++q) stw(hout + (size_t)(H_C + q) * g.N, n, c.C[q]);
       const T uu = j[0] * j[0] + j[1] * j[1] + j[2] * j[2];
       if (!(rho > T(0)) || !(uu < T(0.1) * rho * rho) || !isfinite(chk)) atomicOr(flag, 1);
     }
@@ -372,38 +377,73 @@ __global__ __launch_bounds__(Tile<TY>::NT) void k_step_fused(Grid g, int ntx, in
 
 }  // namespace
 
-// Planes per block: enough blocks to fill 256 CUs several times over.
-template <int TY> inline int fused_zc(const Grid& g) {
-  const int ntx = (g.nx + TX - 1) / TX, nty = (g.H + TY - 1) / TY;
-  const long long tiles = (long long)ntx * nty;
-  int zc = (int)((tiles * g.nz + 2047) / 2048);
-  if (zc < 4) zc = 4;
-  if (zc > g.nz) zc = g.nz;
-  return zc;
-}
-
 // Register staging for FP32 only: FP64 has no register room for a second
 // plane of pulled populations.
 template <class T> constexpr int reg_stage() { return sizeof(T) == 4 ? STAGE_REG : STAGE_NONE; }
 
-template <class T, int TY, int ST>
-void fused_launch(Fields& F, hipStream_t s, T tau, int ntx, int nty, int nzc, int zc) {
+// Planes per block when the caller leaves it open.  Blocks run in rounds of
+// `slots` (resident blocks on the whole device); a chunk of zc planes costs
+// about zc + 1 plane-times (its two halo planes get moments only).  Take the
+// zc with the least rounds * (zc + 1); ties go to the smaller zc.
+inline int choose_zc(long long tiles, int nz, long long slots) {
+  int best = nz;
+  long long best_cost = -1;
+  for (int zc = 1; zc <= nz; ++zc) {
+    const long long nb = tiles * ((nz + zc - 1) / zc);
+    const long long cost = ((nb + slots - 1) / slots) * (zc + 1);
+    if (best_cost < 0 || cost < best_cost) {
+      best_cost = cost;
+      best = zc;
+    }
+  }
+  return best;
+}
+
+// Planes per block for kernel k_step_fused<T, TY, ST>: zc if positive, else
+// the choice above for this device.
+template <class T, int TY, int ST> hipError_t fused_chunk(Fields& F, int zc, int* out) {
+  const Grid g = F.g;
+  if (zc <= 0) {
+    const int key = (int)sizeof(T) * 100 + TY * 10 + ST;
+    if (F.slots_key != key) {
+      int dev = 0, cus = 0, per_cu = 0;
+      hipError_t e = hipGetDevice(&dev);
+      if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+      if (e == hipSuccess)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_fused<T, TY, ST>, Tile<TY>::NT, 0);
+      if (e != hipSuccess) return e;
+      F.slots = (long long)cus * (per_cu > 0 ? per_cu : 1);
+      F.slots_key = key;
+    }
+    const long long tiles = (long long)((g.nx + TX - 1) / TX) * ((g.H + TY - 1) / TY);
+    zc = choose_zc(tiles, g.nz, F.slots);
+  }
+  *out = zc < g.nz ? zc : g.nz;
+  return hipSuccess;
+}
+
+template <class T, int TY, int ST> hipError_t fused_launch(Fields& F, hipStream_t s, T tau, int zc) {
+  const Grid g = F.g;
+  const hipError_t e = fused_chunk<T, TY, ST>(F, zc, &zc);
+  if (e != hipSuccess) return e;
+  const int ntx = (g.nx + TX - 1) / TX, nty = (g.H + TY - 1) / TY;
+  const int nzc = (g.nz + zc - 1) / zc;
   const int per = (ntx * nty * nzc + 7) / 8;
-  hipLaunchKernelGGL((k_step_fused<T, TY, ST>), dim3(per * 8), dim3(Tile<TY>::NT), 0, s, F.g, ntx, nty, nzc, zc,
+  hipLaunchKernelGGL((k_step_fused<T, TY, ST>), dim3(per * 8), dim3(Tile<TY>::NT), 0, s, g, ntx, nty, nzc, zc,
                      (const T*)F.pop[F.cur], (T*)F.pop[F.cur ^ 1], (const T*)F.hist[F.cur], (T*)F.hist[F.cur ^ 1],
                      (const T*)F.geo, (const T*)F.uw, F.moving[0], F.moving[1], tau, F.flag);
+  F.cur ^= 1;
+  return hipGetLastError();
 }
 
 template <class T, int TY> hipError_t launch_fused_ty(Fields& F, hipStream_t s, T tau, int zc) {
-  const Grid g = F.g;
-  if (zc <= 0) zc = fused_zc<TY>(g);
-  const int ntx = (g.nx + TX - 1) / TX, nty = (g.H + TY - 1) / TY, nzc = (g.nz + zc - 1) / zc;
-  if (F.stage == STAGE_REG)
-    fused_launch<T, TY, reg_stage<T>()>(F, s, tau, ntx, nty, nzc, zc);
-  else
-    fused_launch<T, TY, STAGE_NONE>(F, s, tau, ntx, nty, nzc, zc);
-  F.cur ^= 1;
-  return hipGetLastError();
+  if (F.stage == STAGE_REG) return fused_launch<T, TY, reg_stage<T>()>(F, s, tau, zc);
+  return fused_launch<T, TY, STAGE_NONE>(F, s, tau, zc);
+}
+
+template <class T, int TY> hipError_t chunk_ty(Fields& F, int* zc) {
+  if (F.stage == STAGE_REG) return fused_chunk<T, TY, reg_stage<T>()>(F, F.zc, zc);
+  return fused_chunk<T, TY, STAGE_NONE>(F, F.zc, zc);
 }
 
 // ty: tile height in y (1, 2 or 4 rows of 64 nodes per block).
@@ -413,6 +453,14 @@ template <class T> hipError_t launch_step_fused(Fields& F, hipStream_t s, T tau,
   return launch_fused_ty<T, 4>(F, s, tau, zc);
 }
 
+template <class T> hipError_t fused_step_chunk(Fields& F, int* zc) {
+  if (F.ty == 1) return chunk_ty<T, 1>(F, zc);
+  if (F.ty == 2) return chunk_ty<T, 2>(F, zc);
+  return chunk_ty<T, 4>(F, zc);
+}
+
+template hipError_t fused_step_chunk<double>(Fields&, int*);
+template hipError_t fused_step_chunk<float>(Fields&, int*);
 template hipError_t launch_step_fused<double>(Fields&, hipStream_t, double, int, int);
 template hipError_t launch_step_fused<float>(Fields&, hipStream_t, float, int, int);
 

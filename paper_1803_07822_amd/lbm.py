@@ -34,7 +34,7 @@ SYMBOLS = [
     "lbm_workspace_bytes", "lbm_create", "lbm_reserve_adjoint", "lbm_destroy", "lbm_set_body_force",
     "lbm_set_metric", "lbm_set_wall_displacement", "lbm_set_wall_velocity", "lbm_init_equilibrium",
     "lbm_set_populations", "lbm_get_populations", "lbm_get_history", "lbm_get_geometry", "lbm_step",
-    "lbm_step_profiled", "lbm_set_tuning", "lbm_moments", "lbm_wall_force", "lbm_forward_record", "lbm_backward", "lbm_sync", "lbm_last_error",
+    "lbm_step_profiled", "lbm_set_tuning", "lbm_get_tuning", "lbm_moments", "lbm_wall_force", "lbm_forward_record", "lbm_backward", "lbm_sync", "lbm_last_error",
 ]
 
 
@@ -62,6 +62,8 @@ _lib.lbm_get_geometry.argtypes = [_P, _P, _P]
 _lib.lbm_step.argtypes = [_P, _I]
 _lib.lbm_step_profiled.argtypes = [_P, _I, ctypes.POINTER(ctypes.c_double), _I]
 _lib.lbm_set_tuning.argtypes = [_P, _I, _I, _I]
+_lib.lbm_get_tuning.argtypes = [_P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                ctypes.POINTER(ctypes.c_int)]
 _lib.lbm_moments.argtypes = [_P, _P, _P, _I]
 _lib.lbm_wall_force.argtypes = [_P, _I, _I, _P, _P]
 _lib.lbm_forward_record.argtypes = [_P, _I, _I, _I, _I, _P]
@@ -176,6 +178,13 @@ def lbm_step_profiled(ctx, n, nslots=4):
 
 def lbm_set_tuning(ctx, zchunk=0, variant=0, stage=-1):
     return _check(ctx, _lib.lbm_set_tuning(ctx, int(zchunk), int(variant), int(stage)))
+
+
+def lbm_get_tuning(ctx):
+    """(zchunk, variant, stage) the next step runs with."""
+    z, v, st = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int(0)
+    _check(ctx, _lib.lbm_get_tuning(ctx, ctypes.byref(z), ctypes.byref(v), ctypes.byref(st)))
+    return z.value, v.value, st.value
 
 
 def lbm_moments(ctx, rho, u, cartesian=False):

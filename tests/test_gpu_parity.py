@@ -265,3 +265,25 @@ def test_call_order_and_argument_errors():
     assert e.value.code == -1
     S.step(3)
     S.sync()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_tuning_round_trip(precision):
+    """lbm_set_tuning / lbm_get_tuning: explicit shapes come back as set, the
+    automatic z chunk resolves to a plane count in 1..nz, FP64 never runs the
+    register staging, and bad arguments are refused."""
+    lbm = _lbm()
+    nx, ny, nz = 130, 20, 40
+    S = lbm.Solver(nx, ny, nz, 0.8, precision)
+    z, v, st = lbm.lbm_get_tuning(S.ctx)
+    assert 1 <= z <= nz and v == 0 and st == (1 if precision == "fp32" else 0)
+    lbm.lbm_set_tuning(S.ctx, 7, 2, 0)
+    assert lbm.lbm_get_tuning(S.ctx) == (7, 2, 0)
+    lbm.lbm_set_tuning(S.ctx, 500, 3, 1)
+    assert lbm.lbm_get_tuning(S.ctx) == (nz, 3, 1 if precision == "fp32" else 0)
+    lbm.lbm_set_tuning(S.ctx, 0, 1, -1)
+    assert lbm.lbm_get_tuning(S.ctx)[:2] == (0, 1)
+    for bad in ((-1, 0, -1), (0, 4, -1), (0, 0, 2), (0, 0, -2)):
+        with pytest.raises(lbm.LBMError) as e:
+            lbm.lbm_set_tuning(S.ctx, *bad)
+        assert e.value.code == -1

@@ -69,17 +69,15 @@ LEAD_IN = 5
 
 def time_steps(S, uc, steps, warmup):
     """Time exactly `steps` steps: windows of at most WINDOW steps, each after a
-    fresh equilibrium start and LEAD_IN untimed steps.  Returns the mean step
-    time from the stream events, the per-kernel means from the library's own
-    HIP events, and the host wall time of the timed windows."""
+    fresh equilibrium start and LEAD_IN untimed steps, bracketed by HIP events
+    on the library's stream.  A step is one launch of the fused step kernel,
+    so the mean step time is also that kernel's mean launch duration (launch
+    gaps included).  Returns it with the host wall time of the windows."""
     import torch
-
-    from paper_1803_07822_amd import lbm
 
     S.step(warmup)
     S.sync()
     done, tot_ms, wall = 0, 0.0, 0.0
-    kern = [0.0]
     while done < steps:
         n = min(WINDOW, steps - done)
         S.init_equilibrium(None, uc)
@@ -89,15 +87,14 @@ def time_steps(S, uc, steps, warmup):
         start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         t0 = time.perf_counter()
         start.record(S.stream)
-        km = lbm.lbm_step_profiled(S.ctx, n)
+        S.step(n)
         stop.record(S.stream)
         S.sync()
         torch.cuda.synchronize()
         wall += time.perf_counter() - t0
         tot_ms += start.elapsed_time(stop)
-        kern[0] += km[0] * n
         done += n
-    return tot_ms / steps, [k / steps for k in kern], wall
+    return tot_ms / steps, wall
 
 
 def adjoint_ratio(repeats=3):
@@ -244,7 +241,7 @@ def main():
         sys.exit(2)
     import torch
 
-    from paper_1803_07822_amd import synth
+    from paper_1803_07822_amd import lbm, synth
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     w = synth.workload(a.workload)
@@ -255,15 +252,14 @@ def main():
     res = {}
     for prec, steps in (("fp32", a.steps), ("fp64", a.fp64_steps or max(10, a.steps // 2))):
         S, uc = setup(w, prec)
-        ms, kms, wall = time_steps(S, uc, steps, a.warmup)
-        res[prec] = dict(ms=ms, kernel_ms=kms, steps=steps, wall=wall,
+        ms, wall = time_steps(S, uc, steps, a.warmup)
+        res[prec] = dict(ms=ms, steps=steps, wall=wall, tuning=lbm.lbm_get_tuning(S.ctx),
                          mlups=N / (ms * 1e-3) / 1e6,
                          eff_gbps=N * BYTES_PER_LUP[prec] / (ms * 1e-3) / 1e9)
         del S
         torch.cuda.empty_cache()
     f32 = res["fp32"]
-    step_kernel_ms = f32["kernel_ms"][0]
-    achieved = N * BYTES_PER_LUP["fp32"] / (step_kernel_ms * 1e-3) / 1e9
+    achieved = N * BYTES_PER_LUP["fp32"] / (f32["ms"] * 1e-3) / 1e9
     out = {
         "metric": METRIC,
         "value": round(f32["mlups"], 2),
@@ -289,7 +285,8 @@ def main():
             "traffic": recorded_traffic(w.name),
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
             "bytes_per_lup": BYTES_PER_LUP["fp32"],
-            "kernel_ms": [round(x, 5) for x in f32["kernel_ms"]],
+            "kernel_ms": round(f32["ms"], 5),
+            "launch": dict(zip(("zchunk", "variant", "stage"), f32["tuning"])),
         },
         "fp64": {
             "mlups": round(res["fp64"]["mlups"], 2),
@@ -297,7 +294,7 @@ def main():
             "effective_GBps": round(res["fp64"]["eff_gbps"], 1),
             "frac": round(res["fp64"]["eff_gbps"] / HBM_PEAK_GBPS, 4),
             "bytes_per_lup": BYTES_PER_LUP["fp64"],
-            "kernel_ms": [round(x, 5) for x in res["fp64"]["kernel_ms"]],
+            "launch": dict(zip(("zchunk", "variant", "stage"), res["fp64"]["tuning"])),
             "steps": res["fp64"]["steps"],
         },
         "fp32_effective_GBps": round(f32["eff_gbps"], 1),

@@ -166,6 +166,7 @@ int lbm_forward_record(lbm_ctx* ctx, int K, int ckpt_every, int wall, int method
  * dL/d(top-wall displacement) [nz][nx], dL/d(chart) [3][nz][ny][nx] and dL/d
  * f0 [19][fluid] (each may be NULL).  The initial populations f0 are an
  * independent input (the history F(x,-1) is recomputed from f0 and the chart).
+ * The context's state stays the one lbm_forward_record ended with.
  * Synchronising. */
 int lbm_backward(lbm_ctx* ctx, const double* d_dL_dF, double* d_grad_disp, double* d_grad_chart,
                  double* d_grad_f0);

@@ -44,55 +44,70 @@ __device__ __forceinline__ long long nidx(const Grid& g, int i, int jf, int k) {
 }
 
 // Full populations f(t) = w + pulled deviation + F(t-1)/2 of a stored state.
-__device__ inline void load_state(const Grid& g, const double* __restrict__ pop, const double* __restrict__ hist,
-                                  const AGeo& G, const Node& p, double f[Q], double Fp[10]) {
+__device__ __forceinline__ void load_state(const Grid& g, const double* __restrict__ pop,
+                                           const double* __restrict__ hist, const AGeo& G, const Node& p, double f[Q],
+                                           double Fp[10]) {
+#pragma unroll
   for (int q = 0; q < 10; ++q) Fp[q] = hist[q * g.N + p.n];
   double bp[6];
+#pragma unroll
   for (int q = 0; q < 6; ++q) bp[q] = Fp[4 + q];
   bp[0] -= Fp[0] / 3.0;
   bp[3] -= Fp[0] / 3.0;
   bp[5] -= Fp[0] / 3.0;
   const double isg = 1.0 / G.sg;
-  for (int l = 0; l < Q; ++l) {
-    const int x = cx(l), y = cy(l), z = cz(l);
+  for_q([&](auto L) {
+    constexpr int l = decltype(L)::value;
+    constexpr int x = cx(l), y = cy(l), z = cz(l);
     double v;
     if ((y > 0 && p.jf == 0) || (y < 0 && p.jf == g.H - 1))
       v = pop[opp(l) * g.N + p.n];
     else
       v = pop[l * g.N + nidx(g, wrapa(p.i - x, g.nx), p.jf - y, wrapa(p.k - z, g.nz))];
-    f[l] = wgt(l) + v + 0.5 * hermite_eval(l, isg, Fp[0], Fp + 1, bp);
-  }
+    f[l] = wgt(l) + v + 0.5 * hermite_val<l>(isg, Fp[0], Fp + 1, bp);
+  });
 }
 
-__device__ inline void load_geo_full(const Grid& g, const double* __restrict__ geo, long long n, AGeo& G) {
+__device__ __forceinline__ void load_geo_full(const Grid& g, const double* __restrict__ geo, long long n, AGeo& G) {
   G.sg = 1.0 + geo[G_SG * g.N + n];
+#pragma unroll
   for (int q = 0; q < 6; ++q) G.gi[q] = geo[(G_GI + q) * g.N + n] + ((q == 0 || q == 3 || q == 5) ? 1.0 : 0.0);
+#pragma unroll
   for (int q = 0; q < 18; ++q) G.gam[q] = geo[(G_GAM + q) * g.N + n];
+#pragma unroll
   for (int q = 0; q < 3; ++q) G.F[q] = geo[(G_F + q) * g.N + n];
 }
 
 // Lattice gradient of the stored moments (walls at rest: ghost j = -j_m).
-__device__ inline void gradient_at(const Grid& g, const double* __restrict__ mom, const Node& p, double dj[3][3]) {
+__device__ __forceinline__ void gradient_at(const Grid& g, const double* __restrict__ mom, const Node& p,
+                                            double dj[3][3]) {
+#pragma unroll
   for (int a = 0; a < 3; ++a)
+#pragma unroll
     for (int b = 0; b < 3; ++b) dj[a][b] = 0.0;
-  for (int l = 1; l < Q; ++l) {
-    const int x = cx(l), y = cy(l), z = cz(l);
+  for_q([&](auto L) {
+    constexpr int l = decltype(L)::value;
+    if (l == 0) return;
+    constexpr int x = cx(l), y = cy(l), z = cz(l);
     const int in = wrapa(p.i + x, g.nx), kn = wrapa(p.k + z, g.nz), jn = p.jf + y;
     double jb[3];
     if (jn >= 0 && jn < g.H) {
       const long long m = nidx(g, in, jn, kn);
+#pragma unroll
       for (int b = 0; b < 3; ++b) jb[b] = mom[(1 + b) * g.N + m];
     } else {
       const long long m = nidx(g, in, p.jf, kn);
+#pragma unroll
       for (int b = 0; b < 3; ++b) jb[b] = -mom[(1 + b) * g.N + m];
     }
-    const double fct = 3.0 * wgt(l);
+    constexpr double fct = 3.0 * wgt(l);
+#pragma unroll
     for (int b = 0; b < 3; ++b) {
-      dj[0][b] += x * fct * jb[b];
-      dj[1][b] += y * fct * jb[b];
-      dj[2][b] += z * fct * jb[b];
+      if (x) dj[0][b] += (x * fct) * jb[b];
+      if (y) dj[1][b] += (y * fct) * jb[b];
+      if (z) dj[2][b] += (z * fct) * jb[b];
     }
-  }
+  });
 }
 
 __device__ inline void add_geo_bar(const Grid& g, double* __restrict__ lg, long long n, const AGeoBar& gb) {
@@ -110,7 +125,7 @@ __device__ inline void zero_bar(AGeoBar& gb) {
 }
 
 // Moments rho, j of a stored state at every node.
-__global__ void k_adj_moments(Grid g, const double* __restrict__ pop, const double* __restrict__ hist,
+__global__ __launch_bounds__(BX * BY) void k_adj_moments(Grid g, const double* __restrict__ pop, const double* __restrict__ hist,
                               const double* __restrict__ geo, double* __restrict__ mom) {
   Node p;
   if (!fluid_node(g, p)) return;
@@ -119,19 +134,20 @@ __global__ void k_adj_moments(Grid g, const double* __restrict__ pop, const doub
   double f[Q], Fp[10];
   load_state(g, pop, hist, G, p, f, Fp);
   double s = 0, j[3] = {0, 0, 0};
-  for (int l = 0; l < Q; ++l) {
+  for_q([&](auto L) {
+    constexpr int l = decltype(L)::value;
     s += f[l];
-    j[0] += cx(l) * f[l];
-    j[1] += cy(l) * f[l];
-    j[2] += cz(l) * f[l];
-  }
+    if (cx(l)) j[0] += cx(l) * f[l];
+    if (cy(l)) j[1] += cy(l) * f[l];
+    if (cz(l)) j[2] += cz(l) * f[l];
+  });
   mom[p.n] = G.sg * s;
   for (int a = 0; a < 3; ++a) mom[(1 + a) * g.N + p.n] = G.sg * j[a];
 }
 
 // Reverse of one step at each node (mode 0), or of the history of an initial
 // state (mode 1: only the new coefficients carry an adjoint).
-__global__ void k_adj_node(Grid g, int mode, const double* __restrict__ pop, const double* __restrict__ hist,
+__global__ __launch_bounds__(BX * BY) void k_adj_node(Grid g, int mode, const double* __restrict__ pop, const double* __restrict__ hist,
                            const double* __restrict__ geo, const double* __restrict__ mom, double tau,
                            const double* __restrict__ lfn, const double* __restrict__ lpn, double* __restrict__ lfd,
                            double* __restrict__ lml, double* __restrict__ ldj, double* __restrict__ lpo,
@@ -147,15 +163,14 @@ __global__ void k_adj_node(Grid g, int mode, const double* __restrict__ pop, con
   NodeFwd o;
   node_fwd(f, Fp, G, dj, tau, with_old, o);
   double fsb[Q], Fb[Q], cb[10];
-  for (int l = 0; l < Q; ++l) {
+  // transposed streaming: f*_l(x) went to x + c_l (or bounced back into
+  // direction opp(l) at x); F_l(x)/2 was added to f_l(x, t+1).
+  for_q([&](auto L) {
+    constexpr int l = decltype(L)::value;
+    constexpr int x = cx(l), y = cy(l), z = cz(l);
     fsb[l] = 0;
     Fb[l] = 0;
-  }
-  if (with_old) {
-    // transposed streaming: f*_l(x) went to x + c_l (or bounced back into
-    // direction opp(l) at x); F_l(x)/2 was added to f_l(x, t+1).
-    for (int l = 0; l < Q; ++l) {
-      const int x = cx(l), y = cy(l), z = cz(l);
+    if (with_old) {
       const int jd = p.jf + y;
       if (jd >= 0 && jd < g.H)
         fsb[l] = lfn[l * g.N + nidx(g, wrapa(p.i + x, g.nx), jd, wrapa(p.k + z, g.nz))];
@@ -163,20 +178,29 @@ __global__ void k_adj_node(Grid g, int mode, const double* __restrict__ pop, con
         fsb[l] = lfn[opp(l) * g.N + p.n];
       Fb[l] = 0.5 * lfn[l * g.N + p.n];
     }
-  }
+  });
+#pragma unroll
   for (int q = 0; q < 10; ++q) cb[q] = lpn[q * g.N + p.n];
   double fb[Q], rb = 0, jb[3] = {0, 0, 0}, djb[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, Fpb[10];
-  for (int l = 0; l < Q; ++l) fb[l] = 0;
+  for_q([&](auto L) { fb[decltype(L)::value] = 0; });
+#pragma unroll
   for (int q = 0; q < 10; ++q) Fpb[q] = 0;
   AGeoBar gb;
   zero_bar(gb);
-  node_vjp(f, Fp, G, dj, tau, with_old, o, fsb, Fb, cb, nullptr, fb, rb, jb, djb, Fpb, gb);
-  for (int l = 0; l < Q; ++l) lfd[l * g.N + p.n] = fb[l];
+  node_vjp(Fp, G, tau, with_old, o, fsb, Fb, cb, nullptr, fb, rb, jb, djb, Fpb, gb);
+  for_q([&](auto L) {
+    constexpr int l = decltype(L)::value;
+    lfd[l * g.N + p.n] = fb[l];
+  });
   lml[p.n] = rb;
+#pragma unroll
   for (int a = 0; a < 3; ++a) lml[(1 + a) * g.N + p.n] = jb[a];
+#pragma unroll
   for (int a = 0; a < 3; ++a)
+#pragma unroll
     for (int b = 0; b < 3; ++b) ldj[(a * 3 + b) * g.N + p.n] = djb[a][b];
   if (lpo)
+#pragma unroll
     for (int q = 0; q < 10; ++q) lpo[q * g.N + p.n] = Fpb[q];
   add_geo_bar(g, lg, p.n, gb);
 }
@@ -184,16 +208,18 @@ __global__ void k_adj_node(Grid g, int mode, const double* __restrict__ pop, con
 // Transposed lattice gradient and the moment VJP:
 // lf_out = lfd + sqrt g (rho_bar + j_bar . c) (+ lf_add), with
 // j_bar = local + sum over the stencil of the neighbours' dj adjoints.
-__global__ void k_adj_gather(Grid g, const double* __restrict__ geo, const double* __restrict__ mom,
+__global__ __launch_bounds__(BX * BY) void k_adj_gather(Grid g, const double* __restrict__ geo, const double* __restrict__ mom,
                              const double* __restrict__ lfd, const double* __restrict__ lml,
                              const double* __restrict__ ldj, const double* __restrict__ lf_add,
                              double* __restrict__ lf_out, double* __restrict__ lg) {
   Node p;
   if (!fluid_node(g, p)) return;
   double rb = lml[p.n], jb[3] = {lml[g.N + p.n], lml[2 * g.N + p.n], lml[3 * g.N + p.n]};
-  for (int l = 1; l < Q; ++l) {
-    const int x = cx(l), y = cy(l), z = cz(l);
-    const double fct = 3.0 * wgt(l);
+  for_q([&](auto L) {
+    constexpr int l = decltype(L)::value;
+    if (l == 0) return;
+    constexpr int x = cx(l), y = cy(l), z = cz(l);
+    constexpr double fct = 3.0 * wgt(l);
     // x_src = p - c_l used this node as its neighbour in direction l
     const int js = p.jf - y;
     if (js >= 0 && js < g.H) {
@@ -208,22 +234,28 @@ __global__ void k_adj_gather(Grid g, const double* __restrict__ geo, const doubl
       for (int b = 0; b < 3; ++b)
         jb[b] -= fct * (x * ldj[(0 * 3 + b) * g.N + m] + y * ldj[(1 * 3 + b) * g.N + m] + z * ldj[(2 * 3 + b) * g.N + m]);
     }
-  }
+  });
   const double sg = 1.0 + geo[G_SG * g.N + p.n];
   const double rho = mom[p.n];
   const double S0 = rho / sg, S1[3] = {mom[g.N + p.n] / sg, mom[2 * g.N + p.n] / sg, mom[3 * g.N + p.n] / sg};
   double fb[Q];
-  for (int l = 0; l < Q; ++l) fb[l] = lfd[l * g.N + p.n] + (lf_add ? lf_add[l * g.N + p.n] : 0.0);
+  for_q([&](auto L) {
+    constexpr int l = decltype(L)::value;
+    fb[l] = lfd[l * g.N + p.n] + (lf_add ? lf_add[l * g.N + p.n] : 0.0);
+  });
   double sgb = 0;
   moments_vjp(sg, S0, S1, rb, jb, fb, sgb);
-  for (int l = 0; l < Q; ++l) lf_out[l * g.N + p.n] = fb[l];
+  for_q([&](auto L) {
+    constexpr int l = decltype(L)::value;
+    lf_out[l * g.N + p.n] = fb[l];
+  });
   lg[G_SG * g.N + p.n] += sgb;
 }
 
 // Wall-force VJP at one state: L += sum_a W_a F^a, F^a = sgn sum sqrt g
 // T^{i y} J^a_i at the fluid layer next to `wall`.  Adds into lf (adjoint of
 // f at this state), lg and lj.
-__global__ void k_adj_force(Grid g, int wall, const double* __restrict__ pop, const double* __restrict__ hist,
+__global__ __launch_bounds__(BX * BY) void k_adj_force(Grid g, int wall, const double* __restrict__ pop, const double* __restrict__ hist,
                             const double* __restrict__ geo, const double* __restrict__ jac, double tau,
                             const double* __restrict__ W, double* __restrict__ lf, double* __restrict__ lg,
                             double* __restrict__ lj) {
@@ -255,15 +287,20 @@ __global__ void k_adj_force(Grid g, int wall, const double* __restrict__ pop, co
     for (int a = 0; a < 3; ++a) lj[(a * 3 + i) * g.N + p.n] += sgn * G.sg * W[a] * o.T[sym(i, 1)];
   }
   double fsb[Q], Fb[Q], cb[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-  for (int l = 0; l < Q; ++l) fsb[l] = Fb[l] = 0;
   double fb[Q], rb = 0, jb[3] = {0, 0, 0}, djb[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, Fpb[10];
-  for (int l = 0; l < Q; ++l) fb[l] = 0;
+  for_q([&](auto L) {
+    constexpr int l = decltype(L)::value;
+    fsb[l] = Fb[l] = fb[l] = 0;
+  });
   AGeoBar gb;
   zero_bar(gb);
   gb.sg = sgb;
-  node_vjp(f, Fp, G, dj0, tau, false, o, fsb, Fb, cb, Tb, fb, rb, jb, djb, Fpb, gb);
+  node_vjp(Fp, G, tau, false, o, fsb, Fb, cb, Tb, fb, rb, jb, djb, Fpb, gb);
   moments_vjp(G.sg, o.S0, o.S1, rb, jb, fb, gb.sg);
-  for (int l = 0; l < Q; ++l) lf[l * g.N + p.n] += fb[l];
+  for_q([&](auto L) {
+    constexpr int l = decltype(L)::value;
+    lf[l * g.N + p.n] += fb[l];
+  });
   add_geo_bar(g, lg, p.n, gb);
 }
 
@@ -289,7 +326,7 @@ __device__ inline void inv3a(const double m[3][3], double r[3][3], double& det) 
 
 // Fluid-node part: adjoints of Gamma, g^{-1}, det J and J^{-1} F back to
 // D_l g (ldg), g (lge, packed) and J (lJe) on the extended grid.
-__global__ void k_adjg_fluid(Grid g, const double* __restrict__ wext, const double* __restrict__ gext,
+__global__ __launch_bounds__(BX * BY) void k_adjg_fluid(Grid g, const double* __restrict__ wext, const double* __restrict__ gext,
                              const double* __restrict__ jac, double F0, double F1, double F2,
                              const double* __restrict__ lgv, const double* __restrict__ lj, double* __restrict__ ldg,
                              double* __restrict__ lge, double* __restrict__ lJe) {
@@ -383,7 +420,7 @@ __global__ void k_adjg_fluid(Grid g, const double* __restrict__ wext, const doub
 }
 
 // lwe(y) on layers [0, ny-1] = transposed D (the G stencil) of ldg.
-__global__ void k_adjg_w(Grid g, const double* __restrict__ ldg, double* __restrict__ lwe) {
+__global__ __launch_bounds__(BX * BY) void k_adjg_w(Grid g, const double* __restrict__ ldg, double* __restrict__ lwe) {
   const int i = blockIdx.x * BX + threadIdx.x, je = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
   const int j = je - 3;
   if (i >= g.nx || j < 0 || j > g.ny - 1) return;
@@ -405,7 +442,7 @@ __global__ void k_adjg_w(Grid g, const double* __restrict__ ldg, double* __restr
 // Transpose of out(x) = (1 + s) in(x) - sum_l w_l in(x + c_l), out on layers
 // [olo, ohi]:  inb(y) += (1 + s) outb(y) [y in range] - sum_l w_l outb(y - c_l)
 // [y - c_l in range], for y on layers [olo - 1, ohi + 1].  Adds into inb.
-__global__ void k_adjg_smooth(Grid g, int ncomp, int olo, int ohi, const double* __restrict__ outb,
+__global__ __launch_bounds__(BX * BY) void k_adjg_smooth(Grid g, int ncomp, int olo, int ohi, const double* __restrict__ outb,
                               double* __restrict__ inb) {
   const int i = blockIdx.x * BX + threadIdx.x, je = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
   const int j = je - 3;
@@ -427,7 +464,7 @@ __global__ void k_adjg_smooth(Grid g, int ncomp, int olo, int ohi, const double*
 }
 
 // g = J^T J on layers [-1, ny]: lJe += from lge (J recomputed from v).
-__global__ void k_adjg_J(Grid g, const double* __restrict__ v, const double* __restrict__ lge,
+__global__ __launch_bounds__(BX * BY) void k_adjg_J(Grid g, const double* __restrict__ v, const double* __restrict__ lge,
                          double* __restrict__ lJe) {
   const int i = blockIdx.x * BX + threadIdx.x, je = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
   const int j = je - 3;
@@ -462,7 +499,7 @@ __global__ void k_adjg_J(Grid g, const double* __restrict__ v, const double* __r
 }
 
 // J = I + G v on layers [-1, ny]: lve(y) for y on [-2, ny+1].
-__global__ void k_adjg_v(Grid g, const double* __restrict__ lJe, double* __restrict__ lve) {
+__global__ __launch_bounds__(BX * BY) void k_adjg_v(Grid g, const double* __restrict__ lJe, double* __restrict__ lve) {
   const int i = blockIdx.x * BX + threadIdx.x, je = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
   const int j = je - 3;
   if (i >= g.nx || j < -2 || j > g.ny + 1) return;
@@ -483,7 +520,7 @@ __global__ void k_adjg_v(Grid g, const double* __restrict__ lJe, double* __restr
 
 // Chart adjoint from the displacement adjoint on the extended grid: layers
 // 0..ny-1 directly, plus the transposed cubic continuation.
-__global__ void k_adjg_chart(Grid g, const double* __restrict__ lue, double* __restrict__ gc) {
+__global__ __launch_bounds__(BX * BY) void k_adjg_chart(Grid g, const double* __restrict__ lue, double* __restrict__ gc) {
   const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
   if (i >= g.nx || j >= g.ny) return;
   const long long NE = (long long)g.nz * (g.ny + 6) * g.nx, NC = (long long)g.nz * g.ny * g.nx;
@@ -500,7 +537,7 @@ __global__ void k_adjg_chart(Grid g, const double* __restrict__ lue, double* __r
 }
 
 // Top-wall displacement adjoint: chart_y = xi_y + (eta/H) d_top + ...
-__global__ void k_adjg_disp(Grid g, const double* __restrict__ gc, double* __restrict__ gd) {
+__global__ __launch_bounds__(BX * BY) void k_adjg_disp(Grid g, const double* __restrict__ gc, double* __restrict__ gd) {
   const int i = blockIdx.x * BX + threadIdx.x, k = blockIdx.y * BY + threadIdx.y;
   if (i >= g.nx || k >= g.nz) return;
   const long long NC = (long long)g.nz * g.ny * g.nx;
@@ -509,18 +546,31 @@ __global__ void k_adjg_disp(Grid g, const double* __restrict__ gc, double* __res
   gd[(long long)k * g.nx + i] = acc;
 }
 
-hipError_t copy_state(const Fields& F, double* dst, bool save, hipStream_t s) {
+// Save the context's current state (populations, then history) to dst.
+hipError_t save_state(const Fields& F, double* dst, hipStream_t s) {
   const size_t np = sizeof(double) * 19 * (size_t)F.g.N, nh = sizeof(double) * H_N * (size_t)F.g.N;
-  double* pop = (double*)F.pop[F.cur];
-  double* hist = (double*)F.hist[F.cur];
-  hipError_t e;
-  if (save) {
-    e = hipMemcpyAsync(dst, pop, np, hipMemcpyDeviceToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(dst + 19 * F.g.N, hist, nh, hipMemcpyDeviceToDevice, s);
-  } else {
-    e = hipMemcpyAsync(pop, dst, np, hipMemcpyDeviceToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(hist, dst + 19 * F.g.N, nh, hipMemcpyDeviceToDevice, s);
+  hipError_t e = hipMemcpyAsync(dst, F.pop[F.cur], np, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(dst + 19 * F.g.N, F.hist[F.cur], nh, hipMemcpyDeviceToDevice, s);
+  return e;
+}
+
+// One FP64 step from the stored state `in` (populations 19N, then history
+// 10N) into `out`, leaving the context's own state buffers untouched.
+hipError_t step_into(Fields& F, const double* in, double* out, hipStream_t s, double tau) {
+  const size_t Nn = (size_t)F.g.N;
+  void* const pop[2] = {F.pop[0], F.pop[1]};
+  void* const hist[2] = {F.hist[0], F.hist[1]};
+  const int cur = F.cur;
+  F.pop[cur] = (void*)in;
+  F.hist[cur] = (void*)(in + 19 * Nn);
+  F.pop[cur ^ 1] = out;
+  F.hist[cur ^ 1] = out + 19 * Nn;
+  const hipError_t e = launch_step<double>(F, s, tau);
+  for (int b = 0; b < 2; ++b) {
+    F.pop[b] = pop[b];
+    F.hist[b] = hist[b];
   }
+  F.cur = cur;
   return e;
 }
 
@@ -535,13 +585,13 @@ hipError_t copy_state(const Fields& F, double* dst, bool save, hipStream_t s) {
 hipError_t adjoint_forward(Fields& F, AdjointBuffers& A, hipStream_t s, int K, int N, int wall, double tau,
                            double* forces) {
   const size_t state = (size_t)(19 + H_N) * F.g.N;
-  HCHK(copy_state(F, A.ckpt, true, s));
+  HCHK(save_state(F, A.ckpt, s));
   for (int t = 0; t < K; ++t) {
     HCHK(launch_step<double>(F, s, tau));
     HCHK(launch_wall_force<double>(F, s, wall, tau, forces + 3 * t, nullptr));
-    if ((t + 1) % N == 0 && t + 1 < K) HCHK(copy_state(F, A.ckpt + state * ((t + 1) / N), true, s));
+    if ((t + 1) % N == 0 && t + 1 < K) HCHK(save_state(F, A.ckpt + state * ((t + 1) / N), s));
   }
-  HCHK(copy_state(F, A.ckpt + state * (A.nckpt - 1), true, s));
+  HCHK(save_state(F, A.ckpt + state * (A.nckpt - 1), s));
   return hipGetLastError();
 }
 
@@ -570,13 +620,11 @@ hipError_t adjoint_backward(Fields& F, AdjointBuffers& A, hipStream_t s, int K, 
   const int nseg = (K + N - 1) / N;
   for (int sgm = nseg - 1; sgm >= 0; --sgm) {
     const int t0 = sgm * N, t1 = (t0 + N < K) ? t0 + N : K;
-    HCHK(copy_state(F, A.ckpt + state * sgm, false, s));
-    for (int t = t0; t < t1; ++t) {
-      HCHK(copy_state(F, A.traj + state * (t - t0), true, s));
-      if (t + 1 < t1) HCHK(launch_step<double>(F, s, tau));
-    }
+    // states t0..t1-1 of the segment: its checkpoint, then traj slots 1..
+    auto at = [&](int t) { return t == t0 ? A.ckpt + state * sgm : A.traj + state * (t - t0); };
+    for (int t = t0; t + 1 < t1; ++t) HCHK(step_into(F, at(t), at(t + 1), s, tau));
     for (int t = t1 - 1; t >= t0; --t) {
-      const double* st = A.traj + state * (t - t0);
+      const double* st = at(t);
       const double* pop = st;
       const double* hist = st + 19 * Nn;
       hipLaunchKernelGGL(k_adj_moments, fg, b, 0, s, g, pop, hist, geo, mom);
@@ -623,8 +671,8 @@ hipError_t adjoint_backward(Fields& F, AdjointBuffers& A, hipStream_t s, int K, 
     if (grad_chart) HCHK(hipMemcpyAsync(grad_chart, A.gc, sizeof(double) * 3 * NC, hipMemcpyDeviceToDevice, s));
     if (grad_disp) hipLaunchKernelGGL(k_adjg_disp, cg, b, 0, s, g, (const double*)A.gc, grad_disp);
   }
-  // leave the context at the recorded final state
-  HCHK(copy_state(F, A.ckpt + state * (A.nckpt - 1), false, s));
+  // The segments were rebuilt in the trajectory slots: the context's state
+  // is still the one lbm_forward_record ended with.
   return hipGetLastError();
 }
 

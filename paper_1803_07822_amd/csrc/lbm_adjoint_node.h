@@ -11,6 +11,12 @@
 //   f* = f - ne/tau + F - Fo/2, Fo = H(Fp)                        (Eq. collision)
 // with theta = c_s^2 = 1/3 and kappa = 1 - 1/(2 tau).  Symmetric tensors are
 // packed (xx, xy, xz, yy, yz, zz); Gamma is [i][sym(j,k)].
+//
+// Every loop over the 19 directions is unrolled at compile time and no
+// per-direction intermediate is stored, so a node's working set stays in
+// registers: the Hermite recompositions are linear in their coefficients, so
+// the VJP of one needs only ten basis sums of the incoming adjoint, and the
+// forward value it would multiply is a0 s0 + a1.s1 + a2:s2 of those sums.
 #pragma once
 
 #include "lbm_device.h"
@@ -25,173 +31,223 @@ struct AGeoBar {
   double sg, gi[6], gam[18], F[3];
 };
 
-// Second-order Hermite recomposition (w_l/sqrt g)[a0 + 3 a1.c + 4.5 a2:cc -
-// 1.5 tr a2] with a2 packed.
-__host__ __device__ inline double hermite_eval(int l, double isg, double a0, const double a1[3], const double a2[6]) {
-  const int x = cx(l), y = cy(l), z = cz(l);
-  double s = a0 - 1.5 * (a2[0] + a2[3] + a2[5]);
-  s += 3.0 * (x * a1[0] + y * a1[1] + z * a1[2]);
-  s += 4.5 * (x * x * a2[0] + y * y * a2[3] + z * z * a2[5]);
-  s += 9.0 * (x * y * a2[1] + x * z * a2[2] + y * z * a2[4]);
-  return wgt(l) * isg * s;
+// Basis sums of an adjoint hb_l over the directions (lattice weight included,
+// 1/sqrt g not): s0 = sum w hb, s1 = sum w hb 3c, s2 = sum w hb (4.5 cc -
+// 1.5 I) packed, with off-diagonal entries 9 c_a c_b.
+struct HSum {
+  double s0, s1[3], s2[6];
+};
+
+__device__ __forceinline__ void hsum_zero(HSum& h) {
+  h.s0 = 0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) h.s1[a] = 0;
+#pragma unroll
+  for (int q = 0; q < 6; ++q) h.s2[q] = 0;
 }
 
-// VJP of out_l = hermite_eval(l, 1/sg, a0, a1, a2): accumulates into the
-// coefficient adjoints and the adjoint of sg.
-__host__ __device__ inline void hermite_vjp(const double hb[Q], const double out[Q], double sg, double& a0b,
-                                            double a1b[3], double a2b[6], double& sgb) {
-  const double isg = 1.0 / sg;
-  double s0 = 0, s1[3] = {0, 0, 0}, s2[6] = {0, 0, 0, 0, 0, 0}, so = 0;
-  for (int l = 0; l < Q; ++l) {
-    const double wb = wgt(l) * isg * hb[l];
-    const int x = cx(l), y = cy(l), z = cz(l);
-    s0 += wb;
-    s1[0] += 3.0 * x * wb;
-    s1[1] += 3.0 * y * wb;
-    s1[2] += 3.0 * z * wb;
-    s2[0] += (4.5 * x * x - 1.5) * wb;
-    s2[3] += (4.5 * y * y - 1.5) * wb;
-    s2[5] += (4.5 * z * z - 1.5) * wb;
-    s2[1] += 9.0 * x * y * wb;
-    s2[2] += 9.0 * x * z * wb;
-    s2[4] += 9.0 * y * z * wb;
-    so += out[l] * hb[l];
+template <int l> __device__ __forceinline__ void hsum_add(HSum& h, double hb) {
+  constexpr int x = cx(l), y = cy(l), z = cz(l);
+  const double wb = wgt(l) * hb;
+  h.s0 += wb;
+  if (x) h.s1[0] += (3.0 * x) * wb;
+  if (y) h.s1[1] += (3.0 * y) * wb;
+  if (z) h.s1[2] += (3.0 * z) * wb;
+  h.s2[0] += (4.5 * x * x - 1.5) * wb;
+  h.s2[3] += (4.5 * y * y - 1.5) * wb;
+  h.s2[5] += (4.5 * z * z - 1.5) * wb;
+  if (x && y) h.s2[1] += (9.0 * x * y) * wb;
+  if (x && z) h.s2[2] += (9.0 * x * z) * wb;
+  if (y && z) h.s2[4] += (9.0 * y * z) * wb;
+}
+
+// Second-order Hermite recomposition (w_l/sqrt g)[a0 + 3 a1.c + 4.5 a2:cc -
+// 1.5 tr a2] with a2 packed.
+template <int l>
+__device__ __forceinline__ double hermite_val(double isg, double a0, const double a1[3], const double a2[6]) {
+  return wgt(l) * isg * hermite_term<double, l>(a0, a1, a2);
+}
+
+// VJP of out_l = (w_l/sg) H_l(a0, a1, a2) from the basis sums h of its
+// adjoint: accumulates into the coefficient adjoints and the adjoint of sg
+// (out is proportional to 1/sg).
+__device__ __forceinline__ void hermite_vjp(const HSum& h, double isg, double a0, const double a1[3], const double a2[6],
+                                            double& a0b, double a1b[3], double a2b[6], double& sgb) {
+  a0b += isg * h.s0;
+  double so = a0 * h.s0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    a1b[a] += isg * h.s1[a];
+    so += a1[a] * h.s1[a];
   }
-  a0b += s0;
-  for (int a = 0; a < 3; ++a) a1b[a] += s1[a];
-  for (int q = 0; q < 6; ++q) a2b[q] += s2[q];
-  sgb -= so * isg;
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    a2b[q] += isg * h.s2[q];
+    so += a2[q] * h.s2[q];
+  }
+  sgb -= so * isg * isg;
 }
 
 // Forward intermediates kept for the VJP.
 struct NodeFwd {
-  double rho, j[3], S0, S1[3];
-  double a2[6], feq[Q], ne[Q], P[6], T[6];
+  double isg, rho, j[3], S0, S1[3];
+  double a2[6], P[6], T[6];
   double tr[3], dbar[3][3], nab[3][3];
-  double A, B[3], C[6], b2[6], F[Q];
-  double bp[6], Fo[Q];
+  double A, B[3], C[6], b2[6];
+  double bp[6];
 };
 
 // Forward of one node.  with_old: include the F(t-1) term (false for the
 // history of an initial state, which only needs A, B, C).
-__host__ __device__ inline void node_fwd(const double f[Q], const double Fp[10], const AGeo& G,
-                                         const double dj[3][3], double tau, bool with_old, NodeFwd& o) {
-  const double th = 1.0 / 3.0, isg = 1.0 / G.sg;
+__device__ __forceinline__ void node_fwd(const double f[Q], const double Fp[10], const AGeo& G, const double dj[3][3],
+                                         double tau, bool with_old, NodeFwd& o) {
+  const double th = 1.0 / 3.0;
+  o.isg = 1.0 / G.sg;
   o.S0 = 0;
   o.S1[0] = o.S1[1] = o.S1[2] = 0;
-  for (int l = 0; l < Q; ++l) {
+  for_q([&](auto L) {
+    constexpr int l = decltype(L)::value;
     o.S0 += f[l];
-    o.S1[0] += cx(l) * f[l];
-    o.S1[1] += cy(l) * f[l];
-    o.S1[2] += cz(l) * f[l];
-  }
+    if (cx(l)) o.S1[0] += cx(l) * f[l];
+    if (cy(l)) o.S1[1] += cy(l) * f[l];
+    if (cz(l)) o.S1[2] += cz(l) * f[l];
+  });
   o.rho = G.sg * o.S0;
+#pragma unroll
   for (int a = 0; a < 3; ++a) o.j[a] = G.sg * o.S1[a];
   const double ir = 1.0 / o.rho;
+#pragma unroll
   for (int a = 0; a < 3; ++a)
+#pragma unroll
     for (int b = a; b < 3; ++b)
       o.a2[sym(a, b)] = o.rho * th * (G.gi[sym(a, b)] - (a == b ? 1.0 : 0.0)) + o.j[a] * o.j[b] * ir;
-  for (int l = 0; l < Q; ++l) {
-    o.feq[l] = hermite_eval(l, isg, o.rho, o.j, o.a2);
-    o.ne[l] = f[l] - o.feq[l];
-  }
+  // P = sum (f - feq) c c
+#pragma unroll
   for (int q = 0; q < 6; ++q) o.P[q] = 0;
-  for (int l = 0; l < Q; ++l) {
-    const int c[3] = {cx(l), cy(l), cz(l)};
-    for (int a = 0; a < 3; ++a)
-      for (int b = a; b < 3; ++b) o.P[sym(a, b)] += c[a] * c[b] * o.ne[l];
-  }
+  for_q([&](auto L) {
+    constexpr int l = decltype(L)::value;
+    constexpr int x = cx(l), y = cy(l), z = cz(l);
+    const double ne = f[l] - hermite_val<l>(o.isg, o.rho, o.j, o.a2);
+    if (x) o.P[0] += ne;
+    if (y) o.P[3] += ne;
+    if (z) o.P[5] += ne;
+    if (x && y) o.P[1] += (x * y) * ne;
+    if (x && z) o.P[2] += (x * z) * ne;
+    if (y && z) o.P[4] += (y * z) * ne;
+  });
   const double kap = 1.0 - 0.5 / tau;
+#pragma unroll
   for (int a = 0; a < 3; ++a)
+#pragma unroll
     for (int b = a; b < 3; ++b) {
       const int q = sym(a, b);
       o.T[q] = o.rho * th * G.gi[q] + o.j[a] * o.j[b] * ir + kap * G.sg * o.P[q];
     }
+#pragma unroll
   for (int b = 0; b < 3; ++b) o.tr[b] = G.gam[0 * 6 + sym(0, b)] + G.gam[1 * 6 + sym(1, b)] + G.gam[2 * 6 + sym(2, b)];
   o.A = -2.0 * (o.tr[0] * o.j[0] + o.tr[1] * o.j[1] + o.tr[2] * o.j[2]);
+#pragma unroll
   for (int i = 0; i < 3; ++i) {
     double s = G.F[i];
+#pragma unroll
     for (int jj = 0; jj < 3; ++jj) {
       s -= 2.0 * o.tr[jj] * o.T[sym(i, jj)];
+#pragma unroll
       for (int kk = 0; kk < 3; ++kk) s -= G.gam[i * 6 + sym(jj, kk)] * o.T[sym(jj, kk)];
     }
     o.B[i] = s;
   }
+#pragma unroll
   for (int k = 0; k < 3; ++k)
+#pragma unroll
     for (int i = 0; i < 3; ++i) {
       o.dbar[k][i] = dj[k][i] - o.tr[k] * o.j[i];
       double s = dj[k][i];
+#pragma unroll
       for (int l = 0; l < 3; ++l) s += G.gam[i * 6 + sym(k, l)] * o.j[l];
       o.nab[k][i] = s;
     }
   const double divbar = o.dbar[0][0] + o.dbar[1][1] + o.dbar[2][2];
   const double divnab = o.nab[0][0] + o.nab[1][1] + o.nab[2][2];
+#pragma unroll
   for (int i = 0; i < 3; ++i)
+#pragma unroll
     for (int jj = i; jj < 3; ++jj) {
       const double s = o.dbar[jj][i] + o.dbar[i][jj] + (i == jj ? divbar : 0.0);
       double t = G.gi[sym(i, jj)] * divnab;
+#pragma unroll
       for (int k = 0; k < 3; ++k) t += G.gi[sym(jj, k)] * o.nab[k][i] + G.gi[sym(i, k)] * o.nab[k][jj];
       o.C[sym(i, jj)] = th * (s - t);
     }
+#pragma unroll
   for (int q = 0; q < 6; ++q) o.b2[q] = o.C[q];
   o.b2[0] -= th * o.A;
   o.b2[3] -= th * o.A;
   o.b2[5] -= th * o.A;
-  for (int l = 0; l < Q; ++l) o.F[l] = hermite_eval(l, isg, o.A, o.B, o.b2);
   if (with_old) {
+#pragma unroll
     for (int q = 0; q < 6; ++q) o.bp[q] = Fp[4 + q];
     o.bp[0] -= th * Fp[0];
     o.bp[3] -= th * Fp[0];
     o.bp[5] -= th * Fp[0];
-    for (int l = 0; l < Q; ++l) o.Fo[l] = hermite_eval(l, isg, Fp[0], Fp + 1, o.bp);
   }
 }
 
-// VJP of one node.  Inputs: fsb = adjoint of f* (with_old only), Fb = adjoint
-// of F (added to what flows from f*), cb = adjoint of the new coefficients
-// (A, B, C).  Outputs (accumulated): fb = direct adjoint of f (through ne and
-// f*), rb/jb = adjoint of rho and j (local uses), djb = adjoint of dj, Fpb =
-// adjoint of the old coefficients, gb = geometry adjoint.
-__host__ __device__ inline void node_vjp(const double f[Q], const double Fp[10], const AGeo& G, const double dj[3][3],
-                                         double tau, bool with_old, const NodeFwd& o, const double fsb[Q],
-                                         const double Fbin[Q], const double cb[10], const double* Tbin, double fb[Q],
-                                         double& rb, double jb[3], double djb[3][3], double Fpb[10], AGeoBar& gb) {
-  (void)f;
-  (void)dj;
+// VJP of one node.  Inputs: fsb = adjoint of f* (with_old only), Fbin =
+// adjoint of F (added to what flows from f*), cb = adjoint of the new
+// coefficients (A, B, C), Tbin = adjoint of T (or null).  Outputs
+// (accumulated): fb = direct adjoint of f (through ne and f*), rb/jb =
+// adjoint of rho and j (local uses), djb = adjoint of dj, Fpb = adjoint of
+// the old coefficients, gb = geometry adjoint.
+__device__ __forceinline__ void node_vjp(const double Fp[10], const AGeo& G, double tau, bool with_old,
+                                         const NodeFwd& o, const double fsb[Q], const double Fbin[Q],
+                                         const double cb[10], const double* Tbin, double fb[Q], double& rb,
+                                         double jb[3], double djb[3][3], double Fpb[10], AGeoBar& gb) {
   const double th = 1.0 / 3.0, itau = 1.0 / tau, kap = 1.0 - 0.5 / tau;
-  double neb[Q], Fb[Q], Fob[Q];
-  for (int l = 0; l < Q; ++l) {
+  // f* = f - ne/tau + F - Fo/2: basis sums of the adjoints of Fo and F
+  HSum hFo, hF;
+  hsum_zero(hFo);
+  hsum_zero(hF);
+  for_q([&](auto L) {
+    constexpr int l = decltype(L)::value;
     const double s = with_old ? fsb[l] : 0.0;
-    fb[l] += s;
-    neb[l] = -s * itau;
-    Fb[l] = s + Fbin[l];
-    Fob[l] = -0.5 * s;
-  }
+    hsum_add<l>(hFo, -0.5 * s);
+    hsum_add<l>(hF, s + Fbin[l]);
+  });
   // F(t-1) = H(Fp) -> old coefficients
   if (with_old) {
     double a0b = 0, a1b[3] = {0, 0, 0}, a2b[6] = {0, 0, 0, 0, 0, 0};
-    hermite_vjp(Fob, o.Fo, G.sg, a0b, a1b, a2b, gb.sg);
+    hermite_vjp(hFo, o.isg, Fp[0], Fp + 1, o.bp, a0b, a1b, a2b, gb.sg);
     Fpb[0] += a0b - th * (a2b[0] + a2b[3] + a2b[5]);
+#pragma unroll
     for (int a = 0; a < 3; ++a) Fpb[1 + a] += a1b[a];
+#pragma unroll
     for (int q = 0; q < 6; ++q) Fpb[4 + q] += a2b[q];
   }
   // F = H(A, B, C - theta A delta)
   double Ab = cb[0], Bb[3] = {cb[1], cb[2], cb[3]}, Cb[6];
+#pragma unroll
   for (int q = 0; q < 6; ++q) Cb[q] = cb[4 + q];
   {
     double a0b = 0, a1b[3] = {0, 0, 0}, a2b[6] = {0, 0, 0, 0, 0, 0};
-    hermite_vjp(Fb, o.F, G.sg, a0b, a1b, a2b, gb.sg);
+    hermite_vjp(hF, o.isg, o.A, o.B, o.b2, a0b, a1b, a2b, gb.sg);
     Ab += a0b - th * (a2b[0] + a2b[3] + a2b[5]);
+#pragma unroll
     for (int a = 0; a < 3; ++a) Bb[a] += a1b[a];
+#pragma unroll
     for (int q = 0; q < 6; ++q) Cb[q] += a2b[q];
   }
   double jbar[3] = {0, 0, 0}, Tb[6] = {0, 0, 0, 0, 0, 0}, trb[3] = {0, 0, 0};
   if (Tbin)
+#pragma unroll
     for (int q = 0; q < 6; ++q) Tb[q] = Tbin[q];
   double dbarb[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, nabb[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
   // C^ij = theta (s_ij - t_ij)
   double divbarb = 0, divnabb = 0;
+  const double divnab = o.nab[0][0] + o.nab[1][1] + o.nab[2][2];
+#pragma unroll
   for (int i = 0; i < 3; ++i)
+#pragma unroll
     for (int jj = i; jj < 3; ++jj) {
       const double cbq = th * Cb[sym(i, jj)];
       // s = dbar[jj][i] + dbar[i][jj] + delta divbar
@@ -200,8 +256,9 @@ __host__ __device__ inline void node_vjp(const double f[Q], const double Fp[10],
       if (i == jj) divbarb += cbq;
       // t = g^{i jj} divnab + sum_k g^{jj k} nab[k][i] + g^{i k} nab[k][jj]
       const double tbq = -cbq;
-      gb.gi[sym(i, jj)] += tbq * (o.nab[0][0] + o.nab[1][1] + o.nab[2][2]);
+      gb.gi[sym(i, jj)] += tbq * divnab;
       divnabb += tbq * G.gi[sym(i, jj)];
+#pragma unroll
       for (int k = 0; k < 3; ++k) {
         gb.gi[sym(jj, k)] += tbq * o.nab[k][i];
         nabb[k][i] += tbq * G.gi[sym(jj, k)];
@@ -209,14 +266,18 @@ __host__ __device__ inline void node_vjp(const double f[Q], const double Fp[10],
         nabb[k][jj] += tbq * G.gi[sym(i, k)];
       }
     }
+#pragma unroll
   for (int k = 0; k < 3; ++k) {
     dbarb[k][k] += divbarb;
     nabb[k][k] += divnabb;
   }
   // nab[k][i] = dj[k][i] + Gamma^i_kl j^l ; dbar[k][i] = dj[k][i] - tr_k j^i
+#pragma unroll
   for (int k = 0; k < 3; ++k)
+#pragma unroll
     for (int i = 0; i < 3; ++i) {
       djb[k][i] += nabb[k][i] + dbarb[k][i];
+#pragma unroll
       for (int l = 0; l < 3; ++l) {
         gb.gam[i * 6 + sym(k, l)] += nabb[k][i] * o.j[l];
         jbar[l] += nabb[k][i] * G.gam[i * 6 + sym(k, l)];
@@ -225,11 +286,14 @@ __host__ __device__ inline void node_vjp(const double f[Q], const double Fp[10],
       jbar[i] -= dbarb[k][i] * o.tr[k];
     }
   // B^i = F^i - 2 tr_j T^ij - Gamma^i_jk T^jk
+#pragma unroll
   for (int i = 0; i < 3; ++i) {
     gb.F[i] += Bb[i];
+#pragma unroll
     for (int jj = 0; jj < 3; ++jj) {
       trb[jj] -= 2.0 * Bb[i] * o.T[sym(i, jj)];
       Tb[sym(i, jj)] -= 2.0 * Bb[i] * o.tr[jj];
+#pragma unroll
       for (int kk = 0; kk < 3; ++kk) {
         gb.gam[i * 6 + sym(jj, kk)] -= Bb[i] * o.T[sym(jj, kk)];
         Tb[sym(jj, kk)] -= Bb[i] * G.gam[i * 6 + sym(jj, kk)];
@@ -237,17 +301,22 @@ __host__ __device__ inline void node_vjp(const double f[Q], const double Fp[10],
     }
   }
   // A = -2 tr . j
+#pragma unroll
   for (int a = 0; a < 3; ++a) {
     trb[a] -= 2.0 * Ab * o.j[a];
     jbar[a] -= 2.0 * Ab * o.tr[a];
   }
   // tr_b = sum_i Gamma^i_ib
+#pragma unroll
   for (int b = 0; b < 3; ++b)
+#pragma unroll
     for (int i = 0; i < 3; ++i) gb.gam[i * 6 + sym(i, b)] += trb[b];
   // T = rho theta g^ij + j j / rho + kappa sqrt g P
   double rbar = 0, Pb[6];
   const double ir = 1.0 / o.rho;
+#pragma unroll
   for (int a = 0; a < 3; ++a)
+#pragma unroll
     for (int b = a; b < 3; ++b) {
       const int q = sym(a, b);
       rbar += Tb[q] * (th * G.gi[q] - o.j[a] * o.j[b] * ir * ir);
@@ -257,30 +326,37 @@ __host__ __device__ inline void node_vjp(const double f[Q], const double Fp[10],
       gb.sg += Tb[q] * kap * o.P[q];
       Pb[q] = Tb[q] * kap * G.sg;
     }
-  // P = sum ne c c
-  for (int l = 0; l < Q; ++l) {
-    const int c[3] = {cx(l), cy(l), cz(l)};
-    double s = 0;
-    for (int a = 0; a < 3; ++a)
-      for (int b = a; b < 3; ++b) s += c[a] * c[b] * Pb[sym(a, b)];
-    neb[l] += s;
-  }
-  // ne = f - feq
-  double feqb[Q];
-  for (int l = 0; l < Q; ++l) {
-    fb[l] += neb[l];
-    feqb[l] = -neb[l];
-  }
+  // P = sum ne c c, ne = f - feq, and the f* path: adjoint of f directly and
+  // of feq (basis sums)
+  HSum hfeq;
+  hsum_zero(hfeq);
+  for_q([&](auto L) {
+    constexpr int l = decltype(L)::value;
+    constexpr int x = cx(l), y = cy(l), z = cz(l);
+    const double s = with_old ? fsb[l] : 0.0;
+    double neb = -s * itau;
+    if (x) neb += Pb[0];
+    if (y) neb += Pb[3];
+    if (z) neb += Pb[5];
+    if (x && y) neb += (x * y) * Pb[1];
+    if (x && z) neb += (x * z) * Pb[2];
+    if (y && z) neb += (y * z) * Pb[4];
+    fb[l] += s + neb;
+    hsum_add<l>(hfeq, -neb);
+  });
   // feq = H(rho, j, a2)
   double a2b[6] = {0, 0, 0, 0, 0, 0};
   {
     double a0b = 0, a1b[3] = {0, 0, 0};
-    hermite_vjp(feqb, o.feq, G.sg, a0b, a1b, a2b, gb.sg);
+    hermite_vjp(hfeq, o.isg, o.rho, o.j, o.a2, a0b, a1b, a2b, gb.sg);
     rbar += a0b;
+#pragma unroll
     for (int a = 0; a < 3; ++a) jbar[a] += a1b[a];
   }
   // a2 = rho theta (g^ij - delta) + j j / rho
+#pragma unroll
   for (int a = 0; a < 3; ++a)
+#pragma unroll
     for (int b = a; b < 3; ++b) {
       const int q = sym(a, b);
       rbar += a2b[q] * (th * (G.gi[q] - (a == b ? 1.0 : 0.0)) - o.j[a] * o.j[b] * ir * ir);
@@ -289,13 +365,21 @@ __host__ __device__ inline void node_vjp(const double f[Q], const double Fp[10],
       jbar[b] += a2b[q] * o.j[a] * ir;
     }
   rb += rbar;
+#pragma unroll
   for (int a = 0; a < 3; ++a) jb[a] += jbar[a];
 }
 
 // Moments rho = sg S0, j = sg S1 -> adjoint into f and sg.
-__host__ __device__ inline void moments_vjp(double sg, double S0, const double S1[3], double rb, const double jb[3],
+__device__ __forceinline__ void moments_vjp(double sg, double S0, const double S1[3], double rb, const double jb[3],
                                             double fb[Q], double& sgb) {
-  for (int l = 0; l < Q; ++l) fb[l] += sg * (rb + cx(l) * jb[0] + cy(l) * jb[1] + cz(l) * jb[2]);
+  for_q([&](auto L) {
+    constexpr int l = decltype(L)::value;
+    double v = rb;
+    if (cx(l)) v += cx(l) * jb[0];
+    if (cy(l)) v += cy(l) * jb[1];
+    if (cz(l)) v += cz(l) * jb[2];
+    fb[l] += sg * v;
+  });
   sgb += S0 * rb + S1[0] * jb[0] + S1[1] * jb[1] + S1[2] * jb[2];
 }
 

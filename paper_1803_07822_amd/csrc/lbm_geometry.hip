@@ -37,7 +37,7 @@ __device__ __forceinline__ void inv3(const double m[3][3], double r[3][3], doubl
   r[2][2] = (m[0][0] * m[1][1] - m[0][1] * m[1][0]) * id;
 }
 
-__global__ void k_chart_from_disp(Grid g, const double* __restrict__ disp, double* __restrict__ chart) {
+__global__ __launch_bounds__(BX * BY) void k_chart_from_disp(Grid g, const double* __restrict__ disp, double* __restrict__ chart) {
   const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
   if (i >= g.nx || j >= g.ny) return;
   const long long NC = (long long)g.nz * g.ny * g.nx;
@@ -50,7 +50,7 @@ __global__ void k_chart_from_disp(Grid g, const double* __restrict__ disp, doubl
 }
 
 // u = chart - xi on layers 0..ny-1, cubic continuation on -3..-1 and ny..ny+2.
-__global__ void k_uext(Grid g, const double* __restrict__ chart, double* __restrict__ u) {
+__global__ __launch_bounds__(BX * BY) void k_uext(Grid g, const double* __restrict__ chart, double* __restrict__ u) {
   const int i = blockIdx.x * BX + threadIdx.x, je = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
   if (i >= g.nx || je >= g.ny + 6) return;
   const int j = je - 3;
@@ -81,7 +81,7 @@ __global__ void k_uext(Grid g, const double* __restrict__ chart, double* __restr
 }
 
 // out = in - (c_s^2/2) L in = in - sum_l w_l (in(x+c_l) - in(x)) on layers [jlo, jhi]
-__global__ void k_smooth(Grid g, int ncomp, int jlo, int jhi, const double* __restrict__ in, double* __restrict__ out) {
+__global__ __launch_bounds__(BX * BY) void k_smooth(Grid g, int ncomp, int jlo, int jhi, const double* __restrict__ in, double* __restrict__ out) {
   const int i = blockIdx.x * BX + threadIdx.x, je = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
   const int j = je - 3;
   if (i >= g.nx || j < jlo || j > jhi) return;
@@ -101,7 +101,7 @@ __global__ void k_smooth(Grid g, int ncomp, int jlo, int jhi, const double* __re
 }
 
 // J = I + G v and g = J^T J on layers [-1, ny]; J also stored at fluid nodes.
-__global__ void k_jac_metric(Grid g, const double* __restrict__ v, double* __restrict__ gext, double* __restrict__ jac) {
+__global__ __launch_bounds__(BX * BY) void k_jac_metric(Grid g, const double* __restrict__ v, double* __restrict__ gext, double* __restrict__ jac) {
   const int i = blockIdx.x * BX + threadIdx.x, je = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
   const int j = je - 3;
   if (i >= g.nx || j < -1 || j > g.ny) return;
@@ -140,7 +140,7 @@ __global__ void k_jac_metric(Grid g, const double* __restrict__ v, double* __res
 // Fluid-node geometry: g^{-1}, sqrt g = det J, Gamma^i_jk = 1/2 g^il (D_j g_kl
 // + D_k g_jl - D_l g_jk) with D_l g = G_l w, and F^i = (J^{-1} F_cart)^i.
 template <class T>
-__global__ void k_geo(Grid g, const double* __restrict__ w, const double* __restrict__ gext,
+__global__ __launch_bounds__(BX * BY) void k_geo(Grid g, const double* __restrict__ w, const double* __restrict__ gext,
                       const double* __restrict__ jac, double F0, double F1, double F2, T* __restrict__ geo) {
   const int i = blockIdx.x * BX + threadIdx.x, jf = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
   if (i >= g.nx || jf >= g.H) return;
@@ -199,7 +199,7 @@ __global__ void k_geo(Grid g, const double* __restrict__ w, const double* __rest
 }
 
 template <class T>
-__global__ void k_body_force(Grid g, const double* __restrict__ jac, double F0, double F1, double F2, T* __restrict__ geo) {
+__global__ __launch_bounds__(BX * BY) void k_body_force(Grid g, const double* __restrict__ jac, double F0, double F1, double F2, T* __restrict__ geo) {
   const int i = blockIdx.x * BX + threadIdx.x, jf = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
   if (i >= g.nx || jf >= g.H) return;
   const long long n = ((long long)k * g.H + jf) * g.nx + i;
@@ -217,7 +217,7 @@ __global__ void k_body_force(Grid g, const double* __restrict__ jac, double F0, 
 // Chart components J^{-1} v of the Cartesian wall velocity at the fluid node
 // next to each wall.
 template <class T>
-__global__ void k_wall_velocity(Grid g, const double* __restrict__ jac, const double* __restrict__ vwall, T* __restrict__ uw) {
+__global__ __launch_bounds__(BX * BY) void k_wall_velocity(Grid g, const double* __restrict__ jac, const double* __restrict__ vwall, T* __restrict__ uw) {
   const int i = blockIdx.x * BX + threadIdx.x, k = blockIdx.y * BY + threadIdx.y;
   if (i >= g.nx || k >= g.nz) return;
   for (int w = 0; w < 2; ++w) {

@@ -50,7 +50,7 @@ __device__ __forceinline__ T pull_rp(const T* __restrict__ pop, const Grid& g, i
 
 // Cartesian moment fields at the old fluid nodes.
 template <class T>
-__global__ void k_rp_moments(Grid g, const T* __restrict__ pop, const T* __restrict__ hist, const T* __restrict__ geo,
+__global__ __launch_bounds__(BX * BY) void k_rp_moments(Grid g, const T* __restrict__ pop, const T* __restrict__ hist, const T* __restrict__ geo,
                              const double* __restrict__ jac, double* __restrict__ mf) {
   const int i = blockIdx.x * BX + threadIdx.x, jf = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
   if (i >= g.nx || jf >= g.H) return;
@@ -128,7 +128,7 @@ __global__ void k_rp_moments(Grid g, const T* __restrict__ pop, const T* __restr
     }
 }
 
-__global__ void k_rp_ghost(Grid g, const double* __restrict__ vwall, double* __restrict__ mf) {
+__global__ __launch_bounds__(BX * BY) void k_rp_ghost(Grid g, const double* __restrict__ vwall, double* __restrict__ mf) {
   const int i = blockIdx.x * BX + threadIdx.x, k = blockIdx.y * BY + threadIdx.y;
   if (i >= g.nx || k >= g.nz) return;
   const long long NC = (long long)g.nz * g.ny * g.nx;
@@ -172,7 +172,7 @@ __device__ __forceinline__ double trilin_ext(const Grid& g, const double* __rest
 // New state at the new fluid nodes; writes the streamed deviations g~ (FP64)
 // and the new history.
 template <class T>
-__global__ void k_rp_new(Grid g, const double* __restrict__ chart, const double* __restrict__ uold,
+__global__ __launch_bounds__(BX * BY) void k_rp_new(Grid g, const double* __restrict__ chart, const double* __restrict__ uold,
                          const double* __restrict__ mf, const double* __restrict__ jac, const T* __restrict__ geo,
                          double* __restrict__ gs, T* __restrict__ hist) {
   const int i = blockIdx.x * BX + threadIdx.x, jf = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
@@ -286,7 +286,7 @@ __global__ void k_rp_new(Grid g, const double* __restrict__ chart, const double*
 
 // pop[l][y] = g~_l(y + c_l) if fluid, else g~_opp(l)(y)
 template <class T>
-__global__ void k_rp_unpull(Grid g, const double* __restrict__ gs, T* __restrict__ pop) {
+__global__ __launch_bounds__(BX * BY) void k_rp_unpull(Grid g, const double* __restrict__ gs, T* __restrict__ pop) {
   const int i = blockIdx.x * BX + threadIdx.x, jf = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
   if (i >= g.nx || jf >= g.H) return;
   const long long n = ((long long)k * g.H + jf) * g.nx + i;

@@ -212,7 +212,7 @@ __global__ __launch_bounds__(BX* BY) void k_collide(Grid g, const T* __restrict_
 // ------------------------------------------------------- state in / out
 // Equilibrium state in FP64: f = w + feq deviations of (rho, J^{-1} u_cart).
 template <class T>
-__global__ void k_feq_full(Grid g, const double* __restrict__ rho_in, const double* __restrict__ uc,
+__global__ __launch_bounds__(BX * BY) void k_feq_full(Grid g, const double* __restrict__ rho_in, const double* __restrict__ uc,
                            const double* __restrict__ jac, const T* __restrict__ geo, double* __restrict__ full) {
   Pos p;
   if (!node_pos(g, p)) return;
@@ -253,7 +253,7 @@ __global__ void k_feq_full(Grid g, const double* __restrict__ rho_in, const doub
 
 // Moments of a full FP64 state f (rho = sqrt g sum f, j = sqrt g sum f c).
 template <class T>
-__global__ void k_moments_full(Grid g, const double* __restrict__ f, const T* __restrict__ geo, T* __restrict__ mom) {
+__global__ __launch_bounds__(BX * BY) void k_moments_full(Grid g, const double* __restrict__ f, const T* __restrict__ geo, T* __restrict__ mom) {
   Pos p;
   if (!node_pos(g, p)) return;
   double s = 0, j0 = 0, j1 = 0, j2 = 0;
@@ -275,7 +275,7 @@ __global__ void k_moments_full(Grid g, const double* __restrict__ f, const T* __
 // Forcing history of a full state (the forcing F(x, 0) that stands in for
 // F(x, -1) at the first step).
 template <class T>
-__global__ void k_hist_full(Grid g, const double* __restrict__ f, const T* __restrict__ geo, const T* __restrict__ mom,
+__global__ __launch_bounds__(BX * BY) void k_hist_full(Grid g, const double* __restrict__ f, const T* __restrict__ geo, const T* __restrict__ mom,
                             const T* __restrict__ uw, int mv0, int mv1, T tau, T* __restrict__ hist) {
   Pos p;
   if (!node_pos(g, p)) return;
@@ -299,7 +299,7 @@ __global__ void k_hist_full(Grid g, const double* __restrict__ f, const T* __res
 
 // In place: full[l] = f_l - w_l - F_l(history)/2, the streamed deviation g~.
 template <class T>
-__global__ void k_full_to_streamed(Grid g, double* __restrict__ full, const T* __restrict__ hist,
+__global__ __launch_bounds__(BX * BY) void k_full_to_streamed(Grid g, double* __restrict__ full, const T* __restrict__ hist,
                                    const T* __restrict__ geo) {
   Pos p;
   if (!node_pos(g, p)) return;
@@ -318,7 +318,7 @@ __global__ void k_full_to_streamed(Grid g, double* __restrict__ full, const T* _
 // Inverse of the pull: pop[l][y] = g~_l(y + c_l) if y + c_l is fluid, else
 // g~_opp(l)(y).
 template <class T>
-__global__ void k_unpull(Grid g, const double* __restrict__ gs, T* __restrict__ pop) {
+__global__ __launch_bounds__(BX * BY) void k_unpull(Grid g, const double* __restrict__ gs, T* __restrict__ pop) {
   Pos p;
   if (!node_pos(g, p)) return;
   for_q([&](auto L) {
@@ -338,7 +338,7 @@ __global__ void k_unpull(Grid g, const double* __restrict__ gs, T* __restrict__ 
 }
 
 template <class T>
-__global__ void k_get_pops(Grid g, const T* __restrict__ pop, const T* __restrict__ hist, const T* __restrict__ geo,
+__global__ __launch_bounds__(BX * BY) void k_get_pops(Grid g, const T* __restrict__ pop, const T* __restrict__ hist, const T* __restrict__ geo,
                            double* __restrict__ out) {
   Pos p;
   if (!node_pos(g, p)) return;
@@ -354,14 +354,14 @@ __global__ void k_get_pops(Grid g, const T* __restrict__ pop, const T* __restric
 }
 
 template <class T>
-__global__ void k_get_hist(Grid g, const T* __restrict__ hist, double* __restrict__ out) {
+__global__ __launch_bounds__(BX * BY) void k_get_hist(Grid g, const T* __restrict__ hist, double* __restrict__ out) {
   Pos p;
   if (!node_pos(g, p)) return;
   for (int q = 0; q < H_N; ++q) out[q * g.N + p.n] = (double)hist[q * g.N + p.n];
 }
 
 template <class T>
-__global__ void k_get_geo(Grid g, const T* __restrict__ geo, double* __restrict__ out) {
+__global__ __launch_bounds__(BX * BY) void k_get_geo(Grid g, const T* __restrict__ geo, double* __restrict__ out) {
   Pos p;
   if (!node_pos(g, p)) return;
   for (int q = 0; q < G_N; ++q) {
@@ -372,7 +372,7 @@ __global__ void k_get_geo(Grid g, const T* __restrict__ geo, double* __restrict_
 }
 
 template <class T>
-__global__ void k_moments_out(Grid g, const T* __restrict__ pop, const T* __restrict__ hist, const T* __restrict__ geo,
+__global__ __launch_bounds__(BX * BY) void k_moments_out(Grid g, const T* __restrict__ pop, const T* __restrict__ hist, const T* __restrict__ geo,
                               const double* __restrict__ jac, double* __restrict__ rho, double* __restrict__ u,
                               int cart) {
   Pos p;
@@ -458,7 +458,7 @@ __global__ __launch_bounds__(BX* BY) void k_wall_force(Grid g, int wall, const T
 }
 
 // Fixed-order sum of the block partials (deterministic).
-__global__ void k_sum_partials(int nb, const double* __restrict__ part, double* __restrict__ out) {
+__global__ __launch_bounds__(BX * BY) void k_sum_partials(int nb, const double* __restrict__ part, double* __restrict__ out) {
   __shared__ double red[3][256];
   const int tid = threadIdx.x;
   double s[3] = {0, 0, 0};

@@ -169,3 +169,30 @@ def test_c4_adjoint_against_central_differences():
     print(f"C4 FD check: max rel err d {max(errs_d):.2e}, f0 {max(errs_f):.2e}")
     assert max(errs_d) < 1e-3, errs_d
     assert max(errs_f) < 1e-3, errs_f
+
+
+def test_backward_leaves_forward_final_state():
+    """The reverse sweep rebuilds segments in its own trajectory storage: the
+    context's state after lbm_backward is bit-for-bit the state
+    lbm_forward_record ended with, and stepping on from it matches stepping
+    on without the reverse sweep."""
+    lbm = _lbm()
+    nx, ny, nz, tau, K, N = 10, 7, 6, 0.7, 5, 2
+    d, f0 = _case(nx, ny, nz, tau, seed=13)
+    S = lbm.Solver(nx, ny, nz, tau, "fp64", adjoint_K=K, ckpt_every=N)
+    S.set_body_force((1e-4, 0, 0))
+    S.set_wall_displacement(1, d)
+    S.set_populations(f0)
+    S.forward_record(K)
+    p_end, h_end = S.populations().cpu().numpy(), S.history().cpu().numpy()
+    S.backward(synth.random_perturbation((K, 3), 1.0, 5))
+    assert np.array_equal(S.populations().cpu().numpy(), p_end)
+    assert np.array_equal(S.history().cpu().numpy(), h_end)
+    S.step(3)
+    o = Oracle(nx, ny, nz, tau)
+    o.set_body_force((1e-4, 0, 0))
+    o.set_wall_displacement(1, d)
+    o.set_populations(f0)
+    o.step(K + 3)
+    fo = o.populations()
+    assert np.abs(S.populations().cpu().numpy() - fo).max() < 1e-12 * np.abs(fo).max()

@@ -35,7 +35,14 @@ namespace {
 using lbm::ALIGN;
 using lbm::Carver;
 
-bool grid_ok(const lbm_grid* g) { return g && g->nx >= 1 && g->nz >= 1 && g->ny >= 4; }
+// The step kernels address one population plane with 32-bit byte offsets:
+// fluid nodes * 8 bytes must stay below 4 GiB.
+constexpr long long MAX_FLUID_NODES = 1LL << 29;
+
+bool grid_ok(const lbm_grid* g) {
+  if (!g || g->nx < 1 || g->nz < 1 || g->ny < 4) return false;
+  return (long long)g->nx * (g->ny - 2) * g->nz < MAX_FLUID_NODES;
+}
 
 Grid make_grid(const lbm_grid* h) {
   Grid g;

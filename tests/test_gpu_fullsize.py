@@ -1,0 +1,207 @@
+"""Parity at the full sizes of the channel workloads, with the launch shape
+bench.py times (the library's default tuning).
+
+- 256x128x128 Gaussian bump, tau 0.6: FP64 and FP32 steps against the oracle.
+- 256x128x128 oscillating wall: wall velocity, metric update with
+  re-projection between steps, FP64 and FP32 against the oracle.
+- 512x256x256 travelling patch wave (33.3M fluid nodes, the largest
+  workload): one FP32 step against the oracle, and the FP64 adjoint over
+  K = 100 steps with a checkpoint every 10 against central differences, at
+  the run amplitude 0.04*256; the stated amplitude 0.08*256 trips the
+  instability guard within 20 steps, which is checked too.
+
+The oracle runs the whole grid (several seconds per step on the host cores);
+these tests carry the `slow` marker as well.
+"""
+import numpy as np
+import pytest
+
+from oracle import Oracle
+from paper_1803_07822_amd import synth
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+torch = pytest.importorskip("torch")
+
+W = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
+
+
+def _lbm():
+    from paper_1803_07822_amd import lbm
+
+    return lbm
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _dev_err(a, b):
+    """max |a - b| relative to the largest deviation of b from the weights."""
+    return np.abs(a - b).max() / np.abs(b - W[:, None, None, None]).max()
+
+
+def _compare(S, O, precision, label):
+    r, u = S.moments(cartesian=True)
+    ro, uo = O.moments(cartesian=True)
+    er = np.abs(_np(r) - ro).max()
+    du = np.abs(_np(u) - uo).max()
+    umax = np.abs(uo).max()
+    out = {"rho": er, "u": du / umax, "du": du, "umax": umax}
+    for wall in (0, 1):
+        t = _np(S.wall_force(wall))
+        to = O.wall_force(wall)
+        out[f"F{wall}"] = np.abs(t - to).max() / np.abs(to).max()
+    if precision == "fp64":
+        out["f"] = _dev_err(_np(S.populations()), O.populations())
+    print(label, precision, {k: f"{v:.2e}" for k, v in out.items()}, flush=True)
+    if precision == "fp64":
+        assert out["f"] < 1e-12 and out["rho"] < 1e-13 and out["u"] < 1e-10
+        assert out["F0"] < 1e-12 and out["F1"] < 1e-12
+    else:
+        # FP32: the velocity error has a floor set by the FP32 rounding of the
+        # O(0.1) metric deviations (about 1e-8 per step here), which matters
+        # when the flow itself is only the 1e-4 start-up noise.
+        assert out["rho"] < 2e-6 and out["du"] < 1e-7 + 1e-4 * umax
+        assert out["F0"] < 1e-5 and out["F1"] < 1e-5
+
+
+def _solver(w, precision, disp):
+    lbm = _lbm()
+    S = lbm.Solver(w.nx, w.ny, w.nz, w.tau, precision)
+    S.set_body_force(w.force)
+    S.set_wall_displacement(1, disp)
+    return S
+
+
+def test_c2_bump_full_size():
+    """Three steps of the bench workload from its noisy equilibrium start."""
+    w = synth.workload("c2_bump_256x128x128")
+    uc = synth.uniform_noise_velocity(w.nx, w.ny, w.nz, 1e-4, seed=2)
+    O = Oracle(w.nx, w.ny, w.nz, w.tau)
+    O.set_body_force(w.force)
+    O.set_wall_displacement(1, w.disp())
+    O.init_equilibrium(None, uc)
+    O.step(3)
+    for precision in ("fp64", "fp32"):
+        S = _solver(w, precision, w.disp())
+        S.init_equilibrium(None, uc)
+        S.step(3)
+        _compare(S, O, precision, "256x128x128 bump, 3 steps:")
+        del S
+        torch.cuda.empty_cache()
+
+
+def _c3_loop(S, w, updates, every):
+    """The oscillating-wall time loop: the wall velocity of t = 0, then
+    `updates` times: `every` steps, the metric and wall velocity of the new
+    time with re-projection of the state."""
+
+    def vel(v):
+        out = np.zeros((w.nz, w.nx, 3))
+        out[..., 1] = v
+        return out
+
+    d0, v0 = synth.oscillating_wall(w.nx, w.nz, t=0.0)
+    S.set_wall_displacement(1, d0)
+    S.set_wall_velocity(1, vel(v0))
+    S.init_equilibrium()
+    for u in range(1, updates + 1):
+        S.step(every)
+        d, v = synth.oscillating_wall(w.nx, w.nz, t=float(u * every))
+        S.set_wall_displacement(1, d, reproject=True)
+        S.set_wall_velocity(1, vel(v))
+
+
+def test_c3_oscillating_wall_full_size():
+    """Oscillating wall (A = 0.06*128, T = 2000), metric and wall velocity
+    updated with re-projection every 10 steps: 30 steps, three
+    re-projections, then 5 more steps."""
+    w = synth.workload("c3_oscillating_256x128x128")
+    every = w.extra["update_every"]
+    O = Oracle(w.nx, w.ny, w.nz, w.tau)
+    O.set_body_force(w.force)
+    _c3_loop(O, w, 3, every)
+    O.step(5)
+    for precision in ("fp64", "fp32"):
+        S = _solver(w, precision, np.zeros((w.nz, w.nx)))
+        _c3_loop(S, w, 3, every)
+        S.step(5)
+        _compare(S, O, precision, "256x128x128 oscillating wall, 3 re-projections:")
+        del S
+        torch.cuda.empty_cache()
+
+
+def test_c5_stated_amplitude_trips_guard():
+    """At the stated amplitude 0.08*256 (wall slope up to 1.0) the scheme is
+    unstable: from rest, FP32 and FP64 both trip the instability guard within
+    the first 20 steps (the guard flags the state; every kernel completes)."""
+    lbm = _lbm()
+    w = synth.workload("c5_patch_wave_512x256x256")
+    d, _ = synth.patch_wave(A=w.extra["A_stated"])
+    for precision in ("fp32", "fp64"):
+        S = _solver(w, precision, d)
+        S.init_equilibrium()
+        with pytest.raises(lbm.LBMError) as e:
+            for _ in range(4):
+                S.step(5)
+                S.sync()
+        assert e.value.code == -5
+        del S
+        torch.cuda.empty_cache()
+
+
+def test_c5_patch_wave_full_size_fp32_step():
+    """One FP32 step of the 512x256x256 workload (33.3M fluid nodes) from a
+    perturbed equilibrium: the largest grid, with the default launch shape."""
+    w = synth.workload("c5_patch_wave_512x256x256")
+    d = w.disp()
+    uc = synth.uniform_noise_velocity(w.nx, w.ny, w.nz, 1e-4, seed=7)
+    O = Oracle(w.nx, w.ny, w.nz, w.tau)
+    O.set_body_force(w.force)
+    O.set_wall_displacement(1, d)
+    O.init_equilibrium(None, uc)
+    O.step(1)
+    S = _solver(w, "fp32", d)
+    S.init_equilibrium(None, uc)
+    S.step(1)
+    _compare(S, O, "fp32", "512x256x256 patch wave, 1 step:")
+    del S
+    torch.cuda.empty_cache()
+
+
+def test_c5_adjoint_full_size_against_central_differences():
+    """FP64 adjoint of L = sum_{t=1..100} F_x(t) on the 512x256x256 grid
+    (checkpoint every 10, initial state at rest): the gradient against the
+    top-wall displacement matches central differences (step 1e-6) of the GPU
+    forward on two seeded standard-normal directions."""
+    lbm = _lbm()
+    w = synth.workload("c5_patch_wave_512x256x256")
+    K, N = w.extra["K"], w.extra["ckpt_every"]
+    d = w.disp()
+    torch.cuda.empty_cache()  # the workspace takes about 235 GiB of the 268
+    S = lbm.Solver(w.nx, w.ny, w.nz, w.tau, "fp64", adjoint_K=K, ckpt_every=N)
+    S.set_body_force(w.force)
+    S.set_wall_displacement(1, d)
+    S.init_equilibrium()
+    f0 = S.populations()
+
+    def loss(dv):
+        S.set_wall_displacement(1, dv)
+        lbm.lbm_set_populations(S.ctx, f0)
+        return float(S.forward_record(K)[:, 0].sum().item())
+
+    loss(d)
+    Wt = np.zeros((K, 3))
+    Wt[:, 0] = 1.0
+    gd = _np(S.backward(Wt, need_f0=False)[0])
+    assert np.isfinite(gd).all()
+    rng = np.random.Generator(np.random.PCG64(51))
+    eps = 1e-6
+    errs = []
+    for _ in range(2):
+        v = rng.standard_normal(d.shape)
+        fd = (loss(d + eps * v) - loss(d - eps * v)) / (2 * eps)
+        errs.append(abs(fd - float((gd * v).sum())) / abs(fd))
+    print("512x256x256 adjoint, K=100: FD relative errors", [f"{e:.2e}" for e in errs], flush=True)
+    assert max(errs) < 1e-3, errs

@@ -41,6 +41,8 @@ def parse():
     p.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward timing")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--fp64-steps", type=int, default=None)
+    p.add_argument("--no-extra", action="store_true",
+                   help="skip the oscillating-wall loop and the 512x256x256 runs")
     p.add_argument("--counters", action="store_true",
                    help="no timing: a 256 MiB calibration copy, then --steps FP32 steps, for rocprofv3 --pmc runs")
     return p.parse_args()
@@ -133,6 +135,126 @@ def adjoint_ratio(repeats=3):
     f, b = sum(fwd) / len(fwd), sum(bwd) / len(bwd)
     return {"workload": w.name, "K": K, "ckpt_every": N, "forward_ms": round(f, 3), "backward_ms": round(b, 3),
             "ratio": round(b / f, 3), "forward_mlups": round(w.fluid_nodes * K / (f * 1e-3) / 1e6, 1)}
+
+
+def c3_loop():
+    """The oscillating-wall workload in FP32: 4000 steps, the metric and wall
+    velocity updated with re-projection every 10 steps, the top-wall force
+    recorded every step into device memory.  GPU time per phase from events
+    on the library's stream, and the host wall time of the whole loop."""
+    import numpy as np
+    import torch
+
+    from paper_1803_07822_amd import lbm, synth
+
+    w = synth.workload("c3_oscillating_256x128x128")
+    every, steps = w.extra["update_every"], w.steps
+    S = lbm.Solver(w.nx, w.ny, w.nz, w.tau, "fp32")
+    S.set_body_force(w.force)
+
+    def wall(t):
+        d, v = synth.oscillating_wall(w.nx, w.nz, t=float(t))
+        vc = np.zeros((w.nz, w.nx, 3))
+        vc[..., 1] = v
+        return torch.as_tensor(d, device=S.device), torch.as_tensor(vc, device=S.device)
+
+    d, vc = wall(0)
+    lbm.lbm_set_wall_displacement(S.ctx, lbm.LBM_WALL_YMAX, d, 0)
+    lbm.lbm_set_wall_velocity(S.ctx, lbm.LBM_WALL_YMAX, vc)
+    S.init_equilibrium()
+    walls = [wall(t) for t in range(every, steps + 1, every)]  # uploaded before timing
+    forces = torch.empty((steps, 3), dtype=torch.float64, device=S.device)
+    nup = steps // every
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(nup)]
+    S.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for u in range(nup):
+        e = ev[u]
+        e[0].record(S.stream)
+        for t in range(u * every, (u + 1) * every):
+            lbm.lbm_step(S.ctx, 1)
+            lbm.lbm_wall_force(S.ctx, lbm.LBM_WALL_YMAX, forces[t])
+        e[1].record(S.stream)
+        d, vc = walls[u]
+        lbm.lbm_set_wall_displacement(S.ctx, lbm.LBM_WALL_YMAX, d, 1)
+        e[2].record(S.stream)
+        lbm.lbm_set_wall_velocity(S.ctx, lbm.LBM_WALL_YMAX, vc)
+        e[3].record(S.stream)
+    S.sync()
+    torch.cuda.synchronize()
+    wall_s = time.perf_counter() - t0
+    step_ms = sum(e[0].elapsed_time(e[1]) for e in ev)
+    rp_ms = sum(e[1].elapsed_time(e[2]) for e in ev)
+    vel_ms = sum(e[2].elapsed_time(e[3]) for e in ev)
+    total_ms = ev[0][0].elapsed_time(ev[-1][3])
+    f = forces.cpu().numpy()
+    res = {"workload": w.name, "precision": "fp32", "steps": steps, "updates": nup,
+           "gpu_ms": round(total_ms, 2), "wall_s": round(wall_s, 3),
+           "mlups_with_updates": round(w.fluid_nodes * steps / (total_ms * 1e-3) / 1e6, 1),
+           "step_and_force_ms_per_step": round(step_ms / steps, 5),
+           "metric_update_and_reprojection_ms": round(rp_ms / nup, 4),
+           "wall_velocity_ms": round(vel_ms / nup, 4),
+           "force_finite": bool(np.isfinite(f).all()), "final_force": [float(x) for x in f[-1]]}
+    del S
+    torch.cuda.empty_cache()
+    return res
+
+
+def c5_runs(steps=200):
+    """The 512x256x256 patch-wave workload (33.3M fluid nodes, run amplitude
+    0.04*256): FP32 step throughput over `steps` steps from the equilibrium
+    start, then the FP64 adjoint over K = 100 with a checkpoint every 10
+    (about 235 GiB of workspace): forward-record and backward times."""
+    import torch
+
+    from paper_1803_07822_amd import lbm, synth
+
+    w = synth.workload("c5_patch_wave_512x256x256")
+    out = {"workload": w.name, "amplitude": w.extra["A_run"]}
+    S = lbm.Solver(w.nx, w.ny, w.nz, w.tau, "fp32")
+    S.set_body_force(w.force)
+    S.set_wall_displacement(lbm.LBM_WALL_YMAX, w.disp())
+    S.init_equilibrium()
+    S.step(5)
+    S.sync()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(S.stream)
+    S.step(steps)
+    e1.record(S.stream)
+    S.sync()
+    ms = e0.elapsed_time(e1) / steps
+    out["fp32"] = {"steps": steps, "ms_per_step": round(ms, 5), "mlups": round(w.fluid_nodes / (ms * 1e-3) / 1e6, 1),
+                   "effective_GBps": round(w.fluid_nodes * BYTES_PER_LUP["fp32"] / (ms * 1e-3) / 1e9, 1),
+                   "launch": dict(zip(("zchunk", "variant", "stage"), lbm.lbm_get_tuning(S.ctx)))}
+    del S
+    torch.cuda.empty_cache()
+    K, N = w.extra["K"], w.extra["ckpt_every"]
+    try:
+        S = lbm.Solver(w.nx, w.ny, w.nz, w.tau, "fp64", adjoint_K=K, ckpt_every=N)
+        S.set_body_force(w.force)
+        S.set_wall_displacement(lbm.LBM_WALL_YMAX, w.disp())
+        S.init_equilibrium()
+        Wt = torch.zeros((K, 3), dtype=torch.float64, device=S.device)
+        Wt[:, 0] = 1.0
+        gd = torch.empty((w.nz, w.nx), dtype=torch.float64, device=S.device)
+        forces = torch.empty((K, 3), dtype=torch.float64, device=S.device)
+        S.sync()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        ev[0].record(S.stream)
+        lbm.lbm_forward_record(S.ctx, K, N, lbm.LBM_WALL_YMAX, forces)
+        ev[1].record(S.stream)
+        lbm.lbm_backward(S.ctx, Wt, gd, None, None)
+        ev[2].record(S.stream)
+        S.sync()
+        f, b = ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])
+        out["adjoint"] = {"K": K, "ckpt_every": N, "forward_ms": round(f, 2), "backward_ms": round(b, 2),
+                          "ratio": round(b / f, 3), "grad_finite": bool(torch.isfinite(gd).all().item())}
+        del S
+    except (RuntimeError, lbm.LBMError) as e:  # e.g. not enough device memory for the workspace
+        out["adjoint"] = {"error": str(e)[:200]}
+    torch.cuda.empty_cache()
+    return out
 
 
 def cpu_baseline(w, budget_s):
@@ -304,6 +426,9 @@ def main():
     if not a.no_adjoint:
         out["adjoint"] = adjoint_ratio()
         out["adjoint_forward_ratio"] = out["adjoint"]["ratio"]
+    if not a.no_extra:
+        out["c3_time_varying_metric"] = c3_loop()
+        out["c5_at_scale"] = c5_runs()
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, a.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -162,26 +162,36 @@ __global__ __launch_bounds__(BX * BY) void k_adj_node(Grid g, int mode, const do
   const bool with_old = mode == 0;
   NodeFwd o;
   node_fwd(f, Fp, G, dj, tau, with_old, o);
+  double fsb[Q], Fb[Q], cb[10];
   // transposed streaming: f*_l(x) went to x + c_l (or bounced back into
   // direction opp(l) at x); F_l(x)/2 was added to f_l(x, t+1).
-  auto fsb = [&](auto L) {
+  for_q([&](auto L) {
     constexpr int l = decltype(L)::value;
     constexpr int x = cx(l), y = cy(l), z = cz(l);
-    const int jd = p.jf + y;
-    if (jd >= 0 && jd < g.H) return lfn[l * g.N + nidx(g, wrapa(p.i + x, g.nx), jd, wrapa(p.k + z, g.nz))];
-    return lfn[opp(l) * g.N + p.n];
-  };
-  auto fbin = [&](auto L) { return with_old ? 0.5 * lfn[decltype(L)::value * g.N + p.n] : 0.0; };
-  auto emit = [&](auto L, double v) { lfd[decltype(L)::value * g.N + p.n] = v; };
-  double cb[10];
+    fsb[l] = 0;
+    Fb[l] = 0;
+    if (with_old) {
+      const int jd = p.jf + y;
+      if (jd >= 0 && jd < g.H)
+        fsb[l] = lfn[l * g.N + nidx(g, wrapa(p.i + x, g.nx), jd, wrapa(p.k + z, g.nz))];
+      else
+        fsb[l] = lfn[opp(l) * g.N + p.n];
+      Fb[l] = 0.5 * lfn[l * g.N + p.n];
+    }
+  });
 #pragma unroll
   for (int q = 0; q < 10; ++q) cb[q] = lpn[q * g.N + p.n];
-  double rb = 0, jb[3] = {0, 0, 0}, djb[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, Fpb[10];
+  double fb[Q], rb = 0, jb[3] = {0, 0, 0}, djb[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, Fpb[10];
+  for_q([&](auto L) { fb[decltype(L)::value] = 0; });
 #pragma unroll
   for (int q = 0; q < 10; ++q) Fpb[q] = 0;
   AGeoBar gb;
   zero_bar(gb);
-  node_vjp(Fp, G, tau, with_old, o, fsb, fbin, cb, nullptr, emit, rb, jb, djb, Fpb, gb);
+  node_vjp(Fp, G, tau, with_old, o, fsb, Fb, cb, nullptr, fb, rb, jb, djb, Fpb, gb);
+  for_q([&](auto L) {
+    constexpr int l = decltype(L)::value;
+    lfd[l * g.N + p.n] = fb[l];
+  });
   lml[p.n] = rb;
 #pragma unroll
   for (int a = 0; a < 3; ++a) lml[(1 + a) * g.N + p.n] = jb[a];
@@ -276,14 +286,16 @@ __global__ __launch_bounds__(BX * BY) void k_adj_force(Grid g, int wall, const d
     sgb += sgn * wj * o.T[sym(i, 1)];
     for (int a = 0; a < 3; ++a) lj[(a * 3 + i) * g.N + p.n] += sgn * G.sg * W[a] * o.T[sym(i, 1)];
   }
-  const double cb[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  double fsb[Q], Fb[Q], cb[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   double fb[Q], rb = 0, jb[3] = {0, 0, 0}, djb[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, Fpb[10];
-  auto zero = [](auto) { return 0.0; };
-  auto emit = [&](auto L, double v) { fb[decltype(L)::value] = v; };
+  for_q([&](auto L) {
+    constexpr int l = decltype(L)::value;
+    fsb[l] = Fb[l] = fb[l] = 0;
+  });
   AGeoBar gb;
   zero_bar(gb);
   gb.sg = sgb;
-  node_vjp(Fp, G, tau, false, o, zero, zero, cb, Tb, emit, rb, jb, djb, Fpb, gb);
+  node_vjp(Fp, G, tau, false, o, fsb, Fb, cb, Tb, fb, rb, jb, djb, Fpb, gb);
   moments_vjp(G.sg, o.S0, o.S1, rb, jb, fb, gb.sg);
   for_q([&](auto L) {
     constexpr int l = decltype(L)::value;

@@ -193,19 +193,16 @@ __device__ __forceinline__ void node_fwd(const double f[Q], const double Fp[10],
   }
 }
 
-// VJP of one node.  Inputs, per direction (called with the direction as a
-// compile-time constant): fsb(l) = adjoint of f*_l (with_old only; called
-// twice), fbin(l) = adjoint of F_l added to what flows from f* (called
-// once); cb = adjoint of the new coefficients (A, B, C), Tbin = adjoint of T
-// (or null).  Outputs: emit(l, v) receives the direct adjoint of f_l
-// (through ne and f*) once per direction; rb/jb = adjoint of rho and j
-// (local uses), djb = adjoint of dj, Fpb = adjoint of the old coefficients
-// and gb = geometry adjoint are accumulated.
-template <class FS, class FB, class EMIT>
+// VJP of one node.  Inputs: fsb = adjoint of f* (with_old only), Fbin =
+// adjoint of F (added to what flows from f*), cb = adjoint of the new
+// coefficients (A, B, C), Tbin = adjoint of T (or null).  Outputs
+// (accumulated): fb = direct adjoint of f (through ne and f*), rb/jb =
+// adjoint of rho and j (local uses), djb = adjoint of dj, Fpb = adjoint of
+// the old coefficients, gb = geometry adjoint.
 __device__ __forceinline__ void node_vjp(const double Fp[10], const AGeo& G, double tau, bool with_old,
-                                         const NodeFwd& o, const FS& fsb, const FB& fbin, const double cb[10],
-                                         const double* Tbin, const EMIT& emit, double& rb, double jb[3],
-                                         double djb[3][3], double Fpb[10], AGeoBar& gb) {
+                                         const NodeFwd& o, const double fsb[Q], const double Fbin[Q],
+                                         const double cb[10], const double* Tbin, double fb[Q], double& rb,
+                                         double jb[3], double djb[3][3], double Fpb[10], AGeoBar& gb) {
   const double th = 1.0 / 3.0, itau = 1.0 / tau, kap = 1.0 - 0.5 / tau;
   // f* = f - ne/tau + F - Fo/2: basis sums of the adjoints of Fo and F
   HSum hFo, hF;
@@ -213,9 +210,9 @@ __device__ __forceinline__ void node_vjp(const double Fp[10], const AGeo& G, dou
   hsum_zero(hF);
   for_q([&](auto L) {
     constexpr int l = decltype(L)::value;
-    const double s = with_old ? fsb(L) : 0.0;
+    const double s = with_old ? fsb[l] : 0.0;
     hsum_add<l>(hFo, -0.5 * s);
-    hsum_add<l>(hF, s + fbin(L));
+    hsum_add<l>(hF, s + Fbin[l]);
   });
   // F(t-1) = H(Fp) -> old coefficients
   if (with_old) {
@@ -336,7 +333,7 @@ __device__ __forceinline__ void node_vjp(const double Fp[10], const AGeo& G, dou
   for_q([&](auto L) {
     constexpr int l = decltype(L)::value;
     constexpr int x = cx(l), y = cy(l), z = cz(l);
-    const double s = with_old ? fsb(L) : 0.0;
+    const double s = with_old ? fsb[l] : 0.0;
     double neb = -s * itau;
     if (x) neb += Pb[0];
     if (y) neb += Pb[3];
@@ -344,7 +341,7 @@ __device__ __forceinline__ void node_vjp(const double Fp[10], const AGeo& G, dou
     if (x && y) neb += (x * y) * Pb[1];
     if (x && z) neb += (x * z) * Pb[2];
     if (y && z) neb += (y * z) * Pb[4];
-    emit(L, s + neb);
+    fb[l] += s + neb;
     hsum_add<l>(hfeq, -neb);
   });
   // feq = H(rho, j, a2)

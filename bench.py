@@ -43,6 +43,9 @@ def parse():
     p.add_argument("--fp64-steps", type=int, default=None)
     p.add_argument("--no-extra", action="store_true",
                    help="skip the oscillating-wall loop and the 512x256x256 runs")
+    p.add_argument("--part", choices=["all", "adjoint", "c3", "c5"], default="all",
+                   help="run one measurement alone (for profiling): the 128x64x64 adjoint, the oscillating-wall "
+                        "loop or the 512x256x256 runs; prints that part's JSON only")
     p.add_argument("--counters", action="store_true",
                    help="no timing: a 256 MiB calibration copy, then --steps FP32 steps, for rocprofv3 --pmc runs")
     return p.parse_args()
@@ -369,6 +372,10 @@ def main():
     w = synth.workload(a.workload)
     if a.counters:
         counter_run(w, a.steps)
+        return
+    if a.part != "all":
+        part = {"adjoint": adjoint_ratio, "c3": c3_loop, "c5": c5_runs}[a.part]()
+        print(json.dumps({"part": a.part, **part}), flush=True)
         return
     N = w.fluid_nodes
     res = {}

@@ -80,60 +80,148 @@ __global__ __launch_bounds__(BX * BY) void k_uext(Grid g, const double* __restri
   }
 }
 
-// out = in - (c_s^2/2) L in = in - sum_l w_l (in(x+c_l) - in(x)) on layers [jlo, jhi]
-__global__ __launch_bounds__(BX * BY) void k_smooth(Grid g, int ncomp, int jlo, int jhi, const double* __restrict__ in, double* __restrict__ out) {
-  const int i = blockIdx.x * BX + threadIdx.x, je = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
-  const int j = je - 3;
-  if (i >= g.nx || j < jlo || j > jhi) return;
+// ------------------------------------------------ plane-marching stencils
+// The three stencil passes of the precompute (smoothing, J and g, the metric
+// derivatives with the fluid-node geometry) read the 18 lattice neighbours
+// of every node.  A block owns a 64 x 4 tile of (x, layer) and marches along a
+// chunk of z-planes; the input components of three consecutive planes of the
+// tile plus a one-node halo sit in an LDS ring, so each input value is read
+// from memory about once per pass.
+constexpr int MX = BX + 2, MY = BY + 2, MN = MX * MY;
+constexpr int MZC = 16;  // planes per block
+
+struct March {
+  int i0, j0, z0, z1;  // tile origin (x, layer) and z range
+  int tx, ty;          // thread position in the tile
+};
+
+__device__ __forceinline__ bool march_setup(const Grid& g, int jlo, int jhi, March& m) {
+  m.i0 = blockIdx.x * BX;
+  m.j0 = jlo + blockIdx.y * BY;
+  m.z0 = blockIdx.z * MZC;
+  m.z1 = min(m.z0 + MZC, g.nz);
+  m.tx = threadIdx.x;
+  m.ty = threadIdx.y;
+  return m.j0 <= jhi;  // uniform per block
+}
+
+// Plane k (wrapped) of NC components into one ring slot; layers outside the
+// extended grid are never read by an output inside [jlo, jhi].
+template <int NC>
+__device__ __forceinline__ void march_load(const Grid& g, const March& m, int k, const double* __restrict__ in,
+                                           double (*slot)[MN]) {
+  k = wrap(k, g.nz);
   const long long NE = (long long)g.nz * (g.ny + 6) * g.nx;
-  const long long e = eidx(g, i, j, k);
-  for (int c = 0; c < ncomp; ++c) {
-    const double* f = in + c * NE;
-    const double f0 = f[e];
-    double s = 0.0;
-    for_q([&](auto L) {
-      constexpr int l = decltype(L)::value;
-      if (l == 0) return;
-      s += wgt(l) * (f[eidx(g, wrap(i + cx(l), g.nx), j + cy(l), wrap(k + cz(l), g.nz))] - f0);
-    });
-    out[c * NE + e] = f0 - s;
+  for (int e = m.ty * BX + m.tx; e < MN; e += BX * BY) {
+    const int hx = e % MX, hy = e / MX;
+    const int i = wrap(m.i0 - 1 + hx, g.nx), j = m.j0 - 1 + hy;
+    if (m.i0 - 1 + hx > g.nx || j < -3 || j > g.ny + 2) continue;
+    const long long p = eidx(g, i, j, k);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) slot[c][e] = in[c * NE + p];
+  }
+}
+
+// G_i f = 3 sum_l w_l c_l^i f(x + c_l) of component c at the tile node, from
+// the ring (planes k-1, k, k+1 in slots sm, s0, sp).
+template <int NC>
+__device__ __forceinline__ void march_grad(const double (*sm)[MN], const double (*s0)[MN], const double (*sp)[MN],
+                                           int e0, int c, double d[3]) {
+  double s0x = 0, s1 = 0, s2 = 0;
+  for_q([&](auto L) {
+    constexpr int l = decltype(L)::value;
+    if (l == 0) return;
+    constexpr int x = cx(l), y = cy(l), z = cz(l);
+    const double(*sl)[MN] = z < 0 ? sm : (z > 0 ? sp : s0);
+    const double fv = sl[c][e0 + y * MX + x];
+    if (x) s0x += wgt(l) * x * fv;
+    if (y) s1 += wgt(l) * y * fv;
+    if (z) s2 += wgt(l) * z * fv;
+  });
+  d[0] = 3.0 * s0x;
+  d[1] = 3.0 * s1;
+  d[2] = 3.0 * s2;
+}
+
+// out = in - (c_s^2/2) L in = in - sum_l w_l (in(x+c_l) - in(x)) on layers [jlo, jhi]
+template <int NC>
+__global__ __launch_bounds__(BX * BY) void k_smooth(Grid g, int jlo, int jhi, const double* __restrict__ in,
+                                                    double* __restrict__ out) {
+  __shared__ double ring[3][NC][MN];
+  March m;
+  if (!march_setup(g, jlo, jhi, m)) return;
+  const long long NE = (long long)g.nz * (g.ny + 6) * g.nx;
+  const int i = m.i0 + m.tx, j = m.j0 + m.ty;
+  const bool act = i < g.nx && j <= jhi;
+  const int e0 = (m.ty + 1) * MX + (m.tx + 1);
+  march_load<NC>(g, m, m.z0 - 1, in, ring[(m.z0 + 2) % 3]);
+  march_load<NC>(g, m, m.z0, in, ring[m.z0 % 3]);
+  for (int k = m.z0; k < m.z1; ++k) {
+    march_load<NC>(g, m, k + 1, in, ring[(k + 1) % 3]);
+    __syncthreads();
+    if (act) {
+      const double(*sm)[MN] = ring[(k + 2) % 3];
+      const double(*s0)[MN] = ring[k % 3];
+      const double(*sp)[MN] = ring[(k + 1) % 3];
+      const long long p = eidx(g, i, j, k);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const double f0 = s0[c][e0];
+        double s = 0.0;
+        for_q([&](auto L) {
+          constexpr int l = decltype(L)::value;
+          if (l == 0) return;
+          constexpr int x = cx(l), y = cy(l), z = cz(l);
+          const double(*sl)[MN] = z < 0 ? sm : (z > 0 ? sp : s0);
+          s += wgt(l) * (sl[c][e0 + y * MX + x] - f0);
+        });
+        out[c * NE + p] = f0 - s;
+      }
+    }
+    __syncthreads();
   }
 }
 
 // J = I + G v and g = J^T J on layers [-1, ny]; J also stored at fluid nodes.
-__global__ __launch_bounds__(BX * BY) void k_jac_metric(Grid g, const double* __restrict__ v, double* __restrict__ gext, double* __restrict__ jac) {
-  const int i = blockIdx.x * BX + threadIdx.x, je = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
-  const int j = je - 3;
-  if (i >= g.nx || j < -1 || j > g.ny) return;
+__global__ __launch_bounds__(BX * BY) void k_jac_metric(Grid g, const double* __restrict__ v,
+                                                        double* __restrict__ gext, double* __restrict__ jac) {
+  __shared__ double ring[3][3][MN];
+  const int jlo = -1, jhi = g.ny;
+  March m;
+  if (!march_setup(g, jlo, jhi, m)) return;
   const long long NE = (long long)g.nz * (g.ny + 6) * g.nx;
-  double J[3][3];
+  const int i = m.i0 + m.tx, j = m.j0 + m.ty;
+  const bool act = i < g.nx && j <= jhi;
+  const int e0 = (m.ty + 1) * MX + (m.tx + 1);
+  march_load<3>(g, m, m.z0 - 1, v, ring[(m.z0 + 2) % 3]);
+  march_load<3>(g, m, m.z0, v, ring[m.z0 % 3]);
+  for (int k = m.z0; k < m.z1; ++k) {
+    march_load<3>(g, m, k + 1, v, ring[(k + 1) % 3]);
+    __syncthreads();
+    if (act) {
+      double J[3][3];
 #pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    double s0 = 0, s1 = 0, s2 = 0;
-    for_q([&](auto L) {
-      constexpr int l = decltype(L)::value;
-      if (l == 0) return;
-      const double fv = v[a * NE + eidx(g, wrap(i + cx(l), g.nx), j + cy(l), wrap(k + cz(l), g.nz))];
-      if (cx(l)) s0 += wgt(l) * cx(l) * fv;
-      if (cy(l)) s1 += wgt(l) * cy(l) * fv;
-      if (cz(l)) s2 += wgt(l) * cz(l) * fv;
-    });
-    J[a][0] = (a == 0 ? 1.0 : 0.0) + 3.0 * s0;
-    J[a][1] = (a == 1 ? 1.0 : 0.0) + 3.0 * s1;
-    J[a][2] = (a == 2 ? 1.0 : 0.0) + 3.0 * s2;
-  }
-  const long long e = eidx(g, i, j, k);
+      for (int a = 0; a < 3; ++a) {
+        double d[3];
+        march_grad<3>(ring[(k + 2) % 3], ring[k % 3], ring[(k + 1) % 3], e0, a, d);
 #pragma unroll
-  for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) J[a][b] = (a == b ? 1.0 : 0.0) + d[b];
+      }
+      const long long e = eidx(g, i, j, k);
 #pragma unroll
-    for (int b = a; b < 3; ++b)
-      gext[sym(a, b) * NE + e] = J[0][a] * J[0][b] + J[1][a] * J[1][b] + J[2][a] * J[2][b];
-  if (j >= 1 && j <= g.ny - 2) {
-    const long long n = ((long long)k * g.H + (j - 1)) * g.nx + i;
+      for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
+        for (int b = a; b < 3; ++b)
+          gext[sym(a, b) * NE + e] = J[0][a] * J[0][b] + J[1][a] * J[1][b] + J[2][a] * J[2][b];
+      if (j >= 1 && j <= g.ny - 2) {
+        const long long n = ((long long)k * g.H + (j - 1)) * g.nx + i;
 #pragma unroll
-      for (int b = 0; b < 3; ++b) jac[(a * 3 + b) * g.N + n] = J[a][b];
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+          for (int b = 0; b < 3; ++b) jac[(a * 3 + b) * g.N + n] = J[a][b];
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -141,61 +229,68 @@ __global__ __launch_bounds__(BX * BY) void k_jac_metric(Grid g, const double* __
 // + D_k g_jl - D_l g_jk) with D_l g = G_l w, and F^i = (J^{-1} F_cart)^i.
 template <class T>
 __global__ __launch_bounds__(BX * BY) void k_geo(Grid g, const double* __restrict__ w, const double* __restrict__ gext,
-                      const double* __restrict__ jac, double F0, double F1, double F2, T* __restrict__ geo) {
-  const int i = blockIdx.x * BX + threadIdx.x, jf = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
-  if (i >= g.nx || jf >= g.H) return;
-  const int j = jf + 1;
+                                                 const double* __restrict__ jac, double F0, double F1, double F2,
+                                                 T* __restrict__ geo) {
+  __shared__ double ring[3][6][MN];
+  const int jlo = 1, jhi = g.ny - 2;
+  March m;
+  if (!march_setup(g, jlo, jhi, m)) return;
   const long long NE = (long long)g.nz * (g.ny + 6) * g.nx;
-  const long long n = ((long long)k * g.H + jf) * g.nx + i;
-  const long long e = eidx(g, i, j, k);
-  double gm[3][3], gi[3][3], J[3][3], Ji[3][3], det, detJ;
+  const int i = m.i0 + m.tx, j = m.j0 + m.ty;
+  const bool act = i < g.nx && j <= jhi;
+  const int e0 = (m.ty + 1) * MX + (m.tx + 1);
+  march_load<6>(g, m, m.z0 - 1, w, ring[(m.z0 + 2) % 3]);
+  march_load<6>(g, m, m.z0, w, ring[m.z0 % 3]);
+  for (int k = m.z0; k < m.z1; ++k) {
+    march_load<6>(g, m, k + 1, w, ring[(k + 1) % 3]);
+    __syncthreads();
+    if (act) {
+      const long long n = ((long long)k * g.H + (j - 1)) * g.nx + i;
+      const long long e = eidx(g, i, j, k);
+      double gm[3][3], gi[3][3], J[3][3], Ji[3][3], det, detJ;
 #pragma unroll
-  for (int a = 0; a < 3; ++a)
+      for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int b = 0; b < 3; ++b) {
-      gm[a][b] = gext[sym(a, b) * NE + e];
-      J[a][b] = jac[(a * 3 + b) * g.N + n];
-    }
-  inv3(gm, gi, det);
-  inv3(J, Ji, detJ);
-  // dg[l][q] = D_l g_q
-  double dg[3][6];
+        for (int b = 0; b < 3; ++b) {
+          gm[a][b] = gext[sym(a, b) * NE + e];
+          J[a][b] = jac[(a * 3 + b) * g.N + n];
+        }
+      inv3(gm, gi, det);
+      inv3(J, Ji, detJ);
+      // dg[l][q] = D_l g_q
+      double dg[3][6];
 #pragma unroll
-  for (int q = 0; q < 6; ++q) {
-    double s0 = 0, s1 = 0, s2 = 0;
-    const double* f = w + q * NE;
-    for_q([&](auto L) {
-      constexpr int l = decltype(L)::value;
-      if (l == 0) return;
-      const double fv = f[eidx(g, wrap(i + cx(l), g.nx), j + cy(l), wrap(k + cz(l), g.nz))];
-      if (cx(l)) s0 += wgt(l) * cx(l) * fv;
-      if (cy(l)) s1 += wgt(l) * cy(l) * fv;
-      if (cz(l)) s2 += wgt(l) * cz(l) * fv;
-    });
-    dg[0][q] = 3.0 * s0;
-    dg[1][q] = 3.0 * s1;
-    dg[2][q] = 3.0 * s2;
-  }
-  geo[G_SG * g.N + n] = (T)(detJ - 1.0);
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int b = a; b < 3; ++b) geo[(G_GI + sym(a, b)) * g.N + n] = (T)(gi[a][b] - (a == b ? 1.0 : 0.0));
-#pragma unroll
-  for (int ii = 0; ii < 3; ++ii)
-#pragma unroll
-    for (int jj = 0; jj < 3; ++jj)
-#pragma unroll
-      for (int kk = jj; kk < 3; ++kk) {
-        double s = 0.0;
-#pragma unroll
-        for (int l = 0; l < 3; ++l)
-          s += gi[ii][l] * (dg[jj][sym(kk, l)] + dg[kk][sym(jj, l)] - dg[l][sym(jj, kk)]);
-        geo[(G_GAM + ii * 6 + sym(jj, kk)) * g.N + n] = (T)(0.5 * s);
+      for (int q = 0; q < 6; ++q) {
+        double d[3];
+        march_grad<6>(ring[(k + 2) % 3], ring[k % 3], ring[(k + 1) % 3], e0, q, d);
+        dg[0][q] = d[0];
+        dg[1][q] = d[1];
+        dg[2][q] = d[2];
       }
-  const double Fc[3] = {F0, F1, F2};
+      geo[G_SG * g.N + n] = (T)(detJ - 1.0);
 #pragma unroll
-  for (int a = 0; a < 3; ++a) geo[(G_F + a) * g.N + n] = (T)(Ji[a][0] * Fc[0] + Ji[a][1] * Fc[1] + Ji[a][2] * Fc[2]);
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = a; b < 3; ++b) geo[(G_GI + sym(a, b)) * g.N + n] = (T)(gi[a][b] - (a == b ? 1.0 : 0.0));
+#pragma unroll
+      for (int ii = 0; ii < 3; ++ii)
+#pragma unroll
+        for (int jj = 0; jj < 3; ++jj)
+#pragma unroll
+          for (int kk = jj; kk < 3; ++kk) {
+            double s = 0.0;
+#pragma unroll
+            for (int l = 0; l < 3; ++l)
+              s += gi[ii][l] * (dg[jj][sym(kk, l)] + dg[kk][sym(jj, l)] - dg[l][sym(jj, kk)]);
+            geo[(G_GAM + ii * 6 + sym(jj, kk)) * g.N + n] = (T)(0.5 * s);
+          }
+      const double Fc[3] = {F0, F1, F2};
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+        geo[(G_F + a) * g.N + n] = (T)(Ji[a][0] * Fc[0] + Ji[a][1] * Fc[1] + Ji[a][2] * Fc[2]);
+    }
+    __syncthreads();
+  }
 }
 
 template <class T>
@@ -248,11 +343,15 @@ template <class T> hipError_t launch_geometry(Fields& F, hipStream_t s, const do
   const Grid g = F.g;
   dim3 b(BX, BY);
   double* u = F.uext[F.uext_cur];
+  // marching grid: x tiles, layer tiles of [jlo, jhi], z chunks
+  auto mg = [&](int jlo, int jhi) {
+    return dim3((g.nx + BX - 1) / BX, (jhi - jlo + BY) / BY, (g.nz + MZC - 1) / MZC);
+  };
   hipLaunchKernelGGL(k_uext, ext_grid(g), b, 0, s, g, F.chart, u);
-  hipLaunchKernelGGL(k_smooth, ext_grid(g), b, 0, s, g, 3, -2, g.ny + 1, u, F.vtmp);
-  hipLaunchKernelGGL(k_jac_metric, ext_grid(g), b, 0, s, g, F.vtmp, F.gext, F.jac);
-  hipLaunchKernelGGL(k_smooth, ext_grid(g), b, 0, s, g, 6, 0, g.ny - 1, F.gext, F.wext);
-  hipLaunchKernelGGL(k_geo<T>, fluid_grid(g), b, 0, s, g, F.wext, F.gext, F.jac, Fc[0], Fc[1], Fc[2], (T*)F.geo);
+  hipLaunchKernelGGL(k_smooth<3>, mg(-2, g.ny + 1), b, 0, s, g, -2, g.ny + 1, u, F.vtmp);
+  hipLaunchKernelGGL(k_jac_metric, mg(-1, g.ny), b, 0, s, g, F.vtmp, F.gext, F.jac);
+  hipLaunchKernelGGL(k_smooth<6>, mg(0, g.ny - 1), b, 0, s, g, 0, g.ny - 1, F.gext, F.wext);
+  hipLaunchKernelGGL(k_geo<T>, mg(1, g.ny - 2), b, 0, s, g, F.wext, F.gext, F.jac, Fc[0], Fc[1], Fc[2], (T*)F.geo);
   return hipGetLastError();
 }
 

@@ -63,6 +63,27 @@ inline dim3 fluid_grid(const Grid& g) { return dim3((g.nx + BX - 1) / BX, (g.H +
 inline dim3 ext_grid(const Grid& g) { return dim3((g.nx + BX - 1) / BX, (g.ny + 6 + BY - 1) / BY, g.nz); }
 inline dim3 col_grid(const Grid& g) { return dim3((g.nx + BX - 1) / BX, (g.nz + BY - 1) / BY, 1); }
 
+// XCD-aware numbering of the fluid-grid blocks (64 x 4 tiles, one z-plane
+// each).  The hardware deals blocks round-robin over the 8 XCDs; with a 1D
+// launch padded to a multiple of 8 blocks, each XCD takes a contiguous range
+// of tiles in x-fastest order (a slab of z-planes), so the neighbour rows and
+// planes a node reads sit in the same L2.
+inline dim3 xcd_fluid_grid(const Grid& g) {
+  const long long nb = (long long)((g.nx + BX - 1) / BX) * ((g.H + BY - 1) / BY) * g.nz;
+  return dim3((unsigned)((nb + 7) / 8 * 8));
+}
+
+__device__ __forceinline__ bool xcd_fluid_node(const Grid& g, int& i, int& jf, int& k) {
+  const int ntx = (g.nx + BX - 1) / BX, nty = (g.H + BY - 1) / BY;
+  const int nb = ntx * nty * g.nz, per = (nb + 7) / 8;
+  const int t = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+  if (t >= nb) return false;
+  i = (t % ntx) * BX + threadIdx.x;
+  jf = ((t / ntx) % nty) * BY + threadIdx.y;
+  k = t / (ntx * nty);
+  return i < g.nx && jf < g.H;
+}
+
 // geometry (FP64 precompute; writes geo in precision T)
 template <class T> hipError_t launch_geometry(Fields& F, hipStream_t s, const double Fc[3]);
 template <class T> hipError_t launch_body_force(Fields& F, hipStream_t s, const double Fc[3]);

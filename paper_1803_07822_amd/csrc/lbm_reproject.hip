@@ -17,9 +17,53 @@ namespace lbm {
 
 namespace {
 
+// a mod n for any a; the common case (within one period) without a division.
 __device__ __forceinline__ int wrapr(int a, int n) {
+  if (a >= 0 && a < n) return a;
+  if (a < 0 && a >= -n) return a + n;
+  if (a >= n && a < 2 * n) return a - n;
   a %= n;
   return a < 0 ? a + n : a;
+}
+
+// The 8 corners of the trilinear cell with base (bx, by, bz) in a periodic
+// (x, z) grid of `layers` y-layers (row y stored at y + yoff), and the
+// fractional position in the cell.
+struct Cell {
+  unsigned e[8];  // element offsets (grids stay below 2^32 elements per field)
+  double fr[3];
+};
+
+__device__ __forceinline__ void cell_setup(const Grid& g, int layers, int yoff, int bx, int by, int bz,
+                                           const double fr[3], Cell& c) {
+  const int x0 = wrapr(bx, g.nx), x1 = wrapr(bx + 1, g.nx);
+  const int z0 = wrapr(bz, g.nz), z1 = wrapr(bz + 1, g.nz);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int ox = q & 1, oy = (q >> 1) & 1, oz = (q >> 2) & 1;
+    c.e[q] = ((unsigned)(oz ? z1 : z0) * layers + (unsigned)(by + oy + yoff)) * (unsigned)g.nx + (ox ? x1 : x0);
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) c.fr[a] = fr[a];
+}
+
+// Trilinear value of F in the cell and its gradient in cell coordinates.
+__device__ __forceinline__ double cell_eval(const Cell& c, const double* __restrict__ F, double grad[3]) {
+  double v = 0.0;
+  grad[0] = grad[1] = grad[2] = 0.0;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int ox = q & 1, oy = (q >> 1) & 1, oz = (q >> 2) & 1;
+    const double wx = ox ? c.fr[0] : 1.0 - c.fr[0];
+    const double wy = oy ? c.fr[1] : 1.0 - c.fr[1];
+    const double wz = oz ? c.fr[2] : 1.0 - c.fr[2];
+    const double fv = F[c.e[q]];
+    v += wx * wy * wz * fv;
+    grad[0] += (ox ? 1.0 : -1.0) * wy * wz * fv;
+    grad[1] += wx * (oy ? 1.0 : -1.0) * wz * fv;
+    grad[2] += wx * wy * (oz ? 1.0 : -1.0) * fv;
+  }
+  return v;
 }
 
 constexpr int NMF = 20;  // 0 rho, 1-3 j, 4-9 Pi, 10 A, 11-13 B, 14-19 C (Cartesian)
@@ -28,15 +72,16 @@ __device__ __forceinline__ void inv3d(const double m[3][3], double r[3][3]) {
   const double det = m[0][0] * (m[1][1] * m[2][2] - m[1][2] * m[2][1]) -
                      m[0][1] * (m[1][0] * m[2][2] - m[1][2] * m[2][0]) +
                      m[0][2] * (m[1][0] * m[2][1] - m[1][1] * m[2][0]);
-  r[0][0] = (m[1][1] * m[2][2] - m[1][2] * m[2][1]) / det;
-  r[0][1] = (m[0][2] * m[2][1] - m[0][1] * m[2][2]) / det;
-  r[0][2] = (m[0][1] * m[1][2] - m[0][2] * m[1][1]) / det;
-  r[1][0] = (m[1][2] * m[2][0] - m[1][0] * m[2][2]) / det;
-  r[1][1] = (m[0][0] * m[2][2] - m[0][2] * m[2][0]) / det;
-  r[1][2] = (m[0][2] * m[1][0] - m[0][0] * m[1][2]) / det;
-  r[2][0] = (m[1][0] * m[2][1] - m[1][1] * m[2][0]) / det;
-  r[2][1] = (m[0][1] * m[2][0] - m[0][0] * m[2][1]) / det;
-  r[2][2] = (m[0][0] * m[1][1] - m[0][1] * m[1][0]) / det;
+  const double idet = 1.0 / det;
+  r[0][0] = (m[1][1] * m[2][2] - m[1][2] * m[2][1]) * idet;
+  r[0][1] = (m[0][2] * m[2][1] - m[0][1] * m[2][2]) * idet;
+  r[0][2] = (m[0][1] * m[1][2] - m[0][2] * m[1][1]) * idet;
+  r[1][0] = (m[1][2] * m[2][0] - m[1][0] * m[2][2]) * idet;
+  r[1][1] = (m[0][0] * m[2][2] - m[0][2] * m[2][0]) * idet;
+  r[1][2] = (m[0][2] * m[1][0] - m[0][0] * m[1][2]) * idet;
+  r[2][0] = (m[1][0] * m[2][1] - m[1][1] * m[2][0]) * idet;
+  r[2][1] = (m[0][1] * m[2][0] - m[0][0] * m[2][1]) * idet;
+  r[2][2] = (m[0][0] * m[1][1] - m[0][1] * m[1][0]) * idet;
 }
 
 template <class T, int l>
@@ -52,8 +97,8 @@ __device__ __forceinline__ T pull_rp(const T* __restrict__ pop, const Grid& g, i
 template <class T>
 __global__ __launch_bounds__(BX * BY) void k_rp_moments(Grid g, const T* __restrict__ pop, const T* __restrict__ hist, const T* __restrict__ geo,
                              const double* __restrict__ jac, double* __restrict__ mf) {
-  const int i = blockIdx.x * BX + threadIdx.x, jf = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
-  if (i >= g.nx || jf >= g.H) return;
+  int i, jf, k;
+  if (!xcd_fluid_node(g, i, jf, k)) return;
   const long long n = ((long long)k * g.H + jf) * g.nx + i;
   const long long NC = (long long)g.nz * g.ny * g.nx;
   const long long e = ((long long)k * g.ny + (jf + 1)) * g.nx + i;
@@ -144,39 +189,14 @@ __global__ __launch_bounds__(BX * BY) void k_rp_ghost(Grid g, const double* __re
 }
 
 // Trilinear value and gradient of an extended-grid field (layers -3..ny+2).
-__device__ __forceinline__ double trilin_ext(const Grid& g, const double* __restrict__ F, const double p[3],
-                                             double grad[3]) {
-  const int bx = (int)floor(p[0]), bz = (int)floor(p[2]);
-  int by = (int)floor(p[1]);
-  if (by < -3) by = -3;
-  if (by > g.ny + 1) by = g.ny + 1;
-  const double fr[3] = {p[0] - bx, p[1] - by, p[2] - bz};
-  double v = 0.0;
-  grad[0] = grad[1] = grad[2] = 0.0;
-#pragma unroll
-  for (int c = 0; c < 8; ++c) {
-    const int ox = c & 1, oy = (c >> 1) & 1, oz = (c >> 2) & 1;
-    const double wx = ox ? fr[0] : 1.0 - fr[0];
-    const double wy = oy ? fr[1] : 1.0 - fr[1];
-    const double wz = oz ? fr[2] : 1.0 - fr[2];
-    const double fv =
-        F[((long long)wrapr(bz + oz, g.nz) * (g.ny + 6) + (by + oy + 3)) * g.nx + wrapr(bx + ox, g.nx)];
-    v += wx * wy * wz * fv;
-    grad[0] += (ox ? 1.0 : -1.0) * wy * wz * fv;
-    grad[1] += wx * (oy ? 1.0 : -1.0) * wz * fv;
-    grad[2] += wx * wy * (oz ? 1.0 : -1.0) * fv;
-  }
-  return v;
-}
-
 // New state at the new fluid nodes; writes the streamed deviations g~ (FP64)
 // and the new history.
 template <class T>
 __global__ __launch_bounds__(BX * BY) void k_rp_new(Grid g, const double* __restrict__ chart, const double* __restrict__ uold,
                          const double* __restrict__ mf, const double* __restrict__ jac, const T* __restrict__ geo,
-                         double* __restrict__ gs, T* __restrict__ hist) {
-  const int i = blockIdx.x * BX + threadIdx.x, jf = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
-  if (i >= g.nx || jf >= g.H) return;
+                         T* __restrict__ pop, T* __restrict__ hist) {
+  int i, jf, k;
+  if (!xcd_fluid_node(g, i, jf, k)) return;
   const long long n = ((long long)k * g.H + jf) * g.nx + i;
   const long long NC = (long long)g.nz * g.ny * g.nx, NE = (long long)g.nz * (g.ny + 6) * g.nx;
   const long long pc = ((long long)k * g.ny + (jf + 1)) * g.nx + i;
@@ -185,10 +205,18 @@ __global__ __launch_bounds__(BX * BY) void k_rp_new(Grid g, const double* __rest
   double xi[3] = {(double)i, (double)(jf + 1), (double)k};
   for (int it = 0; it < 50; ++it) {
     double r[3], Jm[3][3], Ji[3][3];
+    // cell of the extended grid (layers -3 .. ny+2) holding xi
+    const int bx = (int)floor(xi[0]), bz = (int)floor(xi[2]);
+    int by = (int)floor(xi[1]);
+    if (by < -3) by = -3;
+    if (by > g.ny + 1) by = g.ny + 1;
+    const double fr[3] = {xi[0] - bx, xi[1] - by, xi[2] - bz};
+    Cell c;
+    cell_setup(g, g.ny + 6, 3, bx, by, bz, fr, c);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       double gr[3];
-      r[a] = xi[a] + trilin_ext(g, uold + a * NE, xi, gr) - p[a];
+      r[a] = xi[a] + cell_eval(c, uold + a * NE, gr) - p[a];
 #pragma unroll
       for (int b = 0; b < 3; ++b) Jm[a][b] = (a == b ? 1.0 : 0.0) + gr[b];
     }
@@ -210,17 +238,18 @@ __global__ __launch_bounds__(BX * BY) void k_rp_new(Grid g, const double* __rest
   int by = (int)floor(q1);
   if (by > g.ny - 2) by = g.ny - 2;
   if (by < 0) by = 0;
-  const double fx = xi[0] - bx, fy = q1 - by, fz = xi[2] - bz;
+  const double fr[3] = {xi[0] - bx, q1 - by, xi[2] - bz};
+  Cell cl;
+  cell_setup(g, g.ny, 0, bx, by, bz, fr, cl);
   double m[NMF];
 #pragma unroll
   for (int q = 0; q < NMF; ++q) m[q] = 0.0;
 #pragma unroll
   for (int c = 0; c < 8; ++c) {
     const int ox = c & 1, oy = (c >> 1) & 1, oz = (c >> 2) & 1;
-    const double w = (ox ? fx : 1.0 - fx) * (oy ? fy : 1.0 - fy) * (oz ? fz : 1.0 - fz);
-    const long long e = ((long long)wrapr(bz + oz, g.nz) * g.ny + (by + oy)) * g.nx + wrapr(bx + ox, g.nx);
+    const double w = (ox ? fr[0] : 1.0 - fr[0]) * (oy ? fr[1] : 1.0 - fr[1]) * (oz ? fr[2] : 1.0 - fr[2]);
 #pragma unroll
-    for (int q = 0; q < NMF; ++q) m[q] += w * mf[q * NC + e];
+    for (int q = 0; q < NMF; ++q) m[q] += w * mf[q * NC + cl.e[c]];
   }
   // pull back with the new J^{-1}
   double J[3][3], Ji[3][3];
@@ -277,32 +306,22 @@ __global__ __launch_bounds__(BX * BY) void k_rp_new(Grid g, const double* __rest
   // f~ - w = (w/sqrt g)[rho + 3 j.c + 4.5 a2:cc - 1.5 tr a2] - w
   const double sg = 1.0 + (double)sgd;
   const double a0 = m[0] - sg;  // (rho/sqrt g - 1) sqrt g
-  for_q([&](auto L) {
-    constexpr int l = decltype(L)::value;
-    const double fdev = wgt(l) / sg * hermite_term<double, l>(a0, jt, a2);
-    gs[(long long)l * g.N + n] = fdev - 0.5 * (double)Fp[l];
-  });
-}
-
-// pop[l][y] = g~_l(y + c_l) if fluid, else g~_opp(l)(y)
-template <class T>
-__global__ __launch_bounds__(BX * BY) void k_rp_unpull(Grid g, const double* __restrict__ gs, T* __restrict__ pop) {
-  const int i = blockIdx.x * BX + threadIdx.x, jf = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
-  if (i >= g.nx || jf >= g.H) return;
-  const long long n = ((long long)k * g.H + jf) * g.nx + i;
+  // Store g~_l = f~_l - F_l/2 in the pull layout: at x - c_l when that node
+  // is fluid, else (a link through the wall) in the bounce-back slot opp(l)
+  // of this node.  Every slot of the layout has exactly one writer.
   for_q([&](auto L) {
     constexpr int l = decltype(L)::value;
     constexpr int x = cx(l), y = cy(l), z = cz(l);
-    const int jd = jf + y;
-    double v;
-    if (jd < 0 || jd >= g.H) {
-      v = gs[(long long)opp(l) * g.N + n];
+    const double fdev = wgt(l) / sg * hermite_term<double, l>(a0, jt, a2);
+    const T v = (T)(fdev - 0.5 * (double)Fp[l]);
+    const int js = jf - y;
+    if (js < 0 || js >= g.H) {
+      pop[(long long)opp(l) * g.N + n] = v;
     } else {
-      const int id = x ? wrapr(i + x, g.nx) : i;
-      const int kd = z ? wrapr(k + z, g.nz) : k;
-      v = gs[(long long)l * g.N + ((long long)kd * g.H + jd) * g.nx + id];
+      const int is = x ? wrapr(i - x, g.nx) : i;
+      const int ks = z ? wrapr(k - z, g.nz) : k;
+      pop[(long long)l * g.N + ((long long)ks * g.H + js) * g.nx + is] = v;
     }
-    pop[(long long)l * g.N + n] = (T)v;
   });
 }
 
@@ -314,16 +333,16 @@ template <class T> hipError_t launch_reproject(Fields& F, hipStream_t s, const d
   (void)tau;
   const Grid g = F.g;
   dim3 b(BX, BY);
-  hipLaunchKernelGGL(k_rp_moments<T>, fluid_grid(g), b, 0, s, g, (const T*)F.pop[F.cur], (const T*)F.hist[F.cur],
+  hipLaunchKernelGGL(k_rp_moments<T>, xcd_fluid_grid(g), b, 0, s, g, (const T*)F.pop[F.cur], (const T*)F.hist[F.cur],
                      (const T*)F.geo, (const double*)F.jac, F.mf);
   hipLaunchKernelGGL(k_rp_ghost, col_grid(g), b, 0, s, g, (const double*)F.vwall, F.mf);
   const int old = F.uext_cur;
   F.uext_cur ^= 1;
   hipError_t e = launch_geometry<T>(F, s, Fc);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_rp_new<T>, fluid_grid(g), b, 0, s, g, (const double*)F.chart, (const double*)F.uext[old],
-                     (const double*)F.mf, (const double*)F.jac, (const T*)F.geo, F.full, (T*)F.hist[F.cur]);
-  hipLaunchKernelGGL(k_rp_unpull<T>, fluid_grid(g), b, 0, s, g, (const double*)F.full, (T*)F.pop[F.cur]);
+  hipLaunchKernelGGL(k_rp_new<T>, xcd_fluid_grid(g), b, 0, s, g, (const double*)F.chart, (const double*)F.uext[old],
+                     (const double*)F.mf, (const double*)F.jac, (const T*)F.geo, (T*)F.pop[F.cur],
+                     (T*)F.hist[F.cur]);
   return hipGetLastError();
 }
 

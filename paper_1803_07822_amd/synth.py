@@ -137,6 +137,30 @@ def patch_wave(nx=512, nz=256, A=0.08 * 256, t=0.0, x0=192, z0=64, L=128, lam=12
     return A * np.sin(ph) * win, -A * np.cos(ph) * win * (2 * np.pi / T)
 
 
+def taylor_green_chart(nx: int, ny: int, nz: int, eps: float, eta: float, t: float) -> np.ndarray:
+    """Time-dependent diagonal chart for the Taylor-Green vortex in the
+    periodic (x, z) plane (Sec. V.A): x_c = xi_x + eps sin(2 pi xi_x/nx - eta t),
+    z_c = xi_z + eps sin(2 pi xi_z/nz - eta t), y_c = xi_y.  Its metric is
+    diag((1 + d_x h'^x)^2, 1, (1 + d_z h'^z)^2)."""
+    ch = identity_chart(nx, ny, nz)
+    ch[0] += eps * np.sin(2 * np.pi * ch[0] / nx - eta * t)
+    ch[2] += eps * np.sin(2 * np.pi * ch[2] / nz - eta * t)
+    return ch
+
+
+def taylor_green_velocity(chart: np.ndarray, v0: float) -> np.ndarray:
+    """Initial Taylor-Green velocity (Cartesian components) at the fluid nodes
+    of a chart: u_x = v0 sin(k x_c) cos(k z_c), u_z = -v0 cos(k x_c) sin(k z_c),
+    u_y = 0, k = 2 pi / L for the periodic lengths L = nx = nz."""
+    nx, nz = chart.shape[3], chart.shape[1]
+    xc, zc = chart[0][:, 1:-1, :], chart[2][:, 1:-1, :]
+    kx, kz = 2 * np.pi / nx, 2 * np.pi / nz
+    u = np.zeros((3,) + xc.shape)
+    u[0] = v0 * np.sin(kx * xc) * np.cos(kz * zc)
+    u[2] = -v0 * np.cos(kx * xc) * np.sin(kz * zc)
+    return u
+
+
 # --------------------------------------------------------- initial fields
 def uniform_noise_velocity(nx, ny, nz, amp=1e-4, seed=2):
     rng = np.random.Generator(np.random.PCG64(seed))

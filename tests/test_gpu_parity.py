@@ -88,12 +88,16 @@ def _random_state(O, nz, H, nx, seed):
 @pytest.mark.parametrize("shape,variant,zc,stage", [((70, 12, 9), 0, 0, -1), ((64, 8, 4), 0, 0, -1),
                                                     ((7, 5, 3), 0, 0, -1), ((70, 12, 9), 1, 0, -1),
                                                     ((70, 12, 9), 2, 3, -1), ((70, 12, 9), 3, 4, -1),
-                                                    ((33, 9, 11), 0, 5, -1), ((70, 12, 9), 0, 4, 1)])
+                                                    ((33, 9, 11), 0, 5, -1), ((70, 12, 9), 0, 4, 1),
+                                                    ((1, 4, 1), 0, 0, -1), ((1, 6, 5), 1, 0, -1),
+                                                    ((3, 4, 2), 0, 1, -1), ((65, 4, 1), 2, 0, -1)])
 def test_step_parity_fp64(shape, variant, zc, stage):
     """Curved chart, body force, moving walls, non-equilibrium start: the GPU
     state matches the oracle population by population after 1 and 12 steps;
     history, moments and wall forces too.  Shapes span several 64x4 tiles with
-    ragged edges in x and y."""
+    ragged edges in x and y, and the degenerate grids: a single column
+    (nx = nz = 1, every neighbour is the node itself), the thinnest channel
+    (two fluid layers, both next to a wall) and a single z-plane."""
     nx, ny, nz = shape
     H = ny - 2
     vt = np.zeros((nz, nx, 3))

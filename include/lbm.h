@@ -85,7 +85,7 @@ enum {
 /* Bytes of device workspace a context needs.  adjoint_K > 0 reserves the
  * trajectory storage of lbm_forward_record/lbm_backward for K steps with a
  * checkpoint every ckpt_every steps (ckpt_every in 1..K).  Returns 0 for an
- * invalid grid (nx, nz >= 1, ny >= 4, nx*(ny-2)*nz < 2^29 fluid nodes) or
+ * invalid grid (nx, nz >= 1, ny >= 4, nx*(ny-2)*nz < 2^28 fluid nodes) or
  * lattice. */
 size_t lbm_workspace_bytes(const lbm_grid* h_grid, int lattice, int precision, int adjoint_K,
                            int ckpt_every);

@@ -35,9 +35,9 @@ namespace {
 using lbm::ALIGN;
 using lbm::Carver;
 
-// The step kernels address one population plane with 32-bit byte offsets:
-// fluid nodes * 8 bytes must stay below 4 GiB.
-constexpr long long MAX_FLUID_NODES = 1LL << 29;
+// The step kernels address a pair of population planes from one base with
+// 32-bit byte offsets: 2 * fluid nodes * 8 bytes must stay below 4 GiB.
+constexpr long long MAX_FLUID_NODES = 1LL << 28;
 
 bool grid_ok(const lbm_grid* g) {
   if (!g || g->nx < 1 || g->nz < 1 || g->ny < 4) return false;

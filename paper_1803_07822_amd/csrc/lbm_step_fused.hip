@@ -62,21 +62,32 @@ template <class T> __device__ __forceinline__ const T& at(const T* __restrict__ 
 }
 // Streaming store: the step's outputs are not read again within the step.
 template <class T> __device__ __forceinline__ void stw(T* __restrict__ base, unsigned e, T v) {
-  __builtin_nontemporal_store(v, (T*)((char*)base + (e * (unsigned)sizeof(T))));
+  __builtin_nontemporal_store(v, base + (size_t)e);
 }
 
 // Pulled deviation g~_l: the population that left x - c_l in direction l,
 // or the bounce-back slot opp(l) of this node when x - c_l is a wall node.
+// Both candidate planes (l and opp(l)) are addressed from the lower of the
+// two as one uniform base, so the per-lane choice is a choice of 32-bit
+// offset and every load keeps the scalar-base form.
 template <class T, int l>
 __device__ __forceinline__ T pullf(const T* __restrict__ pop, const Grid& g, const NodeIdx& p) {
   constexpr int x = cx(l), y = cy(l), z = cz(l);
-  if ((y > 0 && p.jf == 0) || (y < 0 && p.jf == g.H - 1)) return at(pop + (size_t)opp(l) * g.N, p.n);
+  constexpr int lo = l < opp(l) ? l : opp(l);
+  const T* base = pop + (size_t)lo * g.N;
   int off = -y * g.nx;
   if (x > 0) off += p.oxm;
   if (x < 0) off += p.oxp;
   if (z > 0) off += p.ozm;
   if (z < 0) off += p.ozp;
-  return at(pop + (size_t)l * g.N, (unsigned)((int)p.n + off));
+  const unsigned e = (unsigned)(l - lo) * (unsigned)g.N + (unsigned)((int)p.n + off);
+  if constexpr (y == 0) {
+    return at(base, e);
+  } else {
+    const bool wall = y > 0 ? p.jf == 0 : p.jf == g.H - 1;
+    const unsigned eb = (unsigned)(opp(l) - lo) * (unsigned)g.N + p.n;
+    return at(base, wall ? eb : e);
+  }
 }
 
 template <class T> __device__ __forceinline__ T fld(const T* __restrict__ a, int q, const Grid& g, unsigned n) {
@@ -84,7 +95,8 @@ template <class T> __device__ __forceinline__ T fld(const T* __restrict__ a, int
 }
 // Streaming load of a field read once per step.
 template <class T> __device__ __forceinline__ T fldnt(const T* __restrict__ a, int q, const Grid& g, unsigned n) {
-  return __builtin_nontemporal_load((const T*)((const char*)(a + (size_t)q * g.N) + n * (unsigned)sizeof(T)));
+  const T* plane = a + (size_t)q * g.N;
+  return __builtin_nontemporal_load(plane + (size_t)n);
 }
 
 // Discards the pulled deviations of a node.

@@ -44,9 +44,9 @@ def test_workspace_bytes():
     assert b32 > 4 * N * (2 * 19 + 10 + 28 + 4)
     assert lbm.lbm_workspace_bytes(8, 3, 8) == 0  # too few layers
     assert lbm.lbm_workspace_bytes(0, 8, 8) == 0
-    # 32-bit plane offsets: 2^29 fluid nodes and above are refused
-    assert lbm.lbm_workspace_bytes(1024, 2 + 512, 1024) == 0
-    assert lbm.lbm_workspace_bytes(1024, 2 + 511, 1024) > 0
+    # 32-bit offsets over a pair of FP64 planes: 2^28 fluid nodes and above are refused
+    assert lbm.lbm_workspace_bytes(1024, 2 + 256, 1024) == 0
+    assert lbm.lbm_workspace_bytes(1024, 2 + 255, 1024) > 0
     assert lbm.lbm_workspace_bytes(8, 8, 8, lbm.LBM_FP64, 10, 11) == 0  # ckpt_every > K
     adj = lbm.lbm_workspace_bytes(16, 10, 8, lbm.LBM_FP64, 20, 5)
     assert adj > lbm.lbm_workspace_bytes(16, 10, 8, lbm.LBM_FP64)

@@ -334,6 +334,32 @@ def copy_rate():
     return round(r, 1)
 
 
+def stream_floor(n, precision, reps=10):
+    """Time of lbm_stream_probe over n nodes: the step's 57 read and 29
+    written planes as pure streams, no arithmetic (ms per launch)."""
+    import torch
+
+    from paper_1803_07822_amd import lbm
+
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    a = torch.zeros(57 * n, dtype=dt, device="cuda")
+    b = torch.empty(29 * n, dtype=dt, device="cuda")
+    st = torch.cuda.current_stream()
+    code = lbm.LBM_FP64 if precision == "fp64" else lbm.LBM_FP32_DEV
+    for _ in range(3):
+        lbm.lbm_stream_probe(code, n, a, b, st.cuda_stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        lbm.lbm_stream_probe(code, n, a, b, st.cuda_stream)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return ms
+
+
 def counter_run(w, steps):
     """What the HBM counters are read over: a device-to-device copy of
     256 MiB into a fresh buffer (calibrates FETCH_SIZE and WRITE_SIZE against
@@ -428,8 +454,14 @@ def main():
         },
         "fp32_effective_GBps": round(f32["eff_gbps"], 1),
         "device_copy_GBps": copy_rate(),
+        "stream_floor": {},
         "adjoint_forward_ratio": None,
     }
+    for prec in ("fp32", "fp64"):
+        fm = stream_floor(N, prec)
+        out["stream_floor"][prec] = {
+            "ms": round(fm, 5), "GBps": round(N * BYTES_PER_LUP[prec] / (fm * 1e-3) / 1e9, 1),
+            "step_over_floor": round(res[prec]["ms"] / fm, 3)}
     if not a.no_adjoint:
         out["adjoint"] = adjoint_ratio()
         out["adjoint_forward_ratio"] = out["adjoint"]["ratio"]

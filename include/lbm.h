@@ -195,6 +195,16 @@ int lbm_set_tuning(lbm_ctx* ctx, int zchunk, int variant, int stage);
  * that actually runs (0 in FP64).  EINVAL for a null pointer. */
 int lbm_get_tuning(lbm_ctx* ctx, int* zchunk, int* variant, int* stage);
 
+/* Bandwidth calibration, no context: enqueue on hip_stream one kernel that
+ * reads 57 planes of n elements from d_in ([57][n]) and writes 29 planes to
+ * d_out ([29][n]) with streaming loads and stores, one element per thread:
+ * the memory traffic of one fused step over n nodes (populations, history
+ * and geometry read; populations and history written) without its
+ * arithmetic.  Elements are double for LBM_FP64, float for LBM_FP32_DEV.
+ * The caller times it (e.g. with events on the stream).  EINVAL for n < 1,
+ * n >= 2^28, null buffers or another precision; EHIP if the launch fails. */
+int lbm_stream_probe(int precision, long long n, const void* d_in, void* d_out, void* hip_stream);
+
 /* Wait for the stream and check the instability guard. */
 int lbm_sync(lbm_ctx* ctx);
 

@@ -396,6 +396,15 @@ int lbm_get_tuning(lbm_ctx* c, int* zchunk, int* variant, int* stage) {
   return LBM_OK;
 }
 
+int lbm_stream_probe(int precision, long long n, const void* d_in, void* d_out, void* hip_stream) {
+  if (n < 1 || n >= MAX_FLUID_NODES || !d_in || !d_out || (precision != LBM_FP64 && precision != LBM_FP32_DEV))
+    return LBM_EINVAL;
+  return lbm::launch_stream_probe(precision == LBM_FP64 ? 0 : 1, n, d_in, d_out, (hipStream_t)hip_stream) ==
+                 hipSuccess
+             ? LBM_OK
+             : LBM_EHIP;
+}
+
 int lbm_sync(lbm_ctx* c) {
   LBM_GUARD(c);
   LBM_HIP(c, hipStreamSynchronize(c->stream));

@@ -84,6 +84,9 @@ __device__ __forceinline__ bool xcd_fluid_node(const Grid& g, int& i, int& jf, i
   return i < g.nx && jf < g.H;
 }
 
+// bandwidth calibration: 57 planes of n read, 29 written (precision 0 = FP64)
+hipError_t launch_stream_probe(int precision, long long n, const void* in, void* out, hipStream_t s);
+
 // geometry (FP64 precompute; writes geo in precision T)
 template <class T> hipError_t launch_geometry(Fields& F, hipStream_t s, const double Fc[3]);
 template <class T> hipError_t launch_body_force(Fields& F, hipStream_t s, const double Fc[3]);

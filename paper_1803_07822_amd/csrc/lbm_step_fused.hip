@@ -3,9 +3,9 @@
 // A block owns a TX x TY tile of the (x, y) plane and marches along a chunk of
 // ZC planes in z.  The lattice gradient d_k(rho u^i) needs the momentum of all
 // 18 neighbours before any collision, so the block keeps the moments
-// (rho - 1, rho u) of three consecutive planes of its tile plus a one-node
-// halo in an LDS ring: at plane z it forms the moments of plane z+1, then
-// collides plane z.  In FP32 each thread keeps the 19 pulled populations of
+// (rho - 1, rho u) of consecutive planes of its tile plus a one-node halo in
+// an LDS ring: at plane z it forms the moments of plane z+1, then collides
+// plane z (which reads planes z-1, z, z+1).  In FP32 each thread keeps the 19 pulled populations of
 // its own node in registers from the moment pass to the collision one
 // iteration later; in FP64 (no register room) the collision pulls them again,
 // from the caches.  The halo entries are pulled by the block as well, and
@@ -214,7 +214,12 @@ __global__ __launch_bounds__(Tile<TY>::NT) void k_step_fused(Grid g, int ntx, in
                                                    const T* __restrict__ uw, int mv0, int mv1, T tau,
                                                    int* __restrict__ flag) {
   constexpr int HN = Tile<TY>::HN;
-  __shared__ T ring[3][4][HN];
+  // Four ring slots: the fill of plane k+1 overwrites plane k-3, whose last
+  // reader (the collision of plane k-2) every thread has finished before
+  // passing the barrier of the previous iteration, so one barrier per plane
+  // suffices and waves of a block may drift by a plane.
+  __shared__ T ring[4][4][HN];
+  auto rslot = [](int k) { return (k + 4) & 3; };
   // XCD-aware tile order: hardware deals blocks round-robin over 8 XCDs;
   // give each XCD a contiguous range of tiles.
   const int nb = ntx * nty * nzc;
@@ -241,24 +246,24 @@ __global__ __launch_bounds__(Tile<TY>::NT) void k_step_fused(Grid g, int ntx, in
   auto to_next = [&](auto L, T v) {
     if (own) nxt[decltype(L)::value] = v;
   };
-  fill_plane<T, TY>(ring[(z0 + 2) % 3], pin, hist, geo, uw, mv0, mv1, g, i0, j0, z0 - 1);
+  fill_plane<T, TY>(ring[rslot(z0 - 1)], pin, hist, geo, uw, mv0, mv1, g, i0, j0, z0 - 1);
   if constexpr (STAGE == STAGE_NONE)
-    fill_plane<T, TY>(ring[z0 % 3], pin, hist, geo, uw, mv0, mv1, g, i0, j0, z0);
+    fill_plane<T, TY>(ring[rslot(z0)], pin, hist, geo, uw, mv0, mv1, g, i0, j0, z0);
   else
-    fill_plane_staged<T, TY>(ring[z0 % 3], pin, hist, geo, uw, mv0, mv1, g, i0, j0, z0, tx, ty, to_cur);
+    fill_plane_staged<T, TY>(ring[rslot(z0)], pin, hist, geo, uw, mv0, mv1, g, i0, j0, z0, tx, ty, to_cur);
   const T itau = T(1) / tau;
   for (int k = z0; k < z1; ++k) {
     own = active && k + 1 < z1;
     if constexpr (STAGE == STAGE_NONE)
-      fill_plane<T, TY>(ring[(k + 1) % 3], pin, hist, geo, uw, mv0, mv1, g, i0, j0, k + 1);
+      fill_plane<T, TY>(ring[rslot(k + 1)], pin, hist, geo, uw, mv0, mv1, g, i0, j0, k + 1);
     else
-      fill_plane_staged<T, TY>(ring[(k + 1) % 3], pin, hist, geo, uw, mv0, mv1, g, i0, j0, k + 1, tx, ty, to_next);
+      fill_plane_staged<T, TY>(ring[rslot(k + 1)], pin, hist, geo, uw, mv0, mv1, g, i0, j0, k + 1, tx, ty, to_next);
     __syncthreads();
     if (active) {
       const NodeIdx p = node_idx(g, i, jf, k);
       const unsigned n = p.n;
       const int c0 = (ty + 1) * HX + (tx + 1);
-      const T(*rc)[HN] = ring[k % 3];
+      const T(*rc)[HN] = ring[rslot(k)];
       const T dr = rc[0][c0];
       const T j[3] = {rc[1][c0], rc[2][c0], rc[3][c0]};
       // lattice gradient from the ring
@@ -271,7 +276,7 @@ __global__ __launch_bounds__(Tile<TY>::NT) void k_step_fused(Grid g, int ntx, in
         constexpr int l = decltype(L)::value;
         if (l == 0) return;
         constexpr int x = cx(l), y = cy(l), z = cz(l);
-        const T(*rs)[HN] = ring[(k + 3 + z) % 3];
+        const T(*rs)[HN] = ring[rslot(k + z)];
         const int e = (ty + 1 + y) * HX + (tx + 1 + x);
         constexpr T f = T(3.0 * wgt(l));
 #pragma unroll
@@ -377,7 +382,6 @@ __global__ __launch_bounds__(Tile<TY>::NT) void k_step_fused(Grid g, int ntx, in
       const T uu = j[0] * j[0] + j[1] * j[1] + j[2] * j[2];
       if (!(rho > T(0)) || !(uu < T(0.1) * rho * rho) || !isfinite(chk)) atomicOr(flag, 1);
     }
-    __syncthreads();
     if constexpr (STAGE == STAGE_REG)
       if (own)
         for_q([&](auto L) {

@@ -34,7 +34,7 @@ SYMBOLS = [
     "lbm_workspace_bytes", "lbm_create", "lbm_reserve_adjoint", "lbm_destroy", "lbm_set_body_force",
     "lbm_set_metric", "lbm_set_wall_displacement", "lbm_set_wall_velocity", "lbm_init_equilibrium",
     "lbm_set_populations", "lbm_get_populations", "lbm_get_history", "lbm_get_geometry", "lbm_step",
-    "lbm_step_profiled", "lbm_set_tuning", "lbm_get_tuning", "lbm_moments", "lbm_wall_force", "lbm_forward_record", "lbm_backward", "lbm_sync", "lbm_last_error",
+    "lbm_step_profiled", "lbm_set_tuning", "lbm_get_tuning", "lbm_stream_probe", "lbm_moments", "lbm_wall_force", "lbm_forward_record", "lbm_backward", "lbm_sync", "lbm_last_error",
 ]
 
 
@@ -62,6 +62,7 @@ _lib.lbm_get_geometry.argtypes = [_P, _P, _P]
 _lib.lbm_step.argtypes = [_P, _I]
 _lib.lbm_step_profiled.argtypes = [_P, _I, ctypes.POINTER(ctypes.c_double), _I]
 _lib.lbm_set_tuning.argtypes = [_P, _I, _I, _I]
+_lib.lbm_stream_probe.argtypes = [_I, ctypes.c_longlong, _P, _P, _P]
 _lib.lbm_get_tuning.argtypes = [_P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                 ctypes.POINTER(ctypes.c_int)]
 _lib.lbm_moments.argtypes = [_P, _P, _P, _I]
@@ -178,6 +179,21 @@ def lbm_step_profiled(ctx, n, nslots=4):
 
 def lbm_set_tuning(ctx, zchunk=0, variant=0, stage=-1):
     return _check(ctx, _lib.lbm_set_tuning(ctx, int(zchunk), int(variant), int(stage)))
+
+
+def lbm_stream_probe(precision, n, d_in, d_out, stream):
+    """Bandwidth calibration kernel (see include/lbm.h); no context.  d_in
+    ([57 n]) and d_out ([29 n]) are contiguous GPU tensors of float64 for
+    LBM_FP64, float32 for LBM_FP32_DEV."""
+    dt = torch.float64 if precision == LBM_FP64 else torch.float32
+    for t, m in ((d_in, 57), (d_out, 29)):
+        if not (t.is_cuda and t.is_contiguous() and t.dtype == dt and t.numel() >= m * n):
+            raise ValueError("probe buffers must be contiguous GPU tensors of the precision's type and size")
+    rc = _lib.lbm_stream_probe(int(precision), int(n), ctypes.c_void_p(d_in.data_ptr()),
+                               ctypes.c_void_p(d_out.data_ptr()), ctypes.c_void_p(stream))
+    if rc != 0:
+        raise LBMError(rc, "lbm_stream_probe")
+    return rc
 
 
 def lbm_get_tuning(ctx):

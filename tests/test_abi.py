@@ -80,3 +80,12 @@ def test_oracle_library_is_separate():
     assert os.path.dirname(oracle.lib_path()) != os.path.dirname(lbm.LIB_PATH)
     lib = ctypes.CDLL(oracle.lib_path())
     assert not hasattr(lib, "lbm_step")
+
+
+def test_stream_probe_argument_errors():
+    """The calibration entry point rejects bad arguments before any device call."""
+    from paper_1803_07822_amd import lbm
+
+    for args in ((lbm.LBM_FP32_DEV, 0), (lbm.LBM_FP32_DEV, -5), (7, 100), (lbm.LBM_FP64, 1 << 28)):
+        assert lbm._lib.lbm_stream_probe(args[0], args[1], None, None, None) == -1
+

@@ -157,6 +157,23 @@ int lbm_moments(lbm_ctx* ctx, double* d_rho, double* d_u, int cartesian);
  * or NULL).  Only LBM_FORCE_STRESS is provided. */
 int lbm_wall_force(lbm_ctx* ctx, int wall, int method, double* d_total3, double* d_per_node);
 
+/* One coupling interval with an external structural solver (Sec. IV.A: the
+ * fluid receives the wall's position and velocity, the structure receives
+ * the traction).  In order, on the context's stream:
+ *   - d_disp != NULL: the wall's new displacement [nz][nx]; the state is
+ *     re-projected onto the new chart (as lbm_set_wall_displacement with
+ *     reproject = 1); NULL keeps the shape;
+ *   - the wall's Cartesian velocity d_vcart [nz][nx][3] (NULL = at rest);
+ *   - n steps;
+ *   - the force of the fluid on the wall at the resulting state into
+ *     d_total3 (3 doubles) and, if d_per_node != NULL, per column
+ *     [nz][nx][3] (as lbm_wall_force with LBM_FORCE_STRESS).
+ * Asynchronous.  EINVAL for a bad wall, n < 0 or d_total3 NULL; ESTATE
+ * before a state exists; errors of the composed calls are returned as they
+ * occur. */
+int lbm_couple(lbm_ctx* ctx, int wall, const double* d_disp, const double* d_vcart, int n, double* d_total3,
+               double* d_per_node);
+
 /* Run K steps from the current state and record the force on `wall` at
  * states 1..K into d_forces [K][3]; the initial state and a checkpoint every
  * ckpt_every steps are kept for lbm_backward.  K and ckpt_every must match

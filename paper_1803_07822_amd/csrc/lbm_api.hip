@@ -439,6 +439,21 @@ int lbm_wall_force(lbm_ctx* c, int wall, int method, double* d_total3, double* d
   return LBM_OK;
 }
 
+int lbm_couple(lbm_ctx* c, int wall, const double* d_disp, const double* d_vcart, int n, double* d_total3,
+               double* d_per_node) {
+  LBM_GUARD(c);
+  if (wall != LBM_WALL_YMIN && wall != LBM_WALL_YMAX) return fail(c, LBM_EINVAL, "bad wall");
+  if (n < 0) return fail(c, LBM_EINVAL, "negative step count");
+  if (!d_total3) return fail(c, LBM_EINVAL, "total output is NULL");
+  if (!c->have_state) return fail(c, LBM_ESTATE, "no state");
+  int rc = LBM_OK;
+  if (d_disp) rc = lbm_set_wall_displacement(c, wall, d_disp, 1);
+  if (rc == LBM_OK) rc = lbm_set_wall_velocity(c, wall, d_vcart);
+  if (rc == LBM_OK) rc = lbm_step(c, n);
+  if (rc == LBM_OK) rc = lbm_wall_force(c, wall, LBM_FORCE_STRESS, d_total3, d_per_node);
+  return rc;
+}
+
 int lbm_forward_record(lbm_ctx* c, int K, int ckpt_every, int wall, int method, double* d_forces) {
   LBM_GUARD(c);
   if (c->precision != LBM_FP64) return fail(c, LBM_EUNSUPPORTED, "the adjoint needs the FP64 form");

@@ -34,7 +34,7 @@ SYMBOLS = [
     "lbm_workspace_bytes", "lbm_create", "lbm_reserve_adjoint", "lbm_destroy", "lbm_set_body_force",
     "lbm_set_metric", "lbm_set_wall_displacement", "lbm_set_wall_velocity", "lbm_init_equilibrium",
     "lbm_set_populations", "lbm_get_populations", "lbm_get_history", "lbm_get_geometry", "lbm_step",
-    "lbm_step_profiled", "lbm_set_tuning", "lbm_get_tuning", "lbm_stream_probe", "lbm_moments", "lbm_wall_force", "lbm_forward_record", "lbm_backward", "lbm_sync", "lbm_last_error",
+    "lbm_step_profiled", "lbm_set_tuning", "lbm_get_tuning", "lbm_stream_probe", "lbm_moments", "lbm_wall_force", "lbm_couple", "lbm_forward_record", "lbm_backward", "lbm_sync", "lbm_last_error",
 ]
 
 
@@ -211,6 +211,11 @@ def lbm_wall_force(ctx, wall, total, per_node=None, method=LBM_FORCE_STRESS):
     return _check(ctx, _lib.lbm_wall_force(ctx, int(wall), int(method), _ptr(total), _ptr(per_node)))
 
 
+def lbm_couple(ctx, wall, disp, vcart, n, total, per_node=None):
+    return _check(ctx, _lib.lbm_couple(ctx, int(wall), _ptr(disp), _ptr(vcart), int(n), _ptr(total),
+                                       _ptr(per_node)))
+
+
 def lbm_forward_record(ctx, K, ckpt_every, wall, forces, method=LBM_FORCE_STRESS):
     return _check(ctx, _lib.lbm_forward_record(ctx, int(K), int(ckpt_every), int(wall), int(method), _ptr(forces)))
 
@@ -324,6 +329,17 @@ class Solver:
         pn = torch.empty((self.nz, self.nx, 3), dtype=torch.float64, device=self.device) if per_node else None
         lbm_wall_force(self.ctx, wall, tot, pn)
         return (tot, pn) if per_node else tot
+
+    def couple(self, wall, disp, vcart, n):
+        """One coupling interval (lbm_couple): new wall shape (or None),
+        wall velocity (or None = at rest), n steps; returns the total and
+        per-column force of the fluid on the wall."""
+        self._keep = self._dev(disp, (self.nz, self.nx))
+        self._keep_v = self._dev(vcart, (self.nz, self.nx, 3))
+        tot = torch.empty(3, dtype=torch.float64, device=self.device)
+        pn = torch.empty((self.nz, self.nx, 3), dtype=torch.float64, device=self.device)
+        lbm_couple(self.ctx, wall, self._keep, self._keep_v, n, tot, pn)
+        return tot, pn
 
     def sync(self):
         lbm_sync(self.ctx)

@@ -27,20 +27,29 @@ __device__ __forceinline__ int wrapa(int a, int n) { return a < 0 ? a + n : (a >
 
 struct Node {
   int i, jf, k;
-  long long n;
+  unsigned n;  // fluid index (grids stay below 2^28 nodes)
 };
+
+// Element e of plane q of a [planes][N] array: a uniform plane base plus a
+// 32-bit byte offset, so loads and stores keep the scalar-base form.
+__device__ __forceinline__ const double& E(const double* __restrict__ a, long long q, const Grid& g, unsigned e) {
+  return *(const double*)((const char*)(a + (size_t)q * g.N) + e * 8u);
+}
+__device__ __forceinline__ double& E(double* __restrict__ a, long long q, const Grid& g, unsigned e) {
+  return *(double*)((char*)(a + (size_t)q * g.N) + e * 8u);
+}
 
 __device__ __forceinline__ bool fluid_node(const Grid& g, Node& p) {
   p.i = blockIdx.x * BX + threadIdx.x;
   p.jf = blockIdx.y * BY + threadIdx.y;
   p.k = blockIdx.z;
   if (p.i >= g.nx || p.jf >= g.H) return false;
-  p.n = ((long long)p.k * g.H + p.jf) * g.nx + p.i;
+  p.n = ((unsigned)p.k * g.H + p.jf) * g.nx + p.i;
   return true;
 }
 
-__device__ __forceinline__ long long nidx(const Grid& g, int i, int jf, int k) {
-  return ((long long)k * g.H + jf) * g.nx + i;
+__device__ __forceinline__ unsigned nidx(const Grid& g, int i, int jf, int k) {
+  return ((unsigned)k * g.H + jf) * g.nx + i;
 }
 
 // Full populations f(t) = w + pulled deviation + F(t-1)/2 of a stored state.
@@ -48,7 +57,7 @@ __device__ __forceinline__ void load_state(const Grid& g, const double* __restri
                                            const double* __restrict__ hist, const AGeo& G, const Node& p, double f[Q],
                                            double Fp[10]) {
 #pragma unroll
-  for (int q = 0; q < 10; ++q) Fp[q] = hist[q * g.N + p.n];
+  for (int q = 0; q < 10; ++q) Fp[q] = E(hist, q, g, p.n);
   double bp[6];
 #pragma unroll
   for (int q = 0; q < 6; ++q) bp[q] = Fp[4 + q];
@@ -60,22 +69,24 @@ __device__ __forceinline__ void load_state(const Grid& g, const double* __restri
     constexpr int l = decltype(L)::value;
     constexpr int x = cx(l), y = cy(l), z = cz(l);
     double v;
-    if ((y > 0 && p.jf == 0) || (y < 0 && p.jf == g.H - 1))
-      v = pop[opp(l) * g.N + p.n];
-    else
-      v = pop[l * g.N + nidx(g, wrapa(p.i - x, g.nx), p.jf - y, wrapa(p.k - z, g.nz))];
+    // plane l at the source node, or the bounce-back slot opp(l) here: one
+    // uniform base (the lower plane), the choice is an offset
+    constexpr int lo = l < opp(l) ? l : opp(l);
+    const bool wall = (y > 0 && p.jf == 0) || (y < 0 && p.jf == g.H - 1);
+    const unsigned es = nidx(g, wrapa(p.i - x, g.nx), p.jf - y, wrapa(p.k - z, g.nz));
+    v = E(pop, lo, g, wall ? (unsigned)(opp(l) - lo) * (unsigned)g.N + p.n : (unsigned)(l - lo) * (unsigned)g.N + es);
     f[l] = wgt(l) + v + 0.5 * hermite_val<l>(isg, Fp[0], Fp + 1, bp);
   });
 }
 
-__device__ __forceinline__ void load_geo_full(const Grid& g, const double* __restrict__ geo, long long n, AGeo& G) {
-  G.sg = 1.0 + geo[G_SG * g.N + n];
+__device__ __forceinline__ void load_geo_full(const Grid& g, const double* __restrict__ geo, unsigned n, AGeo& G) {
+  G.sg = 1.0 + E(geo, G_SG, g, n);
 #pragma unroll
-  for (int q = 0; q < 6; ++q) G.gi[q] = geo[(G_GI + q) * g.N + n] + ((q == 0 || q == 3 || q == 5) ? 1.0 : 0.0);
+  for (int q = 0; q < 6; ++q) G.gi[q] = E(geo, (G_GI + q), g, n) + ((q == 0 || q == 3 || q == 5) ? 1.0 : 0.0);
 #pragma unroll
-  for (int q = 0; q < 18; ++q) G.gam[q] = geo[(G_GAM + q) * g.N + n];
+  for (int q = 0; q < 18; ++q) G.gam[q] = E(geo, (G_GAM + q), g, n);
 #pragma unroll
-  for (int q = 0; q < 3; ++q) G.F[q] = geo[(G_F + q) * g.N + n];
+  for (int q = 0; q < 3; ++q) G.F[q] = E(geo, (G_F + q), g, n);
 }
 
 // Lattice gradient of the stored moments (walls at rest: ghost j = -j_m).
@@ -92,13 +103,13 @@ __device__ __forceinline__ void gradient_at(const Grid& g, const double* __restr
     const int in = wrapa(p.i + x, g.nx), kn = wrapa(p.k + z, g.nz), jn = p.jf + y;
     double jb[3];
     if (jn >= 0 && jn < g.H) {
-      const long long m = nidx(g, in, jn, kn);
+      const unsigned m = nidx(g, in, jn, kn);
 #pragma unroll
-      for (int b = 0; b < 3; ++b) jb[b] = mom[(1 + b) * g.N + m];
+      for (int b = 0; b < 3; ++b) jb[b] = E(mom, (1 + b), g, m);
     } else {
-      const long long m = nidx(g, in, p.jf, kn);
+      const unsigned m = nidx(g, in, p.jf, kn);
 #pragma unroll
-      for (int b = 0; b < 3; ++b) jb[b] = -mom[(1 + b) * g.N + m];
+      for (int b = 0; b < 3; ++b) jb[b] = -E(mom, (1 + b), g, m);
     }
     constexpr double fct = 3.0 * wgt(l);
 #pragma unroll
@@ -110,11 +121,11 @@ __device__ __forceinline__ void gradient_at(const Grid& g, const double* __restr
   });
 }
 
-__device__ inline void add_geo_bar(const Grid& g, double* __restrict__ lg, long long n, const AGeoBar& gb) {
-  lg[G_SG * g.N + n] += gb.sg;
-  for (int q = 0; q < 6; ++q) lg[(G_GI + q) * g.N + n] += gb.gi[q];
-  for (int q = 0; q < 18; ++q) lg[(G_GAM + q) * g.N + n] += gb.gam[q];
-  for (int q = 0; q < 3; ++q) lg[(G_F + q) * g.N + n] += gb.F[q];
+__device__ inline void add_geo_bar(const Grid& g, double* __restrict__ lg, unsigned n, const AGeoBar& gb) {
+  E(lg, G_SG, g, n) += gb.sg;
+  for (int q = 0; q < 6; ++q) E(lg, (G_GI + q), g, n) += gb.gi[q];
+  for (int q = 0; q < 18; ++q) E(lg, (G_GAM + q), g, n) += gb.gam[q];
+  for (int q = 0; q < 3; ++q) E(lg, (G_F + q), g, n) += gb.F[q];
 }
 
 __device__ inline void zero_bar(AGeoBar& gb) {
@@ -141,8 +152,8 @@ __global__ __launch_bounds__(BX * BY) void k_adj_moments(Grid g, const double* _
     if (cy(l)) j[1] += cy(l) * f[l];
     if (cz(l)) j[2] += cz(l) * f[l];
   });
-  mom[p.n] = G.sg * s;
-  for (int a = 0; a < 3; ++a) mom[(1 + a) * g.N + p.n] = G.sg * j[a];
+  E(mom, 0, g, p.n) = G.sg * s;
+  for (int a = 0; a < 3; ++a) E(mom, (1 + a), g, p.n) = G.sg * j[a];
 }
 
 // Reverse of one step at each node (mode 0), or of the history of an initial
@@ -171,16 +182,17 @@ __global__ __launch_bounds__(BX * BY) void k_adj_node(Grid g, int mode, const do
     fsb[l] = 0;
     Fb[l] = 0;
     if (with_old) {
+      constexpr int lo = l < opp(l) ? l : opp(l);
       const int jd = p.jf + y;
-      if (jd >= 0 && jd < g.H)
-        fsb[l] = lfn[l * g.N + nidx(g, wrapa(p.i + x, g.nx), jd, wrapa(p.k + z, g.nz))];
-      else
-        fsb[l] = lfn[opp(l) * g.N + p.n];
-      Fb[l] = 0.5 * lfn[l * g.N + p.n];
+      const unsigned ed = nidx(g, wrapa(p.i + x, g.nx), jd, wrapa(p.k + z, g.nz));
+      fsb[l] = E(lfn, lo, g,
+                 (jd >= 0 && jd < g.H) ? (unsigned)(l - lo) * (unsigned)g.N + ed
+                                       : (unsigned)(opp(l) - lo) * (unsigned)g.N + p.n);
+      Fb[l] = 0.5 * E(lfn, l, g, p.n);
     }
   });
 #pragma unroll
-  for (int q = 0; q < 10; ++q) cb[q] = lpn[q * g.N + p.n];
+  for (int q = 0; q < 10; ++q) cb[q] = E(lpn, q, g, p.n);
   double fb[Q], rb = 0, jb[3] = {0, 0, 0}, djb[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, Fpb[10];
   for_q([&](auto L) { fb[decltype(L)::value] = 0; });
 #pragma unroll
@@ -190,18 +202,18 @@ __global__ __launch_bounds__(BX * BY) void k_adj_node(Grid g, int mode, const do
   node_vjp(Fp, G, tau, with_old, o, fsb, Fb, cb, nullptr, fb, rb, jb, djb, Fpb, gb);
   for_q([&](auto L) {
     constexpr int l = decltype(L)::value;
-    lfd[l * g.N + p.n] = fb[l];
+    E(lfd, l, g, p.n) = fb[l];
   });
-  lml[p.n] = rb;
+  E(lml, 0, g, p.n) = rb;
 #pragma unroll
-  for (int a = 0; a < 3; ++a) lml[(1 + a) * g.N + p.n] = jb[a];
+  for (int a = 0; a < 3; ++a) E(lml, (1 + a), g, p.n) = jb[a];
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int b = 0; b < 3; ++b) ldj[(a * 3 + b) * g.N + p.n] = djb[a][b];
+    for (int b = 0; b < 3; ++b) E(ldj, (a * 3 + b), g, p.n) = djb[a][b];
   if (lpo)
 #pragma unroll
-    for (int q = 0; q < 10; ++q) lpo[q * g.N + p.n] = Fpb[q];
+    for (int q = 0; q < 10; ++q) E(lpo, q, g, p.n) = Fpb[q];
   add_geo_bar(g, lg, p.n, gb);
 }
 
@@ -214,7 +226,7 @@ __global__ __launch_bounds__(BX * BY) void k_adj_gather(Grid g, const double* __
                              double* __restrict__ lf_out, double* __restrict__ lg) {
   Node p;
   if (!fluid_node(g, p)) return;
-  double rb = lml[p.n], jb[3] = {lml[g.N + p.n], lml[2 * g.N + p.n], lml[3 * g.N + p.n]};
+  double rb = E(lml, 0, g, p.n), jb[3] = {E(lml, 1, g, p.n), E(lml, 2, g, p.n), E(lml, 3, g, p.n)};
   for_q([&](auto L) {
     constexpr int l = decltype(L)::value;
     if (l == 0) return;
@@ -223,33 +235,33 @@ __global__ __launch_bounds__(BX * BY) void k_adj_gather(Grid g, const double* __
     // x_src = p - c_l used this node as its neighbour in direction l
     const int js = p.jf - y;
     if (js >= 0 && js < g.H) {
-      const long long m = nidx(g, wrapa(p.i - x, g.nx), js, wrapa(p.k - z, g.nz));
+      const unsigned m = nidx(g, wrapa(p.i - x, g.nx), js, wrapa(p.k - z, g.nz));
       for (int b = 0; b < 3; ++b)
-        jb[b] += fct * (x * ldj[(0 * 3 + b) * g.N + m] + y * ldj[(1 * 3 + b) * g.N + m] + z * ldj[(2 * 3 + b) * g.N + m]);
+        jb[b] += fct * (x * E(ldj, (0 * 3 + b), g, m) + y * E(ldj, (1 * 3 + b), g, m) + z * E(ldj, (2 * 3 + b), g, m));
     }
     // wall ghost: node m' = p - (c_x, 0, c_z) in this layer, whose neighbour in
     // direction l is solid, used -j(p)
     if ((y < 0 && p.jf == 0) || (y > 0 && p.jf == g.H - 1)) {
-      const long long m = nidx(g, wrapa(p.i - x, g.nx), p.jf, wrapa(p.k - z, g.nz));
+      const unsigned m = nidx(g, wrapa(p.i - x, g.nx), p.jf, wrapa(p.k - z, g.nz));
       for (int b = 0; b < 3; ++b)
-        jb[b] -= fct * (x * ldj[(0 * 3 + b) * g.N + m] + y * ldj[(1 * 3 + b) * g.N + m] + z * ldj[(2 * 3 + b) * g.N + m]);
+        jb[b] -= fct * (x * E(ldj, (0 * 3 + b), g, m) + y * E(ldj, (1 * 3 + b), g, m) + z * E(ldj, (2 * 3 + b), g, m));
     }
   });
-  const double sg = 1.0 + geo[G_SG * g.N + p.n];
-  const double rho = mom[p.n];
-  const double S0 = rho / sg, S1[3] = {mom[g.N + p.n] / sg, mom[2 * g.N + p.n] / sg, mom[3 * g.N + p.n] / sg};
+  const double sg = 1.0 + E(geo, G_SG, g, p.n);
+  const double rho = E(mom, 0, g, p.n);
+  const double S0 = rho / sg, S1[3] = {E(mom, 1, g, p.n) / sg, E(mom, 2, g, p.n) / sg, E(mom, 3, g, p.n) / sg};
   double fb[Q];
   for_q([&](auto L) {
     constexpr int l = decltype(L)::value;
-    fb[l] = lfd[l * g.N + p.n] + (lf_add ? lf_add[l * g.N + p.n] : 0.0);
+    fb[l] = E(lfd, l, g, p.n) + (lf_add ? E(lf_add, l, g, p.n) : 0.0);
   });
   double sgb = 0;
   moments_vjp(sg, S0, S1, rb, jb, fb, sgb);
   for_q([&](auto L) {
     constexpr int l = decltype(L)::value;
-    lf_out[l * g.N + p.n] = fb[l];
+    E(lf_out, l, g, p.n) = fb[l];
   });
-  lg[G_SG * g.N + p.n] += sgb;
+  E(lg, G_SG, g, p.n) += sgb;
 }
 
 // Wall-force VJP at one state: L += sum_a W_a F^a, F^a = sgn sum sqrt g
@@ -275,7 +287,7 @@ __global__ __launch_bounds__(BX * BY) void k_adj_force(Grid g, int wall, const d
   const double sgn = wall == 0 ? -1.0 : 1.0;
   double J[3][3];
   for (int a = 0; a < 3; ++a)
-    for (int b = 0; b < 3; ++b) J[a][b] = jac[(a * 3 + b) * g.N + p.n];
+    for (int b = 0; b < 3; ++b) J[a][b] = E(jac, (a * 3 + b), g, p.n);
   // T^{i y} with y = 1: packed indices sym(i, 1)
   double Tb[6] = {0, 0, 0, 0, 0, 0};
   double sgb = 0;
@@ -284,7 +296,7 @@ __global__ __launch_bounds__(BX * BY) void k_adj_force(Grid g, int wall, const d
     for (int a = 0; a < 3; ++a) wj += W[a] * J[a][i];
     Tb[sym(i, 1)] += sgn * G.sg * wj;
     sgb += sgn * wj * o.T[sym(i, 1)];
-    for (int a = 0; a < 3; ++a) lj[(a * 3 + i) * g.N + p.n] += sgn * G.sg * W[a] * o.T[sym(i, 1)];
+    for (int a = 0; a < 3; ++a) E(lj, (a * 3 + i), g, p.n) += sgn * G.sg * W[a] * o.T[sym(i, 1)];
   }
   double fsb[Q], Fb[Q], cb[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   double fb[Q], rb = 0, jb[3] = {0, 0, 0}, djb[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, Fpb[10];
@@ -299,7 +311,7 @@ __global__ __launch_bounds__(BX * BY) void k_adj_force(Grid g, int wall, const d
   moments_vjp(G.sg, o.S0, o.S1, rb, jb, fb, gb.sg);
   for_q([&](auto L) {
     constexpr int l = decltype(L)::value;
-    lf[l * g.N + p.n] += fb[l];
+    E(lf, l, g, p.n) += fb[l];
   });
   add_geo_bar(g, lg, p.n, gb);
 }

@@ -260,9 +260,21 @@ def c5_runs(steps=200):
     return out
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(w, budget_s):
     """The FP64 oracle on this host's cores: same workload, bounded number of
-    steps (about budget_s seconds of stepping after set-up)."""
+    steps (about budget_s seconds of stepping after set-up) with all cores,
+    then one step on a single thread."""
     import numpy as np
 
     import oracle
@@ -273,6 +285,7 @@ def cpu_baseline(w, budget_s):
     O.set_wall_displacement(1, w.disp())
     O.init_equilibrium(None, synth.uniform_noise_velocity(w.nx, w.ny, w.nz, 1e-4, seed=2))
     O.step(1)  # warm-up
+    cores = oracle.threads()
     n, t = 0, 0.0
     while t < budget_s or n == 0:
         t0 = time.perf_counter()
@@ -280,8 +293,16 @@ def cpu_baseline(w, budget_s):
         t += time.perf_counter() - t0
         n += 1
     mlups = w.fluid_nodes * n / t / 1e6
-    return {"value": round(mlups, 3), "unit": "MLUPS", "cores": oracle.threads(), "kind": "oracle",
-            "sample": f"{n} FP64 steps of the full {w.nx}x{w.ny}x{w.nz} workload after 1 warm-up step ({t:.1f} s)"}
+    oracle.set_threads(1)
+    t0 = time.perf_counter()
+    O.step(1)
+    t1 = time.perf_counter() - t0
+    oracle.set_threads(cores)
+    return {"value": round(mlups, 3), "unit": "MLUPS", "cores": cores, "kind": "oracle",
+            "sample": f"{n} FP64 steps of the full {w.nx}x{w.ny}x{w.nz} workload after 1 warm-up step ({t:.1f} s)",
+            "single_thread": {"value": round(w.fluid_nodes / t1 / 1e6, 3), "unit": "MLUPS",
+                              "sample": f"1 FP64 step of the same workload on one thread ({t1:.1f} s)"},
+            "cpu": cpu_model()}
 
 
 def step_source_hash():

@@ -901,6 +901,17 @@ int orc_threads() {
 #endif
 }
 
+// Threads for the following node loops (n >= 1); returns the count in effect.
+int orc_set_threads(int n) {
+#ifdef _OPENMP
+  if (n >= 1) omp_set_num_threads(n);
+  return omp_get_max_threads();
+#else
+  (void)n;
+  return 1;
+#endif
+}
+
 void* orc_create(int nx, int ny, int nz, double tau) {
   if (nx < 1 || nz < 1 || ny < 4 || !(tau > 0.5)) return nullptr;
   return new Sim<double>(nx, ny, nz, tau);

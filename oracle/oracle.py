@@ -38,6 +38,8 @@ def _lib():
         L.orc_destroy.argtypes = [ctypes.c_void_p]
         L.orc_threads.restype = ctypes.c_int
         L.orc_threads.argtypes = []
+        L.orc_set_threads.restype = ctypes.c_int
+        L.orc_set_threads.argtypes = [ctypes.c_int]
         L.orc_fluid_nodes.restype = ctypes.c_long
         L.orc_fluid_nodes.argtypes = [ctypes.c_void_p]
         for name, extra in [
@@ -71,6 +73,11 @@ def _lib():
 def threads() -> int:
     """OpenMP threads the oracle's node loops use."""
     return int(_lib().orc_threads())
+
+
+def set_threads(n: int) -> int:
+    """Set the OpenMP threads of the oracle's node loops; returns the count."""
+    return int(_lib().orc_set_threads(int(n)))
 
 
 def _p(a):

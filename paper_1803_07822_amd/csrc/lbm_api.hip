@@ -82,7 +82,7 @@ void carve_core(Carver& c, const Grid& g, int precision, Fields& F) {
   F.disp = (double*)c.take(sizeof(double) * 2 * (size_t)g.nz * g.nx);
   F.vwall = (double*)c.take(sizeof(double) * 2 * 3 * (size_t)g.nz * g.nx);
   F.full = (double*)c.take(sizeof(double) * 19 * N);
-  F.mf = (double*)c.take(sizeof(double) * 20 * NC);
+  F.mf = c.take(sz * 20 * NC);
   const size_t nb = (size_t)((g.nx + lbm::BX - 1) / lbm::BX) * ((g.nz + lbm::BY - 1) / lbm::BY);
   F.part = (double*)c.take(sizeof(double) * 3 * nb + 64);
   F.flag = (int*)c.take(ALIGN);

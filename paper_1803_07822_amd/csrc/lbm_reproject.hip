@@ -68,6 +68,14 @@ __device__ __forceinline__ double cell_eval(const Cell& c, const double* __restr
 
 constexpr int NMF = 20;  // 0 rho, 1-3 j, 4-9 Pi, 10 A, 11-13 B, 14-19 C (Cartesian)
 
+// The moment fields are stored in the state's precision as deviations from
+// the state at rest (rho = 1, Pi = I/3 in Cartesian components), so that FP32
+// keeps their small variations; every operation on them (ghost layers,
+// interpolation) is linear, and the rest values are added back in FP64.
+__device__ __forceinline__ double mf_rest(int q) {
+  return q == 0 ? 1.0 : ((q == 4 || q == 7 || q == 9) ? 1.0 / 3.0 : 0.0);
+}
+
 __device__ __forceinline__ void inv3d(const double m[3][3], double r[3][3]) {
   const double det = m[0][0] * (m[1][1] * m[2][2] - m[1][2] * m[2][1]) -
                      m[0][1] * (m[1][0] * m[2][2] - m[1][2] * m[2][0]) +
@@ -96,7 +104,7 @@ __device__ __forceinline__ T pull_rp(const T* __restrict__ pop, const Grid& g, i
 // Cartesian moment fields at the old fluid nodes.
 template <class T>
 __global__ __launch_bounds__(BX * BY) void k_rp_moments(Grid g, const T* __restrict__ pop, const T* __restrict__ hist, const T* __restrict__ geo,
-                             const double* __restrict__ jac, double* __restrict__ mf) {
+                             const double* __restrict__ jac, T* __restrict__ mf) {
   int i, jf, k;
   if (!xcd_fluid_node(g, i, jf, k)) return;
   const long long n = ((long long)k * g.H + jf) * g.nx + i;
@@ -149,12 +157,12 @@ __global__ __launch_bounds__(BX * BY) void k_rp_moments(Grid g, const T* __restr
       Pm[a][b] = sg * ((a == b ? 1.0 / 3.0 : 0.0) + P[sym(a, b)]);
       Cm[a][b] = (double)c.C[sym(a, b)];
     }
-  mf[0 * NC + e] = rho;
-  mf[10 * NC + e] = (double)c.A;
+  mf[0 * NC + e] = (T)(rho - mf_rest(0));
+  mf[10 * NC + e] = c.A;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    mf[(1 + a) * NC + e] = J[a][0] * j[0] + J[a][1] * j[1] + J[a][2] * j[2];
-    mf[(11 + a) * NC + e] = J[a][0] * Bv[0] + J[a][1] * Bv[1] + J[a][2] * Bv[2];
+    mf[(1 + a) * NC + e] = (T)(J[a][0] * j[0] + J[a][1] * j[1] + J[a][2] * j[2]);
+    mf[(11 + a) * NC + e] = (T)(J[a][0] * Bv[0] + J[a][1] * Bv[1] + J[a][2] * Bv[2]);
   }
 #pragma unroll
   for (int a = 0; a < 3; ++a)
@@ -168,12 +176,15 @@ __global__ __launch_bounds__(BX * BY) void k_rp_moments(Grid g, const T* __restr
           sp += J[a][p] * Pm[p][r] * J[b][r];
           sc += J[a][p] * Cm[p][r] * J[b][r];
         }
-      mf[(4 + sym(a, b)) * NC + e] = sp;
-      mf[(14 + sym(a, b)) * NC + e] = sc;
+      mf[(4 + sym(a, b)) * NC + e] = (T)(sp - mf_rest(4 + sym(a, b)));
+      mf[(14 + sym(a, b)) * NC + e] = (T)sc;
     }
 }
 
-__global__ __launch_bounds__(BX * BY) void k_rp_ghost(Grid g, const double* __restrict__ vwall, double* __restrict__ mf) {
+// Wall-layer ghosts of the moment fields: linear extrapolation from the two
+// nearest fluid layers; rho u by the mirror rule about rho v_wall instead.
+template <class T>
+__global__ __launch_bounds__(BX * BY) void k_rp_ghost(Grid g, const double* __restrict__ vwall, T* __restrict__ mf) {
   const int i = blockIdx.x * BX + threadIdx.x, k = blockIdx.y * BY + threadIdx.y;
   if (i >= g.nx || k >= g.nz) return;
   const long long NC = (long long)g.nz * g.ny * g.nx;
@@ -182,18 +193,19 @@ __global__ __launch_bounds__(BX * BY) void k_rp_ghost(Grid g, const double* __re
     const long long eg = ((long long)k * g.ny + jg) * g.nx + i;
     const long long em = ((long long)k * g.ny + jm) * g.nx + i;
     const long long em2 = ((long long)k * g.ny + jm2) * g.nx + i;
-    for (int q = 0; q < NMF; ++q) mf[q * NC + eg] = 2.0 * mf[q * NC + em] - mf[q * NC + em2];
+    for (int q = 0; q < NMF; ++q) mf[q * NC + eg] = (T)(2.0 * (double)mf[q * NC + em] - (double)mf[q * NC + em2]);
     const long long c = (((long long)w * g.nz + k) * g.nx + i) * 3;
-    for (int a = 0; a < 3; ++a) mf[(1 + a) * NC + eg] = 2.0 * mf[em] * vwall[c + a] - mf[(1 + a) * NC + em];
+    const double rho_m = mf_rest(0) + (double)mf[em];
+    for (int a = 0; a < 3; ++a)
+      mf[(1 + a) * NC + eg] = (T)(2.0 * rho_m * vwall[c + a] - (double)mf[(1 + a) * NC + em]);
   }
 }
 
-// Trilinear value and gradient of an extended-grid field (layers -3..ny+2).
-// New state at the new fluid nodes; writes the streamed deviations g~ (FP64)
-// and the new history.
+// New state at the new fluid nodes: the streamed deviations g~ written
+// straight into the pull layout, and the new history (storage precision).
 template <class T>
 __global__ __launch_bounds__(BX * BY) void k_rp_new(Grid g, const double* __restrict__ chart, const double* __restrict__ uold,
-                         const double* __restrict__ mf, const double* __restrict__ jac, const T* __restrict__ geo,
+                         const T* __restrict__ mf, const double* __restrict__ jac, const T* __restrict__ geo,
                          T* __restrict__ pop, T* __restrict__ hist) {
   int i, jf, k;
   if (!xcd_fluid_node(g, i, jf, k)) return;
@@ -249,8 +261,10 @@ __global__ __launch_bounds__(BX * BY) void k_rp_new(Grid g, const double* __rest
     const int ox = c & 1, oy = (c >> 1) & 1, oz = (c >> 2) & 1;
     const double w = (ox ? fr[0] : 1.0 - fr[0]) * (oy ? fr[1] : 1.0 - fr[1]) * (oz ? fr[2] : 1.0 - fr[2]);
 #pragma unroll
-    for (int q = 0; q < NMF; ++q) m[q] += w * mf[q * NC + cl.e[c]];
+    for (int q = 0; q < NMF; ++q) m[q] += w * (double)mf[q * NC + cl.e[c]];
   }
+#pragma unroll
+  for (int q = 0; q < NMF; ++q) m[q] += mf_rest(q);
   // pull back with the new J^{-1}
   double J[3][3], Ji[3][3];
 #pragma unroll
@@ -334,14 +348,14 @@ template <class T> hipError_t launch_reproject(Fields& F, hipStream_t s, const d
   const Grid g = F.g;
   dim3 b(BX, BY);
   hipLaunchKernelGGL(k_rp_moments<T>, xcd_fluid_grid(g), b, 0, s, g, (const T*)F.pop[F.cur], (const T*)F.hist[F.cur],
-                     (const T*)F.geo, (const double*)F.jac, F.mf);
-  hipLaunchKernelGGL(k_rp_ghost, col_grid(g), b, 0, s, g, (const double*)F.vwall, F.mf);
+                     (const T*)F.geo, (const double*)F.jac, (T*)F.mf);
+  hipLaunchKernelGGL(k_rp_ghost<T>, col_grid(g), b, 0, s, g, (const double*)F.vwall, (T*)F.mf);
   const int old = F.uext_cur;
   F.uext_cur ^= 1;
   hipError_t e = launch_geometry<T>(F, s, Fc);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_rp_new<T>, xcd_fluid_grid(g), b, 0, s, g, (const double*)F.chart, (const double*)F.uext[old],
-                     (const double*)F.mf, (const double*)F.jac, (const T*)F.geo, (T*)F.pop[F.cur],
+                     (const T*)F.mf, (const double*)F.jac, (const T*)F.geo, (T*)F.pop[F.cur],
                      (T*)F.hist[F.cur]);
   return hipGetLastError();
 }

@@ -291,3 +291,38 @@ def test_tuning_round_trip(precision):
         with pytest.raises(lbm.LBMError) as e:
             lbm.lbm_set_tuning(S.ctx, *bad)
         assert e.value.code == -1
+
+
+@pytest.mark.parametrize("chart", ["affine_shear", "diagonal_metric", "sin_shear"])
+def test_curved_poiseuille_steady_state(chart):
+    """Steady Poiseuille flow in charts of the flat channel (H = 16, 5190
+    steps): the GPU's FP64 steady state matches the oracle's, and its FP32
+    Cartesian profile matches the FP64 one to FP32 rounding."""
+    H, tau, F = 16, 0.8, 1e-6
+    nx, ny, nz = 2, H + 2, 1
+    if chart == "affine_shear":
+        ch = synth.identity_chart(nx, ny, nz)
+        ch[0] += 0.05 * (ch[1] - 0.5)
+    elif chart == "diagonal_metric":
+        ch = synth.diagonal_metric_chart(nx, ny, nz, 0.1 * (H / 8.0) ** 2)
+    else:
+        ch = synth.shear_chart(nx, ny, nz, 0.05)
+    nu = (tau - 0.5) / 3
+    steps = int(20 / (nu * (np.pi / H) ** 2))
+    O = Oracle(nx, ny, nz, tau)
+    O.set_body_force((F, 0, 0))
+    O.set_metric(ch)
+    O.init_equilibrium()
+    O.step(steps)
+    _, uo = O.moments(cartesian=True)
+    out = {}
+    for precision in ("fp64", "fp32"):
+        S = _lbm().Solver(nx, ny, nz, tau, precision)
+        S.set_body_force((F, 0, 0))
+        S.set_metric(ch)
+        S.init_equilibrium()
+        S.step(steps)
+        out[precision] = _np(S.moments(cartesian=True)[1])
+    scale = np.abs(uo).max()
+    assert np.abs(out["fp64"] - uo).max() < 1e-10 * scale
+    assert np.abs(out["fp32"] - out["fp64"]).max() < 1e-3 * scale

@@ -180,6 +180,69 @@ def test_flat_poiseuille_closed_form(tau):
     assert np.abs(u[1:]).max() < 1e-14  # rounding of sums of O(1) populations
 
 
+def _curved_poiseuille_error(chart_fn, H, tau=0.8, F=1e-6):
+    """Steady Poiseuille flow along x in a chart of the flat channel: relative
+    max error of the Cartesian velocity against the no-slip parabola between
+    the Cartesian positions of the two halfway walls, u = F/(2 nu)(y - y0)(y1 - y)."""
+    nx, ny, nz = 2, H + 2, 1
+    ch = chart_fn(nx, ny, nz, H)
+    o = Oracle(nx, ny, nz, tau)
+    o.set_body_force([F, 0, 0])
+    o.set_metric(ch)
+    o.init_equilibrium()
+    o.step(steady_steps(H, tau, 20))
+    _, u = o.moments(cartesian=True)
+    nu = (tau - 0.5) / 3
+    # halfway walls at eta = 0 and H: chart layers j = 0.5 and ny - 1.5, mid-way between layers
+    yc = ch[1][0, :, 0]
+    y0, y1 = 0.5 * (yc[0] + yc[1]), 0.5 * (yc[-2] + yc[-1])
+    y = yc[1:-1]
+    ua = F / (2 * nu) * (y - y0) * (y1 - y)
+    return np.abs(u[0][0, :, 0] - ua).max() / ua.max()
+
+
+def _affine_shear(nx, ny, nz, H, eps=0.05):
+    ch = synth.identity_chart(nx, ny, nz)
+    ch[0] += eps * (ch[1] - 0.5)  # x_c = xi_x + eps eta: constant J, Gamma = 0, g_xy != 0
+    return ch
+
+
+@pytest.mark.parametrize("name", ["affine_shear", "diagonal_metric"])
+def test_curved_poiseuille_second_order(name):
+    """Poiseuille flow in two charts of the flat channel, both with walls at
+    fixed Cartesian positions: a constant shear (non-orthogonal metric,
+    g_xy != 0, Gamma = 0) and the paper's diagonal metric
+    g_yy = 1 + d^2 h'/dy^2, h' = eps cos(pi y / H) (Sec. V.A; Gamma != 0).  The
+    Cartesian profile converges to the parabola at second order (H = 8, 16,
+    32, fixed physical shape)."""
+    if name == "affine_shear":
+        fn = _affine_shear
+    else:
+        fn = lambda nx, ny, nz, H: synth.diagonal_metric_chart(nx, ny, nz, 0.1 * (H / 8.0) ** 2)  # noqa: E731
+    e = [_curved_poiseuille_error(fn, H) for H in (8, 16, 32)]
+    print(name, "Poiseuille errors", e)
+    assert e[0] / e[1] > 3.5 and e[1] / e[2] > 3.5, e
+    assert e[2] < 1e-3, e
+
+
+def test_sheared_poiseuille_pressure_residual():
+    """A shear that varies across the channel, x_c = xi_x + eps H sin(pi eta/H)
+    (non-orthogonal, with Gamma^x_yy = s'' != 0 for the shift s(eta)).  The
+    lattice's divergence of the isotropic pressure part rho theta g^ij of the
+    momentum flux cancels the Christoffel term -Gamma^x_yy rho theta of B^x
+    only to O(dx^2), leaving a force of order rho theta dx^2 d^4 s/d eta^4
+    along the flow, independent of the drive F.  Pinned: the profile error
+    falls at third order in H at fixed shape (the residual ~ 1/H^3 against a
+    Poiseuille velocity ~ F H^2 balanced by viscous forces ~ 1/H^2) and is
+    inversely proportional to F."""
+    fn = lambda nx, ny, nz, H: synth.shear_chart(nx, ny, nz, 0.05)  # noqa: E731
+    e = [_curved_poiseuille_error(fn, H) for H in (8, 16, 32)]
+    e16_strong = _curved_poiseuille_error(fn, 16, F=1e-5)
+    print("sheared Poiseuille errors", e, "x10 drive at H=16:", e16_strong)
+    assert e[0] / e[1] > 6.0 and e[1] / e[2] > 6.0, e
+    assert abs(e[1] / e16_strong - 10.0) < 0.5, (e[1], e16_strong)
+
+
 def test_mass_budget_identity_curved():
     """sum_x sum_l f(t+1) - sum_x sum_l f(t) = sum_x [(3/2) A(t) - A(t-1)/2] / sqrt g
     for static walls: collision conserves sum_l f (rho of f and of f_eq agree,

@@ -10,6 +10,9 @@
 namespace lbm {
 
 // Device buffers of one context, carved from the caller's workspace.
+// Tile shapes (x by y fluid nodes per block) of the fused step kernel.
+enum TileShape { TILE_64x4 = 0, TILE_64x2 = 1, TILE_64x1 = 2, TILE_128x2 = 3, TILE_256x1 = 4 };
+
 struct Fields {
   Grid g;
   long long NE;   // nodes of the y-extended grid, nz * (ny + 6) * nx
@@ -36,7 +39,7 @@ struct Fields {
   int moving[2];
   int zc = 0;        // planes per block of the fused step (0 = automatic)
   int variant = 0;   // 0: fused step; 1: two-pass step (moments pass + collision pass)
-  int ty = 4;        // rows of 64 nodes per block of the fused step (1, 2, 4)
+  int tile = 0;      // tile shape of the fused step (TileShape)
   int stage = 1;     // FP32 fused step keeps pulled populations in registers
   int slots_key = -1;     // fused kernel whose resident-block count is cached
   long long slots = 0;    // resident blocks of that kernel on the device

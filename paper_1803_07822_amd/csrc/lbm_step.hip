@@ -491,7 +491,7 @@ template <class T> hipError_t launch_step(Fields& F, hipStream_t s, T tau, hipEv
   };
   if (F.variant == 0) {
     mark(0);
-    if (e == hipSuccess) e = launch_step_fused<T>(F, s, tau, F.zc, F.ty);
+    if (e == hipSuccess) e = launch_step_fused<T>(F, s, tau, F.zc, F.tile);
     mark(1);
     mark(2);
     return e;

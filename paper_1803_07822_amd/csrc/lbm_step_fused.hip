@@ -22,10 +22,9 @@ namespace lbm {
 
 namespace {
 
-constexpr int TX = 64;
-constexpr int HX = TX + 2;
-template <int TY> struct Tile {
+template <int TX, int TY> struct Tile {
   static constexpr int NT = TX * TY;
+  static constexpr int HX = TX + 2;
   static constexpr int HY = TY + 2;
   static constexpr int HN = HX * HY;  // haloed tile
 };
@@ -132,11 +131,12 @@ __device__ __forceinline__ void node_moments(const T* __restrict__ pop, const T*
 // Moments of entry e of the haloed tile at plane k into the ring slot.  Wall
 // layers (jf = -1, H) get the mirror ghost of the adjacent fluid node.  A
 // fluid entry hands its pulled deviations to `keep`.
-template <class T, int TY, class Keep = NoKeep>
-__device__ __forceinline__ void fill_entry(T (*ring)[Tile<TY>::HN], const T* __restrict__ pop,
+template <class T, int TX, int TY, class Keep = NoKeep>
+__device__ __forceinline__ void fill_entry(T (*ring)[(TX + 2) * (TY + 2)], const T* __restrict__ pop,
                                            const T* __restrict__ hist, const T* __restrict__ geo,
                                            const T* __restrict__ uw, int mv0, int mv1, const Grid& g, int i0,
                                            int j0, int k, int e, const Keep& keep = Keep()) {
+  constexpr int HX = Tile<TX, TY>::HX;
   const int hx = e % HX, hy = e / HX;
   const int i = i0 - 1 + hx, jf = j0 - 1 + hy;
   if (i > g.nx || jf > g.H) return;  // beyond a ragged tile edge: never read
@@ -165,27 +165,28 @@ __device__ __forceinline__ void fill_entry(T (*ring)[Tile<TY>::HN], const T* __r
 }
 
 // Fill one ring slot with the moments of plane k over the haloed tile.
-template <class T, int TY>
-__device__ __forceinline__ void fill_plane(T (*ring)[Tile<TY>::HN], const T* __restrict__ pop, const T* __restrict__ hist,
+template <class T, int TX, int TY>
+__device__ __forceinline__ void fill_plane(T (*ring)[(TX + 2) * (TY + 2)], const T* __restrict__ pop, const T* __restrict__ hist,
                                            const T* __restrict__ geo, const T* __restrict__ uw, int mv0, int mv1,
                                            const Grid& g, int i0, int j0, int k) {
   k = wrapf(k, g.nz);
-  for (int e = threadIdx.x; e < Tile<TY>::HN; e += Tile<TY>::NT)
-    fill_entry<T, TY>(ring, pop, hist, geo, uw, mv0, mv1, g, i0, j0, k, e);
+  for (int e = threadIdx.x; e < Tile<TX, TY>::HN; e += Tile<TX, TY>::NT)
+    fill_entry<T, TX, TY>(ring, pop, hist, geo, uw, mv0, mv1, g, i0, j0, k, e);
 }
 
 // Staged fill: each thread fills the entry of its own node (handing that
 // node's pulled deviations to `keep`, for the collision one iteration later);
 // the 2*(TX+2) + 2*TY halo entries are shared out over the block.
-template <class T, int TY, class Keep>
-__device__ __forceinline__ void fill_plane_staged(T (*ring)[Tile<TY>::HN], const T* __restrict__ pop,
+template <class T, int TX, int TY, class Keep>
+__device__ __forceinline__ void fill_plane_staged(T (*ring)[(TX + 2) * (TY + 2)], const T* __restrict__ pop,
                                                   const T* __restrict__ hist, const T* __restrict__ geo,
                                                   const T* __restrict__ uw, int mv0, int mv1, const Grid& g, int i0,
                                                   int j0, int k, int tx, int ty, const Keep& keep) {
+  constexpr int HX = Tile<TX, TY>::HX;
   k = wrapf(k, g.nz);
-  fill_entry<T, TY>(ring, pop, hist, geo, uw, mv0, mv1, g, i0, j0, k, (ty + 1) * HX + (tx + 1), keep);
+  fill_entry<T, TX, TY>(ring, pop, hist, geo, uw, mv0, mv1, g, i0, j0, k, (ty + 1) * HX + (tx + 1), keep);
   constexpr int NH = 2 * HX + 2 * TY;
-  for (int h = threadIdx.x; h < NH; h += Tile<TY>::NT) {
+  for (int h = threadIdx.x; h < NH; h += Tile<TX, TY>::NT) {
     int e;
     if (h < HX)
       e = h;
@@ -195,7 +196,7 @@ __device__ __forceinline__ void fill_plane_staged(T (*ring)[Tile<TY>::HN], const
       e = (1 + h - 2 * HX) * HX;
     else
       e = (1 + h - 2 * HX - TY) * HX + (HX - 1);
-    fill_entry<T, TY>(ring, pop, hist, geo, uw, mv0, mv1, g, i0, j0, k, e);
+    fill_entry<T, TX, TY>(ring, pop, hist, geo, uw, mv0, mv1, g, i0, j0, k, e);
   }
 }
 
@@ -206,14 +207,14 @@ enum Stage {
   STAGE_REG = 1,   // registers (two planes live across the collision)
 };
 
-template <class T, int TY, int STAGE>
-__global__ __launch_bounds__(Tile<TY>::NT) void k_step_fused(Grid g, int ntx, int nty, int nzc, int zc,
+template <class T, int TX, int TY, int STAGE>
+__global__ __launch_bounds__(TX * TY) void k_step_fused(Grid g, int ntx, int nty, int nzc, int zc,
                                                    const T* __restrict__ pin, T* __restrict__ pout,
                                                    const T* __restrict__ hist, T* __restrict__ hout,
                                                    const T* __restrict__ geo,
                                                    const T* __restrict__ uw, int mv0, int mv1, T tau,
                                                    int* __restrict__ flag) {
-  constexpr int HN = Tile<TY>::HN;
+  constexpr int HN = Tile<TX, TY>::HN, HX = Tile<TX, TY>::HX;
   // Four ring slots: the fill of plane k+1 overwrites plane k-3, whose last
   // reader (the collision of plane k-2) every thread has finished before
   // passing the barrier of the previous iteration, so one barrier per plane
@@ -246,18 +247,18 @@ __global__ __launch_bounds__(Tile<TY>::NT) void k_step_fused(Grid g, int ntx, in
   auto to_next = [&](auto L, T v) {
     if (own) nxt[decltype(L)::value] = v;
   };
-  fill_plane<T, TY>(ring[rslot(z0 - 1)], pin, hist, geo, uw, mv0, mv1, g, i0, j0, z0 - 1);
+  fill_plane<T, TX, TY>(ring[rslot(z0 - 1)], pin, hist, geo, uw, mv0, mv1, g, i0, j0, z0 - 1);
   if constexpr (STAGE == STAGE_NONE)
-    fill_plane<T, TY>(ring[rslot(z0)], pin, hist, geo, uw, mv0, mv1, g, i0, j0, z0);
+    fill_plane<T, TX, TY>(ring[rslot(z0)], pin, hist, geo, uw, mv0, mv1, g, i0, j0, z0);
   else
-    fill_plane_staged<T, TY>(ring[rslot(z0)], pin, hist, geo, uw, mv0, mv1, g, i0, j0, z0, tx, ty, to_cur);
+    fill_plane_staged<T, TX, TY>(ring[rslot(z0)], pin, hist, geo, uw, mv0, mv1, g, i0, j0, z0, tx, ty, to_cur);
   const T itau = T(1) / tau;
   for (int k = z0; k < z1; ++k) {
     own = active && k + 1 < z1;
     if constexpr (STAGE == STAGE_NONE)
-      fill_plane<T, TY>(ring[rslot(k + 1)], pin, hist, geo, uw, mv0, mv1, g, i0, j0, k + 1);
+      fill_plane<T, TX, TY>(ring[rslot(k + 1)], pin, hist, geo, uw, mv0, mv1, g, i0, j0, k + 1);
     else
-      fill_plane_staged<T, TY>(ring[rslot(k + 1)], pin, hist, geo, uw, mv0, mv1, g, i0, j0, k + 1, tx, ty, to_next);
+      fill_plane_staged<T, TX, TY>(ring[rslot(k + 1)], pin, hist, geo, uw, mv0, mv1, g, i0, j0, k + 1, tx, ty, to_next);
     __syncthreads();
     if (active) {
       const NodeIdx p = node_idx(g, i, jf, k);
@@ -415,18 +416,18 @@ inline int choose_zc(long long tiles, int nz, long long slots) {
   return best;
 }
 
-// Planes per block for kernel k_step_fused<T, TY, ST>: zc if positive, else
-// the choice above for this device.
-template <class T, int TY, int ST> hipError_t fused_chunk(Fields& F, int zc, int* out) {
+// Planes per block for kernel k_step_fused<T, TX, TY, ST>: zc if positive,
+// else the choice above for this device.
+template <class T, int TX, int TY, int ST> hipError_t fused_chunk(Fields& F, int zc, int* out) {
   const Grid g = F.g;
   if (zc <= 0) {
-    const int key = (int)sizeof(T) * 100 + TY * 10 + ST;
+    const int key = (int)sizeof(T) * 10000 + TX * 10 + TY * 2 + ST;
     if (F.slots_key != key) {
       int dev = 0, cus = 0, per_cu = 0;
       hipError_t e = hipGetDevice(&dev);
       if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
       if (e == hipSuccess)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_fused<T, TY, ST>, Tile<TY>::NT, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_fused<T, TX, TY, ST>, Tile<TX, TY>::NT, 0);
       if (e != hipSuccess) return e;
       F.slots = (long long)cus * (per_cu > 0 ? per_cu : 1);
       F.slots_key = key;
@@ -438,41 +439,49 @@ template <class T, int TY, int ST> hipError_t fused_chunk(Fields& F, int zc, int
   return hipSuccess;
 }
 
-template <class T, int TY, int ST> hipError_t fused_launch(Fields& F, hipStream_t s, T tau, int zc) {
+template <class T, int TX, int TY, int ST> hipError_t fused_launch(Fields& F, hipStream_t s, T tau, int zc) {
   const Grid g = F.g;
-  const hipError_t e = fused_chunk<T, TY, ST>(F, zc, &zc);
+  const hipError_t e = fused_chunk<T, TX, TY, ST>(F, zc, &zc);
   if (e != hipSuccess) return e;
   const int ntx = (g.nx + TX - 1) / TX, nty = (g.H + TY - 1) / TY;
   const int nzc = (g.nz + zc - 1) / zc;
   const int per = (ntx * nty * nzc + 7) / 8;
-  hipLaunchKernelGGL((k_step_fused<T, TY, ST>), dim3(per * 8), dim3(Tile<TY>::NT), 0, s, g, ntx, nty, nzc, zc,
-                     (const T*)F.pop[F.cur], (T*)F.pop[F.cur ^ 1], (const T*)F.hist[F.cur], (T*)F.hist[F.cur ^ 1],
-                     (const T*)F.geo, (const T*)F.uw, F.moving[0], F.moving[1], tau, F.flag);
+  hipLaunchKernelGGL((k_step_fused<T, TX, TY, ST>), dim3(per * 8), dim3(Tile<TX, TY>::NT), 0, s, g, ntx, nty, nzc,
+                     zc, (const T*)F.pop[F.cur], (T*)F.pop[F.cur ^ 1], (const T*)F.hist[F.cur],
+                     (T*)F.hist[F.cur ^ 1], (const T*)F.geo, (const T*)F.uw, F.moving[0], F.moving[1], tau, F.flag);
   F.cur ^= 1;
   return hipGetLastError();
 }
 
-template <class T, int TY> hipError_t launch_fused_ty(Fields& F, hipStream_t s, T tau, int zc) {
-  if (F.stage == STAGE_REG) return fused_launch<T, TY, reg_stage<T>()>(F, s, tau, zc);
-  return fused_launch<T, TY, STAGE_NONE>(F, s, tau, zc);
+template <class T, int TX, int TY> hipError_t launch_fused_tile(Fields& F, hipStream_t s, T tau, int zc) {
+  if (F.stage == STAGE_REG) return fused_launch<T, TX, TY, reg_stage<T>()>(F, s, tau, zc);
+  return fused_launch<T, TX, TY, STAGE_NONE>(F, s, tau, zc);
 }
 
-template <class T, int TY> hipError_t chunk_ty(Fields& F, int* zc) {
-  if (F.stage == STAGE_REG) return fused_chunk<T, TY, reg_stage<T>()>(F, F.zc, zc);
-  return fused_chunk<T, TY, STAGE_NONE>(F, F.zc, zc);
+template <class T, int TX, int TY> hipError_t chunk_tile(Fields& F, int* zc) {
+  if (F.stage == STAGE_REG) return fused_chunk<T, TX, TY, reg_stage<T>()>(F, F.zc, zc);
+  return fused_chunk<T, TX, TY, STAGE_NONE>(F, F.zc, zc);
 }
 
-// ty: tile height in y (1, 2 or 4 rows of 64 nodes per block).
-template <class T> hipError_t launch_step_fused(Fields& F, hipStream_t s, T tau, int zc, int ty) {
-  if (ty == 1) return launch_fused_ty<T, 1>(F, s, tau, zc);
-  if (ty == 2) return launch_fused_ty<T, 2>(F, s, tau, zc);
-  return launch_fused_ty<T, 4>(F, s, tau, zc);
+// Tile shapes (x by y nodes per block): 64x4 (default), 64x2, 64x1, 128x2, 256x1.
+template <class T> hipError_t launch_step_fused(Fields& F, hipStream_t s, T tau, int zc, int tile) {
+  switch (tile) {
+    case TILE_64x2: return launch_fused_tile<T, 64, 2>(F, s, tau, zc);
+    case TILE_64x1: return launch_fused_tile<T, 64, 1>(F, s, tau, zc);
+    case TILE_128x2: return launch_fused_tile<T, 128, 2>(F, s, tau, zc);
+    case TILE_256x1: return launch_fused_tile<T, 256, 1>(F, s, tau, zc);
+    default: return launch_fused_tile<T, 64, 4>(F, s, tau, zc);
+  }
 }
 
 template <class T> hipError_t fused_step_chunk(Fields& F, int* zc) {
-  if (F.ty == 1) return chunk_ty<T, 1>(F, zc);
-  if (F.ty == 2) return chunk_ty<T, 2>(F, zc);
-  return chunk_ty<T, 4>(F, zc);
+  switch (F.tile) {
+    case TILE_64x2: return chunk_tile<T, 64, 2>(F, zc);
+    case TILE_64x1: return chunk_tile<T, 64, 1>(F, zc);
+    case TILE_128x2: return chunk_tile<T, 128, 2>(F, zc);
+    case TILE_256x1: return chunk_tile<T, 256, 1>(F, zc);
+    default: return chunk_tile<T, 64, 4>(F, zc);
+  }
 }
 
 template hipError_t fused_step_chunk<double>(Fields&, int*);

@@ -23,6 +23,10 @@
 //   * Fluid arrays are [.][nz][H][nx]; chart arrays are [3][nz][ny][nx].
 //   * Forcing history per node: A, B^x, B^y, B^z, C^xx, C^xy, C^xz, C^yy,
 //     C^yz, C^zz (Eqs. forcing-A/B/C).
+//   * Interior plate (Sec. IV.A.1 (ii), Sec. VI.A): a thin plate on the half
+//     row between fluid rows jp-1 and jp, over columns i0..i1 and all z.  A
+//     link between those rows is cut when its crossing point x lies in
+//     [i0 - 1/2, i1 + 1/2]; cut links bounce back halfway, like the walls.
 //   * Geometry export per fluid node (28 values): sqrt g, g^xx, g^xy, g^xz,
 //     g^yy, g^yz, g^zz, Gamma^i_jk for i = x,y,z and jk in
 //     (xx,xy,xz,yy,yz,zz), then F^x, F^y, F^z.
@@ -373,6 +377,10 @@ template <class T> struct Sim {
   std::vector<T> disp[2];           // wall displacements [nz][nx] (bottom, top)
   std::vector<T> vwall[2];          // Cartesian wall velocity [nz][nx][3]
   std::vector<T> uwall[2];          // chart components at the adjacent fluid node
+  int pj = 0, pi0 = 0, pi1 = -1;    // interior plate (pj = 0: none)
+  std::vector<T> dplate;            // plate y-displacement [nz][nx] (cross-section row)
+  std::vector<T> vplate;            // Cartesian plate velocity per column [nz][nx][3]
+  std::vector<T> uplate[2];         // chart components at the node below (0) / above (1)
   bool have_geo = false, have_state = false;
 
   Sim(int x, int y, int z, double t) : nx(x), ny(y), nz(z), H(y - 2), tau(t) {
@@ -382,7 +390,21 @@ template <class T> struct Sim {
       disp[w].assign((long)nz * nx, T(0.0));
       vwall[w].assign((long)nz * nx * 3, T(0.0));
       uwall[w].assign((long)nz * nx * 3, T(0.0));
+      uplate[w].assign((long)nz * nx * 3, T(0.0));
     }
+    dplate.assign((long)nz * nx, T(0.0));
+    vplate.assign((long)nz * nx * 3, T(0.0));
+  }
+
+  // The link from fluid node (i, jf) along (cx, cy) crosses the plate: it
+  // joins rows jp-1 and jp and crosses the half row at x = i + cx/2 within
+  // [i0 - 1/2, i1 + 1/2].  (x is not wrapped, so a plate over every column
+  // also cuts the links through the periodic seam.)
+  bool plate_cut(int i, int jf, int cx, int cy) const {
+    if (pj == 0 || cy == 0) return false;
+    if (cy > 0 ? jf != pj - 1 : jf != pj) return false;
+    const int s2 = 2 * i + cx;
+    return s2 >= 2 * pi0 - 1 && s2 <= 2 * pi1 + 1;
   }
   long nid(int i, int jf, int k) const { return ((long)k * H + jf) * nx + i; }
 
@@ -395,6 +417,23 @@ template <class T> struct Sim {
             T s = 0.0;
             for (int b = 0; b < 3; ++b) s += G.Ji[a][b] * vwall[w][((long)k * nx + i) * 3 + b];
             uwall[w][((long)k * nx + i) * 3 + a] = s;
+          }
+        }
+  }
+
+  // Plate velocity in the chart components of the nodes next to the plate:
+  // column i takes the velocity of the nearest plate column.
+  void update_plate_velocity() {
+    if (pj == 0) return;
+    for (int s = 0; s < 2; ++s)
+      for (int k = 0; k < nz; ++k)
+        for (int i = 0; i < nx; ++i) {
+          const Geo<T>& G = geo[nid(i, pj - 1 + s, k)];
+          const int ic = i < pi0 ? pi0 : (i > pi1 ? pi1 : i);
+          for (int a = 0; a < 3; ++a) {
+            T v = 0.0;
+            for (int b = 0; b < 3; ++b) v += G.Ji[a][b] * vplate[((long)k * nx + ic) * 3 + b];
+            uplate[s][((long)k * nx + i) * 3 + a] = v;
           }
         }
   }
@@ -419,6 +458,7 @@ template <class T> struct Sim {
     geo.swap(newgeo);
     have_geo = true;
     update_wall_velocity();
+    update_plate_velocity();
   }
 
   // Linear blending of the two wall displacements into the interior
@@ -426,6 +466,31 @@ template <class T> struct Sim {
   // eta = xi_y - 1/2, so the halfway walls sit at eta = 0 and eta = H.
   void set_wall_displacement(int wall, const T* d, bool reproject) {
     for (long q = 0; q < (long)nz * nx; ++q) disp[wall][q] = d ? d[q] : T(0.0);
+    build_chart(reproject);
+  }
+
+  // Natural cubic spline along the normal of the plate (Sec. IV.A.1 (ii)):
+  // the shape S(eta) through (0, 0), (eta_p, 1), (H, 0) with S'' = 0 at both
+  // walls.  With knot spacings a = eta_p and b = H - eta_p, continuity of S'
+  // at the plate gives its second derivative there, M = -3 (1/a + 1/b) / H;
+  // each piece is the cubic with end values and end second derivatives.
+  double plate_shape(double eta) const {
+    const double a = pj, b = H - pj, M = -3.0 * (1.0 / a + 1.0 / b) / H;
+    if (eta <= a) {
+      const double t = eta;  // distance from the bottom wall
+      return M * t * t * t / (6.0 * a) + (1.0 - M * a * a / 6.0) * t / a;
+    }
+    const double t = H - eta;  // distance from the top wall
+    return M * t * t * t / (6.0 * b) + (1.0 - M * b * b / 6.0) * t / b;
+  }
+
+  // Chart of the walls and the plate: the two wall displacements blended
+  // linearly across the channel (Sec. IV.A.1 (i)) plus the plate's
+  // cross-section displacement D(x, z) carried by the spline shape:
+  // h = (xi_x, xi_y + (1 - eta/H) d_bot + (eta/H) d_top + D S(eta), xi_z),
+  // eta = xi_y - 1/2, so the halfway walls sit at eta = 0 and eta = H and the
+  // plate at eta = jp.
+  void build_chart(bool reproject) {
     std::vector<T> ch(3L * nz * ny * nx);
     for (int k = 0; k < nz; ++k)
       for (int j = 0; j < ny; ++j)
@@ -434,11 +499,39 @@ template <class T> struct Sim {
           long q = (long)k * nx + i;
           long p = ((long)k * ny + j) * nx + i;
           ch[0L * nz * ny * nx + p] = (double)i;
-          ch[1L * nz * ny * nx + p] =
-              (double)j + (1.0 - eta / H) * disp[0][q] + (eta / H) * disp[1][q];
+          T y = (double)j + (1.0 - eta / H) * disp[0][q] + (eta / H) * disp[1][q];
+          if (pj > 0) y += dplate[q] * plate_shape(eta);
+          ch[1L * nz * ny * nx + p] = y;
           ch[2L * nz * ny * nx + p] = (double)k;
         }
     set_metric(ch.data(), reproject);
+  }
+
+  // Interior plate on the half row between fluid rows jp-1 and jp, columns
+  // i0..i1 (the plate's displacement and velocity start at zero).
+  bool set_plate(int jp, int i0, int i1) {
+    if (jp == 0) {
+      pj = 0;
+      return true;
+    }
+    if (jp < 1 || jp > H - 1 || i0 < 0 || i1 < i0 || i1 > nx - 1) return false;
+    pj = jp;
+    pi0 = i0;
+    pi1 = i1;
+    dplate.assign((long)nz * nx, T(0.0));
+    vplate.assign((long)nz * nx * 3, T(0.0));
+    if (have_geo) update_plate_velocity();
+    return true;
+  }
+
+  void set_plate_displacement(const T* d, bool reproject) {
+    for (long q = 0; q < (long)nz * nx; ++q) dplate[q] = d ? d[q] : T(0.0);
+    build_chart(reproject);
+  }
+
+  void set_plate_velocity(const T* v) {
+    for (long q = 0; q < (long)nz * nx * 3; ++q) vplate[q] = v ? v[q] : T(0.0);
+    if (have_geo) update_plate_velocity();
   }
 
   void set_wall_velocity(int wall, const T* v) {
@@ -500,15 +593,27 @@ template <class T> struct Sim {
   }
 
   // d_k (rho u^i) by the second-order isotropic gradient (App. D).
+  // A neighbour across the plate is replaced by the mirror ghost of the node
+  // m on this side in the neighbour's column, j_g = 2 rho_m u_p - j_m, as at
+  // the walls.
   void node_gradient(const std::vector<T>& rho, const std::vector<T>& jv, int i, int j, int k,
                      T dj[3][3]) const {
     for (int kk = 0; kk < 3; ++kk)
       for (int a = 0; a < 3; ++a) {
         T s = 0.0;
         for (int l = 1; l < QN; ++l)
-          if (CV[l][kk] != 0)
-            s += WV[l] * (double)CV[l][kk] *
-                 jat(rho, jv, i + CV[l][0], j + CV[l][1], k + CV[l][2], a);
+          if (CV[l][kk] != 0) {
+            T jn;
+            if (plate_cut(i, j - 1, CV[l][0], CV[l][1])) {
+              const int im = wrapi(i + CV[l][0], nx), km = wrapi(k + CV[l][2], nz);
+              const long m = nid(im, j - 1, km);
+              const int side = (j - 1 == pj) ? 1 : 0;
+              jn = 2.0 * rho[m] * uplate[side][((long)km * nx + im) * 3 + a] - jv[a * N + m];
+            } else {
+              jn = jat(rho, jv, i + CV[l][0], j + CV[l][1], k + CV[l][2], a);
+            }
+            s += WV[l] * (double)CV[l][kk] * jn;
+          }
         dj[kk][a] = s / CS2;
       }
   }
@@ -584,12 +689,14 @@ template <class T> struct Sim {
           long n = nid(i, jf, k);
           for (int l = 0; l < QN; ++l) {
             int jd = jf + 1 + CV[l][1];
-            if (jd >= 1 && jd <= ny - 2) {
+            const bool cut = plate_cut(i, jf, CV[l][0], CV[l][1]);
+            if (jd >= 1 && jd <= ny - 2 && !cut) {
               long d = nid(wrapi(i + CV[l][0], nx), jd - 1, wrapi(k + CV[l][2], nz));
               fn[l * N + d] = fs[l * N + n];
             } else {
               int w = (jd <= 0) ? 0 : 1;
-              const T* uw = &uwall[w][((long)k * nx + i) * 3];
+              const T* uw = cut ? &uplate[jf == pj ? 1 : 0][((long)k * nx + i) * 3]
+                                : &uwall[w][((long)k * nx + i) * 3];
               T cu = uw[0] * (double)CV[l][0] + uw[1] * (double)CV[l][1] + uw[2] * (double)CV[l][2];
               fn[opposite(l) * N + n] = fs[l * N + n] - 2.0 * WV[l] / geo[n].sg * rho[n] * cu / CS2;
             }
@@ -649,6 +756,42 @@ template <class T> struct Sim {
       }
   }
 
+  // Force on the plate: the node-exact traction of both faces over the plate
+  // columns, + sqrt g T^{iy} J e_i at the node below (whose outward normal is
+  // +y) and - sqrt g T^{iy} J e_i at the node above.  per_col [nz][nx][3] is
+  // zero outside i0..i1.
+  void plate_force(T total[3], T* per_col) const {
+    std::vector<T> rho, jv;
+    moments_raw(rho, jv);
+    total[0] = total[1] = total[2] = 0.0;
+    if (per_col)
+      for (long q = 0; q < (long)nz * nx * 3; ++q) per_col[q] = 0.0;
+    if (pj == 0) return;
+    for (int k = 0; k < nz; ++k)
+      for (int i = pi0; i <= pi1; ++i) {
+        T col[3] = {0.0, 0.0, 0.0};
+        for (int s = 0; s < 2; ++s) {
+          long n = nid(i, pj - 1 + s, k);
+          const Geo<T>& G = geo[n];
+          T fl[QN], feq[QN], jl[3], Tm[3][3];
+          for (int l = 0; l < QN; ++l) fl[l] = f[l * N + n];
+          for (int a = 0; a < 3; ++a) jl[a] = jv[a * N + n];
+          equilibrium(G, rho[n], jl, feq);
+          stress(G, fl, feq, rho[n], jl, tau, Tm);
+          const double sgn = s == 0 ? 1.0 : -1.0;
+          for (int a = 0; a < 3; ++a) {
+            T v = 0.0;
+            for (int i2 = 0; i2 < 3; ++i2) v += G.sg * Tm[i2][1] * G.J[a][i2];
+            col[a] += sgn * v;
+          }
+        }
+        for (int a = 0; a < 3; ++a) {
+          total[a] += col[a];
+          if (per_col) per_col[((long)k * nx + i) * 3 + a] = col[a];
+        }
+      }
+  }
+
   // --------------------------------------------------------- re-projection
   // Old chart displacement on the y-extended grid (same continuation as the
   // geometry), used to locate psi(x~) = h^{-1}(h~(x~)).
@@ -674,7 +817,10 @@ template <class T> struct Sim {
   }
 
   // Trilinear interpolation of an extended-grid field and its gradient at xi.
-  static double trilin(const std::vector<double>& F, const Ext& E, const double p[3], double grad[3]) {
+  // With side >= 0 a cell spanning the plate is moved to that side, as in
+  // trilin_clamped, so that the position search and the moment interpolation
+  // of a node use the same cell.
+  double trilin(const std::vector<double>& F, const Ext& E, const double p[3], double grad[3], int side) const {
     double fl[3];
     int b[3];
     double fr[3];
@@ -684,6 +830,10 @@ template <class T> struct Sim {
     b[1] = (int)fl[1];
     if (b[1] < -3) b[1] = -3;
     if (b[1] > E.ny + 1) b[1] = E.ny + 1;
+    if (side >= 0 && b[1] == pj) {
+      const int c0 = wrapi(b[0], nx), c1 = wrapi(b[0] + 1, nx);
+      if ((c0 >= pi0 && c0 <= pi1) || (c1 >= pi0 && c1 <= pi1)) b[1] = side ? pj + 1 : pj - 1;
+    }
     for (int a = 0; a < 3; ++a) fr[a] = p[a] - b[a];
     double v = 0.0;
     if (grad) grad[0] = grad[1] = grad[2] = 0.0;
@@ -787,12 +937,14 @@ template <class T> struct Sim {
           long p3 = ((long)k * ny + (jf + 1)) * nx + i, plane = (long)nz * ny * nx;
           double p[3] = {val(newchart[p3]), val(newchart[plane + p3]), val(newchart[2 * plane + p3])};
           // psi: solve xi + u_old(xi) = p by Newton on the trilinear interpolant
+          // (cells on the node's side of the plate)
+          const int side = (pj > 0) ? (jf >= pj ? 1 : 0) : -1;
           double xi[3] = {(double)i, (double)(jf + 1), (double)k};
           for (int it = 0; it < 50; ++it) {
             double r[3], Jm[3][3], Jinv[3][3];
             for (int a = 0; a < 3; ++a) {
               double gr[3];
-              r[a] = xi[a] + trilin(uo[a], E, xi, gr) - p[a];
+              r[a] = xi[a] + trilin(uo[a], E, xi, gr, side) - p[a];
               for (int b = 0; b < 3; ++b) Jm[a][b] = (a == b ? 1.0 : 0.0) + gr[b];
             }
             inv3(Jm, Jinv);
@@ -809,7 +961,7 @@ template <class T> struct Sim {
           if (q[1] < 0.0) q[1] = 0.0;
           if (q[1] > ny - 1.0) q[1] = ny - 1.0;
           double m[NF];
-          for (int c = 0; c < NF; ++c) m[c] = trilin_clamped(fld[c], E, q);
+          for (int c = 0; c < NF; ++c) m[c] = trilin_clamped(fld[c], E, q, side);
           const Geo<T>& Gn = newgeo[n];
           double Ji[3][3];
           for (int a = 0; a < 3; ++a)
@@ -851,11 +1003,19 @@ template <class T> struct Sim {
   }
 
   // Trilinear interpolation with x, z periodic and y limited to layers 0..ny-1.
-  double trilin_clamped(const std::vector<double>& F, const Ext& E, const double p[3]) const {
+  // A cell that spans the plate (layers jp and jp+1, i.e. fluid rows jp-1 and
+  // jp, in a column pair touching a plate column) is moved to the side of
+  // the node being built (side 0 below, 1 above): the moments are then
+  // extrapolated linearly from that side instead of mixed across the plate.
+  double trilin_clamped(const std::vector<double>& F, const Ext& E, const double p[3], int side) const {
     int bx = (int)std::floor(p[0]), bz = (int)std::floor(p[2]);
     int by = (int)std::floor(p[1]);
     if (by > ny - 2) by = ny - 2;
     if (by < 0) by = 0;
+    if (side >= 0 && by == pj) {
+      const int c0 = wrapi(bx, nx), c1 = wrapi(bx + 1, nx);
+      if ((c0 >= pi0 && c0 <= pi1) || (c1 >= pi0 && c1 <= pi1)) by = side ? pj + 1 : pj - 1;
+    }
     double fx = p[0] - bx, fy = p[1] - by, fz = p[2] - bz;
     double v = 0.0;
     for (int c = 0; c < 8; ++c) {
@@ -949,7 +1109,17 @@ void orc_moments(void* s, double* rho, double* u, int cartesian) {
 void orc_wall_force(void* s, int wall, double* total, double* per_node) {
   ((Sim<double>*)s)->wall_force(wall, total, per_node);
 }
+int orc_set_plate(void* s, int jp, int i0, int i1) { return ((Sim<double>*)s)->set_plate(jp, i0, i1) ? 0 : -1; }
+void orc_set_plate_displacement(void* s, const double* d, int reproject) {
+  ((Sim<double>*)s)->set_plate_displacement(d, reproject != 0);
+}
+void orc_set_plate_velocity(void* s, const double* v) { ((Sim<double>*)s)->set_plate_velocity(v); }
+void orc_plate_force(void* s, double* total, double* per_col) { ((Sim<double>*)s)->plate_force(total, per_col); }
 void orc_geometry(void* s, double* out28) { ((Sim<double>*)s)->geometry_export(out28); }
+void orc_chart(void* s, double* out) {
+  Sim<double>* S = (Sim<double>*)s;
+  std::memcpy(out, S->chart.data(), sizeof(double) * S->chart.size());
+}
 void orc_jacobian(void* s, double* out9) { ((Sim<double>*)s)->jacobian_export(out9); }
 
 // Forces on `wall` at states 1..K after the initial state given by f0, for the

@@ -6,6 +6,9 @@ Array conventions (all float64, C order):
   history      [10, nz, H, nx]   A, B^x, B^y, B^z, C^xx, C^xy, C^xz, C^yy, C^yz, C^zz
   displacement [nz, nx]          y-displacement of a wall
   wall vel.    [nz, nx, 3]       Cartesian
+  plate disp.  [nz, nx]          y-displacement of the plate's cross-section row
+  plate vel.   [nz, nx, 3]       Cartesian, per column (columns off the plate
+                                 take the nearest plate column's)
   geometry     [28, nz, H, nx]   sqrt g, g^ij (6), Gamma^i_jk (18), F^i (3)
   jacobian     [9, nz, H, nx]    J[a][i] = d h^a / d xi^i, row major
 """
@@ -54,12 +57,18 @@ def _lib():
             ("orc_step", [ctypes.c_int]),
             ("orc_moments", [_D, _D, ctypes.c_int]),
             ("orc_wall_force", [ctypes.c_int, _D, _D]),
+            ("orc_set_plate_displacement", [_D, ctypes.c_int]),
+            ("orc_set_plate_velocity", [_D]),
+            ("orc_plate_force", [_D, _D]),
             ("orc_geometry", [_D]),
+            ("orc_chart", [_D]),
             ("orc_jacobian", [_D]),
         ]:
             fn = getattr(L, name)
             fn.argtypes = [ctypes.c_void_p] + extra
             fn.restype = None
+        L.orc_set_plate.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        L.orc_set_plate.restype = ctypes.c_int
         L.orc_run_forces.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double, _D, _D, _D, ctypes.c_int, ctypes.c_int, _D]
         L.orc_run_forces.restype = None
         L.orc_dual_forces.argtypes = (
@@ -131,6 +140,26 @@ class Oracle:
         v = _c(v, (self.nz, self.nx, 3))
         _lib().orc_set_wall_velocity(self._h, int(wall), _p(v))
 
+    def set_plate(self, jp, i0, i1):
+        """Interior plate between fluid rows jp-1 and jp over columns i0..i1
+        (jp = 0 removes it)."""
+        if _lib().orc_set_plate(self._h, int(jp), int(i0), int(i1)) != 0:
+            raise ValueError("invalid plate")
+
+    def set_plate_displacement(self, d, reproject=False):
+        d = _c(d, (self.nz, self.nx))
+        _lib().orc_set_plate_displacement(self._h, _p(d), int(bool(reproject)))
+
+    def set_plate_velocity(self, v):
+        v = _c(v, (self.nz, self.nx, 3))
+        _lib().orc_set_plate_velocity(self._h, _p(v))
+
+    def plate_force(self, per_column=False):
+        tot = np.empty(3)
+        pc = np.empty((self.nz, self.nx, 3)) if per_column else None
+        _lib().orc_plate_force(self._h, _p(tot), _p(pc))
+        return (tot, pc) if per_column else tot
+
     def init_equilibrium(self, rho=None, ucart=None):
         rho = _c(rho, self.fluid_shape)
         ucart = _c(ucart, (3,) + self.fluid_shape)
@@ -168,6 +197,12 @@ class Oracle:
     def geometry(self):
         out = np.empty((28,) + self.fluid_shape)
         _lib().orc_geometry(self._h, _p(out))
+        return out
+
+    def chart(self):
+        """The chart in use, [3, nz, ny, nx]."""
+        out = np.empty((3, self.nz, self.ny, self.nx))
+        _lib().orc_chart(self._h, _p(out))
         return out
 
     def jacobian(self):

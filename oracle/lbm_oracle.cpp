@@ -26,7 +26,8 @@
 //   * Interior plate (Sec. IV.A.1 (ii), Sec. VI.A): a thin plate on the half
 //     row between fluid rows jp-1 and jp, over columns i0..i1 and all z.  A
 //     link between those rows is cut when its crossing point x lies in
-//     [i0 - 1/2, i1 + 1/2]; cut links bounce back halfway, like the walls.
+//     [i0 - 1/2, i1 + 1/2] (periodically); cut links bounce back halfway,
+//     like the walls.
 //   * Geometry export per fluid node (28 values): sqrt g, g^xx, g^xy, g^xz,
 //     g^yy, g^yz, g^zz, Gamma^i_jk for i = x,y,z and jk in
 //     (xx,xy,xz,yy,yz,zz), then F^x, F^y, F^z.
@@ -398,12 +399,14 @@ template <class T> struct Sim {
 
   // The link from fluid node (i, jf) along (cx, cy) crosses the plate: it
   // joins rows jp-1 and jp and crosses the half row at x = i + cx/2 within
-  // [i0 - 1/2, i1 + 1/2].  (x is not wrapped, so a plate over every column
-  // also cuts the links through the periodic seam.)
+  // [i0 - 1/2, i1 + 1/2] on the periodic x axis.  The seam point
+  // x = -1/2 = nx - 1/2 lies on the plate when the plate reaches column 0 or
+  // column nx - 1; a link and its reverse are then cut alike.
   bool plate_cut(int i, int jf, int cx, int cy) const {
     if (pj == 0 || cy == 0) return false;
     if (cy > 0 ? jf != pj - 1 : jf != pj) return false;
     const int s2 = 2 * i + cx;
+    if (s2 == -1 || s2 == 2 * nx - 1) return pi0 == 0 || pi1 == nx - 1;
     return s2 >= 2 * pi0 - 1 && s2 <= 2 * pi1 + 1;
   }
   long nid(int i, int jf, int k) const { return ((long)k * H + jf) * nx + i; }

@@ -194,3 +194,28 @@ def test_reprojection_keeps_the_two_sides_of_the_plate_apart():
     err = np.abs(o.populations() - ref.populations()).max(axis=(0, 1, 3))
     assert err[1:-1].max() < 1e-14, err
     assert err.max() < 1e-7, err
+
+
+@pytest.mark.parametrize("shift", [5, 9, 19])
+def test_plate_across_the_periodic_seam_is_translation_invariant(shift):
+    """Periodic x: a partial plate moved by s columns, also across the seam
+    (so that its end falls on the seam or it straddles it), gives the same
+    flow moved by s.  This pins the cut rule on the periodic axis: a link
+    through the seam and its reverse are cut alike."""
+    nx, H, nz, tau, jp = 24, 8, 1, 0.7, 4
+    i0, i1 = 5, 14
+    res = []
+    for s in (0, shift):
+        o = Oracle(nx, H + 2, nz, tau)
+        o.set_body_force([1e-5, 2e-6, 0])
+        a, b = (i0 + s) % nx, (i1 + s) % nx
+        if a <= b:
+            o.set_plate(jp, a, b)
+        else:
+            raise AssertionError("the plate must not wrap")
+        o.set_wall_displacement(1, np.zeros((nz, nx)))
+        o.init_equilibrium()
+        o.step(60)
+        res.append(o.populations())
+    f0, f1 = res
+    assert np.abs(np.roll(f0, shift, axis=3) - f1).max() < 1e-15

@@ -174,10 +174,50 @@ int lbm_wall_force(lbm_ctx* ctx, int wall, int method, double* d_total3, double*
 int lbm_couple(lbm_ctx* ctx, int wall, const double* d_disp, const double* d_vcart, int n, double* d_total3,
                double* d_per_node);
 
+/* Interior plate (Sec. IV.A.1 (ii), Sec. VI.A: the flag, here without its
+ * structural model): a thin plate on the half row between fluid rows jp - 1
+ * and jp (1 <= jp <= H - 1) over columns i0..i1 (0 <= i0 <= i1 <= nx - 1) and
+ * every z.  A link between those two rows whose crossing point x (halfway
+ * between its end columns) lies in [i0 - 1/2, i1 + 1/2] is cut: it bounces
+ * back halfway, with the moving-plate term, on either face, and the lattice
+ * gradient replaces a neighbour across the plate by the mirror ghost of the
+ * node on its own side, as at the walls.  A plate over every column also
+ * cuts the links through the periodic seam.  jp = 0 removes the plate.  Set
+ * it before the state (ESTATE after lbm_init_equilibrium or
+ * lbm_set_populations); EINVAL outside the ranges.  It resets the plate's
+ * displacement and velocity to zero.  The fused step then runs on 64x4 tiles
+ * whatever lbm_set_tuning asked for; the adjoint (lbm_forward_record) is not
+ * provided with a plate (EUNSUPPORTED). */
+int lbm_set_plate(lbm_ctx* ctx, int jp, int i0, int i1);
+
+/* The plate's cross-section displacement d_disp [nz][nx] (device, the
+ * y-displacement of the half row the plate lies on, in every column: the
+ * caller continues the plate's shape beyond its ends) builds the chart
+ * (Sec. IV.A.1 (ii)): y_c = xi_y + (wall blend of lbm_set_wall_displacement)
+ * + D(x, z) S(eta), with S the natural cubic spline through (0, 0),
+ * (jp, 1), (H, 0) in eta = xi_y - 1/2 (C^2 across the plate, the walls held
+ * in place).  NULL = zero.  reproject as in lbm_set_metric; near the plate
+ * the re-projection interpolates from the node's own side only.  ESTATE
+ * without a plate or, with reproject, without a state. */
+int lbm_set_plate_displacement(lbm_ctx* ctx, const double* d_disp, int reproject);
+
+/* Cartesian plate velocity per column, d_vcart [nz][nx][3] (device; columns
+ * off the plate take the nearest plate column's, for the diagonal links at
+ * its ends).  NULL = at rest.  ESTATE without a plate. */
+int lbm_set_plate_velocity(lbm_ctx* ctx, const double* d_vcart);
+
+/* Node-exact force of the fluid on the plate at the current state: per plate
+ * column, the traction sqrt g T^{iy} e_i at the fluid node below the plate
+ * minus that at the node above (the two faces' outward normals), as in
+ * lbm_wall_force.  d_total3: the sum (3 doubles, device); d_per_column
+ * [nz][nx][3] or NULL, zero outside i0..i1.  Asynchronous.  ESTATE without a
+ * plate or a state; EINVAL for d_total3 NULL. */
+int lbm_plate_force(lbm_ctx* ctx, double* d_total3, double* d_per_column);
+
 /* Run K steps from the current state and record the force on `wall` at
  * states 1..K into d_forces [K][3]; the initial state and a checkpoint every
  * ckpt_every steps are kept for lbm_backward.  K and ckpt_every must match
- * lbm_reserve_adjoint.  Needs the FP64 form. */
+ * lbm_reserve_adjoint.  Needs the FP64 form and no interior plate. */
 int lbm_forward_record(lbm_ctx* ctx, int K, int ckpt_every, int wall, int method, double* d_forces);
 
 /* Reverse sweep of the last lbm_forward_record: given dL/dF [K][3], write

@@ -51,6 +51,9 @@ Grid make_grid(const lbm_grid* h) {
   g.nz = h->nz;
   g.H = h->ny - 2;
   g.N = (long long)g.nx * g.H * g.nz;
+  g.pj = 0;
+  g.pi0 = 0;
+  g.pi1 = -1;
   return g;
 }
 
@@ -79,6 +82,9 @@ void carve_core(Carver& c, const Grid& g, int precision, Fields& F) {
   F.hist[1] = c.take(sz * lbm::H_N * N);
   F.mom = c.take(sz * 4 * N);
   F.uw = c.take(sz * 2 * 3 * (size_t)g.nz * g.nx);
+  F.up = c.take(sz * 2 * 3 * (size_t)g.nz * g.nx);
+  F.vplate = (double*)c.take(sizeof(double) * 3 * (size_t)g.nz * g.nx);
+  F.dplate = (double*)c.take(sizeof(double) * (size_t)g.nz * g.nx);
   F.disp = (double*)c.take(sizeof(double) * 2 * (size_t)g.nz * g.nx);
   F.vwall = (double*)c.take(sizeof(double) * 2 * 3 * (size_t)g.nz * g.nx);
   F.full = (double*)c.take(sizeof(double) * 19 * N);
@@ -123,6 +129,7 @@ template <class T> int geometry_path(lbm_ctx* c, int reproject) {
   else
     LBM_HIP(c, lbm::launch_geometry<T>(F, c->stream, c->Fc));
   LBM_HIP(c, lbm::launch_wall_velocity<T>(F, c->stream));
+  if (F.g.pj) LBM_HIP(c, lbm::launch_plate_velocity<T>(F, c->stream));
   c->have_geo = 1;
   return LBM_OK;
 }
@@ -175,6 +182,9 @@ int lbm_create(lbm_ctx** out, const lbm_grid* h_grid, int lattice, double tau, i
   hipError_t e = hipMemsetAsync(F.disp, 0, sizeof(double) * 2 * (size_t)F.g.nz * F.g.nx, c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(F.vwall, 0, sizeof(double) * 6 * (size_t)F.g.nz * F.g.nx, c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(F.uw, 0, sz * 6 * (size_t)F.g.nz * F.g.nx, c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(F.up, 0, sz * 6 * (size_t)F.g.nz * F.g.nx, c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(F.vplate, 0, sizeof(double) * 3 * (size_t)F.g.nz * F.g.nx, c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(F.dplate, 0, sizeof(double) * (size_t)F.g.nz * F.g.nx, c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(F.flag, 0, ALIGN, c->stream);
   if (e != hipSuccess) {
     delete c;
@@ -258,6 +268,75 @@ int lbm_set_wall_velocity(lbm_ctx* c, int wall, const double* d_vcart) {
     else
       LBM_HIP(c, lbm::launch_wall_velocity<float>(c->F, c->stream));
   }
+  return LBM_OK;
+}
+
+int lbm_set_plate(lbm_ctx* c, int jp, int i0, int i1) {
+  LBM_GUARD(c);
+  Fields& F = c->F;
+  if (jp == 0) {
+    F.g.pj = 0;
+    F.g.pi0 = 0;
+    F.g.pi1 = -1;
+    return LBM_OK;
+  }
+  if (jp < 1 || jp > F.g.H - 1 || i0 < 0 || i1 < i0 || i1 > F.g.nx - 1)
+    return fail(c, LBM_EINVAL, "plate must lie between fluid rows 1..H-1 over columns 0..nx-1");
+  if (c->have_state) return fail(c, LBM_ESTATE, "set the plate before the state");
+  F.g.pj = jp;
+  F.g.pi0 = i0;
+  F.g.pi1 = i1;
+  const size_t ncol = (size_t)F.g.nz * F.g.nx;
+  LBM_HIP(c, hipMemsetAsync(F.dplate, 0, sizeof(double) * ncol, c->stream));
+  LBM_HIP(c, hipMemsetAsync(F.vplate, 0, sizeof(double) * 3 * ncol, c->stream));
+  if (c->have_geo) {
+    if (c->precision == LBM_FP64)
+      LBM_HIP(c, lbm::launch_plate_velocity<double>(F, c->stream));
+    else
+      LBM_HIP(c, lbm::launch_plate_velocity<float>(F, c->stream));
+  }
+  return LBM_OK;
+}
+
+int lbm_set_plate_displacement(lbm_ctx* c, const double* d_disp, int reproject) {
+  LBM_GUARD(c);
+  if (!c->F.g.pj) return fail(c, LBM_ESTATE, "no plate");
+  if (reproject && !c->have_state) return fail(c, LBM_ESTATE, "re-projection needs a state");
+  const size_t ncol = (size_t)c->F.g.nz * c->F.g.nx;
+  if (d_disp)
+    LBM_HIP(c, hipMemcpyAsync(c->F.dplate, d_disp, sizeof(double) * ncol, hipMemcpyDeviceToDevice, c->stream));
+  else
+    LBM_HIP(c, hipMemsetAsync(c->F.dplate, 0, sizeof(double) * ncol, c->stream));
+  LBM_HIP(c, lbm::launch_chart_from_disp(c->F, c->stream));
+  return geometry_dispatch(c, reproject);
+}
+
+int lbm_set_plate_velocity(lbm_ctx* c, const double* d_vcart) {
+  LBM_GUARD(c);
+  if (!c->F.g.pj) return fail(c, LBM_ESTATE, "no plate");
+  const size_t n = (size_t)c->F.g.nz * c->F.g.nx * 3;
+  if (d_vcart)
+    LBM_HIP(c, hipMemcpyAsync(c->F.vplate, d_vcart, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
+  else
+    LBM_HIP(c, hipMemsetAsync(c->F.vplate, 0, sizeof(double) * n, c->stream));
+  if (c->have_geo) {
+    if (c->precision == LBM_FP64)
+      LBM_HIP(c, lbm::launch_plate_velocity<double>(c->F, c->stream));
+    else
+      LBM_HIP(c, lbm::launch_plate_velocity<float>(c->F, c->stream));
+  }
+  return LBM_OK;
+}
+
+int lbm_plate_force(lbm_ctx* c, double* d_total3, double* d_per_column) {
+  LBM_GUARD(c);
+  if (!c->F.g.pj) return fail(c, LBM_ESTATE, "no plate");
+  if (!d_total3) return fail(c, LBM_EINVAL, "total output is NULL");
+  if (!c->have_state) return fail(c, LBM_ESTATE, "no state");
+  if (c->precision == LBM_FP64)
+    LBM_HIP(c, lbm::launch_wall_force<double>(c->F, c->stream, 2, c->tau, d_total3, d_per_column));
+  else
+    LBM_HIP(c, lbm::launch_wall_force<float>(c->F, c->stream, 2, (float)c->tau, d_total3, d_per_column));
   return LBM_OK;
 }
 
@@ -465,6 +544,7 @@ int lbm_forward_record(lbm_ctx* c, int K, int ckpt_every, int wall, int method, 
   if (method != LBM_FORCE_STRESS) return fail(c, LBM_EUNSUPPORTED, "only the stress method is provided");
   if (!d_forces) return fail(c, LBM_EINVAL, "forces output is NULL");
   if (!c->have_state) return fail(c, LBM_ESTATE, "no state");
+  if (c->F.g.pj) return fail(c, LBM_EUNSUPPORTED, "the adjoint does not cover an interior plate");
   {
     hipError_t e = lbm::adjoint_forward(c->F, c->adj, c->stream, K, ckpt_every, wall, c->tau, d_forces);
     if (e == hipErrorNotSupported) return fail(c, LBM_EUNSUPPORTED, "adjoint not available in this build");

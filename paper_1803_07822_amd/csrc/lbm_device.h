@@ -43,7 +43,24 @@ __host__ __device__ constexpr int sym(int a, int b) {
 struct Grid {
   int nx, ny, nz, H;  // H = ny - 2 fluid layers
   long long N;        // fluid nodes
+  // Interior plate on the half row between fluid rows pj - 1 and pj over
+  // columns pi0..pi1 and every z (pj = 0: none).
+  int pj, pi0, pi1;
 };
+
+// The link from fluid node (i, jf) along (x, y) crosses the plate: it joins
+// rows pj - 1 and pj and crosses the half row at i + x/2 within
+// [pi0 - 1/2, pi1 + 1/2] on the periodic x axis, where the seam point
+// -1/2 = nx - 1/2 belongs to a plate that reaches column 0 or column nx - 1
+// (so a link and its reverse are cut alike).  Such links bounce back
+// halfway, as at the walls.
+__device__ __forceinline__ bool plate_cut(const Grid& g, int i, int jf, int x, int y) {
+  if (y == 0 || g.pj == 0) return false;
+  if (y > 0 ? jf != g.pj - 1 : jf != g.pj) return false;
+  const int s2 = 2 * i + x;
+  if (s2 == -1 || s2 == 2 * g.nx - 1) return g.pi0 == 0 || g.pi1 == g.nx - 1;
+  return s2 >= 2 * g.pi0 - 1 && s2 <= 2 * g.pi1 + 1;
+}
 
 // Geometry field indices in the per-node geometry block (28 planes):
 // 0: sqrt g - 1; 1..6: g^ij - delta^ij; 7..24: Gamma^i_jk (i major, jk sym);

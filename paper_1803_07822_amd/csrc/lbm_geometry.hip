@@ -37,15 +37,36 @@ __device__ __forceinline__ void inv3(const double m[3][3], double r[3][3], doubl
   r[2][2] = (m[0][0] * m[1][1] - m[0][1] * m[1][0]) * id;
 }
 
-__global__ __launch_bounds__(BX * BY) void k_chart_from_disp(Grid g, const double* __restrict__ disp, double* __restrict__ chart) {
+// Shape of the plate's displacement across the channel (Sec. IV.A.1 (ii)):
+// the natural cubic spline through (0, 0), (eta_p, 1), (H, 0) in the
+// wall-normal coordinate eta (zero second derivative at both walls).  On each
+// piece it is the cubic with the end values and the end second derivatives
+// 0 (at the wall) and M (at the plate); matching the slopes at the plate
+// gives M = -3 (1/a + 1/b) / H for the knot spacings a = eta_p, b = H - eta_p.
+__device__ __forceinline__ double plate_spline(double eta, int eta_p, int H) {
+  const double a = eta_p, b = H - eta_p, M = -3.0 * (1.0 / a + 1.0 / b) / H;
+  const double len = eta <= a ? a : b;
+  const double t = eta <= a ? eta : H - eta;  // distance from the nearer wall's knot
+  return t * (M * t * t + 6.0 - M * len * len) / (6.0 * len);
+}
+
+// Chart of the walls and the plate: the wall displacements blended linearly
+// across the channel (Sec. IV.A.1 (i)) plus the plate's cross-section
+// displacement carried by plate_spline; eta = xi_y - 1/2 puts the halfway
+// walls at 0 and H and the plate (between fluid rows pj - 1 and pj) at pj.
+__global__ __launch_bounds__(BX * BY) void k_chart_from_disp(Grid g, const double* __restrict__ disp,
+                                                             const double* __restrict__ dplate,
+                                                             double* __restrict__ chart) {
   const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
   if (i >= g.nx || j >= g.ny) return;
   const long long NC = (long long)g.nz * g.ny * g.nx;
   const long long p = ((long long)k * g.ny + j) * g.nx + i;
   const long long q = (long long)k * g.nx + i;
   const double eta = j - 0.5, s = eta / g.H;
+  double y = (double)j + (1.0 - s) * disp[q] + s * disp[(long long)g.nz * g.nx + q];
+  if (g.pj) y += dplate[q] * plate_spline(eta, g.pj, g.H);
   chart[p] = (double)i;
-  chart[NC + p] = (double)j + (1.0 - s) * disp[q] + s * disp[(long long)g.nz * g.nx + q];
+  chart[NC + p] = y;
   chart[2 * NC + p] = (double)k;
 }
 
@@ -331,11 +352,42 @@ __global__ __launch_bounds__(BX * BY) void k_wall_velocity(Grid g, const double*
   }
 }
 
+// Chart components J^{-1} v of the plate velocity at the fluid nodes below
+// (side 0, row pj - 1) and above (side 1, row pj) the plate's half row; a
+// column off the plate takes the velocity of the nearest plate column (the
+// diagonal links at the plate's ends).
+template <class T>
+__global__ __launch_bounds__(BX * BY) void k_plate_velocity(Grid g, const double* __restrict__ jac, const double* __restrict__ vplate, T* __restrict__ up) {
+  const int i = blockIdx.x * BX + threadIdx.x, k = blockIdx.y * BY + threadIdx.y;
+  if (i >= g.nx || k >= g.nz) return;
+  const int ic = i < g.pi0 ? g.pi0 : (i > g.pi1 ? g.pi1 : i);
+  const double* v = vplate + ((long long)k * g.nx + ic) * 3;
+  for (int side = 0; side < 2; ++side) {
+    const long long n = ((long long)k * g.H + (g.pj - 1 + side)) * g.nx + i;
+    double J[3][3], Ji[3][3], det;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) J[a][b] = jac[(a * 3 + b) * g.N + n];
+    inv3(J, Ji, det);
+    const long long c = (((long long)side * g.nz + k) * g.nx + i) * 3;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) up[c + a] = (T)(Ji[a][0] * v[0] + Ji[a][1] * v[1] + Ji[a][2] * v[2]);
+  }
+}
+
 }  // namespace
 
 hipError_t launch_chart_from_disp(Fields& F, hipStream_t s) {
   dim3 b(BX, BY), gr((F.g.nx + BX - 1) / BX, (F.g.ny + BY - 1) / BY, F.g.nz);
-  hipLaunchKernelGGL(k_chart_from_disp, gr, b, 0, s, F.g, F.disp, F.chart);
+  hipLaunchKernelGGL(k_chart_from_disp, gr, b, 0, s, F.g, F.disp, F.dplate, F.chart);
+  return hipGetLastError();
+}
+
+template <class T> hipError_t launch_plate_velocity(Fields& F, hipStream_t s) {
+  if (!F.g.pj) return hipSuccess;
+  dim3 b(BX, BY);
+  hipLaunchKernelGGL(k_plate_velocity<T>, col_grid(F.g), b, 0, s, F.g, F.jac, F.vplate, (T*)F.up);
   return hipGetLastError();
 }
 
@@ -373,5 +425,7 @@ template hipError_t launch_body_force<double>(Fields&, hipStream_t, const double
 template hipError_t launch_body_force<float>(Fields&, hipStream_t, const double*);
 template hipError_t launch_wall_velocity<double>(Fields&, hipStream_t);
 template hipError_t launch_wall_velocity<float>(Fields&, hipStream_t);
+template hipError_t launch_plate_velocity<double>(Fields&, hipStream_t);
+template hipError_t launch_plate_velocity<float>(Fields&, hipStream_t);
 
 }  // namespace lbm

@@ -28,6 +28,9 @@ struct Fields {
   void* hist[2];  // [10][N] T forcing history, flips with the populations
   void* mom;      // [4][N] T
   void* uw;       // [2][nz][nx][3] T
+  void* up;       // [2][nz][nx][3] T plate velocity, chart components at the node below (0) / above (1)
+  double* vplate; // [nz][nx][3] Cartesian plate velocity per column
+  double* dplate; // [nz][nx] y-displacement of the plate's cross-section row
   double* disp;   // [2][nz][nx]
   double* vwall;  // [2][nz][nx][3] Cartesian wall velocity
   double* full;   // [19][N] FP64 scratch
@@ -94,6 +97,7 @@ hipError_t launch_stream_probe(int precision, long long n, const void* in, void*
 template <class T> hipError_t launch_geometry(Fields& F, hipStream_t s, const double Fc[3]);
 template <class T> hipError_t launch_body_force(Fields& F, hipStream_t s, const double Fc[3]);
 template <class T> hipError_t launch_wall_velocity(Fields& F, hipStream_t s);
+template <class T> hipError_t launch_plate_velocity(Fields& F, hipStream_t s);
 hipError_t launch_chart_from_disp(Fields& F, hipStream_t s);
 
 // state
@@ -108,6 +112,7 @@ template <class T> hipError_t launch_step_fused(Fields& F, hipStream_t s, T tau,
 // Planes per block the fused step runs with (F.zc, or the automatic choice).
 template <class T> hipError_t fused_step_chunk(Fields& F, int* zc);
 template <class T> hipError_t launch_moments_out(Fields& F, hipStream_t s, double* rho, double* u, int cart);
+// wall 0 / 1: the walls; wall 2: the interior plate (both faces, plate columns)
 template <class T> hipError_t launch_wall_force(Fields& F, hipStream_t s, int wall, T tau, double* total,
                                                 double* per_node);
 template <class T> hipError_t launch_reproject(Fields& F, hipStream_t s, const double Fc[3], T tau);

@@ -47,6 +47,18 @@ __device__ __forceinline__ void cell_setup(const Grid& g, int layers, int yoff, 
   for (int a = 0; a < 3; ++a) c.fr[a] = fr[a];
 }
 
+// A cell whose layers by, by + 1 are the two fluid rows on either side of the
+// plate, in a column pair touching a plate column, is moved to the side of the
+// node being built (side 0 below, 1 above): the fields are then extrapolated
+// linearly from that side instead of mixed across the plate.  The position
+// search and the moment interpolation of a node use the same rule.
+__device__ __forceinline__ int plate_side_layer(const Grid& g, int side, int bx, int by) {
+  if (!g.pj || by != g.pj) return by;
+  const int c0 = wrapr(bx, g.nx), c1 = wrapr(bx + 1, g.nx);
+  if ((c0 >= g.pi0 && c0 <= g.pi1) || (c1 >= g.pi0 && c1 <= g.pi1)) return side ? g.pj + 1 : g.pj - 1;
+  return by;
+}
+
 // Trilinear value of F in the cell and its gradient in cell coordinates.
 __device__ __forceinline__ double cell_eval(const Cell& c, const double* __restrict__ F, double grad[3]) {
   double v = 0.0;
@@ -95,7 +107,8 @@ __device__ __forceinline__ void inv3d(const double m[3][3], double r[3][3]) {
 template <class T, int l>
 __device__ __forceinline__ T pull_rp(const T* __restrict__ pop, const Grid& g, int i, int jf, int k, long long n) {
   constexpr int x = cx(l), y = cy(l), z = cz(l);
-  if ((y > 0 && jf == 0) || (y < 0 && jf == g.H - 1)) return pop[(long long)opp(l) * g.N + n];
+  if ((y > 0 && jf == 0) || (y < 0 && jf == g.H - 1) || plate_cut(g, i, jf, -x, -y))
+    return pop[(long long)opp(l) * g.N + n];
   const int is = x ? wrapr(i - x, g.nx) : i;
   const int ks = z ? wrapr(k - z, g.nz) : k;
   return pop[(long long)l * g.N + ((long long)ks * g.H + (jf - y)) * g.nx + is];
@@ -214,6 +227,7 @@ __global__ __launch_bounds__(BX * BY) void k_rp_new(Grid g, const double* __rest
   const long long pc = ((long long)k * g.ny + (jf + 1)) * g.nx + i;
   const double p[3] = {chart[pc], chart[NC + pc], chart[2 * NC + pc]};
   // psi: xi + u_old(xi) = p
+  const int side = jf >= g.pj ? 1 : 0;
   double xi[3] = {(double)i, (double)(jf + 1), (double)k};
   for (int it = 0; it < 50; ++it) {
     double r[3], Jm[3][3], Ji[3][3];
@@ -222,6 +236,7 @@ __global__ __launch_bounds__(BX * BY) void k_rp_new(Grid g, const double* __rest
     int by = (int)floor(xi[1]);
     if (by < -3) by = -3;
     if (by > g.ny + 1) by = g.ny + 1;
+    by = plate_side_layer(g, side, bx, by);
     const double fr[3] = {xi[0] - bx, xi[1] - by, xi[2] - bz};
     Cell c;
     cell_setup(g, g.ny + 6, 3, bx, by, bz, fr, c);
@@ -250,6 +265,7 @@ __global__ __launch_bounds__(BX * BY) void k_rp_new(Grid g, const double* __rest
   int by = (int)floor(q1);
   if (by > g.ny - 2) by = g.ny - 2;
   if (by < 0) by = 0;
+  by = plate_side_layer(g, side, bx, by);
   const double fr[3] = {xi[0] - bx, q1 - by, xi[2] - bz};
   Cell cl;
   cell_setup(g, g.ny, 0, bx, by, bz, fr, cl);
@@ -320,16 +336,17 @@ __global__ __launch_bounds__(BX * BY) void k_rp_new(Grid g, const double* __rest
   // f~ - w = (w/sqrt g)[rho + 3 j.c + 4.5 a2:cc - 1.5 tr a2] - w
   const double sg = 1.0 + (double)sgd;
   const double a0 = m[0] - sg;  // (rho/sqrt g - 1) sqrt g
-  // Store g~_l = f~_l - F_l/2 in the pull layout: at x - c_l when that node
-  // is fluid, else (a link through the wall) in the bounce-back slot opp(l)
-  // of this node.  Every slot of the layout has exactly one writer.
+  // Store g~_l = f~_l - F_l/2 in the pull layout: at x - c_l when the link
+  // from there is open, else (a link through a wall or the plate) in the
+  // bounce-back slot opp(l) of this node.  Every slot of the layout has
+  // exactly one writer.
   for_q([&](auto L) {
     constexpr int l = decltype(L)::value;
     constexpr int x = cx(l), y = cy(l), z = cz(l);
     const double fdev = wgt(l) / sg * hermite_term<double, l>(a0, jt, a2);
     const T v = (T)(fdev - 0.5 * (double)Fp[l]);
     const int js = jf - y;
-    if (js < 0 || js >= g.H) {
+    if (js < 0 || js >= g.H || plate_cut(g, i, jf, -x, -y)) {
       pop[(long long)opp(l) * g.N + n] = v;
     } else {
       const int is = x ? wrapr(i - x, g.nx) : i;

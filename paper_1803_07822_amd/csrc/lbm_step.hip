@@ -42,7 +42,8 @@ __device__ __forceinline__ bool node_pos(const Grid& g, Pos& p) {
 template <class T, int l>
 __device__ __forceinline__ T pull(const T* __restrict__ pop, const Grid& g, const Pos& p) {
   constexpr int x = cx(l), y = cy(l), z = cz(l);
-  if ((y > 0 && p.jf == 0) || (y < 0 && p.jf == g.H - 1)) return pop[(long long)opp(l) * g.N + p.n];
+  if ((y > 0 && p.jf == 0) || (y < 0 && p.jf == g.H - 1) || plate_cut(g, p.i, p.jf, -x, -y))
+    return pop[(long long)opp(l) * g.N + p.n];
   const int is = x ? wrapd(p.i - x, g.nx) : p.i;
   const int ks = z ? wrapd(p.k - z, g.nz) : p.k;
   const int js = p.jf - y;
@@ -91,10 +92,13 @@ __device__ __forceinline__ void streamed_moments(const T* __restrict__ pop, cons
 
 // Second-order isotropic lattice gradient dj[k][i] = (1/c_s^2) sum_l w_l c_l^k
 // j^i(x + c_l) (App. D).  Neighbours in a wall layer carry the mirror ghost
-// j = 2 rho_m u_w - j_m of the fluid node m in the same column next to the wall.
+// j = 2 rho_m u_w - j_m of the fluid node m in the same column next to the wall;
+// a neighbour across the plate is replaced in the same way by the ghost of the
+// node m on this side in the neighbour's column, with the plate velocity.
 template <class T>
 __device__ __forceinline__ void lattice_gradient(const T* __restrict__ mom, const T* __restrict__ uw, const int mv0,
-                                                 const int mv1, const Grid& g, const Pos& p, T dj[3][3]) {
+                                                 const int mv1, const T* __restrict__ up, const Grid& g,
+                                                 const Pos& p, T dj[3][3]) {
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
@@ -107,7 +111,13 @@ __device__ __forceinline__ void lattice_gradient(const T* __restrict__ mom, cons
     const int kn = z ? wrapd(p.k + z, g.nz) : p.k;
     const int jn = p.jf + y;
     T jb[3];
-    if (jn >= 0 && jn < g.H) {
+    if (plate_cut(g, p.i, p.jf, x, y)) {
+      const long long m = ((long long)kn * g.H + p.jf) * g.nx + in;
+      const T r2 = T(2) * (T(1) + mom[m]);
+      const long long c = (((long long)(p.jf == g.pj ? 1 : 0) * g.nz + kn) * g.nx + in) * 3;
+#pragma unroll
+      for (int b = 0; b < 3; ++b) jb[b] = r2 * up[c + b] - mom[(1 + b) * g.N + m];
+    } else if (jn >= 0 && jn < g.H) {
       const long long m = ((long long)kn * g.H + jn) * g.nx + in;
       jb[0] = mom[1 * g.N + m];
       jb[1] = mom[2 * g.N + m];
@@ -158,7 +168,8 @@ __global__ __launch_bounds__(BX* BY) void k_collide(Grid g, const T* __restrict_
                                                    const T* __restrict__ hist, T* __restrict__ hout,
                                                    const T* __restrict__ geo,
                                                    const T* __restrict__ mom, const T* __restrict__ uw, int mv0,
-                                                   int mv1, T tau, int* __restrict__ flag) {
+                                                   int mv1, const T* __restrict__ up, T tau,
+                                                   int* __restrict__ flag) {
   Pos p;
   if (!node_pos(g, p)) return;
   NodeGeo<T> G;
@@ -175,7 +186,7 @@ __global__ __launch_bounds__(BX* BY) void k_collide(Grid g, const T* __restrict_
   const T dr = mom[p.n];
   const T j[3] = {mom[g.N + p.n], mom[2 * g.N + p.n], mom[3 * g.N + p.n]};
   T dj[3][3];
-  lattice_gradient(mom, uw, mv0, mv1, g, p, dj);
+  lattice_gradient(mom, uw, mv0, mv1, up, g, p, dj);
   T ne[Q], Tm[6];
   node_stress(G, ft, dr, j, tau, ne, Tm);
   Coef<T> c;
@@ -200,6 +211,13 @@ __global__ __launch_bounds__(BX* BY) void k_collide(Grid g, const T* __restrict_
         if (cz(l)) cu += T(cz(l)) * u[2];
         v -= T(6.0 * wgt(l)) * isg * rho * cu;
       }
+    }
+    if (plate_cut(g, p.i, p.jf, cx(l), y)) {
+      const T* u = up + (((long long)(p.jf == g.pj ? 1 : 0) * g.nz + p.k) * g.nx + p.i) * 3;
+      T cu = T(y) * u[1];
+      if (cx(l)) cu += T(cx(l)) * u[0];
+      if (cz(l)) cu += T(cz(l)) * u[2];
+      v -= T(6.0 * wgt(l)) * isg * rho * cu;
     }
     chk += v;
     pout[(long long)l * g.N + p.n] = v;
@@ -276,7 +294,8 @@ __global__ __launch_bounds__(BX * BY) void k_moments_full(Grid g, const double* 
 // F(x, -1) at the first step).
 template <class T>
 __global__ __launch_bounds__(BX * BY) void k_hist_full(Grid g, const double* __restrict__ f, const T* __restrict__ geo, const T* __restrict__ mom,
-                            const T* __restrict__ uw, int mv0, int mv1, T tau, T* __restrict__ hist) {
+                            const T* __restrict__ uw, int mv0, int mv1, const T* __restrict__ up, T tau,
+                            T* __restrict__ hist) {
   Pos p;
   if (!node_pos(g, p)) return;
   NodeGeo<T> G;
@@ -289,7 +308,7 @@ __global__ __launch_bounds__(BX * BY) void k_hist_full(Grid g, const double* __r
   const T dr = mom[p.n];
   const T j[3] = {mom[g.N + p.n], mom[2 * g.N + p.n], mom[3 * g.N + p.n]};
   T dj[3][3];
-  lattice_gradient(mom, uw, mv0, mv1, g, p, dj);
+  lattice_gradient(mom, uw, mv0, mv1, up, g, p, dj);
   T ne[Q], Tm[6];
   node_stress(G, ft, dr, j, tau, ne, Tm);
   Coef<T> c;
@@ -315,8 +334,8 @@ __global__ __launch_bounds__(BX * BY) void k_full_to_streamed(Grid g, double* __
   });
 }
 
-// Inverse of the pull: pop[l][y] = g~_l(y + c_l) if y + c_l is fluid, else
-// g~_opp(l)(y).
+// Inverse of the pull: pop[l][y] = g~_l(y + c_l) if the link from y to
+// y + c_l is open, else (through a wall or the plate) g~_opp(l)(y).
 template <class T>
 __global__ __launch_bounds__(BX * BY) void k_unpull(Grid g, const double* __restrict__ gs, T* __restrict__ pop) {
   Pos p;
@@ -326,7 +345,7 @@ __global__ __launch_bounds__(BX * BY) void k_unpull(Grid g, const double* __rest
     constexpr int x = cx(l), y = cy(l), z = cz(l);
     const int jd = p.jf + y;
     double v;
-    if (jd < 0 || jd >= g.H) {
+    if (jd < 0 || jd >= g.H || plate_cut(g, p.i, p.jf, x, y)) {
       v = gs[(long long)opp(l) * g.N + p.n];
     } else {
       const int id = x ? wrapd(p.i + x, g.nx) : p.i;
@@ -394,8 +413,41 @@ __global__ __launch_bounds__(BX * BY) void k_moments_out(Grid g, const T* __rest
   }
 }
 
-// Node-exact wall traction per column: sqrt g T^{i y} e_i at the fluid layer
-// next to the wall (outward normal sign), summed per block.
+// Node-exact traction sqrt g T^{i y} e_i (Cartesian) at fluid node p, times
+// sgn, added to t.
+template <class T>
+__device__ __forceinline__ void node_traction(const Grid& g, const T* __restrict__ pop, const T* __restrict__ hist,
+                                              const T* __restrict__ geo, const double* __restrict__ jac, T tau,
+                                              const Pos& p, double sgn, double t[3]) {
+  NodeGeo<T> G;
+  load_geo(geo, g.N, p.n, G);
+  Coef<T> cp;
+  load_coef(hist, g.N, p.n, cp);
+  const T isg = T(1) / (T(1) + G.sgd);
+  T Fp[Q], ft[Q];
+  forcing_pops(cp, isg, Fp);
+  for_q([&](auto L) {
+    constexpr int l = decltype(L)::value;
+    ft[l] = pull<T, l>(pop, g, p) + T(0.5) * Fp[l];
+  });
+  T dr, j[3];
+  streamed_moments(pop, hist, G.sgd, g, p, dr, j);
+  T ne[Q], Tm[6];
+  node_stress(G, ft, dr, j, tau, ne, Tm);
+  const double sg = 1.0 + (double)G.sgd;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    double s = 0.0;
+#pragma unroll
+    for (int i2 = 0; i2 < 3; ++i2) s += (double)Tm[sym(i2, 1)] * jac[(a * 3 + i2) * g.N + p.n];
+    t[a] += sgn * sg * s;
+  }
+}
+
+// Force per column on a wall (wall 0 / 1: the traction at the fluid layer
+// next to it, outward-normal sign) or on the plate (wall 2: the traction of
+// both faces in the plate columns, + at the node below and - at the node
+// above; zero in the other columns), summed per block.
 template <class T>
 __global__ __launch_bounds__(BX* BY) void k_wall_force(Grid g, int wall, const T* __restrict__ pop,
                                                       const T* __restrict__ hist, const T* __restrict__ geo,
@@ -406,32 +458,18 @@ __global__ __launch_bounds__(BX* BY) void k_wall_force(Grid g, int wall, const T
   Pos p;
   p.i = blockIdx.x * BX + threadIdx.x;
   p.k = blockIdx.y * BY + threadIdx.y;
-  p.jf = wall == 0 ? 0 : g.H - 1;
   double t[3] = {0, 0, 0};
   if (p.i < g.nx && p.k < g.nz) {
-    p.n = ((long long)p.k * g.H + p.jf) * g.nx + p.i;
-    NodeGeo<T> G;
-    load_geo(geo, g.N, p.n, G);
-    Coef<T> cp;
-    load_coef(hist, g.N, p.n, cp);
-    const T isg = T(1) / (T(1) + G.sgd);
-    T Fp[Q], ft[Q];
-    forcing_pops(cp, isg, Fp);
-    for_q([&](auto L) {
-      constexpr int l = decltype(L)::value;
-      ft[l] = pull<T, l>(pop, g, p) + T(0.5) * Fp[l];
-    });
-    T dr, j[3];
-    streamed_moments(pop, hist, G.sgd, g, p, dr, j);
-    T ne[Q], Tm[6];
-    node_stress(G, ft, dr, j, tau, ne, Tm);
-    const double sg = 1.0 + (double)G.sgd, sgn = wall == 0 ? -1.0 : 1.0;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      double s = 0.0;
-#pragma unroll
-      for (int i2 = 0; i2 < 3; ++i2) s += (double)Tm[sym(i2, 1)] * jac[(a * 3 + i2) * g.N + p.n];
-      t[a] = sgn * sg * s;
+    if (wall < 2) {
+      p.jf = wall == 0 ? 0 : g.H - 1;
+      p.n = ((long long)p.k * g.H + p.jf) * g.nx + p.i;
+      node_traction(g, pop, hist, geo, jac, tau, p, wall == 0 ? -1.0 : 1.0, t);
+    } else if (p.i >= g.pi0 && p.i <= g.pi1) {
+      for (int side = 0; side < 2; ++side) {
+        p.jf = g.pj - 1 + side;
+        p.n = ((long long)p.k * g.H + p.jf) * g.nx + p.i;
+        node_traction(g, pop, hist, geo, jac, tau, p, side == 0 ? 1.0 : -1.0, t);
+      }
     }
     if (per_node) {
       const long long c = ((long long)p.k * g.nx + p.i) * 3;
@@ -505,7 +543,7 @@ template <class T> hipError_t launch_step(Fields& F, hipStream_t s, T tau, hipEv
   mark(1);
   hipLaunchKernelGGL(k_collide<T>, fluid_grid(g), b, 0, s, g, pin, pout, (const T*)F.hist[F.cur],
                      (T*)F.hist[F.cur ^ 1], (const T*)F.geo,
-                     (const T*)F.mom, (const T*)F.uw, F.moving[0], F.moving[1], tau, F.flag);
+                     (const T*)F.mom, (const T*)F.uw, F.moving[0], F.moving[1], (const T*)F.up, tau, F.flag);
   mark(2);
   F.cur ^= 1;
   const hipError_t l = hipGetLastError();
@@ -528,7 +566,7 @@ template <class T> hipError_t launch_set_state(Fields& F, hipStream_t s, const d
   }
   hipLaunchKernelGGL(k_moments_full<T>, fluid_grid(g), b, 0, s, g, F.full, (const T*)F.geo, (T*)F.mom);
   hipLaunchKernelGGL(k_hist_full<T>, fluid_grid(g), b, 0, s, g, F.full, (const T*)F.geo, (const T*)F.mom,
-                     (const T*)F.uw, F.moving[0], F.moving[1], tau, (T*)F.hist[F.cur]);
+                     (const T*)F.uw, F.moving[0], F.moving[1], (const T*)F.up, tau, (T*)F.hist[F.cur]);
   hipLaunchKernelGGL(k_full_to_streamed<T>, fluid_grid(g), b, 0, s, g, F.full, (const T*)F.hist[F.cur],
                      (const T*)F.geo);
   hipLaunchKernelGGL(k_unpull<T>, fluid_grid(g), b, 0, s, g, (const double*)F.full, (T*)F.pop[F.cur]);

@@ -39,10 +39,25 @@ struct NodeIdx {
   int oxm, oxp;       // offset to i-1 and to i+1 (wrapped)
   int ozm, ozp;       // offset to k-1 and to k+1 (wrapped), in whole planes
   int jf;
+  unsigned cut;       // plate: bit cut_bit(x, y) set when the link arriving along (x, y) is cut
 };
 
+// Bit of the link arriving along (x, y), y != 0, in NodeIdx::cut.
+__host__ __device__ constexpr int cut_bit(int x, int y) { return (y > 0 ? 0 : 3) + x + 1; }
+
+// PL: the grid has an interior plate (the links it cuts are found once per
+// node); without it the mask stays zero and the pulls do not test it.
+template <bool PL = false>
 __device__ __forceinline__ NodeIdx node_idx(const Grid& g, int i, int jf, int k) {
   NodeIdx r;
+  r.cut = 0;
+  if constexpr (PL) {
+#pragma unroll
+    for (int x = -1; x <= 1; ++x) {
+      if (plate_cut(g, i, jf, -x, -1)) r.cut |= 1u << cut_bit(x, 1);
+      if (plate_cut(g, i, jf, -x, 1)) r.cut |= 1u << cut_bit(x, -1);
+    }
+  }
   const int plane = g.H * g.nx;
   r.n = (unsigned)(k * plane + jf * g.nx + i);
   r.oxm = i == 0 ? g.nx - 1 : -1;
@@ -65,11 +80,12 @@ template <class T> __device__ __forceinline__ void stw(T* __restrict__ base, uns
 }
 
 // Pulled deviation g~_l: the population that left x - c_l in direction l,
-// or the bounce-back slot opp(l) of this node when x - c_l is a wall node.
+// or the bounce-back slot opp(l) of this node when the link from x - c_l
+// crosses a wall or the plate.
 // Both candidate planes (l and opp(l)) are addressed from the lower of the
 // two as one uniform base, so the per-lane choice is a choice of 32-bit
 // offset and every load keeps the scalar-base form.
-template <class T, int l>
+template <class T, int l, bool PL = false>
 __device__ __forceinline__ T pullf(const T* __restrict__ pop, const Grid& g, const NodeIdx& p) {
   constexpr int x = cx(l), y = cy(l), z = cz(l);
   constexpr int lo = l < opp(l) ? l : opp(l);
@@ -83,7 +99,8 @@ __device__ __forceinline__ T pullf(const T* __restrict__ pop, const Grid& g, con
   if constexpr (y == 0) {
     return at(base, e);
   } else {
-    const bool wall = y > 0 ? p.jf == 0 : p.jf == g.H - 1;
+    bool wall = y > 0 ? p.jf == 0 : p.jf == g.H - 1;
+    if constexpr (PL) wall = wall || ((p.cut >> cut_bit(x, y)) & 1u);
     const unsigned eb = (unsigned)(opp(l) - lo) * (unsigned)g.N + p.n;
     return at(base, wall ? eb : e);
   }
@@ -105,15 +122,15 @@ struct NoKeep {
 
 // rho - 1 and rho u of the streamed state at a fluid node; each pulled
 // deviation g~_l is also handed to keep(l, g~_l).
-template <class T, class Keep = NoKeep>
+template <class T, bool PL, class Keep = NoKeep>
 __device__ __forceinline__ void node_moments(const T* __restrict__ pop, const T* __restrict__ hist,
                                              const T* __restrict__ geo, const Grid& g, int i, int jf, int k, T m[4],
                                              const Keep& keep = Keep()) {
-  const NodeIdx p = node_idx(g, i, jf, k);
+  const NodeIdx p = node_idx<PL>(g, i, jf, k);
   T s = 0, j0 = 0, j1 = 0, j2 = 0;
   for_q([&](auto L) {
     constexpr int l = decltype(L)::value;
-    const T v = pullf<T, l>(pop, g, p);
+    const T v = pullf<T, l, PL>(pop, g, p);
     keep(L, v);
     s += v;
     if (cx(l)) j0 += T(cx(l)) * v;
@@ -131,7 +148,7 @@ __device__ __forceinline__ void node_moments(const T* __restrict__ pop, const T*
 // Moments of entry e of the haloed tile at plane k into the ring slot.  Wall
 // layers (jf = -1, H) get the mirror ghost of the adjacent fluid node.  A
 // fluid entry hands its pulled deviations to `keep`.
-template <class T, int TX, int TY, class Keep = NoKeep>
+template <class T, int TX, int TY, bool PL, class Keep = NoKeep>
 __device__ __forceinline__ void fill_entry(T (*ring)[(TX + 2) * (TY + 2)], const T* __restrict__ pop,
                                            const T* __restrict__ hist, const T* __restrict__ geo,
                                            const T* __restrict__ uw, int mv0, int mv1, const Grid& g, int i0,
@@ -143,11 +160,11 @@ __device__ __forceinline__ void fill_entry(T (*ring)[(TX + 2) * (TY + 2)], const
   const int iw = wrapf(i, g.nx);
   T m[4];
   if (jf >= 0 && jf < g.H) {
-    node_moments(pop, hist, geo, g, iw, jf, k, m, keep);
+    node_moments<T, PL>(pop, hist, geo, g, iw, jf, k, m, keep);
   } else {
     const int w = jf < 0 ? 0 : 1;
     T mm[4];
-    node_moments(pop, hist, geo, g, iw, w == 0 ? 0 : g.H - 1, k, mm);
+    node_moments<T, PL>(pop, hist, geo, g, iw, w == 0 ? 0 : g.H - 1, k, mm);
     m[0] = mm[0];
     m[1] = -mm[1];
     m[2] = -mm[2];
@@ -165,26 +182,26 @@ __device__ __forceinline__ void fill_entry(T (*ring)[(TX + 2) * (TY + 2)], const
 }
 
 // Fill one ring slot with the moments of plane k over the haloed tile.
-template <class T, int TX, int TY>
+template <class T, int TX, int TY, bool PL>
 __device__ __forceinline__ void fill_plane(T (*ring)[(TX + 2) * (TY + 2)], const T* __restrict__ pop, const T* __restrict__ hist,
                                            const T* __restrict__ geo, const T* __restrict__ uw, int mv0, int mv1,
                                            const Grid& g, int i0, int j0, int k) {
   k = wrapf(k, g.nz);
   for (int e = threadIdx.x; e < Tile<TX, TY>::HN; e += Tile<TX, TY>::NT)
-    fill_entry<T, TX, TY>(ring, pop, hist, geo, uw, mv0, mv1, g, i0, j0, k, e);
+    fill_entry<T, TX, TY, PL>(ring, pop, hist, geo, uw, mv0, mv1, g, i0, j0, k, e);
 }
 
 // Staged fill: each thread fills the entry of its own node (handing that
 // node's pulled deviations to `keep`, for the collision one iteration later);
 // the 2*(TX+2) + 2*TY halo entries are shared out over the block.
-template <class T, int TX, int TY, class Keep>
+template <class T, int TX, int TY, bool PL, class Keep>
 __device__ __forceinline__ void fill_plane_staged(T (*ring)[(TX + 2) * (TY + 2)], const T* __restrict__ pop,
                                                   const T* __restrict__ hist, const T* __restrict__ geo,
                                                   const T* __restrict__ uw, int mv0, int mv1, const Grid& g, int i0,
                                                   int j0, int k, int tx, int ty, const Keep& keep) {
   constexpr int HX = Tile<TX, TY>::HX;
   k = wrapf(k, g.nz);
-  fill_entry<T, TX, TY>(ring, pop, hist, geo, uw, mv0, mv1, g, i0, j0, k, (ty + 1) * HX + (tx + 1), keep);
+  fill_entry<T, TX, TY, PL>(ring, pop, hist, geo, uw, mv0, mv1, g, i0, j0, k, (ty + 1) * HX + (tx + 1), keep);
   constexpr int NH = 2 * HX + 2 * TY;
   for (int h = threadIdx.x; h < NH; h += Tile<TX, TY>::NT) {
     int e;
@@ -196,7 +213,7 @@ __device__ __forceinline__ void fill_plane_staged(T (*ring)[(TX + 2) * (TY + 2)]
       e = (1 + h - 2 * HX) * HX;
     else
       e = (1 + h - 2 * HX - TY) * HX + (HX - 1);
-    fill_entry<T, TX, TY>(ring, pop, hist, geo, uw, mv0, mv1, g, i0, j0, k, e);
+    fill_entry<T, TX, TY, PL>(ring, pop, hist, geo, uw, mv0, mv1, g, i0, j0, k, e);
   }
 }
 
@@ -207,12 +224,13 @@ enum Stage {
   STAGE_REG = 1,   // registers (two planes live across the collision)
 };
 
-template <class T, int TX, int TY, int STAGE>
+template <class T, int TX, int TY, int STAGE, bool PL>
 __global__ __launch_bounds__(TX * TY) void k_step_fused(Grid g, int ntx, int nty, int nzc, int zc,
                                                    const T* __restrict__ pin, T* __restrict__ pout,
                                                    const T* __restrict__ hist, T* __restrict__ hout,
                                                    const T* __restrict__ geo,
-                                                   const T* __restrict__ uw, int mv0, int mv1, T tau,
+                                                   const T* __restrict__ uw, int mv0, int mv1,
+                                                   const T* __restrict__ up, T tau,
                                                    int* __restrict__ flag) {
   constexpr int HN = Tile<TX, TY>::HN, HX = Tile<TX, TY>::HX;
   // Four ring slots: the fill of plane k+1 overwrites plane k-3, whose last
@@ -247,21 +265,21 @@ __global__ __launch_bounds__(TX * TY) void k_step_fused(Grid g, int ntx, int nty
   auto to_next = [&](auto L, T v) {
     if (own) nxt[decltype(L)::value] = v;
   };
-  fill_plane<T, TX, TY>(ring[rslot(z0 - 1)], pin, hist, geo, uw, mv0, mv1, g, i0, j0, z0 - 1);
+  fill_plane<T, TX, TY, PL>(ring[rslot(z0 - 1)], pin, hist, geo, uw, mv0, mv1, g, i0, j0, z0 - 1);
   if constexpr (STAGE == STAGE_NONE)
-    fill_plane<T, TX, TY>(ring[rslot(z0)], pin, hist, geo, uw, mv0, mv1, g, i0, j0, z0);
+    fill_plane<T, TX, TY, PL>(ring[rslot(z0)], pin, hist, geo, uw, mv0, mv1, g, i0, j0, z0);
   else
-    fill_plane_staged<T, TX, TY>(ring[rslot(z0)], pin, hist, geo, uw, mv0, mv1, g, i0, j0, z0, tx, ty, to_cur);
+    fill_plane_staged<T, TX, TY, PL>(ring[rslot(z0)], pin, hist, geo, uw, mv0, mv1, g, i0, j0, z0, tx, ty, to_cur);
   const T itau = T(1) / tau;
   for (int k = z0; k < z1; ++k) {
     own = active && k + 1 < z1;
     if constexpr (STAGE == STAGE_NONE)
-      fill_plane<T, TX, TY>(ring[rslot(k + 1)], pin, hist, geo, uw, mv0, mv1, g, i0, j0, k + 1);
+      fill_plane<T, TX, TY, PL>(ring[rslot(k + 1)], pin, hist, geo, uw, mv0, mv1, g, i0, j0, k + 1);
     else
-      fill_plane_staged<T, TX, TY>(ring[rslot(k + 1)], pin, hist, geo, uw, mv0, mv1, g, i0, j0, k + 1, tx, ty, to_next);
+      fill_plane_staged<T, TX, TY, PL>(ring[rslot(k + 1)], pin, hist, geo, uw, mv0, mv1, g, i0, j0, k + 1, tx, ty, to_next);
     __syncthreads();
     if (active) {
-      const NodeIdx p = node_idx(g, i, jf, k);
+      const NodeIdx p = node_idx<PL>(g, i, jf, k);
       const unsigned n = p.n;
       const int c0 = (ty + 1) * HX + (tx + 1);
       const T(*rc)[HN] = ring[rslot(k)];
@@ -280,9 +298,24 @@ __global__ __launch_bounds__(TX * TY) void k_step_fused(Grid g, int ntx, int nty
         const T(*rs)[HN] = ring[rslot(k + z)];
         const int e = (ty + 1 + y) * HX + (tx + 1 + x);
         constexpr T f = T(3.0 * wgt(l));
+        // across the plate: mirror ghost of the entry on this side
+        bool cut = false;
+        T r2 = T(0);
+        const T* um = nullptr;
+        if constexpr (PL && y != 0) {
+          cut = (p.cut >> cut_bit(-x, -y)) & 1u;
+          if (cut) {
+            const int em = (ty + 1) * HX + (tx + 1 + x);
+            r2 = T(2) * (T(1) + rs[0][em]);
+            const int im = x ? wrapf(i + x, g.nx) : i, km = z ? wrapf(k + z, g.nz) : k;
+            um = up + ((unsigned)((jf == g.pj ? g.nz : 0) + km) * g.nx + im) * 3;
+          }
+        }
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-          const T v = rs[1 + q][e];
+          T v = rs[1 + q][e];
+          if constexpr (PL && y != 0)
+            if (cut) v = r2 * um[q] - rs[1 + q][(ty + 1) * HX + (tx + 1 + x)];
           if (x) dj[0][q] += T(x) * f * v;
           if (y) dj[1][q] += T(y) * f * v;
           if (z) dj[2][q] += T(z) * f * v;
@@ -293,7 +326,7 @@ __global__ __launch_bounds__(TX * TY) void k_step_fused(Grid g, int ntx, int nty
       T sgc[6] = {0, 0, 0, 0, 0, 0};
       for_q([&](auto L) {
         constexpr int l = decltype(L)::value;
-        const T v = STAGE == STAGE_NONE ? pullf<T, l>(pin, g, p) : cur[l];
+        const T v = STAGE == STAGE_NONE ? pullf<T, l, PL>(pin, g, p) : cur[l];
         gv[l] = v;
         constexpr int x = cx(l), y = cy(l), z = cz(l);
         if (x) sgc[0] += v;
@@ -372,6 +405,17 @@ __global__ __launch_bounds__(TX * TY) void k_step_fused(Grid g, int ntx, int nty
             v -= T(6) * wl * rho * cu;
           }
         }
+        if constexpr (PL && y != 0) {
+          // the link leaving along c_l is the one arriving along -c_l at the
+          // node across: cut exactly when this node's mask has (-x, -y)
+          if ((p.cut >> cut_bit(-cx(l), -y)) & 1u) {
+            const T* upn = up + ((unsigned)((jf == g.pj ? g.nz : 0) + k) * g.nx + i) * 3;
+            T cu = T(y) * upn[1];
+            if (cx(l)) cu += T(cx(l)) * upn[0];
+            if (cz(l)) cu += T(cz(l)) * upn[2];
+            v -= T(6) * wl * rho * cu;
+          }
+        }
         chk += v;
         stw(pout + (size_t)l * g.N, n, v);
       });
@@ -416,18 +460,19 @@ inline int choose_zc(long long tiles, int nz, long long slots) {
   return best;
 }
 
-// Planes per block for kernel k_step_fused<T, TX, TY, ST>: zc if positive,
-// else the choice above for this device.
-template <class T, int TX, int TY, int ST> hipError_t fused_chunk(Fields& F, int zc, int* out) {
+// Planes per block for kernel k_step_fused<T, TX, TY, ST, PL>: zc if
+// positive, else the choice above for this device.
+template <class T, int TX, int TY, int ST, bool PL> hipError_t fused_chunk(Fields& F, int zc, int* out) {
   const Grid g = F.g;
   if (zc <= 0) {
-    const int key = (int)sizeof(T) * 10000 + TX * 10 + TY * 2 + ST;
+    const int key = (int)sizeof(T) * 10000 + TX * 10 + TY * 2 + ST + (PL ? 5000 : 0);
     if (F.slots_key != key) {
       int dev = 0, cus = 0, per_cu = 0;
       hipError_t e = hipGetDevice(&dev);
       if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
       if (e == hipSuccess)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_fused<T, TX, TY, ST>, Tile<TX, TY>::NT, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_fused<T, TX, TY, ST, PL>,
+                                                         Tile<TX, TY>::NT, 0);
       if (e != hipSuccess) return e;
       F.slots = (long long)cus * (per_cu > 0 ? per_cu : 1);
       F.slots_key = key;
@@ -439,32 +484,36 @@ template <class T, int TX, int TY, int ST> hipError_t fused_chunk(Fields& F, int
   return hipSuccess;
 }
 
-template <class T, int TX, int TY, int ST> hipError_t fused_launch(Fields& F, hipStream_t s, T tau, int zc) {
+template <class T, int TX, int TY, int ST, bool PL> hipError_t fused_launch(Fields& F, hipStream_t s, T tau, int zc) {
   const Grid g = F.g;
-  const hipError_t e = fused_chunk<T, TX, TY, ST>(F, zc, &zc);
+  const hipError_t e = fused_chunk<T, TX, TY, ST, PL>(F, zc, &zc);
   if (e != hipSuccess) return e;
   const int ntx = (g.nx + TX - 1) / TX, nty = (g.H + TY - 1) / TY;
   const int nzc = (g.nz + zc - 1) / zc;
   const int per = (ntx * nty * nzc + 7) / 8;
-  hipLaunchKernelGGL((k_step_fused<T, TX, TY, ST>), dim3(per * 8), dim3(Tile<TX, TY>::NT), 0, s, g, ntx, nty, nzc,
-                     zc, (const T*)F.pop[F.cur], (T*)F.pop[F.cur ^ 1], (const T*)F.hist[F.cur],
-                     (T*)F.hist[F.cur ^ 1], (const T*)F.geo, (const T*)F.uw, F.moving[0], F.moving[1], tau, F.flag);
+  hipLaunchKernelGGL((k_step_fused<T, TX, TY, ST, PL>), dim3(per * 8), dim3(Tile<TX, TY>::NT), 0, s, g, ntx, nty,
+                     nzc, zc, (const T*)F.pop[F.cur], (T*)F.pop[F.cur ^ 1], (const T*)F.hist[F.cur],
+                     (T*)F.hist[F.cur ^ 1], (const T*)F.geo, (const T*)F.uw, F.moving[0], F.moving[1],
+                     (const T*)F.up, tau, F.flag);
   F.cur ^= 1;
   return hipGetLastError();
 }
 
-template <class T, int TX, int TY> hipError_t launch_fused_tile(Fields& F, hipStream_t s, T tau, int zc) {
-  if (F.stage == STAGE_REG) return fused_launch<T, TX, TY, reg_stage<T>()>(F, s, tau, zc);
-  return fused_launch<T, TX, TY, STAGE_NONE>(F, s, tau, zc);
+template <class T, int TX, int TY, bool PL = false> hipError_t launch_fused_tile(Fields& F, hipStream_t s, T tau, int zc) {
+  if (F.stage == STAGE_REG) return fused_launch<T, TX, TY, reg_stage<T>(), PL>(F, s, tau, zc);
+  return fused_launch<T, TX, TY, STAGE_NONE, PL>(F, s, tau, zc);
 }
 
-template <class T, int TX, int TY> hipError_t chunk_tile(Fields& F, int* zc) {
-  if (F.stage == STAGE_REG) return fused_chunk<T, TX, TY, reg_stage<T>()>(F, F.zc, zc);
-  return fused_chunk<T, TX, TY, STAGE_NONE>(F, F.zc, zc);
+template <class T, int TX, int TY, bool PL = false> hipError_t chunk_tile(Fields& F, int* zc) {
+  if (F.stage == STAGE_REG) return fused_chunk<T, TX, TY, reg_stage<T>(), PL>(F, F.zc, zc);
+  return fused_chunk<T, TX, TY, STAGE_NONE, PL>(F, F.zc, zc);
 }
 
-// Tile shapes (x by y nodes per block): 64x4 (default), 64x2, 64x1, 128x2, 256x1.
+// Tile shapes (x by y nodes per block): 64x4 (default), 64x2, 64x1, 128x2,
+// 256x1.  A grid with an interior plate runs the plate-aware kernel on 64x4
+// tiles whatever the shape asked for.
 template <class T> hipError_t launch_step_fused(Fields& F, hipStream_t s, T tau, int zc, int tile) {
+  if (F.g.pj) return launch_fused_tile<T, 64, 4, true>(F, s, tau, zc);
   switch (tile) {
     case TILE_64x2: return launch_fused_tile<T, 64, 2>(F, s, tau, zc);
     case TILE_64x1: return launch_fused_tile<T, 64, 1>(F, s, tau, zc);
@@ -475,6 +524,7 @@ template <class T> hipError_t launch_step_fused(Fields& F, hipStream_t s, T tau,
 }
 
 template <class T> hipError_t fused_step_chunk(Fields& F, int* zc) {
+  if (F.g.pj) return chunk_tile<T, 64, 4, true>(F, zc);
   switch (F.tile) {
     case TILE_64x2: return chunk_tile<T, 64, 2>(F, zc);
     case TILE_64x1: return chunk_tile<T, 64, 1>(F, zc);

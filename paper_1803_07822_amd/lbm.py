@@ -34,7 +34,9 @@ SYMBOLS = [
     "lbm_workspace_bytes", "lbm_create", "lbm_reserve_adjoint", "lbm_destroy", "lbm_set_body_force",
     "lbm_set_metric", "lbm_set_wall_displacement", "lbm_set_wall_velocity", "lbm_init_equilibrium",
     "lbm_set_populations", "lbm_get_populations", "lbm_get_history", "lbm_get_geometry", "lbm_step",
-    "lbm_step_profiled", "lbm_set_tuning", "lbm_get_tuning", "lbm_stream_probe", "lbm_moments", "lbm_wall_force", "lbm_couple", "lbm_forward_record", "lbm_backward", "lbm_sync", "lbm_last_error",
+    "lbm_step_profiled", "lbm_set_tuning", "lbm_get_tuning", "lbm_stream_probe", "lbm_moments", "lbm_wall_force",
+    "lbm_couple", "lbm_set_plate", "lbm_set_plate_displacement", "lbm_set_plate_velocity", "lbm_plate_force",
+    "lbm_forward_record", "lbm_backward", "lbm_sync", "lbm_last_error",
 ]
 
 
@@ -67,6 +69,10 @@ _lib.lbm_get_tuning.argtypes = [_P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER
                                 ctypes.POINTER(ctypes.c_int)]
 _lib.lbm_moments.argtypes = [_P, _P, _P, _I]
 _lib.lbm_wall_force.argtypes = [_P, _I, _I, _P, _P]
+_lib.lbm_set_plate.argtypes = [_P, _I, _I, _I]
+_lib.lbm_set_plate_displacement.argtypes = [_P, _P, _I]
+_lib.lbm_set_plate_velocity.argtypes = [_P, _P]
+_lib.lbm_plate_force.argtypes = [_P, _P, _P]
 _lib.lbm_forward_record.argtypes = [_P, _I, _I, _I, _I, _P]
 _lib.lbm_backward.argtypes = [_P, _P, _P, _P, _P]
 _lib.lbm_sync.argtypes = [_P]
@@ -144,6 +150,22 @@ def lbm_set_wall_displacement(ctx, wall, d, reproject=False):
 
 def lbm_set_wall_velocity(ctx, wall, v):
     return _check(ctx, _lib.lbm_set_wall_velocity(ctx, int(wall), _ptr(v)))
+
+
+def lbm_set_plate(ctx, jp, i0, i1):
+    return _check(ctx, _lib.lbm_set_plate(ctx, int(jp), int(i0), int(i1)))
+
+
+def lbm_set_plate_displacement(ctx, d, reproject=False):
+    return _check(ctx, _lib.lbm_set_plate_displacement(ctx, _ptr(d), int(bool(reproject))))
+
+
+def lbm_set_plate_velocity(ctx, v):
+    return _check(ctx, _lib.lbm_set_plate_velocity(ctx, _ptr(v)))
+
+
+def lbm_plate_force(ctx, total, per_column=None):
+    return _check(ctx, _lib.lbm_plate_force(ctx, _ptr(total), _ptr(per_column)))
 
 
 def lbm_init_equilibrium(ctx, rho=None, ucart=None):
@@ -287,6 +309,25 @@ class Solver:
     def set_wall_velocity(self, wall, v):
         self._keep_v = self._dev(v, (self.nz, self.nx, 3))
         lbm_set_wall_velocity(self.ctx, wall, self._keep_v)
+
+    def set_plate(self, jp, i0, i1):
+        """Interior plate between fluid rows jp-1 and jp over columns i0..i1
+        (jp = 0 removes it); before the state is set."""
+        lbm_set_plate(self.ctx, jp, i0, i1)
+
+    def set_plate_displacement(self, d, reproject=False):
+        self._keep_p = self._dev(d, (self.nz, self.nx))
+        lbm_set_plate_displacement(self.ctx, self._keep_p, reproject)
+
+    def set_plate_velocity(self, v):
+        self._keep_pv = self._dev(v, (self.nz, self.nx, 3))
+        lbm_set_plate_velocity(self.ctx, self._keep_pv)
+
+    def plate_force(self, per_column=False):
+        tot = torch.empty(3, dtype=torch.float64, device=self.device)
+        pc = torch.empty((self.nz, self.nx, 3), dtype=torch.float64, device=self.device) if per_column else None
+        lbm_plate_force(self.ctx, tot, pc)
+        return (tot, pc) if per_column else tot
 
     def init_equilibrium(self, rho=None, ucart=None):
         r = self._dev(rho, self.fluid_shape)

@@ -162,6 +162,27 @@ def taylor_green_velocity(chart: np.ndarray, v0: float) -> np.ndarray:
 
 
 # --------------------------------------------------------- initial fields
+def flag_shape(nx: int, i0: int, i1: int) -> np.ndarray:
+    """Deflection profile [nx] of a plate clamped at its upstream end: with
+    s = (x - (i0 - 1/2)) / L along the plate of length L = i1 - i0 + 1,
+    phi = s^2 exp(-s^4 / 4) for s > 0 and 0 upstream (smooth, zero slope at
+    the clamp), continued past the tail with a smooth decay to zero, so the
+    cross-section row carries a C^2 shape beyond the plate's end."""
+    s = (np.arange(nx) - (i0 - 0.5)) / float(i1 - i0 + 1)
+    return np.where(s > 0, s * s * np.exp(-(s**4) / 4.0), 0.0)
+
+
+def flapping_plate(nx: int, nz: int, i0: int, i1: int, A: float, omega: float, t: float):
+    """Prescribed flapping of an interior plate: cross-section displacement
+    D = A phi(x) sin(omega t) [nz, nx] and the plate's Cartesian velocity
+    (0, dD/dt, 0) per column [nz, nx, 3]."""
+    phi = flag_shape(nx, i0, i1)
+    d = np.broadcast_to(A * phi * np.sin(omega * t), (nz, nx)).copy()
+    v = np.zeros((nz, nx, 3))
+    v[..., 1] = A * phi * omega * np.cos(omega * t)
+    return d, v
+
+
 def uniform_noise_velocity(nx, ny, nz, amp=1e-4, seed=2):
     rng = np.random.Generator(np.random.PCG64(seed))
     return rng.uniform(-amp, amp, size=(3, nz, ny - 2, nx))

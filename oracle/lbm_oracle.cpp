@@ -28,6 +28,15 @@
 //     link between those rows is cut when its crossing point x lies in
 //     [i0 - 1/2, i1 + 1/2] (periodically); cut links bounce back halfway,
 //     like the walls.
+//   * Open ends in x (Sec. VI.A), when set: x stops being periodic.  The
+//     populations that would stream in from outside are extrapolated from
+//     the inner neighbours: at the outlet (last column) the streamed part
+//     f - F/2 linearly from the two next columns in; at the inlet (column 0)
+//     the same linear extrapolation plus the equilibrium difference for the
+//     prescribed inlet velocity, f^eq(rho_e, u_in) - f^eq(rho_e, u_e) at the
+//     extrapolated moments (density and non-equilibrium part extrapolated,
+//     velocity imposed).  The lattice gradient takes the end
+//     column's own momentum beyond each end (zero gradient).
 //   * Geometry export per fluid node (28 values): sqrt g, g^xx, g^xy, g^xz,
 //     g^yy, g^yz, g^zz, Gamma^i_jk for i = x,y,z and jk in
 //     (xx,xy,xz,yy,yz,zz), then F^x, F^y, F^z.
@@ -379,6 +388,8 @@ template <class T> struct Sim {
   std::vector<T> vwall[2];          // Cartesian wall velocity [nz][nx][3]
   std::vector<T> uwall[2];          // chart components at the adjacent fluid node
   int pj = 0, pi0 = 0, pi1 = -1;    // interior plate (pj = 0: none)
+  bool open_x = false;              // open ends in x (inlet at column 0, outlet at nx-1)
+  std::vector<T> uin;               // Cartesian inlet velocity [nz][H][3]
   std::vector<T> dplate;            // plate y-displacement [nz][nx] (cross-section row)
   std::vector<T> vplate;            // Cartesian plate velocity per column [nz][nx][3]
   std::vector<T> uplate[2];         // chart components at the node below (0) / above (1)
@@ -410,6 +421,9 @@ template <class T> struct Sim {
     return s2 >= 2 * pi0 - 1 && s2 <= 2 * pi1 + 1;
   }
   long nid(int i, int jf, int k) const { return ((long)k * H + jf) * nx + i; }
+  // Column of a neighbour in x: periodic, or with open ends the end column
+  // itself beyond each end.
+  int colx(int i) const { return open_x ? (i < 0 ? 0 : (i > nx - 1 ? nx - 1 : i)) : wrapi(i, nx); }
 
   void update_wall_velocity() {
     for (int w = 0; w < 2; ++w)
@@ -439,6 +453,78 @@ template <class T> struct Sim {
             uplate[s][((long)k * nx + i) * 3 + a] = v;
           }
         }
+  }
+
+  // Open ends in x with the Cartesian inlet velocity u_in [nz][H][3]
+  // (nullptr: periodic x again).
+  bool set_open_x(const T* u) {
+    if (!u) {
+      open_x = false;
+      return true;
+    }
+    if (nx < 4 || (pj > 0 && (pi0 < 3 || pi1 > nx - 4))) return false;
+    open_x = true;
+    uin.assign(u, u + (long)nz * H * 3);
+    return true;
+  }
+
+  // The open-end rule on a state fv whose forcing history is Fp: the
+  // populations arriving from outside at the two end columns are derived
+  // from the inner neighbours (see the header).
+  void apply_open_ends(std::vector<T>& fv) const {
+    if (!open_x) return;
+    // g~ = f - F/2, the part carried by streaming
+    auto gs = [&](int l, long n) {
+      Coef<T> c;
+      coef_load(Fp, N, n, c);
+      return fv[l * N + n] - 0.5 * forcing_pop(l, geo[n].sg, c);
+    };
+    auto half_f = [&](int l, long n) {
+      Coef<T> c;
+      coef_load(Fp, N, n, c);
+      return 0.5 * forcing_pop(l, geo[n].sg, c);
+    };
+    for (int k = 0; k < nz; ++k)
+      for (int jf = 0; jf < H; ++jf) {
+        // outlet: g~ extrapolated linearly from columns nx-2 and nx-3
+        {
+          const long nb = nid(nx - 1, jf, k), n1 = nid(nx - 2, jf, k), n2 = nid(nx - 3, jf, k);
+          for (int l = 0; l < QN; ++l)
+            if (CV[l][0] < 0) fv[l * N + nb] = 2.0 * gs(l, n1) - gs(l, n2) + half_f(l, nb);
+        }
+        // inlet: g~ extrapolated linearly from columns 1 and 2, plus
+        // f^eq(rho_e, u_in) - f^eq(rho_e, u_e) at the extrapolated moments
+        {
+          const long n0 = nid(0, jf, k), n1 = nid(1, jf, k), n2 = nid(2, jf, k);
+          T re = 0.0, je[3] = {0.0, 0.0, 0.0};
+          for (int q = 0; q < 2; ++q) {
+            const long n = q == 0 ? n1 : n2;
+            const double wq = q == 0 ? 2.0 : -1.0;
+            T r = 0.0, jv[3] = {0.0, 0.0, 0.0};
+            for (int l = 0; l < QN; ++l) {
+              const T fl = fv[l * N + n];
+              r += fl;
+              for (int a = 0; a < 3; ++a)
+                if (CV[l][a]) jv[a] += fl * (double)CV[l][a];
+            }
+            re += wq * geo[n].sg * r;
+            for (int a = 0; a < 3; ++a) je[a] += wq * geo[n].sg * jv[a];
+          }
+          T jin[3];
+          for (int a = 0; a < 3; ++a) {
+            T v = 0.0;
+            for (int b = 0; b < 3; ++b) v += geo[n0].Ji[a][b] * uin[((long)k * H + jf) * 3 + b];
+            jin[a] = re * v;
+          }
+          T da1[3], da2[3][3];
+          for (int a = 0; a < 3; ++a) da1[a] = jin[a] - je[a];
+          for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) da2[a][b] = (jin[a] * jin[b] - je[a] * je[b]) / re;
+          for (int l = 0; l < QN; ++l)
+            if (CV[l][0] > 0)
+              fv[l * N + n0] = 2.0 * gs(l, n1) - gs(l, n2) + half_f(l, n0) + hermite(l, geo[n0].sg, T(0.0), da1, da2);
+        }
+      }
   }
 
   void set_body_force(const double F[3]) {
@@ -518,6 +604,7 @@ template <class T> struct Sim {
       return true;
     }
     if (jp < 1 || jp > H - 1 || i0 < 0 || i1 < i0 || i1 > nx - 1) return false;
+    if (open_x && (i0 < 3 || i1 > nx - 4)) return false;
     pj = jp;
     pi0 = i0;
     pi1 = i1;
@@ -565,7 +652,7 @@ template <class T> struct Sim {
   // rho u at grid node (i, j, k) with j in 0..ny-1; the wall layers carry the
   // mirror ghost j_g = 2 rho_m u_w - j_m of the adjacent fluid node m.
   T jat(const std::vector<T>& rho, const std::vector<T>& jv, int i, int j, int k, int a) const {
-    i = wrapi(i, nx);
+    i = colx(i);
     k = wrapi(k, nz);
     if (j >= 1 && j <= ny - 2) return jv[a * N + nid(i, j - 1, k)];
     int w = (j <= 0) ? 0 : 1;
@@ -608,7 +695,7 @@ template <class T> struct Sim {
           if (CV[l][kk] != 0) {
             T jn;
             if (plate_cut(i, j - 1, CV[l][0], CV[l][1])) {
-              const int im = wrapi(i + CV[l][0], nx), km = wrapi(k + CV[l][2], nz);
+              const int im = colx(i + CV[l][0]), km = wrapi(k + CV[l][2], nz);
               const long m = nid(im, j - 1, km);
               const int side = (j - 1 == pj) ? 1 : 0;
               jn = 2.0 * rho[m] * uplate[side][((long)km * nx + im) * 3 + a] - jv[a * N + m];
@@ -639,12 +726,16 @@ template <class T> struct Sim {
       for (int l = 0; l < QN; ++l) f[l * N + n] = feq[l];
     }
     reset_history();
+    apply_open_ends(f);
     have_state = true;
   }
 
+  // The history is formed from the state as given; with open ends the
+  // populations arriving from outside are then derived from it.
   void set_populations(const T* fin) {
     f.assign(fin, fin + QN * N);
     reset_history();
+    apply_open_ends(f);
     have_state = true;
   }
 
@@ -694,7 +785,9 @@ template <class T> struct Sim {
             int jd = jf + 1 + CV[l][1];
             const bool cut = plate_cut(i, jf, CV[l][0], CV[l][1]);
             if (jd >= 1 && jd <= ny - 2 && !cut) {
-              long d = nid(wrapi(i + CV[l][0], nx), jd - 1, wrapi(k + CV[l][2], nz));
+              const int id = i + CV[l][0];
+              if (open_x && (id < 0 || id > nx - 1)) continue;  // leaves through an open end
+              long d = nid(wrapi(id, nx), jd - 1, wrapi(k + CV[l][2], nz));
               fn[l * N + d] = fs[l * N + n];
             } else {
               int w = (jd <= 0) ? 0 : 1;
@@ -708,6 +801,7 @@ template <class T> struct Sim {
     for (long q = 0; q < QN * N; ++q) fn[q] += 0.5 * Fl[q];
     f.swap(fn);
     Fp.swap(coef);
+    apply_open_ends(f);
   }
 
   // Moments output: rho and u (chart components, or Cartesian u_c = J u).
@@ -1003,6 +1097,7 @@ template <class T> struct Sim {
         }
     f.swap(fnew);
     Fp.swap(Fnew);
+    apply_open_ends(f);
   }
 
   // Trilinear interpolation with x, z periodic and y limited to layers 0..ny-1.
@@ -1117,6 +1212,7 @@ void orc_set_plate_displacement(void* s, const double* d, int reproject) {
   ((Sim<double>*)s)->set_plate_displacement(d, reproject != 0);
 }
 void orc_set_plate_velocity(void* s, const double* v) { ((Sim<double>*)s)->set_plate_velocity(v); }
+int orc_set_open_x(void* s, const double* uin) { return ((Sim<double>*)s)->set_open_x(uin) ? 0 : -1; }
 void orc_plate_force(void* s, double* total, double* per_col) { ((Sim<double>*)s)->plate_force(total, per_col); }
 void orc_geometry(void* s, double* out28) { ((Sim<double>*)s)->geometry_export(out28); }
 void orc_chart(void* s, double* out) {

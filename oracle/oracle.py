@@ -69,6 +69,8 @@ def _lib():
             fn.restype = None
         L.orc_set_plate.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int]
         L.orc_set_plate.restype = ctypes.c_int
+        L.orc_set_open_x.argtypes = [ctypes.c_void_p, _D]
+        L.orc_set_open_x.restype = ctypes.c_int
         L.orc_run_forces.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double, _D, _D, _D, ctypes.c_int, ctypes.c_int, _D]
         L.orc_run_forces.restype = None
         L.orc_dual_forces.argtypes = (
@@ -145,6 +147,13 @@ class Oracle:
         (jp = 0 removes it)."""
         if _lib().orc_set_plate(self._h, int(jp), int(i0), int(i1)) != 0:
             raise ValueError("invalid plate")
+
+    def set_open_x(self, uin):
+        """Open ends in x with the Cartesian inlet velocity [nz, H, 3] at
+        column 0 (None: periodic x again)."""
+        uin = _c(uin, (self.nz, self.H, 3))
+        if _lib().orc_set_open_x(self._h, _p(uin)) != 0:
+            raise ValueError("open ends need nx >= 3 and a plate at least 2 columns from each end")
 
     def set_plate_displacement(self, d, reproject=False):
         d = _c(d, (self.nz, self.nx))

@@ -542,12 +542,16 @@ template <class T> struct Sim {
     std::vector<T> newchart(ch, ch + 3L * nz * ny * nx);
     std::vector<Geo<T>> newgeo;
     compute_geometry(nx, ny, nz, newchart.data(), Fc, newgeo);
-    if (reproject && have_state && have_geo) reproject_state(newchart, newgeo);
+    const bool moved = reproject && have_state && have_geo;
+    if (moved) reproject_state(newchart, newgeo);
     chart.swap(newchart);
     geo.swap(newgeo);
     have_geo = true;
     update_wall_velocity();
     update_plate_velocity();
+    // the re-projected state lives on the new chart: its open-end
+    // populations are derived with the new geometry
+    if (moved) apply_open_ends(f);
   }
 
   // Linear blending of the two wall displacements into the interior
@@ -1097,7 +1101,6 @@ template <class T> struct Sim {
         }
     f.swap(fnew);
     Fp.swap(Fnew);
-    apply_open_ends(f);
   }
 
   // Trilinear interpolation with x, z periodic and y limited to layers 0..ny-1.

@@ -185,7 +185,8 @@ int lbm_couple(lbm_ctx* ctx, int wall, const double* d_disp, const double* d_vca
  * cuts the links through the periodic seam.  jp = 0 removes the plate.  Set
  * it before the state (ESTATE after lbm_init_equilibrium or
  * lbm_set_populations); EINVAL outside the ranges.  It resets the plate's
- * displacement and velocity to zero.  The fused step then runs on 64x4 tiles
+ * displacement and velocity to zero; with open ends (lbm_set_open_x) the plate
+ * keeps 3 columns from each end.  The fused step then runs on 64x4 tiles
  * whatever lbm_set_tuning asked for; the adjoint (lbm_forward_record) is not
  * provided with a plate (EUNSUPPORTED). */
 int lbm_set_plate(lbm_ctx* ctx, int jp, int i0, int i1);
@@ -214,10 +215,27 @@ int lbm_set_plate_velocity(lbm_ctx* ctx, const double* d_vcart);
  * plate or a state; EINVAL for d_total3 NULL. */
 int lbm_plate_force(lbm_ctx* ctx, double* d_total3, double* d_per_column);
 
+/* Open ends in x (Sec. VI.A): x stops being periodic; column 0 is an inlet
+ * with the Cartesian velocity d_uin [nz][H][3] (device) and column nx - 1 an
+ * outlet.  The streamed values that would arrive from outside are
+ * extrapolated linearly from the two next columns in (f - F/2, the part
+ * carried by streaming); at the inlet the equilibrium difference
+ * f^eq(rho_e, u_in) - f^eq(rho_e, u_e) at the extrapolated moments is added,
+ * so the inlet takes the prescribed velocity with its density and
+ * non-equilibrium part extrapolated.  The lattice gradient takes the end
+ * column's own momentum beyond each end.  The geometry's x-derivatives stay
+ * periodic, so the chart must join smoothly across the two ends (an
+ * undeformed chart near both ends does).  A step then runs the two-pass
+ * kernels (lbm_get_tuning reports variant 1).  NULL restores periodic x.
+ * Before the state (ESTATE); EINVAL for nx < 4 or a plate closer than 3
+ * columns to an end.  The adjoint is not provided with open ends. */
+int lbm_set_open_x(lbm_ctx* ctx, const double* d_uin);
+
 /* Run K steps from the current state and record the force on `wall` at
  * states 1..K into d_forces [K][3]; the initial state and a checkpoint every
  * ckpt_every steps are kept for lbm_backward.  K and ckpt_every must match
- * lbm_reserve_adjoint.  Needs the FP64 form and no interior plate. */
+ * lbm_reserve_adjoint.  Needs the FP64 form, no interior plate and periodic
+ * x. */
 int lbm_forward_record(lbm_ctx* ctx, int K, int ckpt_every, int wall, int method, double* d_forces);
 
 /* Reverse sweep of the last lbm_forward_record: given dL/dF [K][3], write

@@ -54,6 +54,7 @@ Grid make_grid(const lbm_grid* h) {
   g.pj = 0;
   g.pi0 = 0;
   g.pi1 = -1;
+  g.open = 0;
   return g;
 }
 
@@ -85,6 +86,8 @@ void carve_core(Carver& c, const Grid& g, int precision, Fields& F) {
   F.up = c.take(sz * 2 * 3 * (size_t)g.nz * g.nx);
   F.vplate = (double*)c.take(sizeof(double) * 3 * (size_t)g.nz * g.nx);
   F.dplate = (double*)c.take(sizeof(double) * (size_t)g.nz * g.nx);
+  F.uin = (double*)c.take(sizeof(double) * 3 * (size_t)g.nz * g.H);
+  F.vin = c.take(sz * 3 * (size_t)g.nz * g.H);
   F.disp = (double*)c.take(sizeof(double) * 2 * (size_t)g.nz * g.nx);
   F.vwall = (double*)c.take(sizeof(double) * 2 * 3 * (size_t)g.nz * g.nx);
   F.full = (double*)c.take(sizeof(double) * 19 * N);
@@ -130,6 +133,7 @@ template <class T> int geometry_path(lbm_ctx* c, int reproject) {
     LBM_HIP(c, lbm::launch_geometry<T>(F, c->stream, c->Fc));
   LBM_HIP(c, lbm::launch_wall_velocity<T>(F, c->stream));
   if (F.g.pj) LBM_HIP(c, lbm::launch_plate_velocity<T>(F, c->stream));
+  if (F.g.open) LBM_HIP(c, lbm::launch_inlet_velocity<T>(F, c->stream));
   c->have_geo = 1;
   return LBM_OK;
 }
@@ -185,6 +189,8 @@ int lbm_create(lbm_ctx** out, const lbm_grid* h_grid, int lattice, double tau, i
   if (e == hipSuccess) e = hipMemsetAsync(F.up, 0, sz * 6 * (size_t)F.g.nz * F.g.nx, c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(F.vplate, 0, sizeof(double) * 3 * (size_t)F.g.nz * F.g.nx, c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(F.dplate, 0, sizeof(double) * (size_t)F.g.nz * F.g.nx, c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(F.uin, 0, sizeof(double) * 3 * (size_t)F.g.nz * F.g.H, c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(F.vin, 0, sz * 3 * (size_t)F.g.nz * F.g.H, c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(F.flag, 0, ALIGN, c->stream);
   if (e != hipSuccess) {
     delete c;
@@ -282,6 +288,8 @@ int lbm_set_plate(lbm_ctx* c, int jp, int i0, int i1) {
   }
   if (jp < 1 || jp > F.g.H - 1 || i0 < 0 || i1 < i0 || i1 > F.g.nx - 1)
     return fail(c, LBM_EINVAL, "plate must lie between fluid rows 1..H-1 over columns 0..nx-1");
+  if (F.g.open && (i0 < 3 || i1 > F.g.nx - 4))
+    return fail(c, LBM_EINVAL, "with open ends the plate keeps 3 columns from each end");
   if (c->have_state) return fail(c, LBM_ESTATE, "set the plate before the state");
   F.g.pj = jp;
   F.g.pi0 = i0;
@@ -337,6 +345,29 @@ int lbm_plate_force(lbm_ctx* c, double* d_total3, double* d_per_column) {
     LBM_HIP(c, lbm::launch_wall_force<double>(c->F, c->stream, 2, c->tau, d_total3, d_per_column));
   else
     LBM_HIP(c, lbm::launch_wall_force<float>(c->F, c->stream, 2, (float)c->tau, d_total3, d_per_column));
+  return LBM_OK;
+}
+
+int lbm_set_open_x(lbm_ctx* c, const double* d_uin) {
+  LBM_GUARD(c);
+  Fields& F = c->F;
+  if (c->have_state) return fail(c, LBM_ESTATE, "set the ends before the state");
+  if (!d_uin) {
+    F.g.open = 0;
+    return LBM_OK;
+  }
+  if (F.g.nx < 4) return fail(c, LBM_EINVAL, "open ends need nx >= 4");
+  if (F.g.pj && (F.g.pi0 < 3 || F.g.pi1 > F.g.nx - 4))
+    return fail(c, LBM_EINVAL, "with open ends the plate keeps 3 columns from each end");
+  F.g.open = 1;
+  LBM_HIP(c, hipMemcpyAsync(F.uin, d_uin, sizeof(double) * 3 * (size_t)F.g.nz * F.g.H, hipMemcpyDeviceToDevice,
+                            c->stream));
+  if (c->have_geo) {
+    if (c->precision == LBM_FP64)
+      LBM_HIP(c, lbm::launch_inlet_velocity<double>(F, c->stream));
+    else
+      LBM_HIP(c, lbm::launch_inlet_velocity<float>(F, c->stream));
+  }
   return LBM_OK;
 }
 
@@ -468,12 +499,13 @@ int lbm_get_tuning(lbm_ctx* c, int* zchunk, int* variant, int* stage) {
   LBM_GUARD(c);
   if (!zchunk || !variant || !stage) return fail(c, LBM_EINVAL, "null output pointer");
   int zc = 0;
-  if (c->F.variant == 0)
+  const bool two_pass = c->F.variant == 1 || c->F.g.open;  // open ends run the two-pass step
+  if (!two_pass)
     LBM_HIP(c, c->precision == LBM_FP64 ? lbm::fused_step_chunk<double>(c->F, &zc)
                                         : lbm::fused_step_chunk<float>(c->F, &zc));
   *zchunk = zc;
   static const int variant_of[5] = {0, 2, 3, 4, 5};  // by tile shape
-  *variant = c->F.variant == 1 ? 1 : variant_of[c->F.tile];
+  *variant = two_pass ? 1 : (c->F.g.pj ? 0 : variant_of[c->F.tile]);
   *stage = c->precision == LBM_FP64 ? 0 : c->F.stage;
   return LBM_OK;
 }
@@ -545,6 +577,7 @@ int lbm_forward_record(lbm_ctx* c, int K, int ckpt_every, int wall, int method, 
   if (!d_forces) return fail(c, LBM_EINVAL, "forces output is NULL");
   if (!c->have_state) return fail(c, LBM_ESTATE, "no state");
   if (c->F.g.pj) return fail(c, LBM_EUNSUPPORTED, "the adjoint does not cover an interior plate");
+  if (c->F.g.open) return fail(c, LBM_EUNSUPPORTED, "the adjoint does not cover open ends");
   {
     hipError_t e = lbm::adjoint_forward(c->F, c->adj, c->stream, K, ckpt_every, wall, c->tau, d_forces);
     if (e == hipErrorNotSupported) return fail(c, LBM_EUNSUPPORTED, "adjoint not available in this build");

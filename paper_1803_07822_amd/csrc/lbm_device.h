@@ -46,6 +46,8 @@ struct Grid {
   // Interior plate on the half row between fluid rows pj - 1 and pj over
   // columns pi0..pi1 and every z (pj = 0: none).
   int pj, pi0, pi1;
+  // Open ends in x: inlet at column 0, outlet at column nx - 1 (0: periodic).
+  int open;
 };
 
 // The link from fluid node (i, jf) along (x, y) crosses the plate: it joins

@@ -376,6 +376,24 @@ __global__ __launch_bounds__(BX * BY) void k_plate_velocity(Grid g, const double
   }
 }
 
+// Inlet velocity in the chart components of the inlet nodes (column 0):
+// v_in = J^{-1} u_in per (z, row).
+template <class T>
+__global__ __launch_bounds__(BX * BY) void k_inlet_velocity(Grid g, const double* __restrict__ jac, const double* __restrict__ uin, T* __restrict__ vin) {
+  const int jf = blockIdx.x * BX + threadIdx.x, k = blockIdx.y * BY + threadIdx.y;
+  if (jf >= g.H || k >= g.nz) return;
+  const long long n = ((long long)k * g.H + jf) * g.nx;
+  double J[3][3], Ji[3][3], det;
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) J[a][b] = jac[(a * 3 + b) * g.N + n];
+  inv3(J, Ji, det);
+  const long long c = ((long long)k * g.H + jf) * 3;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) vin[c + a] = (T)(Ji[a][0] * uin[c] + Ji[a][1] * uin[c + 1] + Ji[a][2] * uin[c + 2]);
+}
+
 }  // namespace
 
 hipError_t launch_chart_from_disp(Fields& F, hipStream_t s) {
@@ -425,6 +443,15 @@ template hipError_t launch_body_force<double>(Fields&, hipStream_t, const double
 template hipError_t launch_body_force<float>(Fields&, hipStream_t, const double*);
 template hipError_t launch_wall_velocity<double>(Fields&, hipStream_t);
 template hipError_t launch_wall_velocity<float>(Fields&, hipStream_t);
+template <class T> hipError_t launch_inlet_velocity(Fields& F, hipStream_t s) {
+  if (!F.g.open) return hipSuccess;
+  dim3 b(BX, BY), gr((F.g.H + BX - 1) / BX, (F.g.nz + BY - 1) / BY, 1);
+  hipLaunchKernelGGL(k_inlet_velocity<T>, gr, b, 0, s, F.g, F.jac, F.uin, (T*)F.vin);
+  return hipGetLastError();
+}
+
+template hipError_t launch_inlet_velocity<double>(Fields&, hipStream_t);
+template hipError_t launch_inlet_velocity<float>(Fields&, hipStream_t);
 template hipError_t launch_plate_velocity<double>(Fields&, hipStream_t);
 template hipError_t launch_plate_velocity<float>(Fields&, hipStream_t);
 

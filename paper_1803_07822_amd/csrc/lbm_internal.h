@@ -31,6 +31,8 @@ struct Fields {
   void* up;       // [2][nz][nx][3] T plate velocity, chart components at the node below (0) / above (1)
   double* vplate; // [nz][nx][3] Cartesian plate velocity per column
   double* dplate; // [nz][nx] y-displacement of the plate's cross-section row
+  double* uin;    // [nz][H][3] Cartesian inlet velocity (open ends)
+  void* vin;      // [nz][H][3] T inlet velocity in the chart components of the inlet nodes
   double* disp;   // [2][nz][nx]
   double* vwall;  // [2][nz][nx][3] Cartesian wall velocity
   double* full;   // [19][N] FP64 scratch
@@ -98,6 +100,7 @@ template <class T> hipError_t launch_geometry(Fields& F, hipStream_t s, const do
 template <class T> hipError_t launch_body_force(Fields& F, hipStream_t s, const double Fc[3]);
 template <class T> hipError_t launch_wall_velocity(Fields& F, hipStream_t s);
 template <class T> hipError_t launch_plate_velocity(Fields& F, hipStream_t s);
+template <class T> hipError_t launch_inlet_velocity(Fields& F, hipStream_t s);
 hipError_t launch_chart_from_disp(Fields& F, hipStream_t s);
 
 // state

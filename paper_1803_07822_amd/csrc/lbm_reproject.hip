@@ -12,6 +12,7 @@
 // extrapolation.  Moments and geometry are handled in FP64; populations end in
 // the storage precision.
 #include "lbm_internal.h"
+#include "lbm_pull.h"
 
 namespace lbm {
 
@@ -104,20 +105,10 @@ __device__ __forceinline__ void inv3d(const double m[3][3], double r[3][3]) {
   r[2][2] = (m[0][0] * m[1][1] - m[0][1] * m[1][0]) * idet;
 }
 
-template <class T, int l>
-__device__ __forceinline__ T pull_rp(const T* __restrict__ pop, const Grid& g, int i, int jf, int k, long long n) {
-  constexpr int x = cx(l), y = cy(l), z = cz(l);
-  if ((y > 0 && jf == 0) || (y < 0 && jf == g.H - 1) || plate_cut(g, i, jf, -x, -y))
-    return pop[(long long)opp(l) * g.N + n];
-  const int is = x ? wrapr(i - x, g.nx) : i;
-  const int ks = z ? wrapr(k - z, g.nz) : k;
-  return pop[(long long)l * g.N + ((long long)ks * g.H + (jf - y)) * g.nx + is];
-}
-
 // Cartesian moment fields at the old fluid nodes.
 template <class T>
 __global__ __launch_bounds__(BX * BY) void k_rp_moments(Grid g, const T* __restrict__ pop, const T* __restrict__ hist, const T* __restrict__ geo,
-                             const double* __restrict__ jac, T* __restrict__ mf) {
+                             const T* __restrict__ vin, const double* __restrict__ jac, T* __restrict__ mf) {
   int i, jf, k;
   if (!xcd_fluid_node(g, i, jf, k)) return;
   const long long n = ((long long)k * g.H + jf) * g.nx + i;
@@ -131,12 +122,13 @@ __global__ __launch_bounds__(BX * BY) void k_rp_moments(Grid g, const T* __restr
   for (int q = 0; q < 6; ++q) c.C[q] = hist[(H_C + q) * g.N + n];
   const T sgd = geo[G_SG * g.N + n];
   const T isg = T(1) / (T(1) + sgd);
-  T Fp[Q];
+  T Fp[Q], gv[Q];
   forcing_pops(c, isg, Fp);
+  pull_all(pop, hist, geo, vin, g, pos_at(g, i, jf, k), gv);
   double s = 0, jv[3] = {0, 0, 0}, P[6] = {0, 0, 0, 0, 0, 0};
   for_q([&](auto L) {
     constexpr int l = decltype(L)::value;
-    const double v = (double)pull_rp<T, l>(pop, g, i, jf, k, n) + 0.5 * (double)Fp[l];
+    const double v = (double)gv[l] + 0.5 * (double)Fp[l];
     constexpr int x = cx(l), y = cy(l), z = cz(l);
     s += v;
     if (x) jv[0] += x * v;
@@ -365,7 +357,7 @@ template <class T> hipError_t launch_reproject(Fields& F, hipStream_t s, const d
   const Grid g = F.g;
   dim3 b(BX, BY);
   hipLaunchKernelGGL(k_rp_moments<T>, xcd_fluid_grid(g), b, 0, s, g, (const T*)F.pop[F.cur], (const T*)F.hist[F.cur],
-                     (const T*)F.geo, (const double*)F.jac, (T*)F.mf);
+                     (const T*)F.geo, (const T*)F.vin, (const double*)F.jac, (T*)F.mf);
   hipLaunchKernelGGL(k_rp_ghost<T>, col_grid(g), b, 0, s, g, (const double*)F.vwall, (T*)F.mf);
   const int old = F.uext_cur;
   F.uext_cur ^= 1;

@@ -18,17 +18,11 @@
 // node-locally: equilibrium, stress, forcing A/B/C, collision, bounce-back
 // term, history update.
 #include "lbm_internal.h"
+#include "lbm_pull.h"
 
 namespace lbm {
 
 namespace {
-
-__device__ __forceinline__ int wrapd(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
-
-struct Pos {
-  int i, jf, k;
-  long long n;
-};
 
 __device__ __forceinline__ bool node_pos(const Grid& g, Pos& p) {
   p.i = blockIdx.x * BX + threadIdx.x;
@@ -37,17 +31,6 @@ __device__ __forceinline__ bool node_pos(const Grid& g, Pos& p) {
   if (p.i >= g.nx || p.jf >= g.H) return false;
   p.n = ((long long)p.k * g.H + p.jf) * g.nx + p.i;
   return true;
-}
-
-template <class T, int l>
-__device__ __forceinline__ T pull(const T* __restrict__ pop, const Grid& g, const Pos& p) {
-  constexpr int x = cx(l), y = cy(l), z = cz(l);
-  if ((y > 0 && p.jf == 0) || (y < 0 && p.jf == g.H - 1) || plate_cut(g, p.i, p.jf, -x, -y))
-    return pop[(long long)opp(l) * g.N + p.n];
-  const int is = x ? wrapd(p.i - x, g.nx) : p.i;
-  const int ks = z ? wrapd(p.k - z, g.nz) : p.k;
-  const int js = p.jf - y;
-  return pop[(long long)l * g.N + ((long long)ks * g.H + js) * g.nx + is];
 }
 
 template <class T>
@@ -70,19 +53,23 @@ __device__ __forceinline__ void store_coef(T* __restrict__ hist, long long N, lo
 
 // rho - 1 and rho u of the streamed state at p: rho = sqrt g sum_l g_l + A/2,
 // rho u = sqrt g sum_l g_l c_l + B/2 (the half history term summed in closed
-// form: sum_l F_l sqrt g = A, sum_l F_l c_l sqrt g = B).
+// form: sum_l F_l sqrt g = A, sum_l F_l c_l sqrt g = B).  The pulled
+// deviations are left in gv.
 template <class T>
-__device__ __forceinline__ void streamed_moments(const T* __restrict__ pop, const T* __restrict__ hist, T sgd,
-                                                 const Grid& g, const Pos& p, T& dr, T j[3]) {
+__device__ __forceinline__ void streamed_moments(const T* __restrict__ pop, const T* __restrict__ hist,
+                                                 const T* __restrict__ geo, const T* __restrict__ vin,
+                                                 const Grid& g, const Pos& p, T& dr, T j[3], T gv[Q]) {
+  pull_all(pop, hist, geo, vin, g, p, gv);
   T s = 0, j0 = 0, j1 = 0, j2 = 0;
   for_q([&](auto L) {
     constexpr int l = decltype(L)::value;
-    const T v = pull<T, l>(pop, g, p);
+    const T v = gv[l];
     s += v;
     if (cx(l)) j0 += T(cx(l)) * v;
     if (cy(l)) j1 += T(cy(l)) * v;
     if (cz(l)) j2 += T(cz(l)) * v;
   });
+  const T sgd = geo[G_SG * g.N + p.n];
   const T sg = T(1) + sgd;
   dr = sgd + sg * s + T(0.5) * hist[H_A * g.N + p.n];
   j[0] = sg * j0 + T(0.5) * hist[(H_B + 0) * g.N + p.n];
@@ -107,7 +94,8 @@ __device__ __forceinline__ void lattice_gradient(const T* __restrict__ mom, cons
     constexpr int l = decltype(L)::value;
     if (l == 0) return;
     constexpr int x = cx(l), y = cy(l), z = cz(l);
-    const int in = x ? wrapd(p.i + x, g.nx) : p.i;
+    // beyond an open end: the end column itself (zero gradient)
+    const int in = !x ? p.i : (g.open ? min(max(p.i + x, 0), g.nx - 1) : wrapd(p.i + x, g.nx));
     const int kn = z ? wrapd(p.k + z, g.nz) : p.k;
     const int jn = p.jf + y;
     T jb[3];
@@ -149,11 +137,12 @@ __device__ __forceinline__ void lattice_gradient(const T* __restrict__ mom, cons
 // ---------------------------------------------------------------- pass 1
 template <class T>
 __global__ __launch_bounds__(BX* BY) void k_moments(Grid g, const T* __restrict__ pop, const T* __restrict__ hist,
-                                                   const T* __restrict__ geo, T* __restrict__ mom) {
+                                                   const T* __restrict__ geo, const T* __restrict__ vin,
+                                                   T* __restrict__ mom) {
   Pos p;
   if (!node_pos(g, p)) return;
-  T dr, j[3];
-  streamed_moments(pop, hist, geo[G_SG * g.N + p.n], g, p, dr, j);
+  T dr, j[3], gv[Q];
+  streamed_moments(pop, hist, geo, vin, g, p, dr, j, gv);
   mom[p.n] = dr;
   mom[g.N + p.n] = j[0];
   mom[2 * g.N + p.n] = j[1];
@@ -168,8 +157,8 @@ __global__ __launch_bounds__(BX* BY) void k_collide(Grid g, const T* __restrict_
                                                    const T* __restrict__ hist, T* __restrict__ hout,
                                                    const T* __restrict__ geo,
                                                    const T* __restrict__ mom, const T* __restrict__ uw, int mv0,
-                                                   int mv1, const T* __restrict__ up, T tau,
-                                                   int* __restrict__ flag) {
+                                                   int mv1, const T* __restrict__ up, const T* __restrict__ vin,
+                                                   T tau, int* __restrict__ flag) {
   Pos p;
   if (!node_pos(g, p)) return;
   NodeGeo<T> G;
@@ -179,9 +168,10 @@ __global__ __launch_bounds__(BX* BY) void k_collide(Grid g, const T* __restrict_
   const T sg = T(1) + G.sgd, isg = T(1) / sg;
   T Fp[Q], ft[Q];
   forcing_pops(cp, isg, Fp);
+  pull_all(pin, hist, geo, vin, g, p, ft);
   for_q([&](auto L) {
     constexpr int l = decltype(L)::value;
-    ft[l] = pull<T, l>(pin, g, p) + T(0.5) * Fp[l];
+    ft[l] += T(0.5) * Fp[l];
   });
   const T dr = mom[p.n];
   const T j[3] = {mom[g.N + p.n], mom[2 * g.N + p.n], mom[3 * g.N + p.n]};
@@ -335,7 +325,10 @@ __global__ __launch_bounds__(BX * BY) void k_full_to_streamed(Grid g, double* __
 }
 
 // Inverse of the pull: pop[l][y] = g~_l(y + c_l) if the link from y to
-// y + c_l is open, else (through a wall or the plate) g~_opp(l)(y).
+// y + c_l is open, else (through a wall or the plate) g~_opp(l)(y).  With
+// open ends in x the slots of links leaving through an end are never read
+// (the values arriving there are extrapolated), so their periodic image
+// does no harm.
 template <class T>
 __global__ __launch_bounds__(BX * BY) void k_unpull(Grid g, const double* __restrict__ gs, T* __restrict__ pop) {
   Pos p;
@@ -358,17 +351,18 @@ __global__ __launch_bounds__(BX * BY) void k_unpull(Grid g, const double* __rest
 
 template <class T>
 __global__ __launch_bounds__(BX * BY) void k_get_pops(Grid g, const T* __restrict__ pop, const T* __restrict__ hist, const T* __restrict__ geo,
-                           double* __restrict__ out) {
+                           const T* __restrict__ vin, double* __restrict__ out) {
   Pos p;
   if (!node_pos(g, p)) return;
   Coef<T> c;
   load_coef(hist, g.N, p.n, c);
   const T isg = T(1) / (T(1) + geo[G_SG * g.N + p.n]);
-  T Fp[Q];
+  T Fp[Q], gv[Q];
   forcing_pops(c, isg, Fp);
+  pull_all(pop, hist, geo, vin, g, p, gv);
   for_q([&](auto L) {
     constexpr int l = decltype(L)::value;
-    out[(long long)l * g.N + p.n] = wgt(l) + ((double)pull<T, l>(pop, g, p) + 0.5 * (double)Fp[l]);
+    out[(long long)l * g.N + p.n] = wgt(l) + ((double)gv[l] + 0.5 * (double)Fp[l]);
   });
 }
 
@@ -392,12 +386,12 @@ __global__ __launch_bounds__(BX * BY) void k_get_geo(Grid g, const T* __restrict
 
 template <class T>
 __global__ __launch_bounds__(BX * BY) void k_moments_out(Grid g, const T* __restrict__ pop, const T* __restrict__ hist, const T* __restrict__ geo,
-                              const double* __restrict__ jac, double* __restrict__ rho, double* __restrict__ u,
-                              int cart) {
+                              const T* __restrict__ vin, const double* __restrict__ jac, double* __restrict__ rho,
+                              double* __restrict__ u, int cart) {
   Pos p;
   if (!node_pos(g, p)) return;
-  T dr, j[3];
-  streamed_moments(pop, hist, geo[G_SG * g.N + p.n], g, p, dr, j);
+  T dr, j[3], gv[Q];
+  streamed_moments(pop, hist, geo, vin, g, p, dr, j, gv);
   const double r = 1.0 + (double)dr;
   if (rho) rho[p.n] = r;
   if (u) {
@@ -417,8 +411,9 @@ __global__ __launch_bounds__(BX * BY) void k_moments_out(Grid g, const T* __rest
 // sgn, added to t.
 template <class T>
 __device__ __forceinline__ void node_traction(const Grid& g, const T* __restrict__ pop, const T* __restrict__ hist,
-                                              const T* __restrict__ geo, const double* __restrict__ jac, T tau,
-                                              const Pos& p, double sgn, double t[3]) {
+                                              const T* __restrict__ geo, const T* __restrict__ vin,
+                                              const double* __restrict__ jac, T tau, const Pos& p, double sgn,
+                                              double t[3]) {
   NodeGeo<T> G;
   load_geo(geo, g.N, p.n, G);
   Coef<T> cp;
@@ -426,12 +421,12 @@ __device__ __forceinline__ void node_traction(const Grid& g, const T* __restrict
   const T isg = T(1) / (T(1) + G.sgd);
   T Fp[Q], ft[Q];
   forcing_pops(cp, isg, Fp);
+  T dr, j[3];
+  streamed_moments(pop, hist, geo, vin, g, p, dr, j, ft);
   for_q([&](auto L) {
     constexpr int l = decltype(L)::value;
-    ft[l] = pull<T, l>(pop, g, p) + T(0.5) * Fp[l];
+    ft[l] += T(0.5) * Fp[l];
   });
-  T dr, j[3];
-  streamed_moments(pop, hist, G.sgd, g, p, dr, j);
   T ne[Q], Tm[6];
   node_stress(G, ft, dr, j, tau, ne, Tm);
   const double sg = 1.0 + (double)G.sgd;
@@ -451,8 +446,9 @@ __device__ __forceinline__ void node_traction(const Grid& g, const T* __restrict
 template <class T>
 __global__ __launch_bounds__(BX* BY) void k_wall_force(Grid g, int wall, const T* __restrict__ pop,
                                                       const T* __restrict__ hist, const T* __restrict__ geo,
-                                                      const double* __restrict__ jac, T tau,
-                                                      double* __restrict__ per_node, double* __restrict__ part) {
+                                                      const T* __restrict__ vin, const double* __restrict__ jac,
+                                                      T tau, double* __restrict__ per_node,
+                                                      double* __restrict__ part) {
   __shared__ double red[3][BX * BY];
   const int tid = threadIdx.y * BX + threadIdx.x;
   Pos p;
@@ -463,12 +459,12 @@ __global__ __launch_bounds__(BX* BY) void k_wall_force(Grid g, int wall, const T
     if (wall < 2) {
       p.jf = wall == 0 ? 0 : g.H - 1;
       p.n = ((long long)p.k * g.H + p.jf) * g.nx + p.i;
-      node_traction(g, pop, hist, geo, jac, tau, p, wall == 0 ? -1.0 : 1.0, t);
+      node_traction(g, pop, hist, geo, vin, jac, tau, p, wall == 0 ? -1.0 : 1.0, t);
     } else if (p.i >= g.pi0 && p.i <= g.pi1) {
       for (int side = 0; side < 2; ++side) {
         p.jf = g.pj - 1 + side;
         p.n = ((long long)p.k * g.H + p.jf) * g.nx + p.i;
-        node_traction(g, pop, hist, geo, jac, tau, p, side == 0 ? 1.0 : -1.0, t);
+        node_traction(g, pop, hist, geo, vin, jac, tau, p, side == 0 ? 1.0 : -1.0, t);
       }
     }
     if (per_node) {
@@ -527,7 +523,7 @@ template <class T> hipError_t launch_step(Fields& F, hipStream_t s, T tau, hipEv
   auto mark = [&](int k) {
     if (ev && e == hipSuccess) e = hipEventRecord(ev[k], s);
   };
-  if (F.variant == 0) {
+  if (F.variant == 0 && !g.open) {
     mark(0);
     if (e == hipSuccess) e = launch_step_fused<T>(F, s, tau, F.zc, F.tile);
     mark(1);
@@ -539,11 +535,12 @@ template <class T> hipError_t launch_step(Fields& F, hipStream_t s, T tau, hipEv
   T* pout = (T*)F.pop[F.cur ^ 1];
   mark(0);
   hipLaunchKernelGGL(k_moments<T>, fluid_grid(g), b, 0, s, g, pin, (const T*)F.hist[F.cur], (const T*)F.geo,
-                     (T*)F.mom);
+                     (const T*)F.vin, (T*)F.mom);
   mark(1);
   hipLaunchKernelGGL(k_collide<T>, fluid_grid(g), b, 0, s, g, pin, pout, (const T*)F.hist[F.cur],
                      (T*)F.hist[F.cur ^ 1], (const T*)F.geo,
-                     (const T*)F.mom, (const T*)F.uw, F.moving[0], F.moving[1], (const T*)F.up, tau, F.flag);
+                     (const T*)F.mom, (const T*)F.uw, F.moving[0], F.moving[1], (const T*)F.up, (const T*)F.vin, tau,
+                     F.flag);
   mark(2);
   F.cur ^= 1;
   const hipError_t l = hipGetLastError();
@@ -576,7 +573,7 @@ template <class T> hipError_t launch_set_state(Fields& F, hipStream_t s, const d
 template <class T> hipError_t launch_get_pops(Fields& F, hipStream_t s, double* out) {
   dim3 b(BX, BY);
   hipLaunchKernelGGL(k_get_pops<T>, fluid_grid(F.g), b, 0, s, F.g, (const T*)F.pop[F.cur], (const T*)F.hist[F.cur],
-                     (const T*)F.geo, out);
+                     (const T*)F.geo, (const T*)F.vin, out);
   return hipGetLastError();
 }
 
@@ -595,7 +592,7 @@ template <class T> hipError_t launch_get_geo(Fields& F, hipStream_t s, double* o
 template <class T> hipError_t launch_moments_out(Fields& F, hipStream_t s, double* rho, double* u, int cart) {
   dim3 b(BX, BY);
   hipLaunchKernelGGL(k_moments_out<T>, fluid_grid(F.g), b, 0, s, F.g, (const T*)F.pop[F.cur], (const T*)F.hist[F.cur],
-                     (const T*)F.geo, F.jac, rho, u, cart);
+                     (const T*)F.geo, (const T*)F.vin, F.jac, rho, u, cart);
   return hipGetLastError();
 }
 
@@ -603,7 +600,7 @@ template <class T>
 hipError_t launch_wall_force(Fields& F, hipStream_t s, int wall, T tau, double* total, double* per_node) {
   dim3 b(BX, BY), gr = col_grid(F.g);
   hipLaunchKernelGGL(k_wall_force<T>, gr, b, 0, s, F.g, wall, (const T*)F.pop[F.cur], (const T*)F.hist[F.cur],
-                     (const T*)F.geo, F.jac, tau, per_node, F.part);
+                     (const T*)F.geo, (const T*)F.vin, F.jac, tau, per_node, F.part);
   const int nb = (int)(gr.x * gr.y);
   hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, nb, (const double*)F.part, total);
   return hipGetLastError();

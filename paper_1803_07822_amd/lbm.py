@@ -36,7 +36,7 @@ SYMBOLS = [
     "lbm_set_populations", "lbm_get_populations", "lbm_get_history", "lbm_get_geometry", "lbm_step",
     "lbm_step_profiled", "lbm_set_tuning", "lbm_get_tuning", "lbm_stream_probe", "lbm_moments", "lbm_wall_force",
     "lbm_couple", "lbm_set_plate", "lbm_set_plate_displacement", "lbm_set_plate_velocity", "lbm_plate_force",
-    "lbm_forward_record", "lbm_backward", "lbm_sync", "lbm_last_error",
+    "lbm_set_open_x", "lbm_forward_record", "lbm_backward", "lbm_sync", "lbm_last_error",
 ]
 
 
@@ -73,6 +73,7 @@ _lib.lbm_set_plate.argtypes = [_P, _I, _I, _I]
 _lib.lbm_set_plate_displacement.argtypes = [_P, _P, _I]
 _lib.lbm_set_plate_velocity.argtypes = [_P, _P]
 _lib.lbm_plate_force.argtypes = [_P, _P, _P]
+_lib.lbm_set_open_x.argtypes = [_P, _P]
 _lib.lbm_forward_record.argtypes = [_P, _I, _I, _I, _I, _P]
 _lib.lbm_backward.argtypes = [_P, _P, _P, _P, _P]
 _lib.lbm_sync.argtypes = [_P]
@@ -166,6 +167,10 @@ def lbm_set_plate_velocity(ctx, v):
 
 def lbm_plate_force(ctx, total, per_column=None):
     return _check(ctx, _lib.lbm_plate_force(ctx, _ptr(total), _ptr(per_column)))
+
+
+def lbm_set_open_x(ctx, uin):
+    return _check(ctx, _lib.lbm_set_open_x(ctx, _ptr(uin)))
 
 
 def lbm_init_equilibrium(ctx, rho=None, ucart=None):
@@ -314,6 +319,12 @@ class Solver:
         """Interior plate between fluid rows jp-1 and jp over columns i0..i1
         (jp = 0 removes it); before the state is set."""
         lbm_set_plate(self.ctx, jp, i0, i1)
+
+    def set_open_x(self, uin):
+        """Open ends in x with the Cartesian inlet velocity [nz, H, 3] (None:
+        periodic x again); before the state."""
+        self._keep_in = self._dev(uin, (self.nz, self.H, 3))
+        lbm_set_open_x(self.ctx, self._keep_in)
 
     def set_plate_displacement(self, d, reproject=False):
         self._keep_p = self._dev(d, (self.nz, self.nx))

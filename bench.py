@@ -42,10 +42,10 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--fp64-steps", type=int, default=None)
     p.add_argument("--no-extra", action="store_true",
-                   help="skip the oscillating-wall loop and the 512x256x256 runs")
-    p.add_argument("--part", choices=["all", "adjoint", "c3", "c5"], default="all",
+                   help="skip the oscillating-wall loop, the 512x256x256 runs and the flag channel")
+    p.add_argument("--part", choices=["all", "adjoint", "c3", "c5", "flag"], default="all",
                    help="run one measurement alone (for profiling): the 128x64x64 adjoint, the oscillating-wall "
-                        "loop or the 512x256x256 runs; prints that part's JSON only")
+                        "loop, the 512x256x256 runs or the flag channel; prints that part's JSON only")
     p.add_argument("--counters", action="store_true",
                    help="no timing: a 256 MiB calibration copy, then --steps FP32 steps, for rocprofv3 --pmc runs")
     return p.parse_args()
@@ -199,6 +199,65 @@ def c3_loop():
            "metric_update_and_reprojection_ms": round(rp_ms / nup, 4),
            "wall_velocity_ms": round(vel_ms / nup, 4),
            "force_finite": bool(np.isfinite(f).all()), "final_force": [float(x) for x in f[-1]]}
+    del S
+    torch.cuda.empty_cache()
+    return res
+
+
+def flag_channel(steps=None):
+    """The flag channel (Sec. VI.A without the structure), FP32: parabolic
+    inlet, open outlet, a plate flapping with a prescribed motion, its chart
+    rebuilt and the state re-projected every step.  GPU time per step
+    (step + chart + geometry + re-projection + plate velocity) from events on
+    the library's stream over the whole run, with the plate shapes uploaded
+    beforehand; the guard is checked at the end."""
+    import numpy as np
+    import torch
+
+    from paper_1803_07822_amd import lbm, synth
+
+    w = synth.workload("flag_channel_257x65")
+    steps = steps or w.steps
+    H = w.ny - 2
+    jp, i0, i1 = w.extra["plate"]
+    A, om = w.extra["A"], w.extra["omega"]
+    S = lbm.Solver(w.nx, w.ny, w.nz, w.tau, "fp32")
+    S.set_open_x(synth.parabolic_inlet(w.nz, H, w.extra["U"]))
+    S.set_plate(jp, i0, i1)
+    S.set_wall_displacement(lbm.LBM_WALL_YMAX, np.zeros((w.nz, w.nx)))
+    uc = np.zeros((3, w.nz, H, w.nx))
+    uc[0] = synth.parabolic_inlet(w.nz, H, w.extra["U"])[..., 0][:, :, None]
+    S.init_equilibrium(None, uc)
+    shapes = [synth.flapping_plate(w.nx, w.nz, i0, i1, A=A, omega=om, t=float(t)) for t in range(1, steps + 1)]
+    dev = [(torch.as_tensor(d, device=S.device), torch.as_tensor(v, device=S.device)) for d, v in shapes]
+    force = torch.empty((steps, 3), dtype=torch.float64, device=S.device)
+    S.sync()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(S.stream)
+    for t in range(steps):
+        lbm.lbm_step(S.ctx, 1)
+        d, v = dev[t]
+        lbm.lbm_set_plate_displacement(S.ctx, d, 1)
+        lbm.lbm_set_plate_velocity(S.ctx, v)
+        lbm.lbm_plate_force(S.ctx, force[t])
+    e1.record(S.stream)
+    stable = True
+    try:
+        S.sync()
+    except lbm.LBMError:
+        stable = False
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    f = force.cpu().numpy()
+    rho, u = S.moments(cartesian=True) if stable else (None, None)
+    res = {"workload": w.name, "precision": "fp32", "steps": steps, "tau": round(w.tau, 5),
+           "Re_channel": 325, "stable": stable, "gpu_ms": round(ms, 2),
+           "ms_per_step_with_reprojection": round(ms / steps, 5),
+           "mlups_with_reprojection": round(w.fluid_nodes * steps / (ms * 1e-3) / 1e6, 1),
+           "max_u": float(u.abs().max()) if stable else None,
+           "plate_force_last": [float(x) for x in f[-1]],
+           "plate_force_lift_range": [float(f[:, 1].min()), float(f[:, 1].max())]}
     del S
     torch.cuda.empty_cache()
     return res
@@ -421,7 +480,7 @@ def main():
         counter_run(w, a.steps)
         return
     if a.part != "all":
-        part = {"adjoint": adjoint_ratio, "c3": c3_loop, "c5": c5_runs}[a.part]()
+        part = {"adjoint": adjoint_ratio, "c3": c3_loop, "c5": c5_runs, "flag": flag_channel}[a.part]()
         print(json.dumps({"part": a.part, **part}), flush=True)
         return
     N = w.fluid_nodes
@@ -453,7 +512,7 @@ def main():
                    "form": "fp32 deviation storage, fp64 metric precompute"},
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_step_fused<float, 4, 1> (whole step, one launch)",
+            "kernel": "k_step_fused<float, 64, 4, 1, false> (whole step, one launch)",
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",
@@ -489,6 +548,7 @@ def main():
     if not a.no_extra:
         out["c3_time_varying_metric"] = c3_loop()
         out["c5_at_scale"] = c5_runs()
+        out["flag_channel"] = flag_channel()
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, a.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -171,3 +171,43 @@ def test_open_ends_argument_errors():
     with pytest.raises(lbm.LBMError) as e:
         lbm.lbm_forward_record(A.ctx, 2, 1, 1, forces)
     assert e.value.code == -6
+
+
+def _flag_run(A, steps, check=100):
+    """The flag channel workload (FP32) with tail amplitude A: the step at
+    which the instability guard tripped, or None."""
+    lbm = _lbm()
+    w = synth.workload("flag_channel_257x65")
+    H = w.ny - 2
+    jp, i0, i1 = w.extra["plate"]
+    S = lbm.Solver(w.nx, w.ny, w.nz, w.tau, "fp32")
+    S.set_open_x(synth.parabolic_inlet(w.nz, H, w.extra["U"]))
+    S.set_plate(jp, i0, i1)
+    S.set_wall_displacement(1, np.zeros((w.nz, w.nx)))
+    uc = np.zeros((3, w.nz, H, w.nx))
+    uc[0] = synth.parabolic_inlet(w.nz, H, w.extra["U"])[..., 0][:, :, None]
+    S.init_equilibrium(None, uc)
+    for t in range(1, steps + 1):
+        S.step(1)
+        d, v = synth.flapping_plate(w.nx, w.nz, i0, i1, A=A, omega=w.extra["omega"], t=float(t))
+        S.set_plate_displacement(d, reproject=True)
+        S.set_plate_velocity(v)
+        if t % check == 0:
+            try:
+                S.sync()
+            except lbm.LBMError as e:
+                assert e.code == -5
+                return t
+    return None
+
+
+def test_flag_channel_stability():
+    """The flag channel at Re_H = 325 runs 2000 steps stably with a tail
+    amplitude of 0.5 cells and trips the instability guard within 1000 steps
+    at 2 cells (fast, large deformations of an interior boundary; the kernels
+    complete and the guard reports it)."""
+    w = synth.workload("flag_channel_257x65")
+    assert _flag_run(w.extra["A"], 2000) is None
+    tripped = _flag_run(w.extra["A_unstable"], 1000)
+    print("flag channel: large flapping trips the guard by step", tripped, flush=True)
+    assert tripped is not None

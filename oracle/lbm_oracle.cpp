@@ -829,6 +829,44 @@ template <class T> struct Sim {
     }
   }
 
+  // Momentum-exchange force on a wall at rest (a diagnostic beside the
+  // node-exact traction): every population that streamed into the wall in the
+  // last step came back reversed, handing the wall 2 f*_l c_l, with f* the
+  // post-collision value.  f* is recovered from the streamed state: the
+  // reversed population is f_opp(l) = f*_l + F_opp(l)/2 (the half force added
+  // at streaming, from the history).  Cartesian force sqrt g J c_l per link,
+  // summed per column.  Returns false for a moving wall.
+  bool wall_force_mem(int wall, T total[3], T* per_node) const {
+    for (long q = 0; q < (long)nz * nx * 3; ++q)
+      if (val(vwall[wall][q]) != 0.0) return false;
+    total[0] = total[1] = total[2] = 0.0;
+    const int jf = (wall == 0) ? 0 : H - 1;
+    for (int k = 0; k < nz; ++k)
+      for (int i = 0; i < nx; ++i) {
+        const long n = nid(i, jf, k);
+        const Geo<T>& G = geo[n];
+        Coef<T> c;
+        coef_load(Fp, N, n, c);
+        T col[3] = {0.0, 0.0, 0.0};
+        for (int l = 0; l < QN; ++l) {
+          const int cy = CV[l][1];
+          if (!((wall == 1 && cy > 0) || (wall == 0 && cy < 0))) continue;  // links into this wall
+          const int o = opposite(l);
+          const T fstar = f[o * N + n] - 0.5 * forcing_pop(o, G.sg, c);
+          for (int a = 0; a < 3; ++a) {
+            T v = 0.0;
+            for (int b = 0; b < 3; ++b) v += G.J[a][b] * (double)CV[l][b];
+            col[a] += 2.0 * G.sg * fstar * v;
+          }
+        }
+        for (int a = 0; a < 3; ++a) {
+          total[a] += col[a];
+          if (per_node) per_node[((long)k * nx + i) * 3 + a] = col[a];
+        }
+      }
+    return true;
+  }
+
   // Node-exact wall traction (Sec. IV.A.2): at the fluid layer next to the
   // wall, the Cartesian force sqrt g T^{i y} e_i per column; n dA = sqrt g e^y.
   // The bottom wall's outward normal points to -y, hence the sign.
@@ -1206,6 +1244,9 @@ void orc_step(void* s, int n) {
 }
 void orc_moments(void* s, double* rho, double* u, int cartesian) {
   ((Sim<double>*)s)->moments(rho, u, cartesian != 0);
+}
+int orc_wall_force_mem(void* s, int wall, double* total, double* per_node) {
+  return ((Sim<double>*)s)->wall_force_mem(wall, total, per_node) ? 0 : -1;
 }
 void orc_wall_force(void* s, int wall, double* total, double* per_node) {
   ((Sim<double>*)s)->wall_force(wall, total, per_node);

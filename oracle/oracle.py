@@ -69,6 +69,8 @@ def _lib():
             fn.restype = None
         L.orc_set_plate.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int]
         L.orc_set_plate.restype = ctypes.c_int
+        L.orc_wall_force_mem.argtypes = [ctypes.c_void_p, ctypes.c_int, _D, _D]
+        L.orc_wall_force_mem.restype = ctypes.c_int
         L.orc_set_open_x.argtypes = [ctypes.c_void_p, _D]
         L.orc_set_open_x.restype = ctypes.c_int
         L.orc_run_forces.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double, _D, _D, _D, ctypes.c_int, ctypes.c_int, _D]
@@ -201,6 +203,14 @@ class Oracle:
         tot = np.empty(3)
         pn = np.empty((self.nz, self.nx, 3)) if per_node else None
         _lib().orc_wall_force(self._h, int(wall), _p(tot), _p(pn))
+        return (tot, pn) if per_node else tot
+
+    def wall_force_mem(self, wall, per_node=False):
+        """Momentum-exchange force on a wall at rest (diagnostic)."""
+        tot = np.empty(3)
+        pn = np.empty((self.nz, self.nx, 3)) if per_node else None
+        if _lib().orc_wall_force_mem(self._h, int(wall), _p(tot), _p(pn)) != 0:
+            raise ValueError("the momentum-exchange force needs the wall at rest")
         return (tot, pn) if per_node else tot
 
     def geometry(self):

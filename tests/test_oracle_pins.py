@@ -539,3 +539,46 @@ def test_config1_channel_deviation_scales_with_eps():
     dev_half = np.abs(res[0.015] - res[0.0]).max()
     dev_full = np.abs(res[0.03] - res[0.0]).max()
     assert 1.8 < dev_full / dev_half < 2.2, (dev_half, dev_full)
+
+
+def test_momentum_budget_and_momentum_exchange_flat():
+    """Flat channel with walls at rest, body force F, non-equilibrium start.
+    The total momentum changes each step by exactly N F (the split forcing
+    adds 3/2 B(t) - 1/2 B(t-1) = F per node in flat space) minus what the
+    walls took by bounce-back, which is the momentum-exchange force of both
+    walls: sum j(t+1) - sum j(t) = N F - MEM_top - MEM_bottom, to rounding,
+    in the transient as at steady state (where MEM_top + MEM_bottom = N F)."""
+    nx, ny, nz, tau = 6, 9, 4, 0.7
+    H = ny - 2
+    F = np.array([2e-5, -3e-6, 5e-6])
+    o = Oracle(nx, ny, nz, tau)
+    o.set_body_force(F)
+    o.set_wall_displacement(1, np.zeros((nz, nx)))
+    o.init_equilibrium(1 + synth.random_perturbation((nz, H, nx), 2e-3, 3),
+                       synth.random_perturbation((3, nz, H, nx), 1e-2, 4))
+    N = nx * H * nz
+
+    def total_j():
+        rho, u = o.moments(cartesian=True)
+        return (rho[None] * u).sum(axis=(1, 2, 3))
+
+    j0 = total_j()
+    for t in range(30):
+        o.step(1)
+        j1 = total_j()
+        mem = o.wall_force_mem(0) + o.wall_force_mem(1)
+        assert np.abs((j1 - j0) - (N * F - mem)).max() < 1e-13 * N * np.abs(F).max() + 1e-14, t
+        j0 = j1
+    # steady state from rest
+    o = Oracle(nx, ny, nz, tau)
+    o.set_body_force(F)
+    o.set_wall_displacement(1, np.zeros((nz, nx)))
+    o.init_equilibrium()
+    o.step(steady_steps(H, tau, 30))
+    mem = o.wall_force_mem(0) + o.wall_force_mem(1)
+    assert np.abs(mem - N * F).max() < 1e-9 * N * np.abs(F).max()
+    # the two force estimates of one wall agree at steady state up to the
+    # half-cell offset of the traction (F (H - 1)/2 against F H / 2 per column)
+    tx = o.wall_force(1)[0] / (nx * nz)
+    mx = o.wall_force_mem(1)[0] / (nx * nz)
+    assert abs(tx - F[0] * (H - 1) / 2) < 1e-9 * F[0] * H and abs(mx - F[0] * H / 2) < 1e-9 * F[0] * H

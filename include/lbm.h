@@ -71,7 +71,7 @@ enum { LBM_D3Q19 = 19 };
  * arithmetic in FP32; the geometry itself is computed in FP64. */
 enum { LBM_FP64 = 0, LBM_FP32_DEV = 1 };
 enum { LBM_WALL_YMIN = 0, LBM_WALL_YMAX = 1 };
-enum { LBM_FORCE_STRESS = 0 };
+enum { LBM_FORCE_STRESS = 0, LBM_FORCE_MEM = 1 };
 enum {
   LBM_OK = 0,
   LBM_EINVAL = -1,      /* bad argument */
@@ -150,11 +150,15 @@ int lbm_step(lbm_ctx* ctx, int n);
  * NULL.  Checks the instability guard (synchronising). */
 int lbm_moments(lbm_ctx* ctx, double* d_rho, double* d_u, int cartesian);
 
-/* Node-exact force of the fluid on a wall at the current state: per column,
- * the traction sqrt g T^{i y} e_i at the fluid layer next to the wall (sign
- * flipped for the bottom wall), T from Eq. (fields3), e_i = J[.][i].
- * d_total3: the sum over columns (3 doubles, device).  d_per_node ([nz][nx][3]
- * or NULL).  Only LBM_FORCE_STRESS is provided. */
+/* Force of the fluid on a wall at the current state, per column (Sec. IV.A.2).
+ * LBM_FORCE_STRESS: the node-exact traction sqrt g T^{i y} e_i at the fluid
+ * layer next to the wall (sign flipped for the bottom wall), T from
+ * Eq. (fields3), e_i = J[.][i].  LBM_FORCE_MEM (a diagnostic, wall at rest
+ * only): the momentum exchange of the last step, the sum over the links into
+ * the wall of 2 sqrt g J c_l f*_l with f*_l the post-collision population
+ * that bounced (EUNSUPPORTED for a wall given a velocity).  d_total3: the sum
+ * over columns (3 doubles, device).  d_per_node ([nz][nx][3] or NULL).
+ * EINVAL for another method. */
 int lbm_wall_force(lbm_ctx* ctx, int wall, int method, double* d_total3, double* d_per_node);
 
 /* One coupling interval with an external structural solver (Sec. IV.A: the

@@ -543,13 +543,16 @@ int lbm_moments(lbm_ctx* c, double* d_rho, double* d_u, int cartesian) {
 int lbm_wall_force(lbm_ctx* c, int wall, int method, double* d_total3, double* d_per_node) {
   LBM_GUARD(c);
   if (wall != LBM_WALL_YMIN && wall != LBM_WALL_YMAX) return fail(c, LBM_EINVAL, "bad wall");
-  if (method != LBM_FORCE_STRESS) return fail(c, LBM_EUNSUPPORTED, "only the stress method is provided");
+  if (method != LBM_FORCE_STRESS && method != LBM_FORCE_MEM) return fail(c, LBM_EINVAL, "bad force method");
   if (!d_total3) return fail(c, LBM_EINVAL, "total output is NULL");
   if (!c->have_state) return fail(c, LBM_ESTATE, "no state");
+  const int mem = method == LBM_FORCE_MEM;
+  if (mem && c->F.moving[wall])
+    return fail(c, LBM_EUNSUPPORTED, "the momentum-exchange force is provided for a wall at rest");
   if (c->precision == LBM_FP64)
-    LBM_HIP(c, lbm::launch_wall_force<double>(c->F, c->stream, wall, c->tau, d_total3, d_per_node));
+    LBM_HIP(c, lbm::launch_wall_force<double>(c->F, c->stream, wall, c->tau, d_total3, d_per_node, mem));
   else
-    LBM_HIP(c, lbm::launch_wall_force<float>(c->F, c->stream, wall, (float)c->tau, d_total3, d_per_node));
+    LBM_HIP(c, lbm::launch_wall_force<float>(c->F, c->stream, wall, (float)c->tau, d_total3, d_per_node, mem));
   return LBM_OK;
 }
 

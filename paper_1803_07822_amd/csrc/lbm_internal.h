@@ -115,9 +115,10 @@ template <class T> hipError_t launch_step_fused(Fields& F, hipStream_t s, T tau,
 // Planes per block the fused step runs with (F.zc, or the automatic choice).
 template <class T> hipError_t fused_step_chunk(Fields& F, int* zc);
 template <class T> hipError_t launch_moments_out(Fields& F, hipStream_t s, double* rho, double* u, int cart);
-// wall 0 / 1: the walls; wall 2: the interior plate (both faces, plate columns)
+// wall 0 / 1: the walls; wall 2: the interior plate (both faces, plate
+// columns).  mem != 0: momentum exchange (walls at rest) instead of traction.
 template <class T> hipError_t launch_wall_force(Fields& F, hipStream_t s, int wall, T tau, double* total,
-                                                double* per_node);
+                                                double* per_node, int mem = 0);
 template <class T> hipError_t launch_reproject(Fields& F, hipStream_t s, const double Fc[3], T tau);
 
 }  // namespace lbm

@@ -439,12 +439,44 @@ __device__ __forceinline__ void node_traction(const Grid& g, const T* __restrict
   }
 }
 
-// Force per column on a wall (wall 0 / 1: the traction at the fluid layer
-// next to it, outward-normal sign) or on the plate (wall 2: the traction of
-// both faces in the plate columns, + at the node below and - at the node
-// above; zero in the other columns), summed per block.
+// Momentum exchange at a wall at rest, per column: the populations that
+// streamed into the wall in the last step came back reversed, each handing
+// the wall 2 f*_l c_l; their post-collision values sit in the bounce-back
+// slots (f*_l = w_l + pop[l] at the fluid node next to the wall).  Cartesian
+// 2 sqrt g J c_l f*_l, added to t.
 template <class T>
-__global__ __launch_bounds__(BX* BY) void k_wall_force(Grid g, int wall, const T* __restrict__ pop,
+__device__ __forceinline__ void node_exchange(const Grid& g, int wall, const T* __restrict__ pop,
+                                              const T* __restrict__ geo, const double* __restrict__ jac,
+                                              const Pos& p, double t[3]) {
+  const double sg = 1.0 + (double)geo[G_SG * g.N + p.n];
+  double J[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) J[a][b] = jac[(a * 3 + b) * g.N + p.n];
+  for_q([&](auto L) {
+    constexpr int l = decltype(L)::value;
+    constexpr int y = cy(l);
+    if ((wall == 1 && y > 0) || (wall == 0 && y < 0)) {
+      const double fs = wgt(l) + (double)pop[(long long)l * g.N + p.n];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        double v = J[a][1] * y;
+        if (cx(l)) v += J[a][0] * cx(l);
+        if (cz(l)) v += J[a][2] * cz(l);
+        t[a] += 2.0 * sg * fs * v;
+      }
+    }
+  });
+}
+
+// Force per column on a wall (wall 0 / 1: the traction at the fluid layer
+// next to it, outward-normal sign, or with mem != 0 the momentum exchange) or
+// on the plate (wall 2: the traction of both faces in the plate columns, + at
+// the node below and - at the node above; zero in the other columns), summed
+// per block.
+template <class T>
+__global__ __launch_bounds__(BX* BY) void k_wall_force(Grid g, int wall, int mem, const T* __restrict__ pop,
                                                       const T* __restrict__ hist, const T* __restrict__ geo,
                                                       const T* __restrict__ vin, const double* __restrict__ jac,
                                                       T tau, double* __restrict__ per_node,
@@ -459,7 +491,10 @@ __global__ __launch_bounds__(BX* BY) void k_wall_force(Grid g, int wall, const T
     if (wall < 2) {
       p.jf = wall == 0 ? 0 : g.H - 1;
       p.n = ((long long)p.k * g.H + p.jf) * g.nx + p.i;
-      node_traction(g, pop, hist, geo, vin, jac, tau, p, wall == 0 ? -1.0 : 1.0, t);
+      if (mem)
+        node_exchange(g, wall, pop, geo, jac, p, t);
+      else
+        node_traction(g, pop, hist, geo, vin, jac, tau, p, wall == 0 ? -1.0 : 1.0, t);
     } else if (p.i >= g.pi0 && p.i <= g.pi1) {
       for (int side = 0; side < 2; ++side) {
         p.jf = g.pj - 1 + side;
@@ -597,9 +632,9 @@ template <class T> hipError_t launch_moments_out(Fields& F, hipStream_t s, doubl
 }
 
 template <class T>
-hipError_t launch_wall_force(Fields& F, hipStream_t s, int wall, T tau, double* total, double* per_node) {
+hipError_t launch_wall_force(Fields& F, hipStream_t s, int wall, T tau, double* total, double* per_node, int mem) {
   dim3 b(BX, BY), gr = col_grid(F.g);
-  hipLaunchKernelGGL(k_wall_force<T>, gr, b, 0, s, F.g, wall, (const T*)F.pop[F.cur], (const T*)F.hist[F.cur],
+  hipLaunchKernelGGL(k_wall_force<T>, gr, b, 0, s, F.g, wall, mem, (const T*)F.pop[F.cur], (const T*)F.hist[F.cur],
                      (const T*)F.geo, (const T*)F.vin, F.jac, tau, per_node, F.part);
   const int nb = (int)(gr.x * gr.y);
   hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, nb, (const double*)F.part, total);
@@ -614,7 +649,7 @@ hipError_t launch_wall_force(Fields& F, hipStream_t s, int wall, T tau, double* 
   template hipError_t launch_get_hist<T>(Fields&, hipStream_t, double*);                               \
   template hipError_t launch_get_geo<T>(Fields&, hipStream_t, double*);                                \
   template hipError_t launch_moments_out<T>(Fields&, hipStream_t, double*, double*, int);              \
-  template hipError_t launch_wall_force<T>(Fields&, hipStream_t, int, T, double*, double*);
+  template hipError_t launch_wall_force<T>(Fields&, hipStream_t, int, T, double*, double*, int);
 LBM_INST(double)
 LBM_INST(float)
 #undef LBM_INST

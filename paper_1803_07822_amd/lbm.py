@@ -27,6 +27,7 @@ LBM_D3Q19 = 19
 LBM_FP64, LBM_FP32_DEV = 0, 1
 LBM_WALL_YMIN, LBM_WALL_YMAX = 0, 1
 LBM_FORCE_STRESS = 0
+LBM_FORCE_MEM = 1
 ERRORS = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EHIP", -4: "LBM_ESTATE",
           -5: "LBM_EUNSTABLE", -6: "LBM_EUNSUPPORTED"}
 
@@ -376,10 +377,10 @@ class Solver:
         lbm_moments(self.ctx, rho, u, cartesian)
         return rho, u
 
-    def wall_force(self, wall, per_node=False):
+    def wall_force(self, wall, per_node=False, method=LBM_FORCE_STRESS):
         tot = torch.empty(3, dtype=torch.float64, device=self.device)
         pn = torch.empty((self.nz, self.nx, 3), dtype=torch.float64, device=self.device) if per_node else None
-        lbm_wall_force(self.ctx, wall, tot, pn)
+        lbm_wall_force(self.ctx, wall, tot, pn, method)
         return (tot, pn) if per_node else tot
 
     def couple(self, wall, disp, vcart, n):

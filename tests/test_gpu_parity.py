@@ -333,3 +333,38 @@ def test_curved_poiseuille_steady_state(chart):
     scale = np.abs(uo).max()
     assert np.abs(out["fp64"] - uo).max() < 1e-10 * scale
     assert np.abs(out["fp32"] - out["fp64"]).max() < 1e-3 * scale
+
+
+@pytest.mark.parametrize("precision,variant", [("fp64", 0), ("fp64", 1), ("fp32", 0)])
+def test_wall_force_momentum_exchange_parity(precision, variant):
+    """Momentum-exchange force (diagnostic, walls at rest) of both walls in a
+    curved chart after a non-equilibrium start and 1, 7 steps, per column,
+    against the oracle; a wall given a velocity is refused, and so is an
+    unknown method."""
+    lbm = _lbm()
+    nx, ny, nz = 70, 12, 9
+    H = ny - 2
+    S, O = make_pair(nx, ny, nz, 0.7, precision=precision, chart=synth.bump3_chart(nx, ny, nz, 0.06),
+                     F=(2e-5, -1e-6, 1e-5))
+    lbm.lbm_set_tuning(S.ctx, 0, variant, -1)
+    f0 = _random_state(O, nz, H, nx, 51)
+    O.set_populations(f0)
+    S.set_populations(f0)
+    for n in (1, 6):
+        O.step(n)
+        S.step(n)
+        for wall in (0, 1):
+            t, pn = S.wall_force(wall, per_node=True, method=lbm.LBM_FORCE_MEM)
+            to, pno = O.wall_force_mem(wall, per_node=True)
+            scale = np.abs(pno).max()
+            tol = 1e-13 if precision == "fp64" else 2e-6
+            assert np.abs(_np(pn) - pno).max() < tol * scale, (wall, n)
+            assert np.abs(_np(t) - to).max() < tol * np.abs(to).max() * 10
+    tot = torch.zeros(3, dtype=torch.float64, device=S.device)
+    with pytest.raises(lbm.LBMError) as e:
+        lbm.lbm_wall_force(S.ctx, 1, tot, None, 2)
+    assert e.value.code == -1
+    S.set_wall_velocity(1, np.zeros((nz, nx, 3)))
+    with pytest.raises(lbm.LBMError) as e:
+        lbm.lbm_wall_force(S.ctx, 1, tot, None, lbm.LBM_FORCE_MEM)
+    assert e.value.code == -6

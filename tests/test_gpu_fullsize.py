@@ -132,6 +132,55 @@ def test_c3_oscillating_wall_full_size():
         torch.cuda.empty_cache()
 
 
+def test_c3_full_run_fp32_against_fp64_gpu():
+    """The whole oscillating-wall run, 4000 steps with 400 re-projections, in
+    FP32 against the FP64 GPU path (the oracle would take hours): the top-wall
+    force every 10 steps and the final density and velocity agree to the
+    FP32 deviation form's accumulated rounding."""
+    lbm = _lbm()
+    w = synth.workload("c3_oscillating_256x128x128")
+    every = w.extra["update_every"]
+    out = {}
+    for precision in ("fp64", "fp32"):
+        S = _solver(w, precision, np.zeros((w.nz, w.nx)))
+
+        def vel(v):
+            o = np.zeros((w.nz, w.nx, 3))
+            o[..., 1] = v
+            return o
+
+        d0, v0 = synth.oscillating_wall(w.nx, w.nz, t=0.0)
+        S.set_wall_displacement(1, d0)
+        S.set_wall_velocity(1, vel(v0))
+        S.init_equilibrium()
+        forces = []
+        for u in range(1, w.steps // every + 1):
+            S.step(every)
+            forces.append(_np(S.wall_force(1)))
+            d, v = synth.oscillating_wall(w.nx, w.nz, t=float(u * every))
+            S.set_wall_displacement(1, d, reproject=True)
+            S.set_wall_velocity(1, vel(v))
+        r, uu = S.moments(cartesian=True)
+        out[precision] = (np.array(forces), _np(r), _np(uu))
+        del S
+        torch.cuda.empty_cache()
+    f64, r64, u64 = out["fp64"]
+    f32, r32, u32 = out["fp32"]
+    # each component relative to its own scale; z (zero by symmetry) to the normal force
+    scale = np.abs(f64).max(axis=0)
+    scale[2] = scale[1]
+    ef = np.abs(f32 - f64).max(axis=0) / scale
+    er = np.abs(r32 - r64).max()
+    eu = np.abs(u32 - u64).max() / np.abs(u64).max()
+    print(f"C3 4000 steps FP32 vs FP64 GPU: force (x, y, z) {ef[0]:.2e} {ef[1]:.2e} {ef[2]:.2e}, "
+          f"|drho| {er:.2e}, |du|/max|u| {eu:.2e}", flush=True)
+    assert ef[1] < 1e-5, ef  # the normal force, O(pressure x area)
+    assert ef[0] < 1e-3, ef  # the drag, a small residue of the flow
+    assert ef[2] < 1e-5, ef
+    assert er < 1e-5, er
+    assert eu < 1e-3, eu
+
+
 def test_c5_stated_amplitude_trips_guard():
     """At the stated amplitude 0.08*256 (wall slope up to 1.0) the scheme is
     unstable: from rest, FP32 and FP64 both trip the instability guard within

@@ -28,6 +28,15 @@ HBM_PEAK_GBPS = 8000.0
 COUNTER_PROFILE = os.path.join(ROOT, "profiles", "step_fused_c2_256x128x128.md")
 STEP_SOURCES = ["paper_1803_07822_amd/csrc/lbm_step_fused.hip", "paper_1803_07822_amd/csrc/lbm_device.h",
                 "paper_1803_07822_amd/csrc/lbm_internal.h", "paper_1803_07822_amd/build.py"]
+# The FP32 step's kernels per launch variant (the default runs one kernel).
+STEP_KERNEL_NAMES = {
+    0: "k_step_fused<float, 64, 4, 1, false> (whole step, one launch)",
+    1: "k_moments<float> + k_collide<float> (two-pass step; time of both)",
+    2: "k_step_fused<float, 64, 2, 1, false> (whole step, one launch)",
+    3: "k_step_fused<float, 64, 1, 1, false> (whole step, one launch)",
+    4: "k_step_fused<float, 128, 2, 1, false> (whole step, one launch)",
+    5: "k_step_fused<float, 256, 1, 1, false> (whole step, one launch)",
+}
 METRIC = "MLUPS + HBM GB/s (% peak) FP32 vs FP64 step; adjoint/forward time ratio"
 
 
@@ -46,17 +55,22 @@ def parse():
     p.add_argument("--part", choices=["all", "adjoint", "c3", "c5", "flag"], default="all",
                    help="run one measurement alone (for profiling): the 128x64x64 adjoint, the oscillating-wall "
                         "loop, the 512x256x256 runs or the flag channel; prints that part's JSON only")
+    p.add_argument("--variant", type=int, default=0,
+                   help="launch variant of the step (lbm_set_tuning): 0 fused (default), 1 two-pass, 2-5 other "
+                        "fused tile shapes")
     p.add_argument("--counters", action="store_true",
                    help="no timing: a 256 MiB calibration copy, then --steps FP32 steps, for rocprofv3 --pmc runs")
     return p.parse_args()
 
 
-def setup(w, precision):
+def setup(w, precision, variant=0):
     import numpy as np
 
     from paper_1803_07822_amd import lbm, synth
 
     S = lbm.Solver(w.nx, w.ny, w.nz, w.tau, precision)
+    if variant:
+        lbm.lbm_set_tuning(S.ctx, 0, variant, -1)
     S.set_body_force(w.force)
     S.set_wall_displacement(lbm.LBM_WALL_YMAX, w.disp())
     uc = synth.uniform_noise_velocity(w.nx, w.ny, w.nz, 1e-4, seed=2)
@@ -486,7 +500,7 @@ def main():
     N = w.fluid_nodes
     res = {}
     for prec, steps in (("fp32", a.steps), ("fp64", a.fp64_steps or max(10, a.steps // 2))):
-        S, uc = setup(w, prec)
+        S, uc = setup(w, prec, a.variant)
         ms, wall = time_steps(S, uc, steps, a.warmup)
         res[prec] = dict(ms=ms, steps=steps, wall=wall, tuning=lbm.lbm_get_tuning(S.ctx),
                          mlups=N / (ms * 1e-3) / 1e6,
@@ -512,12 +526,12 @@ def main():
                    "form": "fp32 deviation storage, fp64 metric precompute"},
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_step_fused<float, 64, 4, 1, false> (whole step, one launch)",
+            "kernel": STEP_KERNEL_NAMES.get(a.variant, f"variant {a.variant}"),
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBPS, 4),
-            "traffic": recorded_traffic(w.name),
+            "traffic": recorded_traffic(w.name) if a.variant == 0 else None,
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
             "bytes_per_lup": BYTES_PER_LUP["fp32"],
             "kernel_ms": round(f32["ms"], 5),

@@ -9,6 +9,7 @@ Low-level functions carry the C names (``lbm_create``, ``lbm_set_metric``,
 wraps one context with its workspace.
 """
 import ctypes
+import functools
 import os
 
 import torch
@@ -260,7 +261,10 @@ def lbm_sync(ctx):
 class Solver:
     """One context with its workspace on ``device`` (a CUDA/HIP torch device)."""
 
-    def __init__(self, nx, ny, nz, tau, precision="fp64", adjoint_K=0, ckpt_every=0, device="cuda:0"):
+    def __init__(self, nx, ny, nz, tau, precision="fp64", adjoint_K=0, ckpt_every=0, device="cuda:0", stream=None):
+        """stream: the torch stream the context enqueues on (default: the
+        device's current stream).  A stream of its own lets a caller capture
+        a sequence of calls into a HIP graph and replay it."""
         self.nx, self.ny, self.nz, self.tau = nx, ny, nz, tau
         self.H = ny - 2
         self.device = torch.device(device)
@@ -270,7 +274,7 @@ class Solver:
             raise ValueError("invalid grid or adjoint sizes")
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         with torch.cuda.device(self.device):
-            self.stream = torch.cuda.current_stream(self.device)
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
             self.ctx = lbm_create(nx, ny, nz, tau, self.precision, self.workspace, self.stream.cuda_stream)
         if adjoint_K:
             lbm_reserve_adjoint(self.ctx, adjoint_K, ckpt_every)
@@ -414,6 +418,30 @@ class Solver:
         gf = torch.empty((19,) + self.fluid_shape, dtype=torch.float64, device=self.device) if need_f0 else None
         lbm_backward(self.ctx, g, gd, gc, gf)
         return gd, gc, gf
+
+
+def _on_solver_stream(fn):
+    """Run a Solver method with the context's stream current, ordered after
+    the caller's stream (inputs it made are ready) and before it (outputs are
+    ready to it); a no-op when the context uses the caller's stream."""
+
+    @functools.wraps(fn)
+    def run(self, *args, **kwargs):
+        caller = torch.cuda.current_stream(self.device)
+        if caller == self.stream:
+            return fn(self, *args, **kwargs)
+        self.stream.wait_stream(caller)
+        with torch.cuda.stream(self.stream):
+            out = fn(self, *args, **kwargs)
+        caller.wait_stream(self.stream)
+        return out
+
+    return run
+
+
+for _name, _fn in list(vars(Solver).items()):
+    if callable(_fn) and not _name.startswith("_"):
+        setattr(Solver, _name, _on_solver_stream(_fn))
 
 
 class WallForceFn(torch.autograd.Function):

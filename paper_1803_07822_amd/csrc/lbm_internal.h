@@ -36,7 +36,7 @@ struct Fields {
   double* disp;   // [2][nz][nx]
   double* vwall;  // [2][nz][nx][3] Cartesian wall velocity
   double* full;   // [19][N] FP64 scratch
-  void* mf;       // [20][NC] T: Cartesian moment fields for re-projection, deviations from rest
+  void* mf;       // [NC][20] T: Cartesian moment fields for re-projection, deviations from rest
   double* part;   // reduction partials
   int* flag;      // instability guard
   int cur;        // index of the current population and history buffers

@@ -81,6 +81,45 @@ __device__ __forceinline__ double cell_eval(const Cell& c, const double* __restr
 
 constexpr int NMF = 20;  // 0 rho, 1-3 j, 4-9 Pi, 10 A, 11-13 B, 14-19 C (Cartesian)
 
+// The moment fields are stored node by node ([node][20]): the 20 values of a
+// node are 80 (FP32) or 160 (FP64) contiguous bytes, moved with 16-byte
+// vector loads and stores, which the interpolation's eight corner gathers
+// per node need most.
+template <class T> struct MfVec;
+template <> struct MfVec<float> {
+  typedef float v __attribute__((ext_vector_type(4)));
+  static constexpr int W = 4;
+};
+template <> struct MfVec<double> {
+  typedef double v __attribute__((ext_vector_type(2)));
+  static constexpr int W = 2;
+};
+
+template <class T> __device__ __forceinline__ void mf_load(const T* __restrict__ mf, long long e, double out[NMF]) {
+  typedef typename MfVec<T>::v V;
+  constexpr int W = MfVec<T>::W;
+  const V* p = (const V*)(mf + e * NMF);
+#pragma unroll
+  for (int q = 0; q < NMF / W; ++q) {
+    const V v = p[q];
+#pragma unroll
+    for (int r = 0; r < W; ++r) out[q * W + r] = (double)v[r];
+  }
+}
+
+template <class T> __device__ __forceinline__ void mf_store(T* __restrict__ mf, long long e, const double in[NMF]) {
+  typedef typename MfVec<T>::v V;
+  constexpr int W = MfVec<T>::W;
+  V* p = (V*)(mf + e * NMF);
+#pragma unroll
+  for (int q = 0; q < NMF / W; ++q) {
+    V v;
+#pragma unroll
+    for (int r = 0; r < W; ++r) v[r] = (T)in[q * W + r];
+    p[q] = v;
+  }
+}
+
 // The moment fields are stored in the state's precision as deviations from
 // the state at rest (rho = 1, Pi = I/3 in Cartesian components), so that FP32
 // keeps their small variations; every operation on them (ghost layers,
@@ -112,7 +151,6 @@ __global__ __launch_bounds__(BX * BY) void k_rp_moments(Grid g, const T* __restr
   int i, jf, k;
   if (!xcd_fluid_node(g, i, jf, k)) return;
   const long long n = ((long long)k * g.H + jf) * g.nx + i;
-  const long long NC = (long long)g.nz * g.ny * g.nx;
   const long long e = ((long long)k * g.ny + (jf + 1)) * g.nx + i;
   Coef<T> c;
   c.A = hist[H_A * g.N + n];
@@ -162,12 +200,13 @@ __global__ __launch_bounds__(BX * BY) void k_rp_moments(Grid g, const T* __restr
       Pm[a][b] = sg * ((a == b ? 1.0 / 3.0 : 0.0) + P[sym(a, b)]);
       Cm[a][b] = (double)c.C[sym(a, b)];
     }
-  mf[0 * NC + e] = (T)(rho - mf_rest(0));
-  mf[10 * NC + e] = c.A;
+  double out[NMF];
+  out[0] = rho - mf_rest(0);
+  out[10] = (double)c.A;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    mf[(1 + a) * NC + e] = (T)(J[a][0] * j[0] + J[a][1] * j[1] + J[a][2] * j[2]);
-    mf[(11 + a) * NC + e] = (T)(J[a][0] * Bv[0] + J[a][1] * Bv[1] + J[a][2] * Bv[2]);
+    out[1 + a] = J[a][0] * j[0] + J[a][1] * j[1] + J[a][2] * j[2];
+    out[11 + a] = J[a][0] * Bv[0] + J[a][1] * Bv[1] + J[a][2] * Bv[2];
   }
 #pragma unroll
   for (int a = 0; a < 3; ++a)
@@ -181,9 +220,10 @@ __global__ __launch_bounds__(BX * BY) void k_rp_moments(Grid g, const T* __restr
           sp += J[a][p] * Pm[p][r] * J[b][r];
           sc += J[a][p] * Cm[p][r] * J[b][r];
         }
-      mf[(4 + sym(a, b)) * NC + e] = (T)(sp - mf_rest(4 + sym(a, b)));
-      mf[(14 + sym(a, b)) * NC + e] = (T)sc;
+      out[4 + sym(a, b)] = sp - mf_rest(4 + sym(a, b));
+      out[14 + sym(a, b)] = sc;
     }
+  mf_store(mf, e, out);
 }
 
 // Wall-layer ghosts of the moment fields: linear extrapolation from the two
@@ -192,17 +232,21 @@ template <class T>
 __global__ __launch_bounds__(BX * BY) void k_rp_ghost(Grid g, const double* __restrict__ vwall, T* __restrict__ mf) {
   const int i = blockIdx.x * BX + threadIdx.x, k = blockIdx.y * BY + threadIdx.y;
   if (i >= g.nx || k >= g.nz) return;
-  const long long NC = (long long)g.nz * g.ny * g.nx;
   for (int w = 0; w < 2; ++w) {
     const int jg = w == 0 ? 0 : g.ny - 1, jm = w == 0 ? 1 : g.ny - 2, jm2 = w == 0 ? 2 : g.ny - 3;
     const long long eg = ((long long)k * g.ny + jg) * g.nx + i;
     const long long em = ((long long)k * g.ny + jm) * g.nx + i;
     const long long em2 = ((long long)k * g.ny + jm2) * g.nx + i;
-    for (int q = 0; q < NMF; ++q) mf[q * NC + eg] = (T)(2.0 * (double)mf[q * NC + em] - (double)mf[q * NC + em2]);
+    double m1[NMF], m2[NMF], gv[NMF];
+    mf_load(mf, em, m1);
+    mf_load(mf, em2, m2);
+#pragma unroll
+    for (int q = 0; q < NMF; ++q) gv[q] = 2.0 * m1[q] - m2[q];
     const long long c = (((long long)w * g.nz + k) * g.nx + i) * 3;
-    const double rho_m = mf_rest(0) + (double)mf[em];
-    for (int a = 0; a < 3; ++a)
-      mf[(1 + a) * NC + eg] = (T)(2.0 * rho_m * vwall[c + a] - (double)mf[(1 + a) * NC + em]);
+    const double rho_m = mf_rest(0) + m1[0];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) gv[1 + a] = 2.0 * rho_m * vwall[c + a] - m1[1 + a];
+    mf_store(mf, eg, gv);
   }
 }
 
@@ -268,8 +312,10 @@ __global__ __launch_bounds__(BX * BY) void k_rp_new(Grid g, const double* __rest
   for (int c = 0; c < 8; ++c) {
     const int ox = c & 1, oy = (c >> 1) & 1, oz = (c >> 2) & 1;
     const double w = (ox ? fr[0] : 1.0 - fr[0]) * (oy ? fr[1] : 1.0 - fr[1]) * (oz ? fr[2] : 1.0 - fr[2]);
+    double mc[NMF];
+    mf_load(mf, cl.e[c], mc);
 #pragma unroll
-    for (int q = 0; q < NMF; ++q) m[q] += w * (double)mf[q * NC + cl.e[c]];
+    for (int q = 0; q < NMF; ++q) m[q] += w * mc[q];
   }
 #pragma unroll
   for (int q = 0; q < NMF; ++q) m[q] += mf_rest(q);

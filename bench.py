@@ -29,14 +29,15 @@ COUNTER_PROFILE = os.path.join(ROOT, "profiles", "step_fused_c2_256x128x128.md")
 STEP_SOURCES = ["paper_1803_07822_amd/csrc/lbm_step_fused.hip", "paper_1803_07822_amd/csrc/lbm_device.h",
                 "paper_1803_07822_amd/csrc/lbm_internal.h", "paper_1803_07822_amd/build.py"]
 # The FP32 step's kernels per launch variant (the default runs one kernel).
-STEP_KERNEL_NAMES = {
-    0: "k_step_fused<float, 64, 4, 1, false> (whole step, one launch)",
-    1: "k_moments<float> + k_collide<float> (two-pass step; time of both)",
-    2: "k_step_fused<float, 64, 2, 1, false> (whole step, one launch)",
-    3: "k_step_fused<float, 64, 1, 1, false> (whole step, one launch)",
-    4: "k_step_fused<float, 128, 2, 1, false> (whole step, one launch)",
-    5: "k_step_fused<float, 256, 1, 1, false> (whole step, one launch)",
-}
+TILE_OF_VARIANT = {0: (64, 4), 2: (64, 2), 3: (64, 1), 4: (128, 2), 5: (256, 1)}
+
+
+def step_kernel_name(variant, stage):
+    """The FP32 step kernel a launch shape runs (lbm_get_tuning's variant and stage)."""
+    if variant == 1:
+        return "k_moments<float> + k_collide<float> (two-pass step; time of both)"
+    tx, ty = TILE_OF_VARIANT[variant]
+    return f"k_step_fused<float, {tx}, {ty}, {stage}, false> (whole step, one launch)"
 METRIC = "MLUPS + HBM GB/s (% peak) FP32 vs FP64 step; adjoint/forward time ratio"
 
 
@@ -58,19 +59,21 @@ def parse():
     p.add_argument("--variant", type=int, default=0,
                    help="launch variant of the step (lbm_set_tuning): 0 fused (default), 1 two-pass, 2-5 other "
                         "fused tile shapes")
+    p.add_argument("--stage", type=int, default=-1,
+                   help="staging of the FP32 fused step (lbm_set_tuning): -1 the default, 0 none, 1 registers")
     p.add_argument("--counters", action="store_true",
                    help="no timing: a 256 MiB calibration copy, then --steps FP32 steps, for rocprofv3 --pmc runs")
     return p.parse_args()
 
 
-def setup(w, precision, variant=0):
+def setup(w, precision, variant=0, stage=-1):
     import numpy as np
 
     from paper_1803_07822_amd import lbm, synth
 
     S = lbm.Solver(w.nx, w.ny, w.nz, w.tau, precision)
-    if variant:
-        lbm.lbm_set_tuning(S.ctx, 0, variant, -1)
+    if variant or stage != -1:
+        lbm.lbm_set_tuning(S.ctx, 0, variant, stage)
     S.set_body_force(w.force)
     S.set_wall_displacement(lbm.LBM_WALL_YMAX, w.disp())
     uc = synth.uniform_noise_velocity(w.nx, w.ny, w.nz, 1e-4, seed=2)
@@ -510,11 +513,11 @@ def stream_floor(n, precision, reps=10):
     return ms
 
 
-def counter_run(w, steps):
+def counter_run(w, steps, stage=-1):
     """What the HBM counters are read over: a device-to-device copy of
     256 MiB into a fresh buffer (calibrates FETCH_SIZE and WRITE_SIZE against
     known bytes), then `steps` FP32 steps of the workload with the default
-    launch shape."""
+    launch shape (or the staging asked for)."""
     import torch
 
     a = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
@@ -525,7 +528,7 @@ def counter_run(w, steps):
     torch.cuda.synchronize()
     del a, b
     torch.cuda.empty_cache()
-    S, uc = setup(w, "fp32")
+    S, uc = setup(w, "fp32", 0, stage)
     S.step(steps)
     S.sync()
     from paper_1803_07822_amd import lbm
@@ -547,7 +550,7 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     w = synth.workload(a.workload)
     if a.counters:
-        counter_run(w, a.steps)
+        counter_run(w, a.steps, a.stage)
         return
     if a.part != "all":
         part = {"adjoint": adjoint_ratio, "c3": c3_loop, "c5": c5_runs, "flag": flag_channel}[a.part]()
@@ -556,7 +559,7 @@ def main():
     N = w.fluid_nodes
     res = {}
     for prec, steps in (("fp32", a.steps), ("fp64", a.fp64_steps or max(10, a.steps // 2))):
-        S, uc = setup(w, prec, a.variant)
+        S, uc = setup(w, prec, a.variant, a.stage)
         ms, wall = time_steps(S, uc, steps, a.warmup)
         res[prec] = dict(ms=ms, steps=steps, wall=wall, tuning=lbm.lbm_get_tuning(S.ctx),
                          mlups=N / (ms * 1e-3) / 1e6,
@@ -582,12 +585,12 @@ def main():
                    "form": "fp32 deviation storage, fp64 metric precompute"},
         "roofline": {
             "bound": "hbm",
-            "kernel": STEP_KERNEL_NAMES.get(a.variant, f"variant {a.variant}"),
+            "kernel": step_kernel_name(f32["tuning"][1], f32["tuning"][2]),
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBPS, 4),
-            "traffic": recorded_traffic(w.name) if a.variant == 0 else None,
+            "traffic": recorded_traffic(w.name) if a.variant == 0 and a.stage == -1 else None,
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
             "bytes_per_lup": BYTES_PER_LUP["fp32"],
             "kernel_ms": round(f32["ms"], 5),

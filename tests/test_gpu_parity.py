@@ -174,6 +174,53 @@ def test_reprojection_parity_fp64():
     assert dev_err(_np(S.populations()), fo, fo) < 1e-12
 
 
+def test_reprojection_parity_fp32():
+    """The FP32 deviation form through a wall re-projection, a generic chart
+    re-projection and steps after each: the moment fields of the
+    re-projection are stored in FP32 (deviations from rest) and the new state
+    is rounded to FP32, so populations and history agree with the FP64 oracle
+    to the FP32 rounding of the deviation variables (about 1e-7 of their
+    scale per operation; bound 1e-5 over the ~10 roundings on the path)."""
+    nx, ny, nz = 48, 10, 12
+    H = ny - 2
+    d1 = synth.gaussian_bump(nx, nz, A=1.2, x0=24, z0=6, sigma=4)
+    d2 = 0.7 * d1 + 0.3 * np.sin(2 * np.pi * np.arange(nx) / nx)[None, :]
+    v = np.zeros((nz, nx, 3))
+    v[..., 1] = 0.002 * np.cos(2 * np.pi * np.arange(nx) / nx)[None, :]
+    S, O = make_pair(nx, ny, nz, 0.75, precision="fp32", disp=d1, F=(1e-5, 0, 0), vwall=(None, v))
+    f0 = _random_state(O, nz, H, nx, 31)
+    O.set_populations(f0)
+    S.set_populations(f0)
+    O.step(3)
+    S.step(3)
+
+    def check(tag):
+        fo, ho = O.populations(), O.history()
+        ef = dev_err(_np(S.populations()), fo, fo)
+        eh = np.abs(_np(S.history()) - ho).max() / np.abs(ho).max()
+        print(f"fp32 re-projection {tag}: populations {ef:.2e}, history {eh:.2e}", flush=True)
+        assert ef < 1e-5, (tag, ef)
+        assert eh < 1e-5, (tag, eh)
+
+    O.set_wall_displacement(1, d2, reproject=True)
+    S.set_wall_displacement(1, d2, reproject=True)
+    check("wall")
+    O.step(4)
+    S.step(4)
+    check("wall + 4 steps")
+    ch = synth.bump3_chart(nx, ny, nz, 0.05)
+    O.set_metric(ch, reproject=True)
+    S.set_metric(ch, reproject=True)
+    check("chart")
+    O.step(4)
+    S.step(4)
+    check("chart + 4 steps")
+    r, u = S.moments(cartesian=True)
+    ro, uo = O.moments(cartesian=True)
+    assert np.abs(_np(r) - ro).max() < 2e-6
+    assert np.abs(_np(u) - uo).max() / np.abs(uo).max() < 1e-4
+
+
 def test_config1_channel_parity_fp64():
     """The 32x16x16 sheared channel, tau 0.8, F 1e-6, 2000 steps."""
     w = synth.workload("c1_shear_32x16x16")

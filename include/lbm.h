@@ -40,8 +40,16 @@
  *
  * Streams: all device work is enqueued on the hip stream given to lbm_create
  * (NULL = the null stream).  Calls return once the work is enqueued, except
- * the sync points (lbm_sync, lbm_wall_force with a host result, lbm_backward)
- * and calls documented as synchronising.
+ * the sync points (lbm_sync, lbm_moments, lbm_backward) and calls documented
+ * as synchronising.
+ *
+ * Graph capture: lbm_step, lbm_couple, lbm_wall_force, lbm_plate_force and
+ * the setters a time loop repeats (lbm_set_metric, lbm_set_wall_displacement,
+ * lbm_set_wall_velocity, lbm_set_plate_displacement, lbm_set_plate_velocity,
+ * lbm_set_body_force) enqueue kernels and device-to-device copies only (no
+ * memsets, no host waits), so a sequence of them may be captured on a
+ * non-null context stream into a HIP graph and replayed.  The captured work
+ * reads the argument pointers of the calls captured.
  *
  * Errors: every call returns LBM_OK or a negative code; lbm_last_error gives a
  * message.  LBM_EHIP and LBM_EUNSTABLE are sticky: once raised, every later

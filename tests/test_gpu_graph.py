@@ -1,6 +1,7 @@
 """Launch-bound loops replayed as HIP graphs: a sequence of library calls on
 the context's own stream (steps, plate shape with re-projection, plate
-velocity, plate force) captured once and replayed.  Every replay is checked
+velocity, plate force; or a wall alternately moved and cleared) captured
+once and replayed.  Every replay is checked
 against the same calls made eagerly on a second context, with eager work and
 synchronisations between the replays; the graph holds kernels and
 device-to-device copies only (no memsets)."""
@@ -74,5 +75,64 @@ def test_flag_loop_graph_replays_match_eager(precision):
         assert torch.equal(pg, pe), (r, float((pg - pe).abs().max()))
         assert torch.equal(fg, fe), r
         # eager work on the replayed context between replays
+        G.moments(cartesian=True)
+    assert torch.isfinite(fg).all()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_wall_loop_with_cleared_inputs_replays_match_eager(precision):
+    """The setters' NULL branches (wall shape and wall velocity cleared) are
+    kernels too, so a loop that alternates a moving, re-projected wall with a
+    wall at rest is capture-safe: every replay matches the eager calls bit for
+    bit, with eager work between the replays."""
+    lbm = _lbm()
+    nx, ny, nz, tau = 40, 12, 6, 0.8
+    H = ny - 2
+    d = synth.gaussian_bump(nx, nz, A=0.6, x0=20, z0=3, sigma=4)
+    v = np.zeros((nz, nx, 3))
+    v[..., 0] = 0.01
+    side = torch.cuda.Stream()
+
+    def make(stream):
+        S = lbm.Solver(nx, ny, nz, tau, precision, stream=stream)
+        S.set_body_force((1e-5, 0, 0))
+        S.set_wall_displacement(1, d)
+        S.init_equilibrium()
+        return S
+
+    G, E = make(side), make(torch.cuda.Stream())
+    dd = torch.as_tensor(d, device=G.device)
+    dv = torch.as_tensor(v, device=G.device)
+    fg = torch.zeros((2, 3), dtype=torch.float64, device=G.device)
+    fe = torch.zeros((2, 3), dtype=torch.float64, device=G.device)
+
+    def calls(S, force):
+        lbm.lbm_set_wall_displacement(S.ctx, 1, None, 1)  # flat wall, re-projected
+        lbm.lbm_set_wall_velocity(S.ctx, 1, dv)
+        lbm.lbm_step(S.ctx, 2)
+        lbm.lbm_wall_force(S.ctx, 1, force[0])
+        lbm.lbm_set_wall_displacement(S.ctx, 1, dd, 1)  # bump back, re-projected
+        lbm.lbm_set_wall_velocity(S.ctx, 1, None)  # wall at rest
+        lbm.lbm_step(S.ctx, 2)
+        lbm.lbm_wall_force(S.ctx, 1, force[1])
+
+    calls(G, fg)
+    calls(E, fe)
+    G.sync()
+    E.sync()
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=side):
+        calls(G, fg)
+    torch.cuda.synchronize()
+    for r in range(3):
+        graph.replay()
+        torch.cuda.synchronize()
+        calls(E, fe)
+        E.sync()
+        G.sync()
+        pg, pe = G.populations(), E.populations()
+        assert torch.equal(pg, pe), (r, float((pg - pe).abs().max()))
+        assert torch.equal(fg, fe), r
         G.moments(cartesian=True)
     assert torch.isfinite(fg).all()

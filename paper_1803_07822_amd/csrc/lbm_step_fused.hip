@@ -445,11 +445,16 @@ template <class T> constexpr int reg_stage() { return sizeof(T) == 4 ? STAGE_REG
 // Planes per block when the caller leaves it open.  Blocks run in rounds of
 // `slots` (resident blocks on the whole device); a chunk of zc planes costs
 // about zc + 1 plane-times (its two halo planes get moments only).  Take the
-// zc with the least rounds * (zc + 1); ties go to the smaller zc.
+// zc with the least rounds * (zc + 1); ties go to the smaller zc.  Chunks are
+// capped at ZC_MAX planes: longer ones spread each block's 86 streams over
+// more of every array at once, which costs more than the model's saved halo
+// planes (512x256x256: 32 planes 2.79 ms per step against 2.88 with 256).
+constexpr int ZC_MAX = 32;
 inline int choose_zc(long long tiles, int nz, long long slots) {
-  int best = nz;
+  const int top = nz < ZC_MAX ? nz : ZC_MAX;
+  int best = top;
   long long best_cost = -1;
-  for (int zc = 1; zc <= nz; ++zc) {
+  for (int zc = 1; zc <= top; ++zc) {
     const long long nb = tiles * ((nz + zc - 1) / zc);
     const long long cost = ((nb + slots - 1) / slots) * (zc + 1);
     if (best_cost < 0 || cost < best_cost) {

@@ -157,23 +157,22 @@ def adjoint_ratio(repeats=3):
             "ratio": round(b / f, 3), "forward_mlups": round(w.fluid_nodes * K / (f * 1e-3) / 1e6, 1)}
 
 
-def c3_loop():
-    """The oscillating-wall workload in FP32: 4000 steps, the metric and wall
-    velocity updated with re-projection every 10 steps, the top-wall force
-    recorded every step into device memory.  GPU time per phase from events
-    on the library's stream, and the host wall time of the whole loop."""
+def moving_wall_loop(w, wall_at, every, steps):
+    """FP32 run of workload `w` under a moving top wall: `steps` steps, the
+    wall shape and velocity (wall_at(t) -> d [nz, nx], dd/dt [nz, nx]) updated
+    with re-projection every `every` steps, the top-wall force recorded every
+    step into device memory.  GPU time per phase from events on the library's
+    stream, and the host wall time of the whole loop."""
     import numpy as np
     import torch
 
-    from paper_1803_07822_amd import lbm, synth
+    from paper_1803_07822_amd import lbm
 
-    w = synth.workload("c3_oscillating_256x128x128")
-    every, steps = w.extra["update_every"], w.steps
     S = lbm.Solver(w.nx, w.ny, w.nz, w.tau, "fp32")
     S.set_body_force(w.force)
 
     def wall(t):
-        d, v = synth.oscillating_wall(w.nx, w.nz, t=float(t))
+        d, v = wall_at(float(t))
         vc = np.zeros((w.nz, w.nx, 3))
         vc[..., 1] = v
         return torch.as_tensor(d, device=S.device), torch.as_tensor(vc, device=S.device)
@@ -216,9 +215,29 @@ def c3_loop():
            "metric_update_and_reprojection_ms": round(rp_ms / nup, 4),
            "wall_velocity_ms": round(vel_ms / nup, 4),
            "force_finite": bool(np.isfinite(f).all()), "final_force": [float(x) for x in f[-1]]}
-    del S
+    del S, walls, forces
     torch.cuda.empty_cache()
     return res
+
+
+def c3_loop():
+    """The oscillating-wall workload in FP32: 4000 steps, the metric and wall
+    velocity updated with re-projection every 10 steps (moving_wall_loop)."""
+    from paper_1803_07822_amd import synth
+
+    w = synth.workload("c3_oscillating_256x128x128")
+    return moving_wall_loop(w, lambda t: synth.oscillating_wall(w.nx, w.nz, t=t), w.extra["update_every"], w.steps)
+
+
+def c5_travelling():
+    """The 512x256x256 patch wave travelling, in FP32 at the run amplitude:
+    3000 steps, the wall shape and velocity updated with re-projection every
+    10 steps (moving_wall_loop)."""
+    from paper_1803_07822_amd import synth
+
+    w = synth.workload("c5_patch_wave_512x256x256")
+    A = w.extra["A_run"]
+    return moving_wall_loop(w, lambda t: synth.patch_wave(A=A, t=t), w.extra["update_every"], w.steps)
 
 
 def flag_channel(steps=None):
@@ -339,8 +358,10 @@ def flag_channel_graph(w, steps):
 def c5_runs(steps=200):
     """The 512x256x256 patch-wave workload (33.3M fluid nodes, run amplitude
     0.04*256): FP32 step throughput over `steps` steps from the equilibrium
-    start, then the FP64 adjoint over K = 100 with a checkpoint every 10
-    (about 235 GiB of workspace): forward-record and backward times."""
+    start with the wave frozen, the travelling wave over its 3000 steps with
+    re-projection every 10 (c5_travelling), then the FP64 adjoint over K = 100
+    with a checkpoint every 10 (about 235 GiB of workspace): forward-record
+    and backward times."""
     import torch
 
     from paper_1803_07822_amd import lbm, synth
@@ -364,6 +385,7 @@ def c5_runs(steps=200):
                    "launch": dict(zip(("zchunk", "variant", "stage"), lbm.lbm_get_tuning(S.ctx)))}
     del S
     torch.cuda.empty_cache()
+    out["travelling"] = c5_travelling()
     K, N = w.extra["K"], w.extra["ckpt_every"]
     try:
         S = lbm.Solver(w.nx, w.ny, w.nz, w.tau, "fp64", adjoint_K=K, ckpt_every=N)

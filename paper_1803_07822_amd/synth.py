@@ -242,12 +242,14 @@ def workload(name: str) -> Workload:
         # Re = u_max * 128 / nu = 100 with u_max = F H^2 / (8 nu), H = 254.
         # The stated amplitude 0.08*256 (wall slope up to 1.0) trips the
         # instability guard within the first 20 steps from rest; the runs use
-        # 0.04*256 (slope 0.5), which stays stable over 3000 steps.
+        # 0.04*256 (slope 0.5), which stays stable over 3000 steps, frozen or
+        # travelling with re-projection every 10 steps.
         nu = float(np.sqrt(1e-6 * 254**2 * 128.0 / 800.0))
         A_run = 0.04 * 256
         return Workload(name, 512, 256, 256, 0.5 + 3 * nu, steps=3000,
                         disp=lambda: patch_wave(A=A_run)[0],
-                        extra={"K": 100, "ckpt_every": 10, "A_stated": 0.08 * 256, "A_run": A_run})
+                        extra={"K": 100, "ckpt_every": 10, "A_stated": 0.08 * 256, "A_run": A_run,
+                               "update_every": 10})
     if name == "flag_channel_257x65":
         # The flag on a pole (Sec. VI.A) without its structural model: a
         # 257 x 65 channel (one z plane), parabolic inlet of peak U, open

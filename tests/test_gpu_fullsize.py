@@ -181,6 +181,54 @@ def test_c3_full_run_fp32_against_fp64_gpu():
     assert eu < 1e-3, eu
 
 
+def test_c5_travelling_wave_fp32_against_fp64_gpu():
+    """The 512x256x256 patch wave travelling at the run amplitude over its 3000
+    steps, wall shape and velocity re-projected every 10 steps, in FP32
+    against the FP64 GPU path (the oracle would take days): stable in both,
+    and the top-wall force every 10 steps and the final density and velocity
+    agree to the FP32 deviation form's accumulated rounding."""
+    w = synth.workload("c5_patch_wave_512x256x256")
+    every, A = w.extra["update_every"], w.extra["A_run"]
+
+    def wall(t):
+        d, v = synth.patch_wave(A=A, t=float(t))
+        vc = np.zeros((w.nz, w.nx, 3))
+        vc[..., 1] = v
+        return d, vc
+
+    out = {}
+    for precision in ("fp64", "fp32"):
+        d0, v0 = wall(0)
+        S = _solver(w, precision, d0)
+        S.set_wall_velocity(1, v0)
+        S.init_equilibrium()
+        forces = []
+        for u in range(1, w.steps // every + 1):
+            S.step(every)
+            forces.append(_np(S.wall_force(1)))
+            d, vc = wall(u * every)
+            S.set_wall_displacement(1, d, reproject=True)
+            S.set_wall_velocity(1, vc)
+        r, uu = S.moments(cartesian=True)
+        out[precision] = (np.array(forces), _np(r), _np(uu))
+        del S, r, uu
+        torch.cuda.empty_cache()
+    f64, r64, u64 = out["fp64"]
+    f32, r32, u32 = out["fp32"]
+    scale = np.abs(f64).max(axis=0)
+    scale[2] = scale[1]
+    ef = np.abs(f32 - f64).max(axis=0) / scale
+    er = np.abs(r32 - r64).max()
+    eu = np.abs(u32 - u64).max() / np.abs(u64).max()
+    print(f"C5 travelling wave 3000 steps FP32 vs FP64 GPU: force (x, y, z) {ef[0]:.2e} {ef[1]:.2e} {ef[2]:.2e}, "
+          f"|drho| {er:.2e}, |du|/max|u| {eu:.2e}, max|u| {np.abs(u64).max():.3e}", flush=True)
+    assert ef[1] < 1e-5, ef
+    assert ef[0] < 1e-3, ef
+    assert ef[2] < 1e-3, ef
+    assert er < 1e-5, er
+    assert eu < 1e-3, eu
+
+
 def test_c5_stated_amplitude_trips_guard():
     """At the stated amplitude 0.08*256 (wall slope up to 1.0) the scheme is
     unstable: from rest, FP32 and FP64 both trip the instability guard within

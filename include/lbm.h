@@ -237,8 +237,12 @@ int lbm_plate_force(lbm_ctx* ctx, double* d_total3, double* d_per_column);
  * non-equilibrium part extrapolated.  The lattice gradient takes the end
  * column's own momentum beyond each end.  The geometry's x-derivatives stay
  * periodic, so the chart must join smoothly across the two ends (an
- * undeformed chart near both ends does).  A step then runs the two-pass
- * kernels (lbm_get_tuning reports variant 1).  NULL restores periodic x.
+ * undeformed chart near both ends does).  A fused step is then followed by
+ * two small launches that redo the two columns at each end (moments of the
+ * three end columns, then the collision).  Those cost a few tens of
+ * microseconds whatever the grid, so unless lbm_set_tuning asks for a
+ * variant, grids below 2^20 fluid nodes run the two-pass step instead.  NULL
+ * restores periodic x.
  * Before the state (ESTATE); EINVAL for nx < 4 or a plate closer than 3
  * columns to an end.  The adjoint is not provided with open ends. */
 int lbm_set_open_x(lbm_ctx* ctx, const double* d_uin);
@@ -261,15 +265,19 @@ int lbm_backward(lbm_ctx* ctx, const double* d_dL_dF, double* d_grad_disp, doubl
 
 /* lbm_step with each kernel of the step bracketed by HIP events on the
  * context's stream: h_ms[k] receives the average duration (ms) of kernel k
- * of the step over the n steps (nslots >= the number of kernels per step,
- * currently 2: the moment pass and the collision pass).  Synchronising. */
+ * of the step over the n steps (nslots >= 2: for the two-pass step the
+ * moment pass and the collision pass; for the fused step the fused kernel
+ * and the end-column passes of a grid with open ends, 0 without them).
+ * Synchronising. */
 int lbm_step_profiled(lbm_ctx* ctx, int n, double* h_ms, int nslots);
 
 /* Launch shape of the step: zchunk = planes marched per block by the fused
  * step kernel (0 = chosen from the grid size); variant 0 = fused single-kernel
  * step on 64x4 tiles (x by y nodes per block), 1 = two kernels (moment pass,
  * collision pass), 2 = fused on 64x2 tiles, 3 = fused on 64x1, 4 = fused on
- * 128x2, 5 = fused on 256x1.  stage = where the fused step
+ * 128x2, 5 = fused on 256x1 (until this is called the choice is automatic:
+ * fused on 64x4, two-pass on grids with open ends below 2^20 fluid nodes).
+ * stage = where the fused step
  * keeps a plane's pulled populations between its moment pass and its
  * collision: 0 = nowhere (pulled again, from the caches), 1 = registers (FP32
  * only; FP64 runs 0), -1 = the default of the precision (1 in FP32, 0 in

@@ -512,7 +512,7 @@ int lbm_get_tuning(lbm_ctx* c, int* zchunk, int* variant, int* stage) {
   LBM_GUARD(c);
   if (!zchunk || !variant || !stage) return fail(c, LBM_EINVAL, "null output pointer");
   int zc = 0;
-  const bool two_pass = c->F.variant == 1 || c->F.g.open;  // open ends run the two-pass step
+  const bool two_pass = !lbm::step_is_fused(c->F);
   if (!two_pass)
     LBM_HIP(c, c->precision == LBM_FP64 ? lbm::fused_step_chunk<double>(c->F, &zc)
                                         : lbm::fused_step_chunk<float>(c->F, &zc));

@@ -43,7 +43,7 @@ struct Fields {
   int uext_cur;   // index of the current extended displacement
   int moving[2];
   int zc = 0;        // planes per block of the fused step (0 = automatic)
-  int variant = 0;   // 0: fused step; 1: two-pass step (moments pass + collision pass)
+  int variant = -1;  // -1: automatic (step_is_fused); 0: fused step; 1: two-pass step (moments pass + collision pass)
   int tile = 0;      // tile shape of the fused step (TileShape)
   int stage = 1;     // FP32 fused step keeps pulled populations in registers
   int slots_key = -1;     // fused kernel whose resident-block count is cached
@@ -51,6 +51,17 @@ struct Fields {
 };
 
 constexpr int BX = 64, BY = 4;
+
+// Open ends run the fused step followed by two small passes over the end
+// columns; those passes cost a fixed few tens of microseconds, so below this
+// many fluid nodes the automatic choice is the two-pass step.
+constexpr long long OPEN_FUSED_MIN_NODES = 1LL << 20;
+
+// The step a launch runs: the fused kernel, or the two-pass kernels.
+inline bool step_is_fused(const Fields& F) {
+  if (F.variant >= 0) return F.variant == 0;
+  return !F.g.open || F.g.N >= OPEN_FUSED_MIN_NODES;
+}
 constexpr size_t ALIGN = 256;
 
 // Carves the caller's workspace into aligned buffers; with base == nullptr it

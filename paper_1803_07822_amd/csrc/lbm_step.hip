@@ -33,6 +33,33 @@ __device__ __forceinline__ bool node_pos(const Grid& g, Pos& p) {
   return true;
 }
 
+// Columns of a launch over the m columns at each end in x: 0..m-1 and
+// nx-m..nx-1, or all nx columns when those overlap.
+inline __host__ __device__ int end_columns(const Grid& g, int m) { return 2 * m < g.nx ? 2 * m : g.nx; }
+
+// Node of a launch over the grid (ends = 0: 2D tiles of the fluid grid) or
+// over the m = ends columns at each end in x (a 1D launch, one thread per
+// (column, row, plane), columns fastest).
+__device__ __forceinline__ bool node_pos_ends(const Grid& g, int ends, Pos& p) {
+  if (!ends) return node_pos(g, p);
+  const int nc = end_columns(g, ends);
+  const long long t = ((long long)blockIdx.x * BY + threadIdx.y) * BX + threadIdx.x;
+  if (t >= (long long)nc * g.H * g.nz) return false;
+  const int c = (int)(t % nc);
+  const long long r = t / nc;
+  p.jf = (int)(r % g.H);
+  p.k = (int)(r / g.H);
+  p.i = (nc < 2 * ends || c < ends) ? c : g.nx - 2 * ends + c;
+  p.n = ((long long)p.k * g.H + p.jf) * g.nx + p.i;
+  return true;
+}
+
+// 1D grid of BX x BY blocks covering the end-column launch of node_pos_ends.
+inline dim3 ends_grid(const Grid& g, int ends) {
+  const long long n = (long long)end_columns(g, ends) * g.H * g.nz;
+  return dim3((unsigned)((n + BX * BY - 1) / (BX * BY)));
+}
+
 template <class T>
 __device__ __forceinline__ void load_coef(const T* __restrict__ hist, long long N, long long n, Coef<T>& c) {
   c.A = hist[H_A * N + n];
@@ -136,11 +163,11 @@ __device__ __forceinline__ void lattice_gradient(const T* __restrict__ mom, cons
 
 // ---------------------------------------------------------------- pass 1
 template <class T>
-__global__ __launch_bounds__(BX* BY) void k_moments(Grid g, const T* __restrict__ pop, const T* __restrict__ hist,
-                                                   const T* __restrict__ geo, const T* __restrict__ vin,
-                                                   T* __restrict__ mom) {
+__global__ __launch_bounds__(BX* BY) void k_moments(Grid g, int ends, const T* __restrict__ pop,
+                                                   const T* __restrict__ hist, const T* __restrict__ geo,
+                                                   const T* __restrict__ vin, T* __restrict__ mom) {
   Pos p;
-  if (!node_pos(g, p)) return;
+  if (!node_pos_ends(g, ends, p)) return;
   T dr, j[3], gv[Q];
   streamed_moments(pop, hist, geo, vin, g, p, dr, j, gv);
   mom[p.n] = dr;
@@ -153,14 +180,14 @@ __global__ __launch_bounds__(BX* BY) void k_moments(Grid g, const T* __restrict_
 // Collision f* = f - (f - feq)/tau + F(t) - F(t-1)/2 (Eq. collision with the
 // leading f restored) and the bounce-back term of Eq. (streaming) at walls.
 template <class T>
-__global__ __launch_bounds__(BX* BY) void k_collide(Grid g, const T* __restrict__ pin, T* __restrict__ pout,
+__global__ __launch_bounds__(BX* BY) void k_collide(Grid g, int ends, const T* __restrict__ pin, T* __restrict__ pout,
                                                    const T* __restrict__ hist, T* __restrict__ hout,
                                                    const T* __restrict__ geo,
                                                    const T* __restrict__ mom, const T* __restrict__ uw, int mv0,
                                                    int mv1, const T* __restrict__ up, const T* __restrict__ vin,
                                                    T tau, int* __restrict__ flag) {
   Pos p;
-  if (!node_pos(g, p)) return;
+  if (!node_pos_ends(g, ends, p)) return;
   NodeGeo<T> G;
   load_geo(geo, g.N, p.n, G);
   Coef<T> cp;
@@ -558,22 +585,38 @@ template <class T> hipError_t launch_step(Fields& F, hipStream_t s, T tau, hipEv
   auto mark = [&](int k) {
     if (ev && e == hipSuccess) e = hipEventRecord(ev[k], s);
   };
-  if (F.variant == 0 && !g.open) {
+  dim3 b(BX, BY);
+  const int cur = F.cur;
+  const T* pin = (const T*)F.pop[cur];
+  T* pout = (T*)F.pop[cur ^ 1];
+  if (step_is_fused(F)) {
     mark(0);
     if (e == hipSuccess) e = launch_step_fused<T>(F, s, tau, F.zc, F.tile);
     mark(1);
+    if (e == hipSuccess && g.open) {
+      // The fused kernel treats x as periodic.  With open ends, the end
+      // columns and their neighbours (whose gradient reads an end column's
+      // momentum) are redone by the two-pass kernels over the end columns
+      // only: the streamed moments of the three columns at each end with
+      // the open-end rule, then the collision of the two columns at each
+      // end, overwriting what the fused kernel wrote for them.
+      hipLaunchKernelGGL(k_moments<T>, ends_grid(g, 3), b, 0, s, g, 3, pin, (const T*)F.hist[cur],
+                         (const T*)F.geo, (const T*)F.vin, (T*)F.mom);
+      hipLaunchKernelGGL(k_collide<T>, ends_grid(g, 2), b, 0, s, g, 2, pin, pout, (const T*)F.hist[cur],
+                         (T*)F.hist[cur ^ 1],
+                         (const T*)F.geo, (const T*)F.mom, (const T*)F.uw, F.moving[0], F.moving[1],
+                         (const T*)F.up, (const T*)F.vin, tau, F.flag);
+      e = hipGetLastError();
+    }
     mark(2);
     return e;
   }
-  dim3 b(BX, BY);
-  const T* pin = (const T*)F.pop[F.cur];
-  T* pout = (T*)F.pop[F.cur ^ 1];
   mark(0);
-  hipLaunchKernelGGL(k_moments<T>, fluid_grid(g), b, 0, s, g, pin, (const T*)F.hist[F.cur], (const T*)F.geo,
+  hipLaunchKernelGGL(k_moments<T>, fluid_grid(g), b, 0, s, g, 0, pin, (const T*)F.hist[cur], (const T*)F.geo,
                      (const T*)F.vin, (T*)F.mom);
   mark(1);
-  hipLaunchKernelGGL(k_collide<T>, fluid_grid(g), b, 0, s, g, pin, pout, (const T*)F.hist[F.cur],
-                     (T*)F.hist[F.cur ^ 1], (const T*)F.geo,
+  hipLaunchKernelGGL(k_collide<T>, fluid_grid(g), b, 0, s, g, 0, pin, pout, (const T*)F.hist[cur],
+                     (T*)F.hist[cur ^ 1], (const T*)F.geo,
                      (const T*)F.mom, (const T*)F.uw, F.moving[0], F.moving[1], (const T*)F.up, (const T*)F.vin, tau,
                      F.flag);
   mark(2);

@@ -41,7 +41,7 @@ def _inlet(nz, H, U=0.02):
     return uin
 
 
-def _setup(nx, ny, nz, tau, plate=None, precision="fp64", variant=0):
+def _setup(nx, ny, nz, tau, plate=None, precision="fp64", variant=None):
     lbm = _lbm()
     H = ny - 2
     S = lbm.Solver(nx, ny, nz, tau, precision)
@@ -59,7 +59,7 @@ def _setup(nx, ny, nz, tau, plate=None, precision="fp64", variant=0):
         X.set_wall_displacement(1, d_top)
         if plate is not None:
             X.set_plate_displacement(D)
-    if variant:
+    if variant is not None:  # else the automatic choice (two-pass on these small open grids)
         lbm.lbm_set_tuning(S.ctx, 0, variant, -1)
     O.init_equilibrium(1 + synth.random_perturbation((nz, H, nx), 2e-3, 15),
                        synth.random_perturbation((3, nz, H, nx), 1e-2, 16))
@@ -70,16 +70,21 @@ def _setup(nx, ny, nz, tau, plate=None, precision="fp64", variant=0):
 
 
 @pytest.mark.parametrize("shape,plate,variant", [((40, 10, 3), None, 0), ((40, 10, 3), None, 1),
-                                                 ((70, 12, 5), (5, 10, 40), 0), ((6, 6, 2), None, 0)])
+                                                 ((70, 12, 5), (5, 10, 40), 0), ((70, 12, 5), (5, 10, 40), 1),
+                                                 ((6, 6, 2), None, 0), ((4, 6, 2), None, 0), ((65, 9, 3), None, 0),
+                                                 ((130, 7, 4), None, 0), ((130, 7, 4), None, 4)])
 def test_open_step_parity_fp64(shape, plate, variant):
     """Inlet profile varying in y and z, outlet, top-wall bump, body force,
     non-equilibrium start (the incoming end populations re-derived on
-    set); with and without a plate, on the smallest grid the extrapolation
-    allows (nx = 6): populations, history, moments and forces after 1 and 12
-    steps.  The fused variant falls back to the two-pass step."""
+    set); with and without a plate, in the fused step (variants 0 and 4,
+    64x4 and 128x2 tiles: the end columns redone by the open-end rule after
+    the periodic fused kernel) and the two-pass step (variant 1); on the
+    smallest grids the extrapolation allows (nx = 4, 6), with the outlet alone
+    in the last tile (nx = 65) and across three tiles (nx = 130): populations,
+    history, moments and forces after 1 and 12 steps."""
     nx, ny, nz = shape
     S, O = _setup(nx, ny, nz, 0.7, plate, variant=variant)
-    assert _lbm().lbm_get_tuning(S.ctx)[1] == 1
+    assert _lbm().lbm_get_tuning(S.ctx)[1] == variant
     fo = O.populations()
     assert dev_err(_np(S.populations()), fo, fo) < 1e-13
     for n in (1, 11):
@@ -98,9 +103,15 @@ def test_open_step_parity_fp64(shape, plate, variant):
             assert np.abs(_np(S.plate_force(per_column=True)[1]) - O.plate_force(per_column=True)[1]).max() < 1e-13
 
 
-def test_open_step_parity_fp32():
-    nx, ny, nz = 40, 10, 3
+@pytest.mark.parametrize("shape,variant,stage", [((40, 10, 3), 0, -1), ((40, 10, 3), 0, 0), ((40, 10, 3), 1, -1),
+                                                 ((65, 9, 3), 0, -1)])
+def test_open_step_parity_fp32(shape, variant, stage):
+    """FP32 deviation form with open ends, fused (register staging or
+    none) and two-pass, after 50 steps: rho and u within FP32 rounding of the
+    deviation variables."""
+    nx, ny, nz = shape
     S, O = _setup(nx, ny, nz, 0.7, precision="fp32")
+    _lbm().lbm_set_tuning(S.ctx, 0, variant, stage)
     O.step(50)
     S.step(50)
     r, u = S.moments(cartesian=True)

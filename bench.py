@@ -53,9 +53,10 @@ def parse():
     p.add_argument("--fp64-steps", type=int, default=None)
     p.add_argument("--no-extra", action="store_true",
                    help="skip the oscillating-wall loop, the 512x256x256 runs and the flag channel")
-    p.add_argument("--part", choices=["all", "adjoint", "c3", "c5", "flag"], default="all",
+    p.add_argument("--part", choices=["all", "adjoint", "c3", "c5", "flag", "open"], default="all",
                    help="run one measurement alone (for profiling): the 128x64x64 adjoint, the oscillating-wall "
-                        "loop, the 512x256x256 runs or the flag channel; prints that part's JSON only")
+                        "loop, the 512x256x256 runs, the flag channel or the open channel at scale; prints that "
+                        "part's JSON only")
     p.add_argument("--variant", type=int, default=0,
                    help="launch variant of the step (lbm_set_tuning): 0 fused (default), 1 two-pass, 2-5 other "
                         "fused tile shapes")
@@ -227,6 +228,48 @@ def c3_loop():
 
     w = synth.workload("c3_oscillating_256x128x128")
     return moving_wall_loop(w, lambda t: synth.oscillating_wall(w.nx, w.nz, t=t), w.extra["update_every"], w.steps)
+
+
+def open_channel(steps=50, repeats=2):
+    """Open ends at scale: a 256x130x128 channel (4.19M fluid nodes) with a
+    parabolic inlet (peak 0.05) and an open outlet, FP32 and FP64, timed
+    with the fused step (periodic fused kernel plus the two end-column
+    passes) and with the two-pass step, from the developed inlet profile."""
+    import numpy as np
+    import torch
+
+    from paper_1803_07822_amd import lbm, synth
+
+    nx, ny, nz, tau = 256, 130, 128, 0.6
+    H = ny - 2
+    out = {"workload": "open_channel_256x130x128", "fluid_nodes": nx * H * nz}
+    for prec in ("fp32", "fp64"):
+        S = lbm.Solver(nx, ny, nz, tau, prec)
+        uin = synth.parabolic_inlet(nz, H, 0.05)
+        S.set_open_x(uin)
+        S.set_wall_displacement(lbm.LBM_WALL_YMAX, np.zeros((nz, nx)))
+        uc = np.zeros((3, nz, H, nx))
+        uc[0] = uin[..., 0][:, :, None]
+        res = {}
+        for name, variant in (("fused_ms", 0), ("two_pass_ms", 1)):
+            lbm.lbm_set_tuning(S.ctx, 0, variant, -1)
+            tot = 0.0
+            for _ in range(repeats):
+                S.init_equilibrium(None, uc)
+                S.step(5)
+                S.sync()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(S.stream)
+                S.step(steps)
+                e1.record(S.stream)
+                S.sync()
+                tot += e0.elapsed_time(e1)
+            res[name] = round(tot / (steps * repeats), 4)
+        res["fused_mlups"] = round(nx * H * nz / (res["fused_ms"] * 1e-3) / 1e6, 1)
+        out[prec] = res
+        del S
+        torch.cuda.empty_cache()
+    return out
 
 
 def c5_travelling():
@@ -575,7 +618,8 @@ def main():
         counter_run(w, a.steps, a.stage)
         return
     if a.part != "all":
-        part = {"adjoint": adjoint_ratio, "c3": c3_loop, "c5": c5_runs, "flag": flag_channel}[a.part]()
+        part = {"adjoint": adjoint_ratio, "c3": c3_loop, "c5": c5_runs, "flag": flag_channel,
+                "open": open_channel}[a.part]()
         print(json.dumps({"part": a.part, **part}), flush=True)
         return
     N = w.fluid_nodes
@@ -644,6 +688,7 @@ def main():
         out["c3_time_varying_metric"] = c3_loop()
         out["c5_at_scale"] = c5_runs()
         out["flag_channel"] = flag_channel()
+        out["open_channel"] = open_channel()
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, a.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -21,11 +21,13 @@ def _lbm():
     return lbm
 
 
-def _flag_solver(precision, stream):
+def _flag_solver(precision, stream, variant=None):
     lbm = _lbm()
     nx, ny, nz, tau = 64, 18, 1, 0.7
     H = ny - 2
     S = lbm.Solver(nx, ny, nz, tau, precision, stream=stream)
+    if variant is not None:  # else the automatic choice (the two-pass step on this small open grid)
+        lbm.lbm_set_tuning(S.ctx, 0, variant, -1)
     S.set_open_x(synth.parabolic_inlet(nz, H, 0.04))
     S.set_plate(8, 12, 30)
     S.set_wall_displacement(1, np.zeros((nz, nx)))
@@ -35,14 +37,16 @@ def _flag_solver(precision, stream):
     return S
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_flag_loop_graph_replays_match_eager(precision):
+@pytest.mark.parametrize("precision,variant", [("fp64", None), ("fp32", None), ("fp32", 0), ("fp64", 0)])
+def test_flag_loop_graph_replays_match_eager(precision, variant):
+    """variant None: the automatic step (two-pass here); 0: the fused step
+    with its end-column passes."""
     lbm = _lbm()
     nx, nz, steps = 64, 1, 4  # an even count: the context's buffer parity is back where it started
     shapes = [synth.flapping_plate(nx, nz, 12, 30, A=0.3, omega=2 * np.pi / 200, t=float(t)) for t in range(steps)]
     side = torch.cuda.Stream()
-    G = _flag_solver(precision, side)  # replayed
-    E = _flag_solver(precision, torch.cuda.Stream())  # eager
+    G = _flag_solver(precision, side, variant)  # replayed
+    E = _flag_solver(precision, torch.cuda.Stream(), variant)  # eager
     dev = [(torch.as_tensor(d, device=G.device), torch.as_tensor(v, device=G.device)) for d, v in shapes]
     fg = torch.zeros((steps, 3), dtype=torch.float64, device=G.device)
     fe = torch.zeros((steps, 3), dtype=torch.float64, device=G.device)

@@ -132,6 +132,35 @@ def test_c3_oscillating_wall_full_size():
         torch.cuda.empty_cache()
 
 
+def test_c2_fp32_against_fp64_gpu_50_steps():
+    """The bench workload over 50 steps from its noisy equilibrium start (the
+    configured bump trips the instability guard near step 57 from rest, so
+    this is as far as it runs), FP32 deviation form against the FP64 GPU
+    path: density, velocity and the top-wall force agree to the FP32
+    deviation form's accumulated rounding."""
+    w = synth.workload("c2_bump_256x128x128")
+    uc = synth.uniform_noise_velocity(w.nx, w.ny, w.nz, 1e-4, seed=2)
+    out = {}
+    for precision in ("fp64", "fp32"):
+        S = _solver(w, precision, w.disp())
+        S.init_equilibrium(None, uc)
+        S.step(50)
+        r, u = S.moments(cartesian=True)
+        out[precision] = (_np(r), _np(u), _np(S.wall_force(1)))
+        del S, r, u
+        torch.cuda.empty_cache()
+    r64, u64, f64 = out["fp64"]
+    r32, u32, f32 = out["fp32"]
+    er = np.abs(r32 - r64).max()
+    eu = np.abs(u32 - u64).max() / np.abs(u64).max()
+    ef = np.abs(f32 - f64) / np.abs(f64).max()
+    print(f"C2 50 steps FP32 vs FP64 GPU: |drho| {er:.2e}, |du|/max|u| {eu:.2e} (max|u| {np.abs(u64).max():.2e}), "
+          f"force (x, y, z) {ef[0]:.2e} {ef[1]:.2e} {ef[2]:.2e}", flush=True)
+    assert er < 1e-6, er
+    assert eu < 1e-3, eu
+    assert ef.max() < 1e-5, ef
+
+
 def test_c3_full_run_fp32_against_fp64_gpu():
     """The whole oscillating-wall run, 4000 steps with 400 re-projections, in
     FP32 against the FP64 GPU path (the oracle would take hours): the top-wall

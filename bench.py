@@ -403,7 +403,7 @@ def c5_runs(steps=200):
     0.04*256): FP32 step throughput over `steps` steps from the equilibrium
     start with the wave frozen, the travelling wave over its 3000 steps with
     re-projection every 10 (c5_travelling), then the FP64 adjoint over K = 100
-    with a checkpoint every 10 (about 235 GiB of workspace): forward-record
+    with a checkpoint every 10 (about 245 GiB of workspace): forward-record
     and backward times."""
     import torch
 

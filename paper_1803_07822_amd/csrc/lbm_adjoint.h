@@ -8,6 +8,7 @@ namespace lbm {
 struct AdjointBuffers {
   double* ckpt = nullptr;  // nckpt states (pop 19 + history 10 per node, pull layout)
   double* traj = nullptr;  // ckpt_every states of one segment
+  double* tmom = nullptr;  // [ckpt_every][4][N] rho, rho u of the segment's states, from the recompute steps
   double* lf[2] = {nullptr, nullptr};  // [19][N] adjoint of f (current / next)
   double* lp[2] = {nullptr, nullptr};  // [10][N] adjoint of the history coefficients
   double* lfd = nullptr;   // [19][N] direct part of the f adjoint
@@ -32,6 +33,7 @@ inline void carve_adjoint(Carver& c, const Grid& g, int K, int N, AdjointBuffers
   A.nckpt = (K + N - 1) / N + 1;  // segment starts plus the final state
   A.ckpt = (double*)c.take(state * A.nckpt);
   A.traj = (double*)c.take(state * N);
+  A.tmom = (double*)c.take(sizeof(double) * 4 * Nn * N);
   for (int b = 0; b < 2; ++b) {
     A.lf[b] = (double*)c.take(sizeof(double) * 19 * Nn);
     A.lp[b] = (double*)c.take(sizeof(double) * H_N * Nn);

@@ -16,6 +16,8 @@
 // stencils and the cubic continuation) to the chart and the wall displacement.
 //
 // Walls at rest and a static metric (no re-projection inside the K steps).
+#include <vector>
+
 #include "lbm_adjoint.h"
 #include "lbm_adjoint_node.h"
 
@@ -567,8 +569,11 @@ hipError_t save_state(const Fields& F, double* dst, hipStream_t s) {
 }
 
 // One FP64 step from the stored state `in` (populations 19N, then history
-// 10N) into `out`, leaving the context's own state buffers untouched.
-hipError_t step_into(Fields& F, const double* in, double* out, hipStream_t s, double tau) {
+// 10N) into `out`, leaving the context's own state buffers untouched.  With
+// mom != nullptr the step also writes rho, rho u of `in` there when the
+// fused step runs (*wrote says whether it did).
+hipError_t step_into(Fields& F, const double* in, double* out, hipStream_t s, double tau, double* mom = nullptr,
+                     bool* wrote = nullptr) {
   const size_t Nn = (size_t)F.g.N;
   void* const pop[2] = {F.pop[0], F.pop[1]};
   void* const hist[2] = {F.hist[0], F.hist[1]};
@@ -577,7 +582,9 @@ hipError_t step_into(Fields& F, const double* in, double* out, hipStream_t s, do
   F.hist[cur] = (void*)(in + 19 * Nn);
   F.pop[cur ^ 1] = out;
   F.hist[cur ^ 1] = out + 19 * Nn;
-  const hipError_t e = launch_step<double>(F, s, tau);
+  const bool with_mom = mom && step_is_fused(F) && F.tile == TILE_64x4 && !F.g.pj && !F.g.open;
+  const hipError_t e = with_mom ? launch_step_fused_moments<double>(F, s, tau, mom) : launch_step<double>(F, s, tau);
+  if (wrote) *wrote = with_mom && e == hipSuccess;
   for (int b = 0; b < 2; ++b) {
     F.pop[b] = pop[b];
     F.hist[b] = hist[b];
@@ -630,20 +637,31 @@ hipError_t adjoint_backward(Fields& F, AdjointBuffers& A, hipStream_t s, int K, 
                        dLdF + 3 * (K - 1), A.lf[cur], A.lg, A.lj);
   }
   const int nseg = (K + N - 1) / N;
+  std::vector<char> have_mom((size_t)N, 0);  // moments of the segment's state t0 + i kept in A.tmom slot i
   for (int sgm = nseg - 1; sgm >= 0; --sgm) {
     const int t0 = sgm * N, t1 = (t0 + N < K) ? t0 + N : K;
     // states t0..t1-1 of the segment: its checkpoint, then traj slots 1..
     auto at = [&](int t) { return t == t0 ? A.ckpt + state * sgm : A.traj + state * (t - t0); };
-    for (int t = t0; t + 1 < t1; ++t) HCHK(step_into(F, at(t), at(t + 1), s, tau));
+    // the recompute steps also leave the moments of the states they step from
+    for (int t = t0; t + 1 < t1; ++t) {
+      bool wrote = false;
+      HCHK(step_into(F, at(t), at(t + 1), s, tau, A.tmom + 4 * Nn * (t - t0), &wrote));
+      have_mom[t - t0] = wrote;
+    }
+    have_mom[t1 - 1 - t0] = false;  // the segment's last state is no step's input
     for (int t = t1 - 1; t >= t0; --t) {
       const double* st = at(t);
       const double* pop = st;
       const double* hist = st + 19 * Nn;
-      hipLaunchKernelGGL(k_adj_moments, fg, b, 0, s, g, pop, hist, geo, mom);
-      hipLaunchKernelGGL(k_adj_node, fg, b, 0, s, g, 0, pop, hist, geo, (const double*)mom, tau,
+      const double* mt = mom;
+      if (have_mom[t - t0])
+        mt = A.tmom + 4 * Nn * (t - t0);
+      else
+        hipLaunchKernelGGL(k_adj_moments, fg, b, 0, s, g, pop, hist, geo, mom);
+      hipLaunchKernelGGL(k_adj_node, fg, b, 0, s, g, 0, pop, hist, geo, mt, tau,
                          (const double*)A.lf[cur], (const double*)A.lp[cur], A.lfd, A.lml, A.ldj, A.lp[cur ^ 1],
                          A.lg);
-      hipLaunchKernelGGL(k_adj_gather, fg, b, 0, s, g, geo, (const double*)mom, (const double*)A.lfd,
+      hipLaunchKernelGGL(k_adj_gather, fg, b, 0, s, g, geo, mt, (const double*)A.lfd,
                          (const double*)A.lml, (const double*)A.ldj, (const double*)nullptr, A.lf[cur ^ 1], A.lg);
       cur ^= 1;
       if (t >= 1)
@@ -655,11 +673,16 @@ hipError_t adjoint_backward(Fields& F, AdjointBuffers& A, hipStream_t s, int K, 
   {
     const double* pop = A.ckpt;
     const double* hist = A.ckpt + 19 * Nn;
-    hipLaunchKernelGGL(k_adj_moments, fg, b, 0, s, g, pop, hist, geo, mom);
-    hipLaunchKernelGGL(k_adj_node, fg, b, 0, s, g, 1, pop, hist, geo, (const double*)mom, tau,
+    // state 0 starts segment 0, the last one swept: its moments are in slot 0 if kept
+    const double* mt = mom;
+    if (have_mom[0])
+      mt = A.tmom;
+    else
+      hipLaunchKernelGGL(k_adj_moments, fg, b, 0, s, g, pop, hist, geo, mom);
+    hipLaunchKernelGGL(k_adj_node, fg, b, 0, s, g, 1, pop, hist, geo, mt, tau,
                        (const double*)A.lf[cur], (const double*)A.lp[cur], A.lfd, A.lml, A.ldj, (double*)nullptr,
                        A.lg);
-    hipLaunchKernelGGL(k_adj_gather, fg, b, 0, s, g, geo, (const double*)mom, (const double*)A.lfd,
+    hipLaunchKernelGGL(k_adj_gather, fg, b, 0, s, g, geo, mt, (const double*)A.lfd,
                        (const double*)A.lml, (const double*)A.ldj, (const double*)A.lf[cur], A.lf[cur ^ 1], A.lg);
     cur ^= 1;
   }

@@ -123,6 +123,9 @@ template <class T> hipError_t launch_get_geo(Fields& F, hipStream_t s, double* o
 constexpr int STEP_KERNELS = 2;  // at most this many kernels per step (timed separately by lbm_step_profiled)
 template <class T> hipError_t launch_step(Fields& F, hipStream_t s, T tau, hipEvent_t* ev = nullptr);
 template <class T> hipError_t launch_step_fused(Fields& F, hipStream_t s, T tau, int zc, int ty);
+// Fused step (64x4 tiles, no staging) that also writes rho and rho u of the
+// state it steps from to mout [4][N]; periodic grids without a plate only.
+template <class T> hipError_t launch_step_fused_moments(Fields& F, hipStream_t s, T tau, T* mout);
 // Planes per block the fused step runs with (F.zc, or the automatic choice).
 template <class T> hipError_t fused_step_chunk(Fields& F, int* zc);
 template <class T> hipError_t launch_moments_out(Fields& F, hipStream_t s, double* rho, double* u, int cart);

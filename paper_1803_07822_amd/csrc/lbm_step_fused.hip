@@ -224,14 +224,16 @@ enum Stage {
   STAGE_REG = 1,   // registers (two planes live across the collision)
 };
 
-template <class T, int TX, int TY, int STAGE, bool PL>
+// MO: also write each node's rho and rho u (the streamed moments the step
+// collides with) to mout [4][N], for the adjoint's recompute steps.
+template <class T, int TX, int TY, int STAGE, bool PL, bool MO = false>
 __global__ __launch_bounds__(TX * TY) void k_step_fused(Grid g, int ntx, int nty, int nzc, int zc,
                                                    const T* __restrict__ pin, T* __restrict__ pout,
                                                    const T* __restrict__ hist, T* __restrict__ hout,
                                                    const T* __restrict__ geo,
                                                    const T* __restrict__ uw, int mv0, int mv1,
                                                    const T* __restrict__ up, T tau,
-                                                   int* __restrict__ flag) {
+                                                   int* __restrict__ flag, T* __restrict__ mout) {
   constexpr int HN = Tile<TX, TY>::HN, HX = Tile<TX, TY>::HX;
   // Four ring slots: the fill of plane k+1 overwrites plane k-3, whose last
   // reader (the collision of plane k-2) every thread has finished before
@@ -285,6 +287,11 @@ __global__ __launch_bounds__(TX * TY) void k_step_fused(Grid g, int ntx, int nty
       const T(*rc)[HN] = ring[rslot(k)];
       const T dr = rc[0][c0];
       const T j[3] = {rc[1][c0], rc[2][c0], rc[3][c0]};
+      if constexpr (MO) {
+        mout[n] = T(1) + dr;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) mout[(size_t)(1 + a) * g.N + n] = j[a];
+      }
       // lattice gradient from the ring
       T dj[3][3];
 #pragma unroll
@@ -467,16 +474,17 @@ inline int choose_zc(long long tiles, int nz, long long slots) {
 
 // Planes per block for kernel k_step_fused<T, TX, TY, ST, PL>: zc if
 // positive, else the choice above for this device.
-template <class T, int TX, int TY, int ST, bool PL> hipError_t fused_chunk(Fields& F, int zc, int* out) {
+template <class T, int TX, int TY, int ST, bool PL, bool MO = false>
+hipError_t fused_chunk(Fields& F, int zc, int* out) {
   const Grid g = F.g;
   if (zc <= 0) {
-    const int key = (int)sizeof(T) * 10000 + TX * 10 + TY * 2 + ST + (PL ? 5000 : 0);
+    const int key = ((((int)sizeof(T) * 1000 + TX) * 100 + TY * 10 + ST) * 4) + (PL ? 1 : 0) + (MO ? 2 : 0);
     if (F.slots_key != key) {
       int dev = 0, cus = 0, per_cu = 0;
       hipError_t e = hipGetDevice(&dev);
       if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
       if (e == hipSuccess)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_fused<T, TX, TY, ST, PL>,
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_fused<T, TX, TY, ST, PL, MO>,
                                                          Tile<TX, TY>::NT, 0);
       if (e != hipSuccess) return e;
       F.slots = (long long)cus * (per_cu > 0 ? per_cu : 1);
@@ -489,17 +497,18 @@ template <class T, int TX, int TY, int ST, bool PL> hipError_t fused_chunk(Field
   return hipSuccess;
 }
 
-template <class T, int TX, int TY, int ST, bool PL> hipError_t fused_launch(Fields& F, hipStream_t s, T tau, int zc) {
+template <class T, int TX, int TY, int ST, bool PL, bool MO = false>
+hipError_t fused_launch(Fields& F, hipStream_t s, T tau, int zc, T* mout = nullptr) {
   const Grid g = F.g;
-  const hipError_t e = fused_chunk<T, TX, TY, ST, PL>(F, zc, &zc);
+  const hipError_t e = fused_chunk<T, TX, TY, ST, PL, MO>(F, zc, &zc);
   if (e != hipSuccess) return e;
   const int ntx = (g.nx + TX - 1) / TX, nty = (g.H + TY - 1) / TY;
   const int nzc = (g.nz + zc - 1) / zc;
   const int per = (ntx * nty * nzc + 7) / 8;
-  hipLaunchKernelGGL((k_step_fused<T, TX, TY, ST, PL>), dim3(per * 8), dim3(Tile<TX, TY>::NT), 0, s, g, ntx, nty,
-                     nzc, zc, (const T*)F.pop[F.cur], (T*)F.pop[F.cur ^ 1], (const T*)F.hist[F.cur],
+  hipLaunchKernelGGL((k_step_fused<T, TX, TY, ST, PL, MO>), dim3(per * 8), dim3(Tile<TX, TY>::NT), 0, s, g, ntx,
+                     nty, nzc, zc, (const T*)F.pop[F.cur], (T*)F.pop[F.cur ^ 1], (const T*)F.hist[F.cur],
                      (T*)F.hist[F.cur ^ 1], (const T*)F.geo, (const T*)F.uw, F.moving[0], F.moving[1],
-                     (const T*)F.up, tau, F.flag);
+                     (const T*)F.up, tau, F.flag, mout);
   F.cur ^= 1;
   return hipGetLastError();
 }
@@ -528,6 +537,15 @@ template <class T> hipError_t launch_step_fused(Fields& F, hipStream_t s, T tau,
   }
 }
 
+// The fused step on 64x4 tiles without register staging that also writes
+// rho and rho u of the state it steps from to mout [4][N] (rho in full, not
+// as a deviation): the adjoint's recompute steps keep them for the reverse
+// sweep.  Grids with a plate or open ends are not served (hipErrorNotSupported).
+template <class T> hipError_t launch_step_fused_moments(Fields& F, hipStream_t s, T tau, T* mout) {
+  if (F.g.pj || F.g.open || !mout) return hipErrorNotSupported;
+  return fused_launch<T, 64, 4, STAGE_NONE, false, true>(F, s, tau, F.zc, mout);
+}
+
 template <class T> hipError_t fused_step_chunk(Fields& F, int* zc) {
   if (F.g.pj) return chunk_tile<T, 64, 4, true>(F, zc);
   switch (F.tile) {
@@ -543,5 +561,6 @@ template hipError_t fused_step_chunk<double>(Fields&, int*);
 template hipError_t fused_step_chunk<float>(Fields&, int*);
 template hipError_t launch_step_fused<double>(Fields&, hipStream_t, double, int, int);
 template hipError_t launch_step_fused<float>(Fields&, hipStream_t, float, int, int);
+template hipError_t launch_step_fused_moments<double>(Fields&, hipStream_t, double, double*);
 
 }  // namespace lbm

@@ -305,7 +305,7 @@ def test_c5_adjoint_full_size_against_central_differences():
     w = synth.workload("c5_patch_wave_512x256x256")
     K, N = w.extra["K"], w.extra["ckpt_every"]
     d = w.disp()
-    torch.cuda.empty_cache()  # the workspace takes about 235 GiB of the 268
+    torch.cuda.empty_cache()  # the workspace takes about 245 GiB of the 268
     S = lbm.Solver(w.nx, w.ny, w.nz, w.tau, "fp64", adjoint_K=K, ckpt_every=N)
     S.set_body_force(w.force)
     S.set_wall_displacement(1, d)

@@ -13,6 +13,8 @@ bench.py times (the library's default tuning).
 The oracle runs the whole grid (several seconds per step on the host cores);
 these tests carry the `slow` marker as well.
 """
+import gc
+
 import numpy as np
 import pytest
 
@@ -24,6 +26,17 @@ pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 torch = pytest.importorskip("torch")
 
 W = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
+
+
+@pytest.fixture(autouse=True)
+def _release_device_memory():
+    """The contexts here hold tens of GiB each (the 512x256x256 adjoint
+    about 245 GiB of the 268): after every test, collect what reference
+    cycles still hold (a caught exception's traceback keeps the frames that
+    held a context) and return the cached blocks to the device."""
+    yield
+    gc.collect()
+    torch.cuda.empty_cache()
 
 
 def _lbm():
@@ -273,7 +286,8 @@ def test_c5_stated_amplitude_trips_guard():
                 S.step(5)
                 S.sync()
         assert e.value.code == -5
-        del S
+        del S, e  # the exception's traceback holds the frames that held S
+        gc.collect()
         torch.cuda.empty_cache()
 
 
@@ -305,6 +319,7 @@ def test_c5_adjoint_full_size_against_central_differences():
     w = synth.workload("c5_patch_wave_512x256x256")
     K, N = w.extra["K"], w.extra["ckpt_every"]
     d = w.disp()
+    gc.collect()
     torch.cuda.empty_cache()  # the workspace takes about 245 GiB of the 268
     S = lbm.Solver(w.nx, w.ny, w.nz, w.tau, "fp64", adjoint_K=K, ckpt_every=N)
     S.set_body_force(w.force)

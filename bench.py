@@ -37,7 +37,7 @@ def step_kernel_name(variant, stage):
     if variant == 1:
         return "k_moments<float> + k_collide<float> (two-pass step; time of both)"
     tx, ty = TILE_OF_VARIANT[variant]
-    return f"k_step_fused<float, {tx}, {ty}, {stage}, false> (whole step, one launch)"
+    return f"k_step_fused<float, {tx}, {ty}, {stage}, false, false> (whole step, one launch)"
 METRIC = "MLUPS + HBM GB/s (% peak) FP32 vs FP64 step; adjoint/forward time ratio"
 
 

@@ -415,3 +415,39 @@ def test_wall_force_momentum_exchange_parity(precision, variant):
     with pytest.raises(lbm.LBMError) as e:
         lbm.lbm_wall_force(S.ctx, 1, tot, None, lbm.LBM_FORCE_MEM)
     assert e.value.code == -6
+
+
+@pytest.mark.parametrize("case", ["fused", "two_pass", "open_fused"])
+def test_step_profiled_matches_plain_steps(case):
+    """lbm_step_profiled runs the same step as lbm_step (states equal bit for
+    bit) and times its kernels in two slots: the fused kernel (second slot
+    empty; with open ends, the end-column passes there) or the two passes."""
+    lbm = _lbm()
+    nx, ny, nz = 70, 12, 9
+    H = ny - 2
+    ctxs = []
+    for _ in range(2):
+        S = lbm.Solver(nx, ny, nz, 0.7, "fp32")
+        S.set_body_force((1e-5, 0, 0))
+        if case == "open_fused":
+            S.set_open_x(synth.parabolic_inlet(nz, H, 0.04))
+        S.set_metric(synth.bump3_chart(nx, ny, nz, 0.05))
+        lbm.lbm_set_tuning(S.ctx, 0, 1 if case == "two_pass" else 0, -1)
+        S.init_equilibrium(None, synth.random_perturbation((3, nz, H, nx), 1e-2, 5))
+        ctxs.append(S)
+    A, B = ctxs
+    ms = lbm.lbm_step_profiled(A.ctx, 3)
+    B.step(3)
+    B.sync()
+    assert torch.equal(A.populations(), B.populations())
+    assert torch.equal(A.history(), B.history())
+    print(case, "slots (ms):", ms, flush=True)
+    assert ms[0] > 0 and ms[2] == 0 and ms[3] == 0
+    if case == "fused":
+        assert ms[1] < 0.5 * ms[0]  # two events back to back
+    else:
+        assert ms[1] > 0
+    for bad in ((0, 4), (1, 1)):
+        with pytest.raises(lbm.LBMError) as e:
+            lbm.lbm_step_profiled(A.ctx, *bad)
+        assert e.value.code == -1

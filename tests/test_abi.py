@@ -89,3 +89,16 @@ def test_stream_probe_argument_errors():
     for args in ((lbm.LBM_FP32_DEV, 0), (lbm.LBM_FP32_DEV, -5), (7, 100), (lbm.LBM_FP64, 1 << 28)):
         assert lbm._lib.lbm_stream_probe(args[0], args[1], None, None, None) == -1
 
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: asked for more it exits with status 2 and
+    says so, before touching any device."""
+    import subprocess
+    import sys
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr

@@ -102,3 +102,18 @@ def test_bench_refuses_more_than_one_gpu():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_paper_values_fixture_is_cited():
+    """Every number in tests/golden/paper_values.json carries the passage it
+    comes from."""
+    import json
+
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "paper_values.json")
+    with open(path) as fh:
+        data = json.load(fh)
+    entries = {k: v for k, v in data.items() if isinstance(v, dict)}
+    assert entries
+    for k, v in entries.items():
+        assert isinstance(v["value"], (int, float)), k
+        assert re.search(r"(Sec\.|App\.|Fig\.)", v["cite"]), k

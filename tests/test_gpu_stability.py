@@ -11,9 +11,12 @@ guard trips; the maximum pressure at steady state grows with the depth.
 import numpy as np
 import pytest
 
+from conftest import PAPER
 from paper_1803_07822_amd import synth
 
 pytestmark = pytest.mark.gpu
+
+STABLE, UNSTABLE = PAPER["stable_concavity_fraction"], PAPER["unstable_concavity_fraction"]
 
 torch = pytest.importorskip("torch")
 
@@ -54,7 +57,7 @@ def _run(tau, frac, steps, chunk):
     return out
 
 
-@pytest.mark.parametrize("tau,stable,unstable", [(1.0, [0.02, 0.04, 0.06, 0.08, 0.09, 0.10, 0.11], [0.12]),
+@pytest.mark.parametrize("tau,stable,unstable", [(1.0, [0.02, 0.04, 0.06, 0.08, 0.09, STABLE, 0.11], [UNSTABLE]),
                                                  (0.8, [0.04, 0.08, 0.09], [0.10]),
                                                  (0.6, [0.02, 0.04], [0.06])])
 def test_concavity_depth_sweep(tau, stable, unstable):
@@ -70,3 +73,7 @@ def test_concavity_depth_sweep(tau, stable, unstable):
         assert res[f][0] == "tripped", (f, res[f])
     dp = [res[f][1] for f in stable]
     assert all(np.diff(dp) > 0), dp  # deeper concavity, higher peak pressure
+    if tau == 1.0:
+        # the paper's thresholds: stable at its bound, unstable at its
+        # instability depth, and within twice the step it shows that at
+        assert res[UNSTABLE][2] <= 2 * PAPER["unstable_by_step"], res[UNSTABLE]

@@ -12,6 +12,7 @@ import numpy as np
 import pytest
 import sympy as sp
 
+from conftest import PAPER
 from oracle import Oracle, dual_forces, run_forces
 from paper_1803_07822_amd import synth
 
@@ -347,14 +348,15 @@ def test_geometry_fourth_order_against_analytic():
             Gam=np.abs(Gam - Gama).max() / np.abs(Gama).max(),
             F=np.abs(Fb - Fba).max() / np.abs(Fba).max(),
         )
+    order = PAPER["derivative_convergence_order"] - 0.5  # the paper's slope, less half an order
     for key in ("J", "gi", "sg", "F"):
         s1 = np.log2(errs[16][key] / errs[32][key])
         s2 = np.log2(errs[32][key] / errs[64][key])
-        assert s1 > 3.5 and s2 > 3.5, (key, s1, s2, errs)
+        assert s1 > order and s2 > order, (key, s1, s2, errs)
     # Gamma takes a second fourth-order derivative of g; its leading error
     # still falls at fourth order once the grid resolves the chart.
     s2 = np.log2(errs[32]["Gam"] / errs[64]["Gam"])
-    assert s2 > 3.5, errs
+    assert s2 > order, errs
     assert errs[64]["Gam"] < 5e-4
 
 
@@ -534,7 +536,7 @@ def test_config1_channel_deviation_scales_with_eps():
         o.step(2000)
         rho, u = o.moments(cartesian=True)
         m1 = (sg * rho).sum()
-        assert abs(m1 / m0 - 1) < 1e-3
+        assert abs(m1 / m0 - 1) < PAPER["piston_mass_error_bound"]
         res[frac] = u
     dev_half = np.abs(res[0.015] - res[0.0]).max()
     dev_full = np.abs(res[0.03] - res[0.0]).max()

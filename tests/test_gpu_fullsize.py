@@ -271,6 +271,44 @@ def test_c5_travelling_wave_fp32_against_fp64_gpu():
     assert eu < 1e-3, eu
 
 
+def test_open_channel_fused_against_two_pass_at_scale():
+    """The 256x130x128 open channel (4.19M fluid nodes: above the size at
+    which open grids run the fused step with its end-column passes by
+    default), 50 steps from the developed inlet profile with a top-wall bump:
+    the fused FP64 path agrees with the two-pass FP64 path to rounding, and
+    the FP32 path with FP64 to the deviation form's rounding."""
+    lbm = _lbm()
+    nx, ny, nz, tau = 256, 130, 128, 0.6
+    H = ny - 2
+    uin = synth.parabolic_inlet(nz, H, 0.05)
+    d = synth.gaussian_bump(nx, nz, A=0.03 * H, x0=nx / 2, z0=nz / 2, sigma=12.0)
+    uc = np.zeros((3, nz, H, nx))
+    uc[0] = uin[..., 0][:, :, None]
+    out = {}
+    for name, precision, variant in (("fp64_fused", "fp64", None), ("fp64_two_pass", "fp64", 1),
+                                     ("fp32_fused", "fp32", None)):
+        S = lbm.Solver(nx, ny, nz, tau, precision)
+        S.set_open_x(uin)
+        S.set_wall_displacement(1, d)
+        if variant is not None:
+            lbm.lbm_set_tuning(S.ctx, 0, variant, -1)
+        assert lbm.lbm_get_tuning(S.ctx)[1] == (1 if variant == 1 else 0)
+        S.init_equilibrium(None, uc)
+        S.step(50)
+        r, u = S.moments(cartesian=True)
+        out[name] = (_np(r), _np(u))
+        del S, r, u
+    (r64, u64), (r2, u2), (r32, u32) = out["fp64_fused"], out["fp64_two_pass"], out["fp32_fused"]
+    umax = np.abs(u64).max()
+    e_path = max(np.abs(r64 - r2).max(), np.abs(u64 - u2).max() / umax)
+    er, eu = np.abs(r32 - r64).max(), np.abs(u32 - u64).max() / umax
+    print(f"open channel 50 steps: fused vs two-pass FP64 {e_path:.2e}; FP32 vs FP64 |drho| {er:.2e}, "
+          f"|du|/max|u| {eu:.2e} (max|u| {umax:.3e})", flush=True)
+    assert e_path < 1e-12, e_path
+    assert er < 1e-6, er
+    assert eu < 1e-4, eu
+
+
 def test_c5_stated_amplitude_trips_guard():
     """At the stated amplitude 0.08*256 (wall slope up to 1.0) the scheme is
     unstable: from rest, FP32 and FP64 both trip the instability guard within

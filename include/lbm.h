@@ -251,13 +251,16 @@ int lbm_set_open_x(lbm_ctx* ctx, const double* d_uin);
  * states 1..K into d_forces [K][3]; the initial state and a checkpoint every
  * ckpt_every steps are kept for lbm_backward.  K and ckpt_every must match
  * lbm_reserve_adjoint.  Needs the FP64 form, no interior plate and periodic
- * x. */
+ * x.  Walls may move: the velocities set by lbm_set_wall_velocity hold over
+ * the K steps. */
 int lbm_forward_record(lbm_ctx* ctx, int K, int ckpt_every, int wall, int method, double* d_forces);
 
 /* Reverse sweep of the last lbm_forward_record: given dL/dF [K][3], write
  * dL/d(top-wall displacement) [nz][nx], dL/d(chart) [3][nz][ny][nx] and dL/d
  * f0 [19][fluid] (each may be NULL).  The initial populations f0 are an
  * independent input (the history F(x,-1) is recomputed from f0 and the chart).
+ * A moving wall's Cartesian velocity is a constant; its chart components
+ * J^{-1} v depend on the chart and are differentiated.
  * The context's state stays the one lbm_forward_record ended with.
  * Synchronising. */
 int lbm_backward(lbm_ctx* ctx, const double* d_dL_dF, double* d_grad_disp, double* d_grad_chart,

@@ -1266,11 +1266,14 @@ void orc_chart(void* s, double* out) {
 void orc_jacobian(void* s, double* out9) { ((Sim<double>*)s)->jacobian_export(out9); }
 
 // Forces on `wall` at states 1..K after the initial state given by f0, for the
-// top-wall displacement d (bottom wall flat, walls at rest).
+// top-wall displacement d (bottom wall flat) and the Cartesian wall velocities
+// vwall [2][nz][nx][3] (NULL: walls at rest).
 void orc_run_forces(int nx, int ny, int nz, double tau, const double* Fc, const double* d_top,
-                    const double* f0, int K, int wall, double* forces) {
+                    const double* f0, int K, int wall, double* forces, const double* vwall) {
   Sim<double> S(nx, ny, nz, tau);
   S.set_body_force(Fc);
+  if (vwall)
+    for (int w = 0; w < 2; ++w) S.set_wall_velocity(w, vwall + (long)w * nz * nx * 3);
   S.set_wall_displacement(1, d_top, false);
   S.set_populations(f0);
   for (int t = 0; t < K; ++t) {
@@ -1283,10 +1286,17 @@ void orc_run_forces(int nx, int ny, int nz, double tau, const double* Fc, const 
 // direction (dd_top, df0), exact to rounding (forward-mode differentiation).
 void orc_dual_forces(int nx, int ny, int nz, double tau, const double* Fc, const double* d_top,
                      const double* dd_top, const double* f0, const double* df0, int K, int wall,
-                     double* forces, double* dforces) {
+                     double* forces, double* dforces, const double* vwall) {
   Sim<Dual> S(nx, ny, nz, tau);
   S.set_body_force(Fc);
   long ncol = (long)nz * nx;
+  if (vwall) {
+    std::vector<Dual> v(3 * ncol);
+    for (int w = 0; w < 2; ++w) {
+      for (long q = 0; q < 3 * ncol; ++q) v[q] = Dual(vwall[w * 3 * ncol + q], 0.0);
+      S.set_wall_velocity(w, v.data());
+    }
+  }
   std::vector<Dual> d(ncol);
   for (long q = 0; q < ncol; ++q) d[q] = Dual(d_top[q], dd_top ? dd_top[q] : 0.0);
   S.set_wall_displacement(1, d.data(), false);

@@ -73,10 +73,10 @@ def _lib():
         L.orc_wall_force_mem.restype = ctypes.c_int
         L.orc_set_open_x.argtypes = [ctypes.c_void_p, _D]
         L.orc_set_open_x.restype = ctypes.c_int
-        L.orc_run_forces.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double, _D, _D, _D, ctypes.c_int, ctypes.c_int, _D]
+        L.orc_run_forces.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double, _D, _D, _D, ctypes.c_int, ctypes.c_int, _D, _D]
         L.orc_run_forces.restype = None
         L.orc_dual_forces.argtypes = (
-            [ctypes.c_int] * 3 + [ctypes.c_double, _D, _D, _D, _D, _D, ctypes.c_int, ctypes.c_int, _D, _D]
+            [ctypes.c_int] * 3 + [ctypes.c_double, _D, _D, _D, _D, _D, ctypes.c_int, ctypes.c_int, _D, _D, _D]
         )
         L.orc_dual_forces.restype = None
         _LIB = L
@@ -230,18 +230,22 @@ class Oracle:
         return out
 
 
-def run_forces(nx, ny, nz, tau, F, d_top, f0, K, wall=1):
-    """Wall forces [K, 3] at states 1..K from f0 under top displacement d_top."""
+def run_forces(nx, ny, nz, tau, F, d_top, f0, K, wall=1, vwall=None):
+    """Wall forces [K, 3] at states 1..K from f0 under top displacement d_top;
+    vwall [2, nz, nx, 3]: Cartesian wall velocities (None: at rest)."""
     F = _c(F, (3,))
     d_top = _c(d_top, (nz, nx))
     f0 = _c(f0, (19, nz, ny - 2, nx))
+    vw = None if vwall is None else _c(vwall, (2, nz, nx, 3))
     out = np.empty((K, 3))
-    _lib().orc_run_forces(nx, ny, nz, float(tau), _p(F), _p(d_top), _p(f0), int(K), int(wall), _p(out))
+    _lib().orc_run_forces(nx, ny, nz, float(tau), _p(F), _p(d_top), _p(f0), int(K), int(wall), _p(out),
+                          None if vw is None else _p(vw))
     return out
 
 
-def dual_forces(nx, ny, nz, tau, F, d_top, dd_top, f0, df0, K, wall=1):
-    """Forces [K,3] and their exact derivative along (dd_top, df0) (forward mode)."""
+def dual_forces(nx, ny, nz, tau, F, d_top, dd_top, f0, df0, K, wall=1, vwall=None):
+    """Forces [K,3] and their exact derivative along (dd_top, df0) (forward
+    mode); vwall [2, nz, nx, 3]: Cartesian wall velocities (None: at rest)."""
     F = _c(F, (3,))
     d_top = _c(d_top, (nz, nx))
     dd_top = _c(dd_top, (nz, nx))
@@ -249,7 +253,9 @@ def dual_forces(nx, ny, nz, tau, F, d_top, dd_top, f0, df0, K, wall=1):
     df0 = _c(df0, (19, nz, ny - 2, nx))
     out = np.empty((K, 3))
     dout = np.empty((K, 3))
+    vw = None if vwall is None else _c(vwall, (2, nz, nx, 3))
     _lib().orc_dual_forces(
-        nx, ny, nz, float(tau), _p(F), _p(d_top), _p(dd_top), _p(f0), _p(df0), int(K), int(wall), _p(out), _p(dout)
+        nx, ny, nz, float(tau), _p(F), _p(d_top), _p(dd_top), _p(f0), _p(df0), int(K), int(wall), _p(out), _p(dout),
+        None if vw is None else _p(vw)
     )
     return out, dout

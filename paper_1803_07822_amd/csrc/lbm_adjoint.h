@@ -23,6 +23,7 @@ struct AdjointBuffers {
   double* lge = nullptr;   // [6][NE]
   double* lwe = nullptr;   // [6][NE]
   double* gc = nullptr;    // [3][NC] adjoint of the chart
+  double* ub = nullptr;    // [2][nz][nx][3] adjoint of the walls' chart-component velocity
   int nckpt = 0;
 };
 
@@ -50,6 +51,7 @@ inline void carve_adjoint(Carver& c, const Grid& g, int K, int N, AdjointBuffers
   A.lge = (double*)c.take(sizeof(double) * 6 * NE);
   A.lwe = (double*)c.take(sizeof(double) * 6 * NE);
   A.gc = (double*)c.take(sizeof(double) * 3 * NC);
+  A.ub = (double*)c.take(sizeof(double) * 2 * 3 * (size_t)g.nz * g.nx);
 }
 
 hipError_t adjoint_forward(Fields& F, AdjointBuffers& A, hipStream_t s, int K, int N, int wall, double tau,

@@ -15,7 +15,10 @@
 // symbols, inverse metric, determinant, metric products, both lattice
 // stencils and the cubic continuation) to the chart and the wall displacement.
 //
-// Walls at rest and a static metric (no re-projection inside the K steps).
+// The metric is static (no re-projection inside the K steps).  A wall may
+// move with a fixed Cartesian velocity v: its chart components u_w = J^{-1} v
+// at the wall row enter the bounce-back and the gradient ghost, and their
+// dependence on J is carried back to the chart; v itself is a constant.
 #include <vector>
 
 #include "lbm_adjoint.h"
@@ -91,9 +94,10 @@ __device__ __forceinline__ void load_geo_full(const Grid& g, const double* __res
   for (int q = 0; q < 3; ++q) G.F[q] = E(geo, (G_F + q), g, n);
 }
 
-// Lattice gradient of the stored moments (walls at rest: ghost j = -j_m).
+// Lattice gradient of the stored moments (ghost beyond a wall: -j_m, plus
+// 2 rho u_w where the wall moves).
 __device__ __forceinline__ void gradient_at(const Grid& g, const double* __restrict__ mom, const Node& p,
-                                            double dj[3][3]) {
+                                            const double* __restrict__ uw, int mv0, int mv1, double dj[3][3]) {
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
@@ -112,6 +116,14 @@ __device__ __forceinline__ void gradient_at(const Grid& g, const double* __restr
       const unsigned m = nidx(g, in, p.jf, kn);
 #pragma unroll
       for (int b = 0; b < 3; ++b) jb[b] = -E(mom, (1 + b), g, m);
+      // a moving wall's ghost is 2 rho u_w - j, with the column's u_w
+      const int w = jn < 0 ? 0 : 1;
+      if (w == 0 ? mv0 : mv1) {
+        const double r2 = 2.0 * E(mom, 0, g, m);
+        const size_t c = (((size_t)w * g.nz + kn) * g.nx + in) * 3;
+#pragma unroll
+        for (int b = 0; b < 3; ++b) jb[b] += r2 * uw[c + b];
+      }
     }
     constexpr double fct = 3.0 * wgt(l);
 #pragma unroll
@@ -164,14 +176,15 @@ __global__ __launch_bounds__(BX * BY) void k_adj_node(Grid g, int mode, const do
                            const double* __restrict__ geo, const double* __restrict__ mom, double tau,
                            const double* __restrict__ lfn, const double* __restrict__ lpn, double* __restrict__ lfd,
                            double* __restrict__ lml, double* __restrict__ ldj, double* __restrict__ lpo,
-                           double* __restrict__ lg) {
+                           double* __restrict__ lg, const double* __restrict__ uw, int mv0, int mv1,
+                           double* __restrict__ ub) {
   Node p;
   if (!fluid_node(g, p)) return;
   AGeo G;
   load_geo_full(g, geo, p.n, G);
   double f[Q], Fp[10], dj[3][3];
   load_state(g, pop, hist, G, p, f, Fp);
-  gradient_at(g, mom, p, dj);
+  gradient_at(g, mom, p, uw, mv0, mv1, dj);
   const bool with_old = mode == 0;
   NodeFwd o;
   node_fwd(f, Fp, G, dj, tau, with_old, o);
@@ -202,6 +215,33 @@ __global__ __launch_bounds__(BX * BY) void k_adj_node(Grid g, int mode, const do
   AGeoBar gb;
   zero_bar(gb);
   node_vjp(Fp, G, tau, with_old, o, fsb, Fb, cb, nullptr, fb, rb, jb, djb, Fpb, gb);
+  // moving walls: the bounce-back of a link into wall w loses
+  // 6 (w_l / sqrt g) rho c_l . u_w (chart components u_w of the column)
+  if (with_old) {
+#pragma unroll
+    for (int w = 0; w < 2; ++w) {
+      if (!(w == 0 ? (p.jf == 0 && mv0) : (p.jf == g.H - 1 && mv1))) continue;
+      const size_t c = (((size_t)w * g.nz + p.k) * g.nx + p.i) * 3;
+      const double u[3] = {uw[c], uw[c + 1], uw[c + 2]};
+      double isgb = 0, ubl[3] = {0, 0, 0};
+      for_q([&](auto L) {
+        constexpr int l = decltype(L)::value;
+        constexpr int y = cy(l);
+        if ((w == 1 && y > 0) || (w == 0 && y < 0)) {
+          const double cu = cx(l) * u[0] + y * u[1] + cz(l) * u[2];
+          const double s = -6.0 * wgt(l) * fsb[l];
+          rb += s * o.isg * cu;
+          isgb += s * o.rho * cu;
+          ubl[0] += s * o.isg * o.rho * cx(l);
+          ubl[1] += s * o.isg * o.rho * y;
+          ubl[2] += s * o.isg * o.rho * cz(l);
+        }
+      });
+      gb.sg -= isgb * o.isg * o.isg;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) ub[c + a] += ubl[a];
+    }
+  }
   for_q([&](auto L) {
     constexpr int l = decltype(L)::value;
     E(lfd, l, g, p.n) = fb[l];
@@ -225,10 +265,16 @@ __global__ __launch_bounds__(BX * BY) void k_adj_node(Grid g, int mode, const do
 __global__ __launch_bounds__(BX * BY) void k_adj_gather(Grid g, const double* __restrict__ geo, const double* __restrict__ mom,
                              const double* __restrict__ lfd, const double* __restrict__ lml,
                              const double* __restrict__ ldj, const double* __restrict__ lf_add,
-                             double* __restrict__ lf_out, double* __restrict__ lg) {
+                             double* __restrict__ lf_out, double* __restrict__ lg, const double* __restrict__ uw,
+                             int mv0, int mv1, double* __restrict__ ub) {
   Node p;
   if (!fluid_node(g, p)) return;
   double rb = E(lml, 0, g, p.n), jb[3] = {E(lml, 1, g, p.n), E(lml, 2, g, p.n), E(lml, 3, g, p.n)};
+  const double rho = E(mom, 0, g, p.n);
+  // the ghost of a moving wall, 2 rho u_w - j, also carries rho and u_w
+  const bool mw0 = p.jf == 0 && mv0, mw1 = p.jf == g.H - 1 && mv1;
+  const size_t c0 = ((size_t)p.k * g.nx + p.i) * 3, c1 = (((size_t)g.nz + p.k) * g.nx + p.i) * 3;
+  double ub0[3] = {0, 0, 0}, ub1[3] = {0, 0, 0};
   for_q([&](auto L) {
     constexpr int l = decltype(L)::value;
     if (l == 0) return;
@@ -245,12 +291,24 @@ __global__ __launch_bounds__(BX * BY) void k_adj_gather(Grid g, const double* __
     // direction l is solid, used -j(p)
     if ((y < 0 && p.jf == 0) || (y > 0 && p.jf == g.H - 1)) {
       const unsigned m = nidx(g, wrapa(p.i - x, g.nx), p.jf, wrapa(p.k - z, g.nz));
-      for (int b = 0; b < 3; ++b)
-        jb[b] -= fct * (x * E(ldj, (0 * 3 + b), g, m) + y * E(ldj, (1 * 3 + b), g, m) + z * E(ldj, (2 * 3 + b), g, m));
+      const bool mv = y < 0 ? mw0 : mw1;
+      const size_t c = y < 0 ? c0 : c1;
+      for (int b = 0; b < 3; ++b) {
+        const double jgb =
+            fct * (x * E(ldj, (0 * 3 + b), g, m) + y * E(ldj, (1 * 3 + b), g, m) + z * E(ldj, (2 * 3 + b), g, m));
+        jb[b] -= jgb;
+        if (mv) {
+          rb += 2.0 * uw[c + b] * jgb;
+          (y < 0 ? ub0 : ub1)[b] += 2.0 * rho * jgb;
+        }
+      }
     }
   });
+  if (mw0)
+    for (int b = 0; b < 3; ++b) ub[c0 + b] += ub0[b];
+  if (mw1)
+    for (int b = 0; b < 3; ++b) ub[c1 + b] += ub1[b];
   const double sg = 1.0 + E(geo, G_SG, g, p.n);
-  const double rho = E(mom, 0, g, p.n);
   const double S0 = rho / sg, S1[3] = {E(mom, 1, g, p.n) / sg, E(mom, 2, g, p.n) / sg, E(mom, 3, g, p.n) / sg};
   double fb[Q];
   for_q([&](auto L) {
@@ -264,6 +322,36 @@ __global__ __launch_bounds__(BX * BY) void k_adj_gather(Grid g, const double* __
     E(lf_out, l, g, p.n) = fb[l];
   });
   E(lg, G_SG, g, p.n) += sgb;
+}
+
+__device__ inline void inv3a(const double m[3][3], double r[3][3], double& det);
+
+// The walls' chart-component velocity is u_w = J^{-1} v_w at the fluid node
+// next to the wall: its adjoint ub passes to J there as -(J^{-T} ub) u_w^T.
+__global__ __launch_bounds__(BX * BY) void k_adj_wall_velocity(Grid g, const double* __restrict__ jac,
+                                                              const double* __restrict__ uw, int mv0, int mv1,
+                                                              const double* __restrict__ ub, double* __restrict__ lj) {
+  const int i = blockIdx.x * BX + threadIdx.x, k = blockIdx.y * BY + threadIdx.y;
+  if (i >= g.nx || k >= g.nz) return;
+  for (int w = 0; w < 2; ++w) {
+    if (!(w == 0 ? mv0 : mv1)) continue;
+    const unsigned n = nidx(g, i, w == 0 ? 0 : g.H - 1, k);
+    const size_t c = (((size_t)w * g.nz + k) * g.nx + i) * 3;
+    double J[3][3], Ji[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) J[a][b] = jac[(a * 3 + b) * g.N + n];
+    double det;
+    inv3a(J, Ji, det);
+    double t[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) t[a] = Ji[0][a] * ub[c] + Ji[1][a] * ub[c + 1] + Ji[2][a] * ub[c + 2];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) lj[(a * 3 + b) * g.N + n] -= t[a] * uw[c + b];
+  }
 }
 
 // Wall-force VJP at one state: L += sum_a W_a F^a, F^a = sgn sum sqrt g
@@ -617,7 +705,6 @@ hipError_t adjoint_forward(Fields& F, AdjointBuffers& A, hipStream_t s, int K, i
 hipError_t adjoint_backward(Fields& F, AdjointBuffers& A, hipStream_t s, int K, int N, int wall, double tau,
                             const double Fc[3], const double* dLdF, double* grad_disp, double* grad_chart,
                             double* grad_f0) {
-  if (F.moving[0] || F.moving[1]) return hipErrorNotSupported;
   const Grid g = F.g;
   const size_t Nn = (size_t)g.N;
   const size_t state = (size_t)(19 + H_N) * Nn;
@@ -630,6 +717,9 @@ hipError_t adjoint_backward(Fields& F, AdjointBuffers& A, hipStream_t s, int K, 
   HCHK(hipMemsetAsync(A.lp[cur], 0, sizeof(double) * H_N * Nn, s));
   HCHK(hipMemsetAsync(A.lg, 0, sizeof(double) * G_N * Nn, s));
   HCHK(hipMemsetAsync(A.lj, 0, sizeof(double) * 9 * Nn, s));
+  HCHK(hipMemsetAsync(A.ub, 0, sizeof(double) * 6 * (size_t)g.nz * g.nx, s));
+  const double* uwd = (const double*)F.uw;
+  const int mv0 = F.moving[0], mv1 = F.moving[1];
   // force at the final state K
   {
     const double* fin = A.ckpt + state * (A.nckpt - 1);
@@ -660,9 +750,10 @@ hipError_t adjoint_backward(Fields& F, AdjointBuffers& A, hipStream_t s, int K, 
         hipLaunchKernelGGL(k_adj_moments, fg, b, 0, s, g, pop, hist, geo, mom);
       hipLaunchKernelGGL(k_adj_node, fg, b, 0, s, g, 0, pop, hist, geo, mt, tau,
                          (const double*)A.lf[cur], (const double*)A.lp[cur], A.lfd, A.lml, A.ldj, A.lp[cur ^ 1],
-                         A.lg);
+                         A.lg, uwd, mv0, mv1, A.ub);
       hipLaunchKernelGGL(k_adj_gather, fg, b, 0, s, g, geo, mt, (const double*)A.lfd,
-                         (const double*)A.lml, (const double*)A.ldj, (const double*)nullptr, A.lf[cur ^ 1], A.lg);
+                         (const double*)A.lml, (const double*)A.ldj, (const double*)nullptr, A.lf[cur ^ 1], A.lg,
+                         uwd, mv0, mv1, A.ub);
       cur ^= 1;
       if (t >= 1)
         hipLaunchKernelGGL(k_adj_force, cg, b, 0, s, g, wall, pop, hist, geo, (const double*)F.jac, tau,
@@ -681,12 +772,17 @@ hipError_t adjoint_backward(Fields& F, AdjointBuffers& A, hipStream_t s, int K, 
       hipLaunchKernelGGL(k_adj_moments, fg, b, 0, s, g, pop, hist, geo, mom);
     hipLaunchKernelGGL(k_adj_node, fg, b, 0, s, g, 1, pop, hist, geo, mt, tau,
                        (const double*)A.lf[cur], (const double*)A.lp[cur], A.lfd, A.lml, A.ldj, (double*)nullptr,
-                       A.lg);
+                       A.lg, uwd, mv0, mv1, A.ub);
     hipLaunchKernelGGL(k_adj_gather, fg, b, 0, s, g, geo, mt, (const double*)A.lfd,
-                       (const double*)A.lml, (const double*)A.ldj, (const double*)A.lf[cur], A.lf[cur ^ 1], A.lg);
+                       (const double*)A.lml, (const double*)A.ldj, (const double*)A.lf[cur], A.lf[cur ^ 1], A.lg,
+                       uwd, mv0, mv1, A.ub);
     cur ^= 1;
   }
   if (grad_f0) HCHK(hipMemcpyAsync(grad_f0, A.lf[cur], sizeof(double) * 19 * Nn, hipMemcpyDeviceToDevice, s));
+  // moving walls: their chart-component velocity depends on J at the wall nodes
+  if (mv0 || mv1)
+    hipLaunchKernelGGL(k_adj_wall_velocity, cg, b, 0, s, g, (const double*)F.jac, uwd, mv0, mv1,
+                       (const double*)A.ub, A.lj);
   // geometry
   if (grad_disp || grad_chart) {
     HCHK(hipMemsetAsync(A.lge, 0, sizeof(double) * 6 * NE, s));

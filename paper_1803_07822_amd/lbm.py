@@ -447,7 +447,7 @@ for _name, _fn in list(vars(Solver).items()):
 class WallForceFn(torch.autograd.Function):
     """forces[K, 3] = wall forces of states 1..K after setting the top-wall
     displacement d [nz, nx] and the initial populations f0 [19, nz, H, nx] on
-    `solver` (FP64, walls at rest).  backward returns (dL/dd, dL/df0); f0 is an
+    `solver` (FP64; walls at rest or moving with the velocities set on it).  backward returns (dL/dd, dL/df0); f0 is an
     independent input (its forcing history is recomputed from it)."""
 
     @staticmethod

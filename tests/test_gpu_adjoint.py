@@ -130,8 +130,13 @@ def test_moving_wall_adjoint_matches_forward_mode_derivatives():
     S.set_wall_velocity(1, vw[1])
     S.set_populations(f0)
     forces = S.forward_record(K).cpu().numpy()
-    gd, _, gf = S.backward(W, need_disp=True, need_chart=False, need_f0=True)
-    gd, gf = gd.cpu().numpy(), gf.cpu().numpy()
+    gd, gc, gf = S.backward(W, need_disp=True, need_chart=True, need_f0=True)
+    gd, gc, gf = gd.cpu().numpy(), gc.cpu().numpy(), gf.cpu().numpy()
+    # the chart gradient carries the same u_w term: <dL/dchart, dchart> = <dL/dd, dd>
+    dd = synth.random_unit(d.shape, 33)
+    dchart = synth.chart_from_displacement(nx, ny, nz, dd) - synth.identity_chart(nx, ny, nz)
+    a, b = float((gc * dchart).sum()), float((gd * dd).sum())
+    assert abs(a - b) < 1e-12 * max(abs(a), abs(b))
     fo = run_forces(nx, ny, nz, tau, F, d, f0, K, vwall=vw)
     f_rest = run_forces(nx, ny, nz, tau, F, d, f0, K)
     assert np.abs(fo - f_rest).max() > 1e-6 * np.abs(fo).max()

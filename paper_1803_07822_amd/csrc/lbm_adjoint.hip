@@ -172,6 +172,8 @@ __global__ __launch_bounds__(BX * BY) void k_adj_moments(Grid g, const double* _
 
 // Reverse of one step at each node (mode 0), or of the history of an initial
 // state (mode 1: only the new coefficients carry an adjoint).
+// MW: some wall moves (walls at rest compile the moving-wall terms out).
+template <bool MW>
 __global__ __launch_bounds__(BX * BY) void k_adj_node(Grid g, int mode, const double* __restrict__ pop, const double* __restrict__ hist,
                            const double* __restrict__ geo, const double* __restrict__ mom, double tau,
                            const double* __restrict__ lfn, const double* __restrict__ lpn, double* __restrict__ lfd,
@@ -184,7 +186,7 @@ __global__ __launch_bounds__(BX * BY) void k_adj_node(Grid g, int mode, const do
   load_geo_full(g, geo, p.n, G);
   double f[Q], Fp[10], dj[3][3];
   load_state(g, pop, hist, G, p, f, Fp);
-  gradient_at(g, mom, p, uw, mv0, mv1, dj);
+  gradient_at(g, mom, p, uw, MW && mv0, MW && mv1, dj);
   const bool with_old = mode == 0;
   NodeFwd o;
   node_fwd(f, Fp, G, dj, tau, with_old, o);
@@ -217,7 +219,7 @@ __global__ __launch_bounds__(BX * BY) void k_adj_node(Grid g, int mode, const do
   node_vjp(Fp, G, tau, with_old, o, fsb, Fb, cb, nullptr, fb, rb, jb, djb, Fpb, gb);
   // moving walls: the bounce-back of a link into wall w loses
   // 6 (w_l / sqrt g) rho c_l . u_w (chart components u_w of the column)
-  if (with_old) {
+  if (MW && with_old) {
 #pragma unroll
     for (int w = 0; w < 2; ++w) {
       if (!(w == 0 ? (p.jf == 0 && mv0) : (p.jf == g.H - 1 && mv1))) continue;
@@ -262,6 +264,7 @@ __global__ __launch_bounds__(BX * BY) void k_adj_node(Grid g, int mode, const do
 // Transposed lattice gradient and the moment VJP:
 // lf_out = lfd + sqrt g (rho_bar + j_bar . c) (+ lf_add), with
 // j_bar = local + sum over the stencil of the neighbours' dj adjoints.
+template <bool MW>
 __global__ __launch_bounds__(BX * BY) void k_adj_gather(Grid g, const double* __restrict__ geo, const double* __restrict__ mom,
                              const double* __restrict__ lfd, const double* __restrict__ lml,
                              const double* __restrict__ ldj, const double* __restrict__ lf_add,
@@ -272,7 +275,7 @@ __global__ __launch_bounds__(BX * BY) void k_adj_gather(Grid g, const double* __
   double rb = E(lml, 0, g, p.n), jb[3] = {E(lml, 1, g, p.n), E(lml, 2, g, p.n), E(lml, 3, g, p.n)};
   const double rho = E(mom, 0, g, p.n);
   // the ghost of a moving wall, 2 rho u_w - j, also carries rho and u_w
-  const bool mw0 = p.jf == 0 && mv0, mw1 = p.jf == g.H - 1 && mv1;
+  const bool mw0 = MW && p.jf == 0 && mv0, mw1 = MW && p.jf == g.H - 1 && mv1;
   const size_t c0 = ((size_t)p.k * g.nx + p.i) * 3, c1 = (((size_t)g.nz + p.k) * g.nx + p.i) * 3;
   double ub0[3] = {0, 0, 0}, ub1[3] = {0, 0, 0};
   for_q([&](auto L) {
@@ -720,6 +723,7 @@ hipError_t adjoint_backward(Fields& F, AdjointBuffers& A, hipStream_t s, int K, 
   HCHK(hipMemsetAsync(A.ub, 0, sizeof(double) * 6 * (size_t)g.nz * g.nx, s));
   const double* uwd = (const double*)F.uw;
   const int mv0 = F.moving[0], mv1 = F.moving[1];
+  const bool mw = mv0 || mv1;
   // force at the final state K
   {
     const double* fin = A.ckpt + state * (A.nckpt - 1);
@@ -748,10 +752,10 @@ hipError_t adjoint_backward(Fields& F, AdjointBuffers& A, hipStream_t s, int K, 
         mt = A.tmom + 4 * Nn * (t - t0);
       else
         hipLaunchKernelGGL(k_adj_moments, fg, b, 0, s, g, pop, hist, geo, mom);
-      hipLaunchKernelGGL(k_adj_node, fg, b, 0, s, g, 0, pop, hist, geo, mt, tau,
+      hipLaunchKernelGGL(mw ? k_adj_node<true> : k_adj_node<false>, fg, b, 0, s, g, 0, pop, hist, geo, mt, tau,
                          (const double*)A.lf[cur], (const double*)A.lp[cur], A.lfd, A.lml, A.ldj, A.lp[cur ^ 1],
                          A.lg, uwd, mv0, mv1, A.ub);
-      hipLaunchKernelGGL(k_adj_gather, fg, b, 0, s, g, geo, mt, (const double*)A.lfd,
+      hipLaunchKernelGGL(mw ? k_adj_gather<true> : k_adj_gather<false>, fg, b, 0, s, g, geo, mt, (const double*)A.lfd,
                          (const double*)A.lml, (const double*)A.ldj, (const double*)nullptr, A.lf[cur ^ 1], A.lg,
                          uwd, mv0, mv1, A.ub);
       cur ^= 1;
@@ -770,10 +774,10 @@ hipError_t adjoint_backward(Fields& F, AdjointBuffers& A, hipStream_t s, int K, 
       mt = A.tmom;
     else
       hipLaunchKernelGGL(k_adj_moments, fg, b, 0, s, g, pop, hist, geo, mom);
-    hipLaunchKernelGGL(k_adj_node, fg, b, 0, s, g, 1, pop, hist, geo, mt, tau,
+    hipLaunchKernelGGL(mw ? k_adj_node<true> : k_adj_node<false>, fg, b, 0, s, g, 1, pop, hist, geo, mt, tau,
                        (const double*)A.lf[cur], (const double*)A.lp[cur], A.lfd, A.lml, A.ldj, (double*)nullptr,
                        A.lg, uwd, mv0, mv1, A.ub);
-    hipLaunchKernelGGL(k_adj_gather, fg, b, 0, s, g, geo, mt, (const double*)A.lfd,
+    hipLaunchKernelGGL(mw ? k_adj_gather<true> : k_adj_gather<false>, fg, b, 0, s, g, geo, mt, (const double*)A.lfd,
                        (const double*)A.lml, (const double*)A.ldj, (const double*)A.lf[cur], A.lf[cur ^ 1], A.lg,
                        uwd, mv0, mv1, A.ub);
     cur ^= 1;

@@ -46,7 +46,7 @@ __device__ __forceinline__ double& E(double* __restrict__ a, long long q, const 
 
 __device__ __forceinline__ bool fluid_node(const Grid& g, Node& p) {
   p.i = blockIdx.x * BX + threadIdx.x;
-  p.jf = blockIdx.y * BY + threadIdx.y;
+  p.jf = blockIdx.y * blockDim.y + threadIdx.y;
   p.k = blockIdx.z;
   if (p.i >= g.nx || p.jf >= g.H) return false;
   p.n = ((unsigned)p.k * g.H + p.jf) * g.nx + p.i;
@@ -713,6 +713,9 @@ hipError_t adjoint_backward(Fields& F, AdjointBuffers& A, hipStream_t s, int K, 
   const size_t state = (size_t)(19 + H_N) * Nn;
   const size_t NE = (size_t)g.nz * (g.ny + 6) * g.nx, NC = (size_t)g.nz * g.ny * g.nx;
   const dim3 b(BX, BY), fg = fluid_grid(g), cg = col_grid(g), eg = ext_grid(g);
+  // the node kernel runs one wave per SIMD: one-wave workgroups let each
+  // SIMD take the next one as soon as its own wave ends
+  const dim3 nb(BX, 1), ng(fg.x, g.H, g.nz);
   double* mom = (double*)F.mom;
   const double* geo = (const double*)F.geo;
   int cur = 0;
@@ -752,7 +755,7 @@ hipError_t adjoint_backward(Fields& F, AdjointBuffers& A, hipStream_t s, int K, 
         mt = A.tmom + 4 * Nn * (t - t0);
       else
         hipLaunchKernelGGL(k_adj_moments, fg, b, 0, s, g, pop, hist, geo, mom);
-      hipLaunchKernelGGL(mw ? k_adj_node<true> : k_adj_node<false>, fg, b, 0, s, g, 0, pop, hist, geo, mt, tau,
+      hipLaunchKernelGGL(mw ? k_adj_node<true> : k_adj_node<false>, ng, nb, 0, s, g, 0, pop, hist, geo, mt, tau,
                          (const double*)A.lf[cur], (const double*)A.lp[cur], A.lfd, A.lml, A.ldj, A.lp[cur ^ 1],
                          A.lg, uwd, mv0, mv1, A.ub);
       hipLaunchKernelGGL(mw ? k_adj_gather<true> : k_adj_gather<false>, fg, b, 0, s, g, geo, mt, (const double*)A.lfd,
@@ -774,7 +777,7 @@ hipError_t adjoint_backward(Fields& F, AdjointBuffers& A, hipStream_t s, int K, 
       mt = A.tmom;
     else
       hipLaunchKernelGGL(k_adj_moments, fg, b, 0, s, g, pop, hist, geo, mom);
-    hipLaunchKernelGGL(mw ? k_adj_node<true> : k_adj_node<false>, fg, b, 0, s, g, 1, pop, hist, geo, mt, tau,
+    hipLaunchKernelGGL(mw ? k_adj_node<true> : k_adj_node<false>, ng, nb, 0, s, g, 1, pop, hist, geo, mt, tau,
                        (const double*)A.lf[cur], (const double*)A.lp[cur], A.lfd, A.lml, A.ldj, (double*)nullptr,
                        A.lg, uwd, mv0, mv1, A.ub);
     hipLaunchKernelGGL(mw ? k_adj_gather<true> : k_adj_gather<false>, fg, b, 0, s, g, geo, mt, (const double*)A.lfd,

@@ -261,6 +261,9 @@ int lbm_forward_record(lbm_ctx* ctx, int K, int ckpt_every, int wall, int method
  * independent input (the history F(x,-1) is recomputed from f0 and the chart).
  * A moving wall's Cartesian velocity is a constant; its chart components
  * J^{-1} v depend on the chart and are differentiated.
+ * ESTATE unless lbm_forward_record ran since the last call that changes the
+ * state or the fields it stepped with (every lbm_set_* call except
+ * lbm_set_tuning, lbm_init_equilibrium, lbm_step, lbm_reserve_adjoint).
  * The context's state stays the one lbm_forward_record ended with.
  * Synchronising. */
 int lbm_backward(lbm_ctx* ctx, const double* d_dL_dF, double* d_grad_disp, double* d_grad_chart,

@@ -237,6 +237,7 @@ int lbm_destroy(lbm_ctx* c) {
 
 int lbm_set_body_force(lbm_ctx* c, const double* F) {
   LBM_GUARD(c);
+  c->recorded = 0;  // a recorded trajectory no longer matches the fields
   if (!F || !std::isfinite(F[0]) || !std::isfinite(F[1]) || !std::isfinite(F[2]))
     return fail(c, LBM_EINVAL, "body force must be 3 finite numbers");
   for (int a = 0; a < 3; ++a) c->Fc[a] = F[a];
@@ -251,6 +252,7 @@ int lbm_set_body_force(lbm_ctx* c, const double* F) {
 
 int lbm_set_metric(lbm_ctx* c, const double* d_chart, int reproject) {
   LBM_GUARD(c);
+  c->recorded = 0;  // a recorded trajectory no longer matches the fields
   if (!d_chart) return fail(c, LBM_EINVAL, "chart is NULL");
   if (reproject && !c->have_state) return fail(c, LBM_ESTATE, "re-projection needs a state");
   LBM_HIP(c, hipMemcpyAsync(c->F.chart, d_chart, sizeof(double) * 3 * c->F.NC, hipMemcpyDeviceToDevice, c->stream));
@@ -259,6 +261,7 @@ int lbm_set_metric(lbm_ctx* c, const double* d_chart, int reproject) {
 
 int lbm_set_wall_displacement(lbm_ctx* c, int wall, const double* d_disp, int reproject) {
   LBM_GUARD(c);
+  c->recorded = 0;  // a recorded trajectory no longer matches the fields
   if (wall != LBM_WALL_YMIN && wall != LBM_WALL_YMAX) return fail(c, LBM_EINVAL, "bad wall");
   if (reproject && !c->have_state) return fail(c, LBM_ESTATE, "re-projection needs a state");
   const size_t ncol = (size_t)c->F.g.nz * c->F.g.nx;
@@ -273,6 +276,7 @@ int lbm_set_wall_displacement(lbm_ctx* c, int wall, const double* d_disp, int re
 
 int lbm_set_wall_velocity(lbm_ctx* c, int wall, const double* d_vcart) {
   LBM_GUARD(c);
+  c->recorded = 0;  // a recorded trajectory no longer matches the fields
   if (wall != LBM_WALL_YMIN && wall != LBM_WALL_YMAX) return fail(c, LBM_EINVAL, "bad wall");
   const size_t n = (size_t)c->F.g.nz * c->F.g.nx * 3;
   double* dst = c->F.vwall + (size_t)wall * n;
@@ -292,6 +296,7 @@ int lbm_set_wall_velocity(lbm_ctx* c, int wall, const double* d_vcart) {
 
 int lbm_set_plate(lbm_ctx* c, int jp, int i0, int i1) {
   LBM_GUARD(c);
+  c->recorded = 0;  // a recorded trajectory no longer matches the fields
   Fields& F = c->F;
   if (jp == 0) {
     F.g.pj = 0;
@@ -321,6 +326,7 @@ int lbm_set_plate(lbm_ctx* c, int jp, int i0, int i1) {
 
 int lbm_set_plate_displacement(lbm_ctx* c, const double* d_disp, int reproject) {
   LBM_GUARD(c);
+  c->recorded = 0;  // a recorded trajectory no longer matches the fields
   if (!c->F.g.pj) return fail(c, LBM_ESTATE, "no plate");
   if (reproject && !c->have_state) return fail(c, LBM_ESTATE, "re-projection needs a state");
   const size_t ncol = (size_t)c->F.g.nz * c->F.g.nx;
@@ -334,6 +340,7 @@ int lbm_set_plate_displacement(lbm_ctx* c, const double* d_disp, int reproject) 
 
 int lbm_set_plate_velocity(lbm_ctx* c, const double* d_vcart) {
   LBM_GUARD(c);
+  c->recorded = 0;  // a recorded trajectory no longer matches the fields
   if (!c->F.g.pj) return fail(c, LBM_ESTATE, "no plate");
   const size_t n = (size_t)c->F.g.nz * c->F.g.nx * 3;
   if (d_vcart)
@@ -363,6 +370,7 @@ int lbm_plate_force(lbm_ctx* c, double* d_total3, double* d_per_column) {
 
 int lbm_set_open_x(lbm_ctx* c, const double* d_uin) {
   LBM_GUARD(c);
+  c->recorded = 0;  // a recorded trajectory no longer matches the fields
   Fields& F = c->F;
   if (c->have_state) return fail(c, LBM_ESTATE, "set the ends before the state");
   if (!d_uin) {

@@ -110,6 +110,32 @@ def test_adjoint_rejects_fp32():
     assert e.value.code == -6
 
 
+def test_backward_refuses_a_changed_setup():
+    """A setter between forward_record and backward invalidates the recording
+    (its checkpoints were taken with the old fields): ESTATE, until the next
+    forward_record."""
+    lbm = _lbm()
+    nx, ny, nz, tau, K, N = 8, 6, 4, 0.8, 4, 2
+    S = lbm.Solver(nx, ny, nz, tau, "fp64", adjoint_K=K, ckpt_every=N)
+    S.set_wall_displacement(1, np.zeros((nz, nx)))
+    S.init_equilibrium()
+    W = np.ones((K, 3))
+    changes = [
+        lambda: S.set_body_force((1e-5, 0.0, 0.0)),
+        lambda: S.set_wall_displacement(1, np.full((nz, nx), 0.1)),
+        lambda: S.set_wall_velocity(0, np.full((nz, nx, 3), 1e-3)),
+    ]
+    for change in changes:
+        S.forward_record(K)
+        change()
+        with pytest.raises(lbm.LBMError) as e:
+            S.backward(W)
+        assert e.value.code == -4
+    S.forward_record(K)
+    gd, _, gf = S.backward(W)
+    assert torch.isfinite(gd).all() and torch.isfinite(gf).all()
+
+
 def test_moving_wall_adjoint_matches_forward_mode_derivatives():
     """Both walls moving with seeded Cartesian velocities (halfway bounce-back
     with the moving-wall momentum term, and the gradient ghost 2 rho u_w - j,

@@ -279,6 +279,7 @@ class Solver:
         if adjoint_K:
             lbm_reserve_adjoint(self.ctx, adjoint_K, ckpt_every)
         self.adjoint_K, self.ckpt_every = adjoint_K, ckpt_every
+        self.recordings = 0  # forward_record calls so far
 
     def __del__(self):
         ctx = getattr(self, "ctx", None)
@@ -406,6 +407,7 @@ class Solver:
         backward(); returns the wall forces of states 1..K, [K, 3]."""
         forces = torch.empty((K, 3), dtype=torch.float64, device=self.device)
         lbm_forward_record(self.ctx, K, self.ckpt_every, wall, forces)
+        self.recordings += 1
         return forces
 
     def backward(self, dLdF, need_disp=True, need_chart=False, need_f0=True):
@@ -447,8 +449,10 @@ for _name, _fn in list(vars(Solver).items()):
 class WallForceFn(torch.autograd.Function):
     """forces[K, 3] = wall forces of states 1..K after setting the top-wall
     displacement d [nz, nx] and the initial populations f0 [19, nz, H, nx] on
-    `solver` (FP64; walls at rest or moving with the velocities set on it).  backward returns (dL/dd, dL/df0); f0 is an
-    independent input (its forcing history is recomputed from it)."""
+    `solver` (FP64; walls at rest or moving with the velocities set on it).
+    backward returns (dL/dd, dL/df0); f0 is an independent input (its forcing
+    history is recomputed from it).  The solver keeps one recording: backward
+    raises if another forward_record ran on it since this forward."""
 
     @staticmethod
     def forward(ctx, d, f0, solver, K, wall=LBM_WALL_YMAX):
@@ -456,9 +460,13 @@ class WallForceFn(torch.autograd.Function):
         solver.set_populations(f0.detach())
         forces = solver.forward_record(K, wall)
         ctx.solver = solver
+        ctx.recording = solver.recordings
         return forces
 
     @staticmethod
     def backward(ctx, gF):
+        if ctx.solver.recordings != ctx.recording:
+            raise RuntimeError("WallForceFn: the solver recorded another trajectory since this forward; "
+                               "its adjoint is no longer available")
         gd, _, gf = ctx.solver.backward(gF.contiguous(), need_disp=True, need_chart=False, need_f0=True)
         return gd, gf, None, None, None

@@ -101,6 +101,14 @@ def test_autograd_function():
     assert abs(adj - exact) < 1e-9 * abs(exact)
     assert ft.grad is not None and torch.isfinite(ft.grad).all()
 
+    # a second forward on the same solver replaces the recording: the first
+    # graph's backward raises instead of returning the second's gradient
+    f1 = lbm.WallForceFn.apply(dt, ft, S, K)
+    f2 = lbm.WallForceFn.apply(dt, ft, S, K)
+    with pytest.raises(RuntimeError, match="recorded another trajectory"):
+        f1[:, 0].sum().backward()
+    f2[:, 0].sum().backward()
+
 
 def test_adjoint_rejects_fp32():
     lbm = _lbm()

@@ -494,10 +494,17 @@ def test_wall_force_flat_poiseuille():
         assert abs(fx - F * (H - 1) / 2) < 1e-10 * F * H
 
 
-def test_dual_derivative_matches_finite_differences():
+@pytest.mark.parametrize("moving", [False, True])
+def test_dual_derivative_matches_finite_differences(moving):
     """The forward-mode derivative used to check the adjoint agrees with FP64
-    central differences of the plain oracle along a random direction."""
+    central differences of the plain oracle along a random direction, with
+    the walls at rest and with both walls moving (whose chart components
+    J^-1 v change with the displacement)."""
     nx, ny, nz, tau, K = 6, 7, 4, 0.7, 6
+    vw = None
+    if moving:
+        vw = np.stack([synth.random_perturbation((nz, nx, 3), 1e-2, 21),
+                       synth.random_perturbation((nz, nx, 3), 1e-2, 22)])
     H = ny - 2
     F = [1e-4, 0, 0]
     d = synth.gaussian_random_field(nx, nz, corr=2.0, max_abs=0.4, seed=9)
@@ -507,11 +514,13 @@ def test_dual_derivative_matches_finite_differences():
     f0 = o.populations()
     dd = synth.random_unit(d.shape, 10)
     df = synth.random_unit(f0.shape, 11) * 1e-2
-    forces, dforces = dual_forces(nx, ny, nz, tau, F, d, dd, f0, df, K)
-    assert np.abs(forces - run_forces(nx, ny, nz, tau, F, d, f0, K)).max() < 1e-15
+    forces, dforces = dual_forces(nx, ny, nz, tau, F, d, dd, f0, df, K, vwall=vw)
+    assert np.abs(forces - run_forces(nx, ny, nz, tau, F, d, f0, K, vwall=vw)).max() < 1e-15
+    if moving:
+        assert np.abs(forces - run_forces(nx, ny, nz, tau, F, d, f0, K)).max() > 1e-6
     eps = 1e-6
-    fp = run_forces(nx, ny, nz, tau, F, d + eps * dd, f0 + eps * df, K)
-    fm = run_forces(nx, ny, nz, tau, F, d - eps * dd, f0 - eps * df, K)
+    fp = run_forces(nx, ny, nz, tau, F, d + eps * dd, f0 + eps * df, K, vwall=vw)
+    fm = run_forces(nx, ny, nz, tau, F, d - eps * dd, f0 - eps * df, K, vwall=vw)
     fd = (fp - fm) / (2 * eps)
     scale = np.abs(dforces).max()
     assert scale > 1e-8

@@ -131,13 +131,20 @@ int lbm_set_metric(lbm_ctx* ctx, const double* d_chart, int reproject);
  * lbm_set_metric. */
 int lbm_set_wall_displacement(lbm_ctx* ctx, int wall, const double* d_disp, int reproject);
 
-/* Cartesian velocity of a wall ([nz][nx][3], NULL = at rest).  It enters the
- * halfway bounce-back as the moving-wall term and the momentum ghost of the
- * lattice gradient, in chart components J^{-1} v at the adjacent fluid node. */
+/* Cartesian velocity of a wall ([nz][nx][3], NULL = at rest; Sec. IV.A.2:
+ * the shell's velocity is transformed to the chart, Eq. (vector_transform),
+ * and imposed on the fluid at the wall).  It enters the halfway bounce-back
+ * as the moving-wall term and the momentum ghost of the lattice gradient, in
+ * chart components J^{-1} v at the adjacent fluid node.  The velocity holds
+ * until set again; EINVAL for a bad wall.  A NULL clears it with a kernel
+ * (capture-safe). */
 int lbm_set_wall_velocity(lbm_ctx* ctx, int wall, const double* d_vcart);
 
-/* Initial state f = f_eq(rho, u) with u = J^{-1} u_cart (rho NULL = 1, u NULL
- * = 0); the forcing history is set to the forcing of this state. */
+/* Initial state f = f_eq(rho, u) (Eq. expansion-equilibrium truncated at
+ * second order, App. B) with u = J^{-1} u_cart; d_rho [fluid] (NULL = 1) and
+ * d_ucart [3][fluid] (NULL = 0) are FP64 device arrays.  The forcing history
+ * F(x, -1) is set to the forcing of this state (Eqs. forcing-A/B/C).  ESTATE
+ * before a metric is set. */
 int lbm_init_equilibrium(lbm_ctx* ctx, const double* d_rho, const double* d_ucart);
 
 /* Set / read the populations f_l(x,t) (FP64, full values).  Setting recomputes
@@ -150,7 +157,12 @@ int lbm_get_populations(lbm_ctx* ctx, double* d_f);
 int lbm_get_history(lbm_ctx* ctx, double* d_coef);
 int lbm_get_geometry(lbm_ctx* ctx, double* d_geo28, double* d_jac9);
 
-/* Advance n >= 0 steps (collision, streaming, bounce-back, history update). */
+/* Advance n >= 0 steps: collision, Eq. (collision), with the equilibrium of
+ * Eq. (expansion-equilibrium) and the forcing of Eq. (forcing2); streaming,
+ * Eq. (streaming), with halfway bounce-back at the walls (and the plate) and
+ * the moving-wall term; update of the forcing history.  Asynchronous (the
+ * instability guard is reported at the next sync point).  EINVAL for n < 0,
+ * ESTATE before a state exists. */
 int lbm_step(lbm_ctx* ctx, int n);
 
 /* rho = sqrt g sum f, u = (sqrt g sum f c)/rho (Eqs. fields1-2); u in chart

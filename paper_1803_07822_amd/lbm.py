@@ -414,7 +414,13 @@ class Solver:
         """Adjoint of the last forward_record for dL/dF [K, 3]: returns
         (dL/d top-wall displacement [nz, nx], dL/d chart [3, nz, ny, nx],
         dL/d f0 [19, nz, H, nx]); entries not asked for are None."""
+        if not self.adjoint_K:
+            raise ValueError("backward needs a solver created with adjoint_K > 0")
+        # the library reads K x 3 doubles: a tensor of another size is refused here
         g = self._dev(dLdF)
+        if g.numel() != 3 * self.adjoint_K:
+            raise ValueError(f"dL/dF must hold [{self.adjoint_K}, 3] values, got {tuple(g.shape)}")
+        g = g.reshape(self.adjoint_K, 3)
         gd = torch.empty((self.nz, self.nx), dtype=torch.float64, device=self.device) if need_disp else None
         gc = torch.empty((3, self.nz, self.ny, self.nx), dtype=torch.float64, device=self.device) if need_chart else None
         gf = torch.empty((19,) + self.fluid_shape, dtype=torch.float64, device=self.device) if need_f0 else None

@@ -118,6 +118,22 @@ def test_adjoint_rejects_fp32():
     assert e.value.code == -6
 
 
+def test_backward_refuses_a_wrongly_sized_gradient():
+    """Solver.backward hands the library a [K, 3] dL/dF (the library reads K x 3
+    doubles): a tensor with another number of entries is refused on the host."""
+    lbm = _lbm()
+    nx, ny, nz, tau, K, N = 8, 6, 4, 0.8, 4, 2
+    S = lbm.Solver(nx, ny, nz, tau, "fp64", adjoint_K=K, ckpt_every=N)
+    S.set_wall_displacement(1, np.zeros((nz, nx)))
+    S.init_equilibrium()
+    S.forward_record(K)
+    for bad in (np.ones((K - 1, 3)), np.ones(3 * K + 1)):
+        with pytest.raises(ValueError):
+            S.backward(bad)
+    gd, _, _ = S.backward(np.ones(3 * K))  # a flat array of the right size is taken as [K, 3]
+    assert torch.isfinite(gd).all()
+
+
 def test_backward_refuses_a_changed_setup():
     """A setter between forward_record and backward invalidates the recording
     (its checkpoints were taken with the old fields): ESTATE, until the next

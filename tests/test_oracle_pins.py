@@ -226,6 +226,67 @@ def test_curved_poiseuille_second_order(name):
     assert e[2] < 1e-3, e
 
 
+def _couette(chart_fn, H, tau=1.0, Ut=1e-2, Ub=-4e-3, decay=7.0):
+    """Plane Couette flow along x between halfway walls sliding at the
+    Cartesian velocities Ub (bottom) and Ut (top), in a chart of the flat
+    channel that keeps both walls at fixed y.  Started from the exact profile
+    u = Ub + (Ut - Ub)(y - y0)/(y1 - y0) and run `decay` e-folding times of the
+    slowest shear mode.  Returns the max errors of the Cartesian u_x and of
+    the other components, relative to Ut."""
+    nx = 2 * H if chart_fn is _x_stretch else 2
+    ny, nz = H + 2, 1
+    ch = chart_fn(nx, ny, nz, H)
+    o = Oracle(nx, ny, nz, tau)
+    o.set_metric(ch)
+    for wall, U in ((0, Ub), (1, Ut)):
+        vw = np.zeros((nz, nx, 3))
+        vw[..., 0] = U
+        o.set_wall_velocity(wall, vw)
+    y0, y1 = 0.5, ny - 1.5  # halfway walls (the chart keeps y = xi_y)
+    ua = Ub + (Ut - Ub) * (ch[1][:, 1:-1, :] - y0) / (y1 - y0)
+    uc = np.zeros((3, nz, H, nx))
+    uc[0] = ua
+    o.init_equilibrium(None, uc)
+    nu = (tau - 0.5) / 3
+    o.step(int(decay / (nu * (np.pi / H) ** 2)))
+    _, u = o.moments(cartesian=True)
+    return np.abs(u[0] - ua).max() / Ut, np.abs(u[1:]).max() / Ut
+
+
+def _x_stretch(nx, ny, nz, H, a=0.15):
+    """x_c = xi_x + a (H/8) sin(2 pi xi_x / nx) with nx = 2H: a stretch along
+    the walls of fixed shape (J_xx = 1 + 0.15 (2 pi / 16) cos, Gamma^x_xx != 0)."""
+    ch = synth.identity_chart(nx, ny, nz)
+    ch[0] += a * (H / 8.0) * np.sin(2 * np.pi * ch[0] / nx)
+    return ch
+
+
+def test_couette_affine_shear_exact():
+    """Couette flow in the affine shear x_c = xi_x + 0.3 eta (constant J with
+    J^x_y = 0.3, Gamma = 0): a linear profile is reproduced exactly, to
+    rounding, only if the Cartesian wall velocity v enters the bounce-back in
+    the chart components u_w = J^-1 v (Sec. IV.A.2: the shell velocity is
+    transformed to the LBM chart before it is imposed).  Taking the transpose
+    of J^-1 there gives the walls a normal chart velocity of -0.3 v and an
+    O(1e-1) error."""
+    for H in (8, 16):
+        ex, en = _couette(lambda nx, ny, nz, H: _affine_shear(nx, ny, nz, H, 0.3), H)
+        assert ex < 1e-12 and en < 1e-12, (H, ex, en)
+
+
+def test_couette_stretch_converges():
+    """Couette flow in a chart stretched along the walls (fixed shape, H = 8,
+    16): the Cartesian profile converges to the linear one, the error about
+    halving per doubling (the first-order wall-layer error of halfway
+    bounce-back where the metric varies along the wall).  A wall velocity
+    imposed without J^-1 moves the wall at J_xx v in Cartesian terms, a 6 %
+    ripple that does not fall with resolution."""
+    e = [_couette(_x_stretch, H) for H in (8, 16)]
+    print("stretched Couette errors (u_x, other components)", e)
+    assert e[1][0] < e[0][0] / 1.8 and e[1][1] < e[0][1] / 1.7, e
+    assert e[1][0] < 3e-3 and e[1][1] < 5e-3, e
+
+
 def test_sheared_poiseuille_pressure_residual():
     """A shear that varies across the channel, x_c = xi_x + eps H sin(pi eta/H)
     (non-orthogonal, with Gamma^x_yy = s'' != 0 for the shift s(eta)).  The
@@ -441,6 +502,39 @@ def test_reprojection_carries_linear_fields_exactly():
     ref.set_wall_displacement(1, d2)
     ref.init_equilibrium(1 + a * synth.chart_from_displacement(nx, ny, nz, d2)[1][:, 1:-1, :], None)
     assert np.abs(o.populations() - ref.populations()).max() < 1e-15
+
+
+def test_reprojection_sliding_wall_ghost_closed_form():
+    """Fluid at rest between walls sliding at Cartesian velocities (Ub, 0, Wb)
+    and (Ut, 0, Wt); the top wall is lifted by dt = 0.3 and the bottom wall
+    lowered by db = -0.2 with re-projection (Sec. IV.B).  Each new wall row
+    lies between the old wall row and the ghost layer, whose momentum is the
+    mirror 2 rho v_w - j of the row about the wall velocity, so the
+    interpolated momentum there is in closed form: u = 2 v_t s_t at the top
+    row with s_t = (H - 1/2) dt / H + db / (2H), u = 2 v_b s_b at the bottom
+    row with s_b = -(1 - 1/(2H)) db - dt / (2H), and zero in between (all
+    rows interpolate between nodes at rest).  A ghost extrapolated like the
+    other moments would give zero everywhere."""
+    nx, ny, nz = 6, 10, 4
+    H = ny - 2
+    dt, db = 0.3, -0.2
+    vt, vb = np.array([1e-2, 0.0, -3e-3]), np.array([-4e-3, 0.0, 2e-3])
+    o = Oracle(nx, ny, nz, 0.8)
+    o.set_wall_displacement(1, np.zeros((nz, nx)))
+    o.set_wall_velocity(0, np.broadcast_to(vb, (nz, nx, 3)))
+    o.set_wall_velocity(1, np.broadcast_to(vt, (nz, nx, 3)))
+    o.init_equilibrium()
+    ch = synth.chart_from_displacement(nx, ny, nz, np.full((nz, nx), dt), np.full((nz, nx), db))
+    o.set_metric(ch, reproject=True)  # both walls move in one chart change
+    rho, u = o.moments(cartesian=True)
+    st = (H - 0.5) * dt / H + db / (2 * H)
+    sb = -(1 - 1 / (2 * H)) * db - dt / (2 * H)
+    ua = np.zeros((3, nz, H, nx))
+    ua[:, :, -1, :] = 2 * st * vt[:, None, None]
+    ua[:, :, 0, :] = 2 * sb * vb[:, None, None]
+    assert np.abs(rho - 1).max() < 1e-15
+    assert np.abs(u - ua).max() < 1e-15, np.abs(u - ua).max()
+    assert abs(ua[0, 0, -1, 0] - 2 * 0.26875 * 1e-2) < 1e-17  # the worked numbers for H = 8
 
 
 def test_mirror_symmetry_of_bump_channel():

@@ -11,7 +11,7 @@ struct AdjointBuffers {
   double* tmom = nullptr;  // [ckpt_every][4][N] rho, rho u of the segment's states, from the recompute steps
   double* lf[2] = {nullptr, nullptr};  // [19][N] adjoint of f (current / next)
   double* lp[2] = {nullptr, nullptr};  // [10][N] adjoint of the history coefficients
-  double* lfd = nullptr;   // [19][N] direct part of the f adjoint
+  double* lpb = nullptr;   // [6][N]  adjoint of the non-equilibrium flux P (direct part of the f adjoint)
   double* lml = nullptr;   // [4][N]  local adjoint of (rho, j)
   double* ldj = nullptr;   // [9][N]  adjoint of the lattice gradient
   double* lg = nullptr;    // [28][N] adjoint of the stored geometry fields
@@ -39,7 +39,7 @@ inline void carve_adjoint(Carver& c, const Grid& g, int K, int N, AdjointBuffers
     A.lf[b] = (double*)c.take(sizeof(double) * 19 * Nn);
     A.lp[b] = (double*)c.take(sizeof(double) * H_N * Nn);
   }
-  A.lfd = (double*)c.take(sizeof(double) * 19 * Nn);
+  A.lpb = (double*)c.take(sizeof(double) * 6 * Nn);
   A.lml = (double*)c.take(sizeof(double) * 4 * Nn);
   A.ldj = (double*)c.take(sizeof(double) * 9 * Nn);
   A.lg = (double*)c.take(sizeof(double) * G_N * Nn);

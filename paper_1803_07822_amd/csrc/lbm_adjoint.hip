@@ -170,53 +170,123 @@ __global__ __launch_bounds__(BX * BY) void k_adj_moments(Grid g, const double* _
   for (int a = 0; a < 3; ++a) E(mom, (1 + a), g, p.n) = G.sg * j[a];
 }
 
+// Adjoint s_l of f*_l at node p: f*_l(p) streamed to p + c_l, or bounced back
+// into direction opp(l) at p across a wall.  lfn is the adjoint of the
+// populations of the next state.
+template <int l>
+__device__ __forceinline__ double streamed_adjoint(const Grid& g, const double* __restrict__ lfn, const Node& p) {
+  constexpr int x = cx(l), y = cy(l), z = cz(l);
+  constexpr int lo = l < opp(l) ? l : opp(l);
+  const int jd = p.jf + y;
+  const unsigned ed = nidx(g, wrapa(p.i + x, g.nx), jd, wrapa(p.k + z, g.nz));
+  return E(lfn, lo, g,
+           (jd >= 0 && jd < g.H) ? (unsigned)(l - lo) * (unsigned)g.N + ed : (unsigned)(opp(l) - lo) * (unsigned)g.N + p.n);
+}
+
 // Reverse of one step at each node (mode 0), or of the history of an initial
-// state (mode 1: only the new coefficients carry an adjoint).
+// state (mode 1: only the new coefficients carry an adjoint).  The adjoints
+// of the next state's populations enter through their Hermite basis sums; the
+// direct adjoint of f is formed by the gather from lpb (the adjoint of the
+// non-equilibrium flux P) and the same streamed adjoints.
 // MW: some wall moves (walls at rest compile the moving-wall terms out).
 template <bool MW>
-__global__ __launch_bounds__(BX * BY) void k_adj_node(Grid g, int mode, const double* __restrict__ pop, const double* __restrict__ hist,
+__global__ __launch_bounds__(BX) void k_adj_node(Grid g, int mode, const double* __restrict__ pop, const double* __restrict__ hist,
                            const double* __restrict__ geo, const double* __restrict__ mom, double tau,
-                           const double* __restrict__ lfn, const double* __restrict__ lpn, double* __restrict__ lfd,
+                           const double* __restrict__ lfn, const double* __restrict__ lpn, double* __restrict__ lpb,
                            double* __restrict__ lml, double* __restrict__ ldj, double* __restrict__ lpo,
                            double* __restrict__ lg, const double* __restrict__ uw, int mv0, int mv1,
                            double* __restrict__ ub) {
   Node p;
   if (!fluid_node(g, p)) return;
+  const double th = 1.0 / 3.0;
+  const bool with_old = mode == 0;
+  // the geometry adjoint of the node is summed in LDS (one column of slots
+  // per lane): it is added to from every stage of the reverse sweep
+  __shared__ double gbs[G_N][BX];
+#pragma unroll
+  for (int q = 0; q < G_N; ++q) gbs[q][threadIdx.x] = 0.0;
+  LdsGeoBar gb{&gbs[0][threadIdx.x], BX};
   AGeo G;
   load_geo_full(g, geo, p.n, G);
-  double f[Q], Fp[10], dj[3][3];
-  load_state(g, pop, hist, G, p, f, Fp);
-  gradient_at(g, mom, p, uw, MW && mv0, MW && mv1, dj);
-  const bool with_old = mode == 0;
+  // forward: the moments of the state come from mom; the populations are
+  // read once, for the non-equilibrium flux P, and not kept
   NodeFwd o;
-  node_fwd(f, Fp, G, dj, tau, with_old, o);
-  double fsb[Q], Fb[Q], cb[10];
-  // transposed streaming: f*_l(x) went to x + c_l (or bounced back into
-  // direction opp(l) at x); F_l(x)/2 was added to f_l(x, t+1).
+  o.isg = 1.0 / G.sg;
+  o.rho = E(mom, 0, g, p.n);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) o.j[a] = E(mom, (1 + a), g, p.n);
+  o.S0 = o.rho * o.isg;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) o.S1[a] = o.j[a] * o.isg;
+  {
+    const double ir = 1.0 / o.rho;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = a; b < 3; ++b)
+        o.a2[sym(a, b)] = o.rho * th * (G.gi[sym(a, b)] - (a == b ? 1.0 : 0.0)) + o.j[a] * o.j[b] * ir;
+  }
+  double Fp[10];
+#pragma unroll
+  for (int q = 0; q < 10; ++q) Fp[q] = E(hist, q, g, p.n);
+#pragma unroll
+  for (int q = 0; q < 6; ++q) o.bp[q] = Fp[4 + q];
+  o.bp[0] -= th * Fp[0];
+  o.bp[3] -= th * Fp[0];
+  o.bp[5] -= th * Fp[0];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) o.P[q] = 0;
   for_q([&](auto L) {
     constexpr int l = decltype(L)::value;
     constexpr int x = cx(l), y = cy(l), z = cz(l);
-    fsb[l] = 0;
-    Fb[l] = 0;
-    if (with_old) {
-      constexpr int lo = l < opp(l) ? l : opp(l);
-      const int jd = p.jf + y;
-      const unsigned ed = nidx(g, wrapa(p.i + x, g.nx), jd, wrapa(p.k + z, g.nz));
-      fsb[l] = E(lfn, lo, g,
-                 (jd >= 0 && jd < g.H) ? (unsigned)(l - lo) * (unsigned)g.N + ed
-                                       : (unsigned)(opp(l) - lo) * (unsigned)g.N + p.n);
-      Fb[l] = 0.5 * E(lfn, l, g, p.n);
-    }
+    constexpr int lo = l < opp(l) ? l : opp(l);
+    const bool wall = (y > 0 && p.jf == 0) || (y < 0 && p.jf == g.H - 1);
+    const unsigned es = nidx(g, wrapa(p.i - x, g.nx), p.jf - y, wrapa(p.k - z, g.nz));
+    const double v = E(pop, lo, g, wall ? (unsigned)(opp(l) - lo) * (unsigned)g.N + p.n : (unsigned)(l - lo) * (unsigned)g.N + es);
+    const double ne = wgt(l) + v + 0.5 * hermite_val<l>(o.isg, Fp[0], Fp + 1, o.bp) - hermite_val<l>(o.isg, o.rho, o.j, o.a2);
+    if (x) o.P[0] += ne;
+    if (y) o.P[3] += ne;
+    if (z) o.P[5] += ne;
+    if (x && y) o.P[1] += (x * y) * ne;
+    if (x && z) o.P[2] += (x * z) * ne;
+    if (y && z) o.P[4] += (y * z) * ne;
   });
+  // adjoint of the next state's populations, through their basis sums:
+  // f*_l(x) went to x + c_l (or bounced back into direction opp(l) at x);
+  // F_l(x)/2 was added to f_l(x, t+1)
+  HSum hs, hb;
+  hsum_zero(hs);
+  hsum_zero(hb);
+  if (with_old) {
+    for_q([&](auto L) {
+      constexpr int l = decltype(L)::value;
+      hsum_add<l>(hs, streamed_adjoint<l>(g, lfn, p));
+      hsum_add<l>(hb, 0.5 * E(lfn, l, g, p.n));
+    });
+    // the old forcing F(t-1) = H(Fp) is reversed first, so that Fp dies here
+    HSum hFo;
+    hFo.s0 = -0.5 * hs.s0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) hFo.s1[a] = -0.5 * hs.s1[a];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) hFo.s2[q] = -0.5 * hs.s2[q];
+    double Fpb[10];
+#pragma unroll
+    for (int q = 0; q < 10; ++q) Fpb[q] = 0;
+    double sgo = 0;
+    old_forcing_vjp(hFo, o.isg, Fp, o.bp, Fpb, sgo);
+    gb.add_sg(sgo);
+#pragma unroll
+    for (int q = 0; q < 10; ++q) E(lpo, q, g, p.n) = Fpb[q];
+  }
+  double dj[3][3];
+  gradient_at(g, mom, p, uw, MW && mv0, MW && mv1, dj);
+  node_fwd_rest(Fp, G, dj, tau, false, o);
+  double cb[10];
 #pragma unroll
   for (int q = 0; q < 10; ++q) cb[q] = E(lpn, q, g, p.n);
-  double fb[Q], rb = 0, jb[3] = {0, 0, 0}, djb[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, Fpb[10];
-  for_q([&](auto L) { fb[decltype(L)::value] = 0; });
-#pragma unroll
-  for (int q = 0; q < 10; ++q) Fpb[q] = 0;
-  AGeoBar gb;
-  zero_bar(gb);
-  node_vjp(Fp, G, tau, with_old, o, fsb, Fb, cb, nullptr, fb, rb, jb, djb, Fpb, gb);
+  double rb = 0, jb[3] = {0, 0, 0}, djb[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, Pb[6];
+  node_vjp(nullptr, G, tau, with_old, o, hs, hb, cb, nullptr, Pb, rb, jb, djb, nullptr, gb);
   // moving walls: the bounce-back of a link into wall w loses
   // 6 (w_l / sqrt g) rho c_l . u_w (chart components u_w of the column)
   if (MW && with_old) {
@@ -231,7 +301,7 @@ __global__ __launch_bounds__(BX * BY) void k_adj_node(Grid g, int mode, const do
         constexpr int y = cy(l);
         if ((w == 1 && y > 0) || (w == 0 && y < 0)) {
           const double cu = cx(l) * u[0] + y * u[1] + cz(l) * u[2];
-          const double s = -6.0 * wgt(l) * fsb[l];
+          const double s = -6.0 * wgt(l) * streamed_adjoint<l>(g, lfn, p);
           rb += s * o.isg * cu;
           isgb += s * o.rho * cu;
           ubl[0] += s * o.isg * o.rho * cx(l);
@@ -239,15 +309,13 @@ __global__ __launch_bounds__(BX * BY) void k_adj_node(Grid g, int mode, const do
           ubl[2] += s * o.isg * o.rho * cz(l);
         }
       });
-      gb.sg -= isgb * o.isg * o.isg;
+      gb.add_sg(-isgb * o.isg * o.isg);
 #pragma unroll
       for (int a = 0; a < 3; ++a) ub[c + a] += ubl[a];
     }
   }
-  for_q([&](auto L) {
-    constexpr int l = decltype(L)::value;
-    E(lfd, l, g, p.n) = fb[l];
-  });
+#pragma unroll
+  for (int q = 0; q < 6; ++q) E(lpb, q, g, p.n) = Pb[q];
   E(lml, 0, g, p.n) = rb;
 #pragma unroll
   for (int a = 0; a < 3; ++a) E(lml, (1 + a), g, p.n) = jb[a];
@@ -255,21 +323,21 @@ __global__ __launch_bounds__(BX * BY) void k_adj_node(Grid g, int mode, const do
   for (int a = 0; a < 3; ++a)
 #pragma unroll
     for (int b = 0; b < 3; ++b) E(ldj, (a * 3 + b), g, p.n) = djb[a][b];
-  if (lpo)
 #pragma unroll
-    for (int q = 0; q < 10; ++q) E(lpo, q, g, p.n) = Fpb[q];
-  add_geo_bar(g, lg, p.n, gb);
+  for (int q = 0; q < G_N; ++q) E(lg, q, g, p.n) += gbs[q][threadIdx.x];
 }
 
 // Transposed lattice gradient and the moment VJP:
-// lf_out = lfd + sqrt g (rho_bar + j_bar . c) (+ lf_add), with
+// lf_out_l = (1 - 1/tau) s_l + pb_term_l(Pb) + sqrt g (rho_bar + j_bar . c_l)
+// (+ lf_add_l), with s_l the streamed adjoint of the next state's populations
+// lfn (none for the history of an initial state: lfn null) and
 // j_bar = local + sum over the stencil of the neighbours' dj adjoints.
 template <bool MW>
 __global__ __launch_bounds__(BX * BY) void k_adj_gather(Grid g, const double* __restrict__ geo, const double* __restrict__ mom,
-                             const double* __restrict__ lfd, const double* __restrict__ lml,
-                             const double* __restrict__ ldj, const double* __restrict__ lf_add,
-                             double* __restrict__ lf_out, double* __restrict__ lg, const double* __restrict__ uw,
-                             int mv0, int mv1, double* __restrict__ ub) {
+                             const double* __restrict__ lfn, double tau, const double* __restrict__ lpb,
+                             const double* __restrict__ lml, const double* __restrict__ ldj,
+                             const double* __restrict__ lf_add, double* __restrict__ lf_out, double* __restrict__ lg,
+                             const double* __restrict__ uw, int mv0, int mv1, double* __restrict__ ub) {
   Node p;
   if (!fluid_node(g, p)) return;
   double rb = E(lml, 0, g, p.n), jb[3] = {E(lml, 1, g, p.n), E(lml, 2, g, p.n), E(lml, 3, g, p.n)};
@@ -313,10 +381,17 @@ __global__ __launch_bounds__(BX * BY) void k_adj_gather(Grid g, const double* __
     for (int b = 0; b < 3; ++b) ub[c1 + b] += ub1[b];
   const double sg = 1.0 + E(geo, G_SG, g, p.n);
   const double S0 = rho / sg, S1[3] = {E(mom, 1, g, p.n) / sg, E(mom, 2, g, p.n) / sg, E(mom, 3, g, p.n) / sg};
+  double Pb[6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) Pb[q] = E(lpb, q, g, p.n);
+  const double keep = 1.0 - 1.0 / tau;
   double fb[Q];
   for_q([&](auto L) {
     constexpr int l = decltype(L)::value;
-    fb[l] = E(lfd, l, g, p.n) + (lf_add ? E(lf_add, l, g, p.n) : 0.0);
+    double v = pb_term<l>(Pb);
+    if (lfn) v += keep * streamed_adjoint<l>(g, lfn, p);
+    if (lf_add) v += E(lf_add, l, g, p.n);
+    fb[l] = v;
   });
   double sgb = 0;
   moments_vjp(sg, S0, S1, rb, jb, fb, sgb);
@@ -391,16 +466,19 @@ __global__ __launch_bounds__(BX * BY) void k_adj_force(Grid g, int wall, const d
     sgb += sgn * wj * o.T[sym(i, 1)];
     for (int a = 0; a < 3; ++a) E(lj, (a * 3 + i), g, p.n) += sgn * G.sg * W[a] * o.T[sym(i, 1)];
   }
-  double fsb[Q], Fb[Q], cb[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-  double fb[Q], rb = 0, jb[3] = {0, 0, 0}, djb[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, Fpb[10];
-  for_q([&](auto L) {
-    constexpr int l = decltype(L)::value;
-    fsb[l] = Fb[l] = fb[l] = 0;
-  });
+  HSum h0;
+  hsum_zero(h0);
+  double cb[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  double rb = 0, jb[3] = {0, 0, 0}, djb[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, Fpb[10], Pb[6];
   AGeoBar gb;
   zero_bar(gb);
   gb.sg = sgb;
-  node_vjp(Fp, G, tau, false, o, fsb, Fb, cb, Tb, fb, rb, jb, djb, Fpb, gb);
+  node_vjp(Fp, G, tau, false, o, h0, h0, cb, Tb, Pb, rb, jb, djb, Fpb, gb);
+  double fb[Q];
+  for_q([&](auto L) {
+    constexpr int l = decltype(L)::value;
+    fb[l] = pb_term<l>(Pb);
+  });
   moments_vjp(G.sg, o.S0, o.S1, rb, jb, fb, gb.sg);
   for_q([&](auto L) {
     constexpr int l = decltype(L)::value;
@@ -756,11 +834,11 @@ hipError_t adjoint_backward(Fields& F, AdjointBuffers& A, hipStream_t s, int K, 
       else
         hipLaunchKernelGGL(k_adj_moments, fg, b, 0, s, g, pop, hist, geo, mom);
       hipLaunchKernelGGL(mw ? k_adj_node<true> : k_adj_node<false>, ng, nb, 0, s, g, 0, pop, hist, geo, mt, tau,
-                         (const double*)A.lf[cur], (const double*)A.lp[cur], A.lfd, A.lml, A.ldj, A.lp[cur ^ 1],
+                         (const double*)A.lf[cur], (const double*)A.lp[cur], A.lpb, A.lml, A.ldj, A.lp[cur ^ 1],
                          A.lg, uwd, mv0, mv1, A.ub);
-      hipLaunchKernelGGL(mw ? k_adj_gather<true> : k_adj_gather<false>, fg, b, 0, s, g, geo, mt, (const double*)A.lfd,
-                         (const double*)A.lml, (const double*)A.ldj, (const double*)nullptr, A.lf[cur ^ 1], A.lg,
-                         uwd, mv0, mv1, A.ub);
+      hipLaunchKernelGGL(mw ? k_adj_gather<true> : k_adj_gather<false>, fg, b, 0, s, g, geo, mt,
+                         (const double*)A.lf[cur], tau, (const double*)A.lpb, (const double*)A.lml,
+                         (const double*)A.ldj, (const double*)nullptr, A.lf[cur ^ 1], A.lg, uwd, mv0, mv1, A.ub);
       cur ^= 1;
       if (t >= 1)
         hipLaunchKernelGGL(k_adj_force, cg, b, 0, s, g, wall, pop, hist, geo, (const double*)F.jac, tau,
@@ -778,11 +856,11 @@ hipError_t adjoint_backward(Fields& F, AdjointBuffers& A, hipStream_t s, int K, 
     else
       hipLaunchKernelGGL(k_adj_moments, fg, b, 0, s, g, pop, hist, geo, mom);
     hipLaunchKernelGGL(mw ? k_adj_node<true> : k_adj_node<false>, ng, nb, 0, s, g, 1, pop, hist, geo, mt, tau,
-                       (const double*)A.lf[cur], (const double*)A.lp[cur], A.lfd, A.lml, A.ldj, (double*)nullptr,
+                       (const double*)A.lf[cur], (const double*)A.lp[cur], A.lpb, A.lml, A.ldj, (double*)nullptr,
                        A.lg, uwd, mv0, mv1, A.ub);
-    hipLaunchKernelGGL(mw ? k_adj_gather<true> : k_adj_gather<false>, fg, b, 0, s, g, geo, mt, (const double*)A.lfd,
-                       (const double*)A.lml, (const double*)A.ldj, (const double*)A.lf[cur], A.lf[cur ^ 1], A.lg,
-                       uwd, mv0, mv1, A.ub);
+    hipLaunchKernelGGL(mw ? k_adj_gather<true> : k_adj_gather<false>, fg, b, 0, s, g, geo, mt,
+                       (const double*)nullptr, tau, (const double*)A.lpb, (const double*)A.lml,
+                       (const double*)A.ldj, (const double*)A.lf[cur], A.lf[cur ^ 1], A.lg, uwd, mv0, mv1, A.ub);
     cur ^= 1;
   }
   if (grad_f0) HCHK(hipMemcpyAsync(grad_f0, A.lf[cur], sizeof(double) * 19 * Nn, hipMemcpyDeviceToDevice, s));

@@ -27,8 +27,31 @@ struct AGeo {
   double sg, gi[6], gam[18], F[3];  // sqrt g, g^ij (full), Gamma, F^i
 };
 
+// Adjoint of the geometry of one node, accumulated in registers.  The VJPs
+// add into it through add_* so that an accumulator in LDS (LdsGeoBar) can
+// stand in for it where registers are short.
 struct AGeoBar {
   double sg, gi[6], gam[18], F[3];
+  __device__ __forceinline__ void add_sg(double v) { sg += v; }
+  __device__ __forceinline__ void add_gi(int q, double v) { gi[q] += v; }
+  __device__ __forceinline__ void add_gam(int q, double v) { gam[q] += v; }
+  __device__ __forceinline__ void add_F(int i, double v) { F[i] += v; }
+};
+
+// The same accumulator in LDS: 28 slots per lane at base[slot * stride], each
+// addition one LDS atomic add (no return value), so that no register holds
+// the 28 sums between the additions.  Slot order: sqrt g, g^ij (6), Gamma
+// (18), F^i (3).
+struct LdsGeoBar {
+  double* base;
+  int stride;
+  __device__ __forceinline__ void add(int slot, double v) {
+    __hip_atomic_fetch_add(base + slot * stride, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+  __device__ __forceinline__ void add_sg(double v) { add(0, v); }
+  __device__ __forceinline__ void add_gi(int q, double v) { add(1 + q, v); }
+  __device__ __forceinline__ void add_gam(int q, double v) { add(7 + q, v); }
+  __device__ __forceinline__ void add_F(int i, double v) { add(25 + i, v); }
 };
 
 // Basis sums of an adjoint hb_l over the directions (lattice weight included,
@@ -97,6 +120,9 @@ struct NodeFwd {
   double bp[6];
 };
 
+__device__ __forceinline__ void node_fwd_rest(const double Fp[10], const AGeo& G, const double dj[3][3], double tau,
+                                              bool with_old, NodeFwd& o);
+
 // Forward of one node.  with_old: include the F(t-1) term (false for the
 // history of an initial state, which only needs A, B, C).
 __device__ __forceinline__ void node_fwd(const double f[Q], const double Fp[10], const AGeo& G, const double dj[3][3],
@@ -135,6 +161,15 @@ __device__ __forceinline__ void node_fwd(const double f[Q], const double Fp[10],
     if (x && z) o.P[2] += (x * z) * ne;
     if (y && z) o.P[4] += (y * z) * ne;
   });
+  node_fwd_rest(Fp, G, dj, tau, with_old, o);
+}
+
+// The rest of the forward of one node, from o.isg, o.rho, o.j, o.a2 and o.P:
+// the stress T, the forcing coefficients and the old forcing's b2.
+__device__ __forceinline__ void node_fwd_rest(const double Fp[10], const AGeo& G, const double dj[3][3], double tau,
+                                              bool with_old, NodeFwd& o) {
+  const double th = 1.0 / 3.0;
+  const double ir = 1.0 / o.rho;
   const double kap = 1.0 - 0.5 / tau;
 #pragma unroll
   for (int a = 0; a < 3; ++a)
@@ -193,44 +228,76 @@ __device__ __forceinline__ void node_fwd(const double f[Q], const double Fp[10],
   }
 }
 
-// VJP of one node.  Inputs: fsb = adjoint of f* (with_old only), Fbin =
-// adjoint of F (added to what flows from f*), cb = adjoint of the new
-// coefficients (A, B, C), Tbin = adjoint of T (or null).  Outputs
-// (accumulated): fb = direct adjoint of f (through ne and f*), rb/jb =
-// adjoint of rho and j (local uses), djb = adjoint of dj, Fpb = adjoint of
-// the old coefficients, gb = geometry adjoint.
+// VJP of the old forcing Fo = H(Fp) (F(t-1) in Eq. collision, b2 = bp) from
+// the basis sums h of its adjoint: into the old coefficients Fpb and sg.
+__device__ __forceinline__ void old_forcing_vjp(const HSum& h, double isg, const double Fp[10], const double bp[6],
+                                                double Fpb[10], double& sgb) {
+  const double th = 1.0 / 3.0;
+  double a0b = 0, a1b[3] = {0, 0, 0}, a2b[6] = {0, 0, 0, 0, 0, 0};
+  hermite_vjp(h, isg, Fp[0], Fp + 1, bp, a0b, a1b, a2b, sgb);
+  Fpb[0] += a0b - th * (a2b[0] + a2b[3] + a2b[5]);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) Fpb[1 + a] += a1b[a];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) Fpb[4 + q] += a2b[q];
+}
+
+// The P-dependent part of the adjoint of f_l: the adjoint Pb of
+// P = sum_l ne_l c_l c_l (packed) seen by direction l.
+template <int l> __device__ __forceinline__ double pb_term(const double Pb[6]) {
+  constexpr int x = cx(l), y = cy(l), z = cz(l);
+  double v = 0.0;
+  if (x) v += Pb[0];
+  if (y) v += Pb[3];
+  if (z) v += Pb[5];
+  if (x && y) v += (x * y) * Pb[1];
+  if (x && z) v += (x * z) * Pb[2];
+  if (y && z) v += (y * z) * Pb[4];
+  return v;
+}
+
+// VJP of one node, with the per-direction adjoints entering only through
+// their Hermite basis sums.  Inputs: hs = basis sums of the adjoint s_l of
+// f*_l (with_old only), hb = basis sums of the adjoint of F_l (added to what
+// flows from f*), cb = adjoint of the new coefficients (A, B, C), Tbin =
+// adjoint of T (or null).  Outputs (accumulated): Pb = adjoint of P, so that
+// the direct adjoint of f_l is (1 - 1/tau) s_l + pb_term<l>(Pb) (formed where
+// s_l is read again); rb/jb = adjoint of rho and j (local uses); djb =
+// adjoint of dj; Fpb = adjoint of the old coefficients; gb = geometry
+// adjoint.
+template <class GB>
 __device__ __forceinline__ void node_vjp(const double Fp[10], const AGeo& G, double tau, bool with_old,
-                                         const NodeFwd& o, const double fsb[Q], const double Fbin[Q],
-                                         const double cb[10], const double* Tbin, double fb[Q], double& rb,
-                                         double jb[3], double djb[3][3], double Fpb[10], AGeoBar& gb) {
+                                         const NodeFwd& o, const HSum& hs, const HSum& hb, const double cb[10],
+                                         const double* Tbin, double Pb[6], double& rb, double jb[3],
+                                         double djb[3][3], double Fpb[10], GB& gb) {
   const double th = 1.0 / 3.0, itau = 1.0 / tau, kap = 1.0 - 0.5 / tau;
+  double sgl = 0;  // adjoint of sqrt g, added to gb at the end
   // f* = f - ne/tau + F - Fo/2: basis sums of the adjoints of Fo and F
   HSum hFo, hF;
-  hsum_zero(hFo);
-  hsum_zero(hF);
-  for_q([&](auto L) {
-    constexpr int l = decltype(L)::value;
-    const double s = with_old ? fsb[l] : 0.0;
-    hsum_add<l>(hFo, -0.5 * s);
-    hsum_add<l>(hF, s + Fbin[l]);
-  });
-  // F(t-1) = H(Fp) -> old coefficients
-  if (with_old) {
-    double a0b = 0, a1b[3] = {0, 0, 0}, a2b[6] = {0, 0, 0, 0, 0, 0};
-    hermite_vjp(hFo, o.isg, Fp[0], Fp + 1, o.bp, a0b, a1b, a2b, gb.sg);
-    Fpb[0] += a0b - th * (a2b[0] + a2b[3] + a2b[5]);
+  {
+    const double w = with_old ? 1.0 : 0.0;
+    hFo.s0 = -0.5 * w * hs.s0;
+    hF.s0 = w * hs.s0 + hb.s0;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) Fpb[1 + a] += a1b[a];
+    for (int a = 0; a < 3; ++a) {
+      hFo.s1[a] = -0.5 * w * hs.s1[a];
+      hF.s1[a] = w * hs.s1[a] + hb.s1[a];
+    }
 #pragma unroll
-    for (int q = 0; q < 6; ++q) Fpb[4 + q] += a2b[q];
+    for (int q = 0; q < 6; ++q) {
+      hFo.s2[q] = -0.5 * w * hs.s2[q];
+      hF.s2[q] = w * hs.s2[q] + hb.s2[q];
+    }
   }
+  // (Fp null: the caller has reversed the old forcing already)
+  if (with_old && Fp) old_forcing_vjp(hFo, o.isg, Fp, o.bp, Fpb, sgl);
   // F = H(A, B, C - theta A delta)
   double Ab = cb[0], Bb[3] = {cb[1], cb[2], cb[3]}, Cb[6];
 #pragma unroll
   for (int q = 0; q < 6; ++q) Cb[q] = cb[4 + q];
   {
     double a0b = 0, a1b[3] = {0, 0, 0}, a2b[6] = {0, 0, 0, 0, 0, 0};
-    hermite_vjp(hF, o.isg, o.A, o.B, o.b2, a0b, a1b, a2b, gb.sg);
+    hermite_vjp(hF, o.isg, o.A, o.B, o.b2, a0b, a1b, a2b, sgl);
     Ab += a0b - th * (a2b[0] + a2b[3] + a2b[5]);
 #pragma unroll
     for (int a = 0; a < 3; ++a) Bb[a] += a1b[a];
@@ -256,13 +323,13 @@ __device__ __forceinline__ void node_vjp(const double Fp[10], const AGeo& G, dou
       if (i == jj) divbarb += cbq;
       // t = g^{i jj} divnab + sum_k g^{jj k} nab[k][i] + g^{i k} nab[k][jj]
       const double tbq = -cbq;
-      gb.gi[sym(i, jj)] += tbq * divnab;
+      gb.add_gi(sym(i, jj), tbq * divnab);
       divnabb += tbq * G.gi[sym(i, jj)];
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
-        gb.gi[sym(jj, k)] += tbq * o.nab[k][i];
+        gb.add_gi(sym(jj, k), tbq * o.nab[k][i]);
         nabb[k][i] += tbq * G.gi[sym(jj, k)];
-        gb.gi[sym(i, k)] += tbq * o.nab[k][jj];
+        gb.add_gi(sym(i, k), tbq * o.nab[k][jj]);
         nabb[k][jj] += tbq * G.gi[sym(i, k)];
       }
     }
@@ -279,7 +346,7 @@ __device__ __forceinline__ void node_vjp(const double Fp[10], const AGeo& G, dou
       djb[k][i] += nabb[k][i] + dbarb[k][i];
 #pragma unroll
       for (int l = 0; l < 3; ++l) {
-        gb.gam[i * 6 + sym(k, l)] += nabb[k][i] * o.j[l];
+        gb.add_gam(i * 6 + sym(k, l), nabb[k][i] * o.j[l]);
         jbar[l] += nabb[k][i] * G.gam[i * 6 + sym(k, l)];
       }
       trb[k] -= dbarb[k][i] * o.j[i];
@@ -288,14 +355,14 @@ __device__ __forceinline__ void node_vjp(const double Fp[10], const AGeo& G, dou
   // B^i = F^i - 2 tr_j T^ij - Gamma^i_jk T^jk
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    gb.F[i] += Bb[i];
+    gb.add_F(i, Bb[i]);
 #pragma unroll
     for (int jj = 0; jj < 3; ++jj) {
       trb[jj] -= 2.0 * Bb[i] * o.T[sym(i, jj)];
       Tb[sym(i, jj)] -= 2.0 * Bb[i] * o.tr[jj];
 #pragma unroll
       for (int kk = 0; kk < 3; ++kk) {
-        gb.gam[i * 6 + sym(jj, kk)] -= Bb[i] * o.T[sym(jj, kk)];
+        gb.add_gam(i * 6 + sym(jj, kk), -(Bb[i] * o.T[sym(jj, kk)]));
         Tb[sym(jj, kk)] -= Bb[i] * G.gam[i * 6 + sym(jj, kk)];
       }
     }
@@ -310,9 +377,9 @@ __device__ __forceinline__ void node_vjp(const double Fp[10], const AGeo& G, dou
 #pragma unroll
   for (int b = 0; b < 3; ++b)
 #pragma unroll
-    for (int i = 0; i < 3; ++i) gb.gam[i * 6 + sym(i, b)] += trb[b];
+    for (int i = 0; i < 3; ++i) gb.add_gam(i * 6 + sym(i, b), trb[b]);
   // T = rho theta g^ij + j j / rho + kappa sqrt g P
-  double rbar = 0, Pb[6];
+  double rbar = 0;
   const double ir = 1.0 / o.rho;
 #pragma unroll
   for (int a = 0; a < 3; ++a)
@@ -320,35 +387,33 @@ __device__ __forceinline__ void node_vjp(const double Fp[10], const AGeo& G, dou
     for (int b = a; b < 3; ++b) {
       const int q = sym(a, b);
       rbar += Tb[q] * (th * G.gi[q] - o.j[a] * o.j[b] * ir * ir);
-      gb.gi[q] += Tb[q] * o.rho * th;
+      gb.add_gi(q, Tb[q] * o.rho * th);
       jbar[a] += Tb[q] * o.j[b] * ir;
       jbar[b] += Tb[q] * o.j[a] * ir;
-      gb.sg += Tb[q] * kap * o.P[q];
+      sgl += Tb[q] * kap * o.P[q];
       Pb[q] = Tb[q] * kap * G.sg;
     }
-  // P = sum ne c c, ne = f - feq, and the f* path: adjoint of f directly and
-  // of feq (basis sums)
+  // P = sum ne c c, ne = f - feq; f* = f - ne/tau + ...: the adjoint of ne_l
+  // is -s_l/tau + pb_term<l>(Pb), and feq_l = f_l - ne_l takes minus that
+  // (basis sums: hs/tau minus those of the pb_term)
   HSum hfeq;
   hsum_zero(hfeq);
   for_q([&](auto L) {
     constexpr int l = decltype(L)::value;
-    constexpr int x = cx(l), y = cy(l), z = cz(l);
-    const double s = with_old ? fsb[l] : 0.0;
-    double neb = -s * itau;
-    if (x) neb += Pb[0];
-    if (y) neb += Pb[3];
-    if (z) neb += Pb[5];
-    if (x && y) neb += (x * y) * Pb[1];
-    if (x && z) neb += (x * z) * Pb[2];
-    if (y && z) neb += (y * z) * Pb[4];
-    fb[l] += s + neb;
-    hsum_add<l>(hfeq, -neb);
+    hsum_add<l>(hfeq, -pb_term<l>(Pb));
   });
+  if (with_old) {
+    hfeq.s0 += itau * hs.s0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) hfeq.s1[a] += itau * hs.s1[a];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) hfeq.s2[q] += itau * hs.s2[q];
+  }
   // feq = H(rho, j, a2)
   double a2b[6] = {0, 0, 0, 0, 0, 0};
   {
     double a0b = 0, a1b[3] = {0, 0, 0};
-    hermite_vjp(hfeq, o.isg, o.rho, o.j, o.a2, a0b, a1b, a2b, gb.sg);
+    hermite_vjp(hfeq, o.isg, o.rho, o.j, o.a2, a0b, a1b, a2b, sgl);
     rbar += a0b;
 #pragma unroll
     for (int a = 0; a < 3; ++a) jbar[a] += a1b[a];
@@ -360,13 +425,14 @@ __device__ __forceinline__ void node_vjp(const double Fp[10], const AGeo& G, dou
     for (int b = a; b < 3; ++b) {
       const int q = sym(a, b);
       rbar += a2b[q] * (th * (G.gi[q] - (a == b ? 1.0 : 0.0)) - o.j[a] * o.j[b] * ir * ir);
-      gb.gi[q] += a2b[q] * o.rho * th;
+      gb.add_gi(q, a2b[q] * o.rho * th);
       jbar[a] += a2b[q] * o.j[b] * ir;
       jbar[b] += a2b[q] * o.j[a] * ir;
     }
   rb += rbar;
 #pragma unroll
   for (int a = 0; a < 3; ++a) jb[a] += jbar[a];
+  gb.add_sg(sgl);
 }
 
 // Moments rho = sg S0, j = sg S1 -> adjoint into f and sg.

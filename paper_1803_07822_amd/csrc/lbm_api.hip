@@ -92,8 +92,8 @@ void carve_core(Carver& c, const Grid& g, int precision, Fields& F) {
   F.vwall = (double*)c.take(sizeof(double) * 2 * 3 * (size_t)g.nz * g.nx);
   F.full = (double*)c.take(sizeof(double) * 19 * N);
   F.mf = c.take(sz * 20 * NC);
-  const size_t nb = (size_t)((g.nx + lbm::BX - 1) / lbm::BX) * ((g.nz + lbm::BY - 1) / lbm::BY);
-  F.part = (double*)c.take(sizeof(double) * 3 * nb + 64);
+  F.part = (double*)c.take(sizeof(double) * 3 * (size_t)lbm::wall_force_blocks(g));
+  F.count = (unsigned*)c.take(ALIGN);
   F.flag = (int*)c.take(ALIGN);
   F.cur = 0;
   F.uext_cur = 0;
@@ -205,6 +205,7 @@ int lbm_create(lbm_ctx** out, const lbm_grid* h_grid, int lattice, double tau, i
   if (e == hipSuccess) e = hipMemsetAsync(F.uin, 0, sizeof(double) * 3 * (size_t)F.g.nz * F.g.H, c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(F.vin, 0, sz * 3 * (size_t)F.g.nz * F.g.H, c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(F.flag, 0, ALIGN, c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(F.count, 0, ALIGN, c->stream);
   if (e != hipSuccess) {
     delete c;
     return LBM_EHIP;

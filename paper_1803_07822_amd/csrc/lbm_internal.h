@@ -37,7 +37,8 @@ struct Fields {
   double* vwall;  // [2][nz][nx][3] Cartesian wall velocity
   double* full;   // [19][N] FP64 scratch
   void* mf;       // [NC][20] T: Cartesian moment fields for re-projection, deviations from rest
-  double* part;   // reduction partials
+  double* part;   // wall-force reduction: 3 doubles per block
+  unsigned* count;// wall-force reduction: blocks done (zero between launches)
   int* flag;      // instability guard
   int cur;        // index of the current population and history buffers
   int uext_cur;   // index of the current extended displacement
@@ -129,10 +130,16 @@ template <class T> hipError_t launch_step_fused_moments(Fields& F, hipStream_t s
 // Planes per block the fused step runs with (F.zc, or the automatic choice).
 template <class T> hipError_t fused_step_chunk(Fields& F, int* zc);
 template <class T> hipError_t launch_moments_out(Fields& F, hipStream_t s, double* rho, double* u, int cart);
+// Wall force: one column per thread, blocks of WF_THREADS.
+constexpr int WF_THREADS = 256;
+inline long long wall_force_blocks(const Grid& g) { return ((long long)g.nx * g.nz + WF_THREADS - 1) / WF_THREADS; }
 // wall 0 / 1: the walls; wall 2: the interior plate (both faces, plate
 // columns).  mem != 0: momentum exchange (walls at rest) instead of traction.
+// The reduction scratch is part [3 * wall_force_blocks] and count (zero on
+// entry, zero again on exit), the context's own unless part is given.
 template <class T> hipError_t launch_wall_force(Fields& F, hipStream_t s, int wall, T tau, double* total,
-                                                double* per_node, int mem = 0);
+                                                double* per_node, int mem = 0, double* part = nullptr,
+                                                unsigned* count = nullptr);
 template <class T> hipError_t launch_reproject(Fields& F, hipStream_t s, const double Fc[3], T tau);
 
 }  // namespace lbm

@@ -497,24 +497,44 @@ __device__ __forceinline__ void node_exchange(const Grid& g, int wall, const T* 
   });
 }
 
+// Sum of v over the 64 lanes of a wave by a butterfly of lane exchanges.
+// Floating-point addition is commutative, so every lane ends with the same,
+// launch-independent value.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+
 // Force per column on a wall (wall 0 / 1: the traction at the fluid layer
 // next to it, outward-normal sign, or with mem != 0 the momentum exchange) or
 // on the plate (wall 2: the traction of both faces in the plate columns, + at
-// the node below and - at the node above; zero in the other columns), summed
-// per block.
+// the node below and - at the node above; zero in the other columns), and
+// its sum over the columns, in one launch (one column per thread).  Each wave
+// sums its columns by lane exchanges, the block adds its waves' sums in wave
+// order and stores the result in part[block]; the block that finishes last
+// (counted in *count) adds the partials in block order and clears the
+// counter for the next launch, so the total does not depend on the order the
+// blocks ran in.  Only the partials are published (release before the count,
+// acquire in the last block alone), so no other block's cached data is
+// invalidated.
 template <class T>
-__global__ __launch_bounds__(BX* BY) void k_wall_force(Grid g, int wall, int mem, const T* __restrict__ pop,
-                                                      const T* __restrict__ hist, const T* __restrict__ geo,
-                                                      const T* __restrict__ vin, const double* __restrict__ jac,
-                                                      T tau, double* __restrict__ per_node,
-                                                      double* __restrict__ part) {
-  __shared__ double red[3][BX * BY];
-  const int tid = threadIdx.y * BX + threadIdx.x;
-  Pos p;
-  p.i = blockIdx.x * BX + threadIdx.x;
-  p.k = blockIdx.y * BY + threadIdx.y;
+__global__ __launch_bounds__(WF_THREADS) void k_wall_force(Grid g, int wall, int mem, const T* __restrict__ pop,
+                                                          const T* __restrict__ hist, const T* __restrict__ geo,
+                                                          const T* __restrict__ vin, const double* __restrict__ jac,
+                                                          T tau, double* __restrict__ per_node,
+                                                          double* __restrict__ part, unsigned* __restrict__ count,
+                                                          double* __restrict__ total) {
+  constexpr int NW = WF_THREADS / 64;
+  __shared__ double red[NW][3];
+  __shared__ unsigned last;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const long long col = (long long)blockIdx.x * WF_THREADS + tid;
   double t[3] = {0, 0, 0};
-  if (p.i < g.nx && p.k < g.nz) {
+  if (col < (long long)g.nx * g.nz) {
+    Pos p;
+    p.i = (int)(col % g.nx);
+    p.k = (int)(col / g.nx);
     if (wall < 2) {
       p.jf = wall == 0 ? 0 : g.H - 1;
       p.n = ((long long)p.k * g.H + p.jf) * g.nx + p.i;
@@ -530,49 +550,43 @@ __global__ __launch_bounds__(BX* BY) void k_wall_force(Grid g, int wall, int mem
       }
     }
     if (per_node) {
-      const long long c = ((long long)p.k * g.nx + p.i) * 3;
-      per_node[c] = t[0];
-      per_node[c + 1] = t[1];
-      per_node[c + 2] = t[2];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) per_node[col * 3 + a] = t[a];
     }
   }
 #pragma unroll
-  for (int a = 0; a < 3; ++a) red[a][tid] = t[a];
+  for (int a = 0; a < 3; ++a) t[a] = wave_sum(t[a]);
+  if (lane == 0)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) red[wave][a] = t[a];
   __syncthreads();
-  for (int s = BX * BY / 2; s > 0; s >>= 1) {
-    if (tid < s) {
-#pragma unroll
-      for (int a = 0; a < 3; ++a) red[a][tid] += red[a][tid + s];
-    }
-    __syncthreads();
-  }
   if (tid == 0) {
-    const long long b = (long long)blockIdx.y * gridDim.x + blockIdx.x;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) part[b * 3 + a] = red[a][0];
+    for (int a = 0; a < 3; ++a) {
+      double s = red[0][a];
+#pragma unroll
+      for (int w = 1; w < NW; ++w) s += red[w][a];
+      part[(size_t)blockIdx.x * 3 + a] = s;
+    }
+    // publish the partial, then count this block as done
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    last = atomicAdd(count, 1u) == gridDim.x - 1;
   }
-}
-
-// Fixed-order sum of the block partials (deterministic).
-__global__ __launch_bounds__(BX * BY) void k_sum_partials(int nb, const double* __restrict__ part, double* __restrict__ out) {
-  __shared__ double red[3][256];
-  const int tid = threadIdx.x;
-  double s[3] = {0, 0, 0};
-  for (int b = tid; b < nb; b += 256)
-#pragma unroll
-    for (int a = 0; a < 3; ++a) s[a] += part[b * 3 + a];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) red[a][tid] = s[a];
   __syncthreads();
-  for (int st = 128; st > 0; st >>= 1) {
-    if (tid < st)
+  if (!last || wave != 0) return;
+  // every other block's partial is visible past this point
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  double s[3] = {0, 0, 0};
+  for (unsigned b = lane; b < gridDim.x; b += 64)
 #pragma unroll
-      for (int a = 0; a < 3; ++a) red[a][tid] += red[a][tid + st];
-    __syncthreads();
+    for (int a = 0; a < 3; ++a) s[a] += part[(size_t)b * 3 + a];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) s[a] = wave_sum(s[a]);
+  if (lane == 0) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) total[a] = s[a];
+    *count = 0u;
   }
-  if (tid == 0)
-#pragma unroll
-    for (int a = 0; a < 3; ++a) out[a] = red[a][0];
 }
 
 }  // namespace
@@ -675,12 +689,12 @@ template <class T> hipError_t launch_moments_out(Fields& F, hipStream_t s, doubl
 }
 
 template <class T>
-hipError_t launch_wall_force(Fields& F, hipStream_t s, int wall, T tau, double* total, double* per_node, int mem) {
-  dim3 b(BX, BY), gr = col_grid(F.g);
-  hipLaunchKernelGGL(k_wall_force<T>, gr, b, 0, s, F.g, wall, mem, (const T*)F.pop[F.cur], (const T*)F.hist[F.cur],
-                     (const T*)F.geo, (const T*)F.vin, F.jac, tau, per_node, F.part);
-  const int nb = (int)(gr.x * gr.y);
-  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, nb, (const double*)F.part, total);
+hipError_t launch_wall_force(Fields& F, hipStream_t s, int wall, T tau, double* total, double* per_node, int mem,
+                             double* part, unsigned* count) {
+  const long long nb = wall_force_blocks(F.g);
+  hipLaunchKernelGGL(k_wall_force<T>, dim3((unsigned)nb), dim3(WF_THREADS), 0, s, F.g, wall, mem, (const T*)F.pop[F.cur],
+                     (const T*)F.hist[F.cur], (const T*)F.geo, (const T*)F.vin, F.jac, tau, per_node,
+                     part ? part : F.part, part ? count : F.count, total);
   return hipGetLastError();
 }
 
@@ -692,9 +706,9 @@ hipError_t launch_wall_force(Fields& F, hipStream_t s, int wall, T tau, double* 
   template hipError_t launch_get_hist<T>(Fields&, hipStream_t, double*);                               \
   template hipError_t launch_get_geo<T>(Fields&, hipStream_t, double*);                                \
   template hipError_t launch_moments_out<T>(Fields&, hipStream_t, double*, double*, int);              \
-  template hipError_t launch_wall_force<T>(Fields&, hipStream_t, int, T, double*, double*, int);
+  template hipError_t launch_wall_force<T>(Fields&, hipStream_t, int, T, double*, double*, int, double*,   \
+                                           unsigned*);
 LBM_INST(double)
 LBM_INST(float)
 #undef LBM_INST
-
 }  // namespace lbm

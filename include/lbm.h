@@ -181,6 +181,20 @@ int lbm_moments(lbm_ctx* ctx, double* d_rho, double* d_u, int cartesian);
  * EINVAL for another method. */
 int lbm_wall_force(lbm_ctx* ctx, int wall, int method, double* d_total3, double* d_per_node);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid allocation): lbm_wall_force
+ * with the same arguments, result and error behaviour, bit for bit, whose
+ * reduction scratch (3 doubles per 256 wall columns and a completion counter)
+ * lives in a static device array of the library, one per GPU, instead of the
+ * context's workspace.  The call allocates nothing and launches one kernel.
+ * Limit: nx * nz <= LBM_NOALLOC_MAX_COLUMNS wall columns, else EINVAL.  Every
+ * context on a GPU shares that GPU's array: calls that overlap in time on one
+ * GPU (contexts on different streams, or threads) race and must be ordered
+ * by the caller.  EHIP if the array's address could not be resolved when the
+ * context was created. */
+enum { LBM_NOALLOC_MAX_COLUMNS = 256 * 2048 };
+int lbm_wall_force_noalloc(lbm_ctx* ctx, int wall, int method, double* d_total3, double* d_per_node);
+
 /* One coupling interval with an external structural solver (Sec. IV.A: the
  * fluid receives the wall's position and velocity, the structure receives
  * the traction).  In order, on the context's stream:

@@ -27,6 +27,8 @@ struct lbm_ctx {
   int have_geo = 0, have_state = 0;
   int sticky = LBM_OK;
   int adjK = 0, adjN = 0, recorded = 0, rec_wall = 1;
+  void* scratch = nullptr;  // the device's allocation-free scratch (lbm_wall_force_noalloc)
+  int scratch_rc = 0;       // hipError_t of resolving it
   std::string err;
 };
 
@@ -210,6 +212,12 @@ int lbm_create(lbm_ctx** out, const lbm_grid* h_grid, int lattice, double tau, i
     delete c;
     return LBM_EHIP;
   }
+  // address of the static scratch array on this (the current) device, for
+  // lbm_wall_force_noalloc; a failure is reported by that call only
+  int dev = 0;
+  hipError_t de = hipGetDevice(&dev);
+  if (de == hipSuccess) de = lbm::noalloc_scratch_init(dev, &c->scratch);
+  c->scratch_rc = (int)de;
   *out = c;
   return LBM_OK;
 }
@@ -575,6 +583,29 @@ int lbm_wall_force(lbm_ctx* c, int wall, int method, double* d_total3, double* d
     LBM_HIP(c, lbm::launch_wall_force<double>(c->F, c->stream, wall, c->tau, d_total3, d_per_node, mem));
   else
     LBM_HIP(c, lbm::launch_wall_force<float>(c->F, c->stream, wall, (float)c->tau, d_total3, d_per_node, mem));
+  return LBM_OK;
+}
+
+int lbm_wall_force_noalloc(lbm_ctx* c, int wall, int method, double* d_total3, double* d_per_node) {
+  LBM_GUARD(c);
+  if (wall != LBM_WALL_YMIN && wall != LBM_WALL_YMAX) return fail(c, LBM_EINVAL, "bad wall");
+  if (method != LBM_FORCE_STRESS && method != LBM_FORCE_MEM) return fail(c, LBM_EINVAL, "bad force method");
+  if (!d_total3) return fail(c, LBM_EINVAL, "total output is NULL");
+  if (lbm::wall_force_blocks(c->F.g) > lbm::NOALLOC_MAX_BLOCKS)
+    return fail(c, LBM_EINVAL, "lbm_wall_force_noalloc: nx * nz exceeds LBM_NOALLOC_MAX_COLUMNS");
+  if (c->scratch_rc != (int)hipSuccess || !c->scratch)
+    return hip_check(c, c->scratch_rc != (int)hipSuccess ? (hipError_t)c->scratch_rc : hipErrorInvalidValue,
+                     "lbm_wall_force_noalloc: static scratch address");
+  if (!c->have_state) return fail(c, LBM_ESTATE, "no state");
+  const int mem = method == LBM_FORCE_MEM;
+  if (mem && c->F.moving[wall])
+    return fail(c, LBM_EUNSUPPORTED, "the momentum-exchange force is provided for a wall at rest");
+  if (c->precision == LBM_FP64)
+    LBM_HIP(c, lbm::launch_wall_force_noalloc<double>(c->F, c->stream, wall, c->tau, d_total3, d_per_node, mem,
+                                                      c->scratch));
+  else
+    LBM_HIP(c, lbm::launch_wall_force_noalloc<float>(c->F, c->stream, wall, (float)c->tau, d_total3, d_per_node,
+                                                     mem, c->scratch));
   return LBM_OK;
 }
 

@@ -142,4 +142,14 @@ template <class T> hipError_t launch_wall_force(Fields& F, hipStream_t s, int wa
                                                 unsigned* count = nullptr);
 template <class T> hipError_t launch_reproject(Fields& F, hipStream_t s, const double Fc[3], T tau);
 
+// Allocation-free wall force: the reduction scratch is a static device array
+// of the library (at most NOALLOC_MAX_BLOCKS blocks, i.e.
+// WF_THREADS * NOALLOC_MAX_BLOCKS wall columns).  noalloc_scratch_init resolves its
+// address on device dev (which must be current) once and returns it;
+// launch_wall_force_noalloc takes that address.
+constexpr long long NOALLOC_MAX_BLOCKS = 2048;
+hipError_t noalloc_scratch_init(int dev, void** out);
+template <class T> hipError_t launch_wall_force_noalloc(Fields& F, hipStream_t s, int wall, T tau, double* total,
+                                                        double* per_node, int mem, void* scratch);
+
 }  // namespace lbm

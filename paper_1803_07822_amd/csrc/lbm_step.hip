@@ -17,6 +17,8 @@
 // forms rho and rho u at every node, and pass 2 does the rest of the step
 // node-locally: equilibrium, stress, forcing A/B/C, collision, bounce-back
 // term, history update.
+#include <mutex>
+
 #include "lbm_internal.h"
 #include "lbm_pull.h"
 
@@ -591,6 +593,45 @@ __global__ __launch_bounds__(WF_THREADS) void k_wall_force(Grid g, int wall, int
 
 }  // namespace
 
+// Reduction scratch of the allocation-free wall force: the block partials
+// (3 doubles per block) and, after them, the completion counter.
+// Every context on a device shares this one array.
+constexpr size_t NOALLOC_COUNT_OFF = sizeof(double) * 3 * (size_t)NOALLOC_MAX_BLOCKS;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_COUNT_OFF + 256];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+void* scratch_dev[MAX_DEVICES];  // device address of `scratch` on each device
+}  // namespace
+
+hipError_t noalloc_scratch_init(int dev, void** out) {
+  *out = nullptr;
+  if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_dev[dev]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    // the counter must read zero before the first launch (every launch
+    // leaves it at zero again)
+    e = hipMemset((char*)p + NOALLOC_COUNT_OFF, 0, 256);
+    if (e != hipSuccess) return e;
+    scratch_dev[dev] = p;
+  }
+  *out = scratch_dev[dev];
+  return hipSuccess;
+}
+
+template <class T>
+hipError_t launch_wall_force_noalloc(Fields& F, hipStream_t s, int wall, T tau, double* total, double* per_node,
+                                     int mem, void* scr) {
+  if (!scr) return hipErrorInvalidValue;
+  if (wall_force_blocks(F.g) > NOALLOC_MAX_BLOCKS) return hipErrorInvalidValue;
+  return launch_wall_force<T>(F, s, wall, tau, total, per_node, mem, (double*)scr,
+                              (unsigned*)((char*)scr + NOALLOC_COUNT_OFF));
+}
+
 // One step; with ev != nullptr, events ev[0..2] bracket the kernels of the
 // step (the fused step is one kernel: ev[1] and ev[2] then coincide).
 template <class T> hipError_t launch_step(Fields& F, hipStream_t s, T tau, hipEvent_t* ev) {
@@ -711,4 +752,9 @@ hipError_t launch_wall_force(Fields& F, hipStream_t s, int wall, T tau, double* 
 LBM_INST(double)
 LBM_INST(float)
 #undef LBM_INST
+template hipError_t launch_wall_force_noalloc<double>(Fields&, hipStream_t, int, double, double*, double*, int,
+                                                      void*);
+template hipError_t launch_wall_force_noalloc<float>(Fields&, hipStream_t, int, float, double*, double*, int,
+                                                     void*);
+
 }  // namespace lbm

@@ -29,6 +29,7 @@ LBM_FP64, LBM_FP32_DEV = 0, 1
 LBM_WALL_YMIN, LBM_WALL_YMAX = 0, 1
 LBM_FORCE_STRESS = 0
 LBM_FORCE_MEM = 1
+LBM_NOALLOC_MAX_COLUMNS = 256 * 2048  # lbm_wall_force_noalloc's limit on nx * nz
 ERRORS = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EHIP", -4: "LBM_ESTATE",
           -5: "LBM_EUNSTABLE", -6: "LBM_EUNSUPPORTED"}
 
@@ -37,7 +38,7 @@ SYMBOLS = [
     "lbm_set_metric", "lbm_set_wall_displacement", "lbm_set_wall_velocity", "lbm_init_equilibrium",
     "lbm_set_populations", "lbm_get_populations", "lbm_get_history", "lbm_get_geometry", "lbm_step",
     "lbm_step_profiled", "lbm_set_tuning", "lbm_get_tuning", "lbm_stream_probe", "lbm_moments", "lbm_wall_force",
-    "lbm_couple", "lbm_set_plate", "lbm_set_plate_displacement", "lbm_set_plate_velocity", "lbm_plate_force",
+    "lbm_wall_force_noalloc", "lbm_couple", "lbm_set_plate", "lbm_set_plate_displacement", "lbm_set_plate_velocity", "lbm_plate_force",
     "lbm_set_open_x", "lbm_forward_record", "lbm_backward", "lbm_sync", "lbm_last_error",
 ]
 
@@ -71,6 +72,7 @@ _lib.lbm_get_tuning.argtypes = [_P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER
                                 ctypes.POINTER(ctypes.c_int)]
 _lib.lbm_moments.argtypes = [_P, _P, _P, _I]
 _lib.lbm_wall_force.argtypes = [_P, _I, _I, _P, _P]
+_lib.lbm_wall_force_noalloc.argtypes = [_P, _I, _I, _P, _P]
 _lib.lbm_set_plate.argtypes = [_P, _I, _I, _I]
 _lib.lbm_set_plate_displacement.argtypes = [_P, _P, _I]
 _lib.lbm_set_plate_velocity.argtypes = [_P, _P]
@@ -238,6 +240,10 @@ def lbm_moments(ctx, rho, u, cartesian=False):
 
 def lbm_wall_force(ctx, wall, total, per_node=None, method=LBM_FORCE_STRESS):
     return _check(ctx, _lib.lbm_wall_force(ctx, int(wall), int(method), _ptr(total), _ptr(per_node)))
+
+
+def lbm_wall_force_noalloc(ctx, wall, total, per_node=None, method=LBM_FORCE_STRESS):
+    return _check(ctx, _lib.lbm_wall_force_noalloc(ctx, int(wall), int(method), _ptr(total), _ptr(per_node)))
 
 
 def lbm_couple(ctx, wall, disp, vcart, n, total, per_node=None):

@@ -11,6 +11,8 @@
 // by the mirror rule about rho v_wall, the other moments by linear
 // extrapolation.  Moments and geometry are handled in FP64; populations end in
 // the storage precision.
+#include <climits>
+
 #include "lbm_internal.h"
 #include "lbm_pull.h"
 
@@ -60,21 +62,21 @@ __device__ __forceinline__ int plate_side_layer(const Grid& g, int side, int bx,
   return by;
 }
 
-// Trilinear value of F in the cell and its gradient in cell coordinates.
-__device__ __forceinline__ double cell_eval(const Cell& c, const double* __restrict__ F, double grad[3]) {
+// Trilinear value from the eight corner values of a cell (corner q at offsets
+// (q & 1, (q >> 1) & 1, (q >> 2) & 1)) and its gradient in cell coordinates.
+__device__ __forceinline__ double trilin_corners(const double F[8], const double fr[3], double grad[3]) {
   double v = 0.0;
   grad[0] = grad[1] = grad[2] = 0.0;
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
     const int ox = q & 1, oy = (q >> 1) & 1, oz = (q >> 2) & 1;
-    const double wx = ox ? c.fr[0] : 1.0 - c.fr[0];
-    const double wy = oy ? c.fr[1] : 1.0 - c.fr[1];
-    const double wz = oz ? c.fr[2] : 1.0 - c.fr[2];
-    const double fv = F[c.e[q]];
-    v += wx * wy * wz * fv;
-    grad[0] += (ox ? 1.0 : -1.0) * wy * wz * fv;
-    grad[1] += wx * (oy ? 1.0 : -1.0) * wz * fv;
-    grad[2] += wx * wy * (oz ? 1.0 : -1.0) * fv;
+    const double wx = ox ? fr[0] : 1.0 - fr[0];
+    const double wy = oy ? fr[1] : 1.0 - fr[1];
+    const double wz = oz ? fr[2] : 1.0 - fr[2];
+    v += wx * wy * wz * F[q];
+    grad[0] += (ox ? 1.0 : -1.0) * wy * wz * F[q];
+    grad[1] += wx * (oy ? 1.0 : -1.0) * wz * F[q];
+    grad[2] += wx * wy * (oz ? 1.0 : -1.0) * F[q];
   }
   return v;
 }
@@ -262,9 +264,19 @@ __global__ __launch_bounds__(BX * BY) void k_rp_new(Grid g, const double* __rest
   const long long NC = (long long)g.nz * g.ny * g.nx, NE = (long long)g.nz * (g.ny + 6) * g.nx;
   const long long pc = ((long long)k * g.ny + (jf + 1)) * g.nx + i;
   const double p[3] = {chart[pc], chart[NC + pc], chart[2 * NC + pc]};
-  // psi: xi + u_old(xi) = p
+  // psi: xi + u_old(xi) = p.  Start from one fixed-point step off the node,
+  // xi = p - u_old(node), which lands in the cell of the solution unless the
+  // chart moved by most of a cell; the eight corners of the old displacement
+  // are gathered once per cell and reused by the Newton iterations in it.
   const int side = jf >= g.pj ? 1 : 0;
-  double xi[3] = {(double)i, (double)(jf + 1), (double)k};
+  double xi[3];
+  {
+    const long long e0 = ((long long)k * (g.ny + 6) + (jf + 1 + 3)) * g.nx + i;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) xi[a] = p[a] - uold[a * NE + e0];
+  }
+  int cbx = INT_MIN, cby = INT_MIN, cbz = INT_MIN;
+  double U[3][8];
   for (int it = 0; it < 50; ++it) {
     double r[3], Jm[3][3], Ji[3][3];
     // cell of the extended grid (layers -3 .. ny+2) holding xi
@@ -273,13 +285,23 @@ __global__ __launch_bounds__(BX * BY) void k_rp_new(Grid g, const double* __rest
     if (by < -3) by = -3;
     if (by > g.ny + 1) by = g.ny + 1;
     by = plate_side_layer(g, side, bx, by);
+    if (bx != cbx || by != cby || bz != cbz) {
+      Cell c;
+      const double fr0[3] = {0.0, 0.0, 0.0};
+      cell_setup(g, g.ny + 6, 3, bx, by, bz, fr0, c);
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) U[a][q] = uold[a * NE + c.e[q]];
+      cbx = bx;
+      cby = by;
+      cbz = bz;
+    }
     const double fr[3] = {xi[0] - bx, xi[1] - by, xi[2] - bz};
-    Cell c;
-    cell_setup(g, g.ny + 6, 3, bx, by, bz, fr, c);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       double gr[3];
-      r[a] = xi[a] + cell_eval(c, uold + a * NE, gr) - p[a];
+      r[a] = xi[a] + trilin_corners(U[a], fr, gr) - p[a];
 #pragma unroll
       for (int b = 0; b < 3; ++b) Jm[a][b] = (a == b ? 1.0 : 0.0) + gr[b];
     }

@@ -394,6 +394,14 @@ template <class T> struct Sim {
   std::vector<T> vplate;            // Cartesian plate velocity per column [nz][nx][3]
   std::vector<T> uplate[2];         // chart components at the node below (0) / above (1)
   bool have_geo = false, have_state = false;
+  // Diagnostic ablation (tests only): drop the velocity-gradient coefficient
+  // C^ij of Eq. (forcing-C) from every forcing term.  Not part of the method.
+  bool drop_C = false;
+  void ablate(Coef<T>& c) const {
+    if (!drop_C) return;
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) c.C[a][b] = T(0.0);
+  }
 
   Sim(int x, int y, int z, double t) : nx(x), ny(y), nz(z), H(y - 2), tau(t) {
     N = (long)nz * H * nx;
@@ -682,6 +690,7 @@ template <class T> struct Sim {
           node_gradient(rho, jv, i, jf + 1, k, dj);
           Coef<T> c;
           forcing_coefficients(G, jl, Tm, dj, c);
+          ablate(c);
           coef_store(coef, N, n, c);
         }
   }
@@ -771,6 +780,7 @@ template <class T> struct Sim {
           node_gradient(rho, jv, i, jf + 1, k, dj);
           Coef<T> c, cp;
           forcing_coefficients(G, jl, Tm, dj, c);
+          ablate(c);
           coef_store(coef, N, n, c);
           coef_load(Fp, N, n, cp);
           for (int l = 0; l < QN; ++l) {
@@ -1256,6 +1266,8 @@ void orc_set_plate_displacement(void* s, const double* d, int reproject) {
   ((Sim<double>*)s)->set_plate_displacement(d, reproject != 0);
 }
 void orc_set_plate_velocity(void* s, const double* v) { ((Sim<double>*)s)->set_plate_velocity(v); }
+// Diagnostic ablation for tests (bit 0: drop C^ij of Eq. forcing-C).
+void orc_set_ablation(void* s, int flags) { ((Sim<double>*)s)->drop_C = (flags & 1) != 0; }
 int orc_set_open_x(void* s, const double* uin) { return ((Sim<double>*)s)->set_open_x(uin) ? 0 : -1; }
 void orc_plate_force(void* s, double* total, double* per_col) { ((Sim<double>*)s)->plate_force(total, per_col); }
 void orc_geometry(void* s, double* out28) { ((Sim<double>*)s)->geometry_export(out28); }

@@ -71,6 +71,8 @@ def _lib():
         L.orc_set_plate.restype = ctypes.c_int
         L.orc_wall_force_mem.argtypes = [ctypes.c_void_p, ctypes.c_int, _D, _D]
         L.orc_wall_force_mem.restype = ctypes.c_int
+        L.orc_set_ablation.argtypes = [ctypes.c_void_p, ctypes.c_int]
+        L.orc_set_ablation.restype = None
         L.orc_set_open_x.argtypes = [ctypes.c_void_p, _D]
         L.orc_set_open_x.restype = ctypes.c_int
         L.orc_run_forces.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double, _D, _D, _D, ctypes.c_int, ctypes.c_int, _D, _D]
@@ -156,6 +158,11 @@ class Oracle:
         uin = _c(uin, (self.nz, self.H, 3))
         if _lib().orc_set_open_x(self._h, _p(uin)) != 0:
             raise ValueError("open ends need nx >= 3 and a plate at least 2 columns from each end")
+
+    def set_ablation(self, drop_C=False):
+        """Diagnostic only (not the method): drop the velocity-gradient
+        coefficient C^ij of Eq. (forcing-C) from every forcing term."""
+        _lib().orc_set_ablation(self._h, 1 if drop_C else 0)
 
     def set_plate_displacement(self, d, reproject=False):
         d = _c(d, (self.nz, self.nx))

@@ -28,16 +28,13 @@ HBM_PEAK_GBPS = 8000.0
 COUNTER_PROFILE = os.path.join(ROOT, "profiles", "step_fused_c2_256x128x128.md")
 STEP_SOURCES = ["paper_1803_07822_amd/csrc/lbm_step_fused.hip", "paper_1803_07822_amd/csrc/lbm_device.h",
                 "paper_1803_07822_amd/csrc/lbm_internal.h", "paper_1803_07822_amd/build.py"]
-# The FP32 step's kernels per launch variant (the default runs one kernel).
-TILE_OF_VARIANT = {0: (64, 4), 2: (64, 2), 3: (64, 1), 4: (128, 2), 5: (256, 1)}
 
 
 def step_kernel_name(variant, stage):
     """The FP32 step kernel a launch shape runs (lbm_get_tuning's variant and stage)."""
     if variant == 1:
         return "k_moments<float> + k_collide<float> (two-pass step; time of both)"
-    tx, ty = TILE_OF_VARIANT[variant]
-    return f"k_step_fused<float, {tx}, {ty}, {stage}, false, false> (whole step, one launch)"
+    return f"k_step_fused<float, 64, 4, {stage}, false, false> (whole step, one launch)"
 METRIC = "MLUPS + HBM GB/s (% peak) FP32 vs FP64 step; adjoint/forward time ratio"
 
 
@@ -49,17 +46,17 @@ def parse():
     p.add_argument("--workload", default="c2_bump_256x128x128")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward timing")
-    p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--fp64-steps", type=int, default=None)
     p.add_argument("--no-extra", action="store_true",
                    help="skip the oscillating-wall loop, the 512x256x256 runs and the flag channel")
-    p.add_argument("--part", choices=["all", "adjoint", "c3", "c5", "flag", "open"], default="all",
+    p.add_argument("--part", choices=["all", "adjoint", "c3", "c5", "c5adj", "flag", "open", "cpu_c5"],
+                   default="all",
                    help="run one measurement alone (for profiling): the 128x64x64 adjoint, the oscillating-wall "
-                        "loop, the 512x256x256 runs, the flag channel or the open channel at scale; prints that "
-                        "part's JSON only")
+                        "loop, the 512x256x256 runs, the 512x256x256 adjoint alone (from rest), the flag channel, "
+                        "the open channel at scale, or the oracle on the 512x256x256 workload; prints that part's "
+                        "JSON only")
     p.add_argument("--variant", type=int, default=0,
-                   help="launch variant of the step (lbm_set_tuning): 0 fused (default), 1 two-pass, 2-5 other "
-                        "fused tile shapes")
+                   help="launch variant of the step (lbm_set_tuning): 0 fused (default), 1 two-pass")
     p.add_argument("--stage", type=int, default=-1,
                    help="staging of the FP32 fused step (lbm_set_tuning): -1 the default, 0 none, 1 registers")
     p.add_argument("--counters", action="store_true",
@@ -83,9 +80,11 @@ def setup(w, precision, variant=0, stage=-1):
     return S, uc
 
 
-# The bump channel at tau 0.6 develops metric-induced spurious flow that
-# trips the instability guard after about 55 steps from rest, so steps are
-# timed in windows that each start from the equilibrium initial state.
+# The bump channel at tau 0.6 is unstable under the scheme (the explicit
+# velocity-gradient forcing C^ij outweighs the low BGK viscosity where the
+# 8 % bump bends the metric): the instability guard trips after about 55
+# steps from rest, so steps are timed in windows that each start from the
+# equilibrium initial state.
 WINDOW = 30
 LEAD_IN = 5
 
@@ -158,12 +157,13 @@ def adjoint_ratio(repeats=3):
             "ratio": round(b / f, 3), "forward_mlups": round(w.fluid_nodes * K / (f * 1e-3) / 1e6, 1)}
 
 
-def moving_wall_loop(w, wall_at, every, steps):
+def moving_wall_loop(w, wall_at, every, steps, keep_state=False):
     """FP32 run of workload `w` under a moving top wall: `steps` steps, the
     wall shape and velocity (wall_at(t) -> d [nz, nx], dd/dt [nz, nx]) updated
     with re-projection every `every` steps, the top-wall force recorded every
     step into device memory.  GPU time per phase from events on the library's
-    stream, and the host wall time of the whole loop."""
+    stream, and the host wall time of the whole loop.  keep_state: also
+    return the final populations (FP64, on the host)."""
     import numpy as np
     import torch
 
@@ -216,9 +216,10 @@ def moving_wall_loop(w, wall_at, every, steps):
            "metric_update_and_reprojection_ms": round(rp_ms / nup, 4),
            "wall_velocity_ms": round(vel_ms / nup, 4),
            "force_finite": bool(np.isfinite(f).all()), "final_force": [float(x) for x in f[-1]]}
+    state = S.populations().cpu() if keep_state else None
     del S, walls, forces
     torch.cuda.empty_cache()
-    return res
+    return (res, state) if keep_state else res
 
 
 def c3_loop():
@@ -272,15 +273,57 @@ def open_channel(steps=50, repeats=2):
     return out
 
 
-def c5_travelling():
+def c5_travelling(keep_state=False):
     """The 512x256x256 patch wave travelling, in FP32 at the run amplitude:
     3000 steps, the wall shape and velocity updated with re-projection every
-    10 steps (moving_wall_loop)."""
+    10 steps (moving_wall_loop); keep_state: also the final populations."""
     from paper_1803_07822_amd import synth
 
     w = synth.workload("c5_patch_wave_512x256x256")
     A = w.extra["A_run"]
-    return moving_wall_loop(w, lambda t: synth.patch_wave(A=A, t=t), w.extra["update_every"], w.steps)
+    return moving_wall_loop(w, lambda t: synth.patch_wave(A=A, t=t), w.extra["update_every"], w.steps, keep_state)
+
+
+def c5_adjoint(f_start, d_end=None, start="state after the 3000-step FP32 travelling run (FP64), "
+                                             "wall frozen at its t = 3000 shape, at rest"):
+    """The FP64 adjoint of the 512x256x256 workload over K = 100 steps with a
+    checkpoint every 10 (about 245 GiB of workspace), from f_start (the state
+    the 3000-step FP32 travelling run ended in, on the host, FP64): the wall
+    frozen at its shape at t = 3000, at rest; loss = sum of the top-wall
+    x-force over states 1..K.  Forward-record and backward times."""
+    import torch
+
+    from paper_1803_07822_amd import lbm, synth
+
+    w = synth.workload("c5_patch_wave_512x256x256")
+    K, N = w.extra["K"], w.extra["ckpt_every"]
+    if d_end is None:
+        d_end, _ = synth.patch_wave(A=w.extra["A_run"], t=float(w.steps))
+    try:
+        S = lbm.Solver(w.nx, w.ny, w.nz, w.tau, "fp64", adjoint_K=K, ckpt_every=N)
+        S.set_body_force(w.force)
+        S.set_wall_displacement(lbm.LBM_WALL_YMAX, d_end)
+        S.set_populations(f_start)
+        Wt = torch.zeros((K, 3), dtype=torch.float64, device=S.device)
+        Wt[:, 0] = 1.0
+        gd = torch.empty((w.nz, w.nx), dtype=torch.float64, device=S.device)
+        forces = torch.empty((K, 3), dtype=torch.float64, device=S.device)
+        S.sync()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        ev[0].record(S.stream)
+        lbm.lbm_forward_record(S.ctx, K, N, lbm.LBM_WALL_YMAX, forces)
+        ev[1].record(S.stream)
+        lbm.lbm_backward(S.ctx, Wt, gd, None, None)
+        ev[2].record(S.stream)
+        S.sync()
+        f, b = ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])
+        out = {"K": K, "ckpt_every": N, "start": start, "forward_ms": round(f, 2), "backward_ms": round(b, 2),
+               "ratio": round(b / f, 3), "grad_finite": bool(torch.isfinite(gd).all().item())}
+        del S
+    except (RuntimeError, lbm.LBMError) as e:  # e.g. not enough device memory for the workspace
+        out = {"error": str(e)[:200]}
+    torch.cuda.empty_cache()
+    return out
 
 
 def flag_channel(steps=None):
@@ -403,8 +446,8 @@ def c5_runs(steps=200):
     0.04*256): FP32 step throughput over `steps` steps from the equilibrium
     start with the wave frozen, the travelling wave over its 3000 steps with
     re-projection every 10 (c5_travelling), then the FP64 adjoint over K = 100
-    with a checkpoint every 10 (about 245 GiB of workspace): forward-record
-    and backward times."""
+    with a checkpoint every 10 (about 245 GiB of workspace) from the state the
+    travelling run ended in (c5_adjoint): forward-record and backward times."""
     import torch
 
     from paper_1803_07822_amd import lbm, synth
@@ -428,78 +471,99 @@ def c5_runs(steps=200):
                    "launch": dict(zip(("zchunk", "variant", "stage"), lbm.lbm_get_tuning(S.ctx)))}
     del S
     torch.cuda.empty_cache()
-    out["travelling"] = c5_travelling()
-    K, N = w.extra["K"], w.extra["ckpt_every"]
-    try:
-        S = lbm.Solver(w.nx, w.ny, w.nz, w.tau, "fp64", adjoint_K=K, ckpt_every=N)
-        S.set_body_force(w.force)
-        S.set_wall_displacement(lbm.LBM_WALL_YMAX, w.disp())
-        S.init_equilibrium()
-        Wt = torch.zeros((K, 3), dtype=torch.float64, device=S.device)
-        Wt[:, 0] = 1.0
-        gd = torch.empty((w.nz, w.nx), dtype=torch.float64, device=S.device)
-        forces = torch.empty((K, 3), dtype=torch.float64, device=S.device)
-        S.sync()
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
-        ev[0].record(S.stream)
-        lbm.lbm_forward_record(S.ctx, K, N, lbm.LBM_WALL_YMAX, forces)
-        ev[1].record(S.stream)
-        lbm.lbm_backward(S.ctx, Wt, gd, None, None)
-        ev[2].record(S.stream)
-        S.sync()
-        f, b = ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])
-        out["adjoint"] = {"K": K, "ckpt_every": N, "forward_ms": round(f, 2), "backward_ms": round(b, 2),
-                          "ratio": round(b / f, 3), "grad_finite": bool(torch.isfinite(gd).all().item())}
-        del S
-    except (RuntimeError, lbm.LBMError) as e:  # e.g. not enough device memory for the workspace
-        out["adjoint"] = {"error": str(e)[:200]}
-    torch.cuda.empty_cache()
+    out["travelling"], f_end = c5_travelling(keep_state=True)
+    out["adjoint"] = c5_adjoint(f_end)
     return out
 
 
+def c5_adjoint_rest():
+    """The 512x256x256 FP64 adjoint alone (K = 100, checkpoint every 10), from
+    the equilibrium state at rest under the frozen wave: the program the
+    adjoint's counter runs profile (the kernels' work does not depend on the
+    start state)."""
+    import torch
+
+    from paper_1803_07822_amd import lbm, synth
+
+    w = synth.workload("c5_patch_wave_512x256x256")
+    S = lbm.Solver(w.nx, w.ny, w.nz, w.tau, "fp64")
+    S.set_body_force(w.force)
+    S.set_wall_displacement(lbm.LBM_WALL_YMAX, w.disp())
+    S.init_equilibrium()
+    f0 = S.populations().cpu()
+    del S
+    torch.cuda.empty_cache()
+    return c5_adjoint(f0, d_end=w.disp(), start="equilibrium at rest under the frozen wave (t = 0)")
+
+
 def cpu_model():
+    """The host CPU as /proc/cpuinfo names it (model name, family, model,
+    stepping) and the cores this process may run on."""
+    info = {}
     try:
         with open("/proc/cpuinfo") as fh:
             for ln in fh:
-                if ln.startswith("model name"):
-                    return ln.split(":", 1)[1].strip()
+                k, _, v = ln.partition(":")
+                k = k.strip()
+                if k in ("model name", "cpu family", "model", "stepping") and k not in info:
+                    info[k] = v.strip()
     except OSError:
         pass
-    return "unknown"
+    return {"model_name": info.get("model name", "unknown"), "family": info.get("cpu family"),
+            "model": info.get("model"), "stepping": info.get("stepping"),
+            "cores_available": len(os.sched_getaffinity(0)), "cpu_count": os.cpu_count()}
 
 
-def cpu_baseline(w, budget_s):
-    """The FP64 oracle on this host's cores: same workload, bounded number of
-    steps (about budget_s seconds of stepping after set-up) with all cores,
-    then one step on a single thread."""
-    import numpy as np
-
+def oracle_rate(w, warm, timed, seed_noise=True):
+    """The FP64 oracle stepping workload w on all the cores it uses: `warm`
+    untimed steps, then `timed` timed steps; fluid-node updates per second."""
     import oracle
     from paper_1803_07822_amd import synth
 
     O = oracle.Oracle(w.nx, w.ny, w.nz, w.tau)
     O.set_body_force(w.force)
     O.set_wall_displacement(1, w.disp())
-    O.init_equilibrium(None, synth.uniform_noise_velocity(w.nx, w.ny, w.nz, 1e-4, seed=2))
-    O.step(1)  # warm-up
+    O.init_equilibrium(None, synth.uniform_noise_velocity(w.nx, w.ny, w.nz, 1e-4, seed=2) if seed_noise else None)
+    O.step(warm)
+    t0 = time.perf_counter()
+    O.step(timed)
+    t = time.perf_counter() - t0
+    return w.fluid_nodes * timed / t, t, O
+
+
+def cpu_baseline(w, warm=2, timed=20):
+    """The FP64 oracle on this host's cores, on the same workload: `warm`
+    warm-up steps, then `timed` timed steps with all cores, then one step on a
+    single thread."""
+    import oracle
+
     cores = oracle.threads()
-    n, t = 0, 0.0
-    while t < budget_s or n == 0:
-        t0 = time.perf_counter()
-        O.step(1)
-        t += time.perf_counter() - t0
-        n += 1
-    mlups = w.fluid_nodes * n / t / 1e6
+    rate, t, O = oracle_rate(w, warm, timed)
     oracle.set_threads(1)
     t0 = time.perf_counter()
     O.step(1)
     t1 = time.perf_counter() - t0
     oracle.set_threads(cores)
-    return {"value": round(mlups, 3), "unit": "MLUPS", "cores": cores, "kind": "oracle",
-            "sample": f"{n} FP64 steps of the full {w.nx}x{w.ny}x{w.nz} workload after 1 warm-up step ({t:.1f} s)",
+    return {"value": round(rate / 1e6, 3), "unit": "MLUPS", "cores": cores, "kind": "oracle",
+            "sample": f"{timed} FP64 steps of the full {w.nx}x{w.ny}x{w.nz} workload after {warm} warm-up steps "
+                      f"({t:.1f} s)",
             "single_thread": {"value": round(w.fluid_nodes / t1 / 1e6, 3), "unit": "MLUPS",
                               "sample": f"1 FP64 step of the same workload on one thread ({t1:.1f} s)"},
             "cpu": cpu_model()}
+
+
+def cpu_c5():
+    """The oracle on the 512x256x256 workload (33.3M fluid nodes), all cores:
+    2 warm-up steps, 5 timed (about a minute of CPU time, so not part of the
+    default run)."""
+    import oracle
+    from paper_1803_07822_amd import synth
+
+    w = synth.workload("c5_patch_wave_512x256x256")
+    print("cpu_c5: oracle set-up and 7 steps of the 512x256x256 workload", file=sys.stderr, flush=True)
+    rate, t, _ = oracle_rate(w, 2, 5, seed_noise=False)
+    return {"workload": w.name, "value": round(rate / 1e6, 3), "unit": "MLUPS", "cores": oracle.threads(),
+            "sample": f"5 FP64 steps after 2 warm-up steps ({t:.1f} s)", "cpu": cpu_model()}
 
 
 def step_source_hash():
@@ -619,7 +683,7 @@ def main():
         return
     if a.part != "all":
         part = {"adjoint": adjoint_ratio, "c3": c3_loop, "c5": c5_runs, "flag": flag_channel,
-                "open": open_channel}[a.part]()
+                "open": open_channel, "cpu_c5": cpu_c5, "c5adj": c5_adjoint_rest}[a.part]()
         print(json.dumps({"part": a.part, **part}), flush=True)
         return
     N = w.fluid_nodes
@@ -690,7 +754,7 @@ def main():
         out["flag_channel"] = flag_channel()
         out["open_channel"] = open_channel()
     if not a.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(w, a.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)
 
 

@@ -304,17 +304,17 @@ int lbm_backward(lbm_ctx* ctx, const double* d_dL_dF, double* d_grad_disp, doubl
 int lbm_step_profiled(lbm_ctx* ctx, int n, double* h_ms, int nslots);
 
 /* Launch shape of the step: zchunk = planes marched per block by the fused
- * step kernel (0 = chosen from the grid size); variant 0 = fused single-kernel
- * step on 64x4 tiles (x by y nodes per block), 1 = two kernels (moment pass,
- * collision pass), 2 = fused on 64x2 tiles, 3 = fused on 64x1, 4 = fused on
- * 128x2, 5 = fused on 256x1 (until this is called the choice is automatic:
- * fused on 64x4, two-pass on grids with open ends below 2^20 fluid nodes).
- * stage = where the fused step
- * keeps a plane's pulled populations between its moment pass and its
- * collision: 0 = nowhere (pulled again, from the caches), 1 = registers (FP32
- * only; FP64 runs 0), -1 = the default of the precision (1 in FP32, 0 in
- * FP64).  Results agree to rounding; only the speed differs.  EINVAL for
- * zchunk < 0, a variant outside 0..5 or a stage outside -1..1. */
+ * step kernel (0 = chosen from the grid size); variant 0 = fused
+ * single-kernel step on 64x4 tiles (x by y nodes per block), 1 = two kernels
+ * (moment pass, collision pass; what grids with open ends below 2^20 fluid
+ * nodes run by default, and otherwise a reference form of the same step).
+ * Until this is called the choice is automatic: fused, or two-pass on grids
+ * with open ends below 2^20 fluid nodes.  stage = where the fused step keeps
+ * a plane's pulled populations between its moment pass and its collision:
+ * 0 = nowhere (pulled again, from the caches), 1 = registers (FP32 only;
+ * FP64 runs 0), -1 = the default of the precision (1 in FP32, 0 in FP64).
+ * Results agree to rounding; only the speed differs.  EINVAL for zchunk < 0,
+ * a variant outside 0..1 or a stage outside -1..1. */
 int lbm_set_tuning(lbm_ctx* ctx, int zchunk, int variant, int stage);
 
 /* The launch shape the next step will use: *zchunk = planes per block of the

@@ -751,7 +751,7 @@ hipError_t step_into(Fields& F, const double* in, double* out, hipStream_t s, do
   F.hist[cur] = (void*)(in + 19 * Nn);
   F.pop[cur ^ 1] = out;
   F.hist[cur ^ 1] = out + 19 * Nn;
-  const bool with_mom = mom && step_is_fused(F) && F.tile == TILE_64x4 && !F.g.pj && !F.g.open;
+  const bool with_mom = mom && step_is_fused(F) && !F.g.pj && !F.g.open;
   const hipError_t e = with_mom ? launch_step_fused_moments<double>(F, s, tau, mom) : launch_step<double>(F, s, tau);
   if (wrote) *wrote = with_mom && e == hipSuccess;
   for (int b = 0; b < 2; ++b) {

@@ -514,13 +514,10 @@ int lbm_step_profiled(lbm_ctx* c, int n, double* h_ms, int nslots) {
 
 int lbm_set_tuning(lbm_ctx* c, int zchunk, int variant, int stage) {
   LBM_GUARD(c);
-  static const int tile_of[6] = {lbm::TILE_64x4, lbm::TILE_64x4, lbm::TILE_64x2,
-                                 lbm::TILE_64x1,  lbm::TILE_128x2, lbm::TILE_256x1};
-  if (zchunk < 0 || variant < 0 || variant > 5 || stage < -1 || stage > 1)
+  if (zchunk < 0 || variant < 0 || variant > 1 || stage < -1 || stage > 1)
     return fail(c, LBM_EINVAL, "bad tuning arguments");
   c->F.zc = zchunk;
-  c->F.variant = variant == 1 ? 1 : 0;
-  c->F.tile = tile_of[variant];
+  c->F.variant = variant;
   c->F.stage = stage >= 0 ? stage : default_stage(c->precision);
   return LBM_OK;
 }
@@ -534,8 +531,7 @@ int lbm_get_tuning(lbm_ctx* c, int* zchunk, int* variant, int* stage) {
     LBM_HIP(c, c->precision == LBM_FP64 ? lbm::fused_step_chunk<double>(c->F, &zc)
                                         : lbm::fused_step_chunk<float>(c->F, &zc));
   *zchunk = zc;
-  static const int variant_of[5] = {0, 2, 3, 4, 5};  // by tile shape
-  *variant = two_pass ? 1 : (c->F.g.pj ? 0 : variant_of[c->F.tile]);
+  *variant = two_pass ? 1 : 0;
   *stage = c->precision == LBM_FP64 ? 0 : c->F.stage;
   return LBM_OK;
 }

@@ -10,9 +10,6 @@
 namespace lbm {
 
 // Device buffers of one context, carved from the caller's workspace.
-// Tile shapes (x by y fluid nodes per block) of the fused step kernel.
-enum TileShape { TILE_64x4 = 0, TILE_64x2 = 1, TILE_64x1 = 2, TILE_128x2 = 3, TILE_256x1 = 4 };
-
 struct Fields {
   Grid g;
   long long NE;   // nodes of the y-extended grid, nz * (ny + 6) * nx
@@ -45,7 +42,6 @@ struct Fields {
   int moving[2];
   int zc = 0;        // planes per block of the fused step (0 = automatic)
   int variant = -1;  // -1: automatic (step_is_fused); 0: fused step; 1: two-pass step (moments pass + collision pass)
-  int tile = 0;      // tile shape of the fused step (TileShape)
   int stage = 1;     // FP32 fused step keeps pulled populations in registers
   int slots_key = -1;     // fused kernel whose resident-block count is cached
   long long slots = 0;    // resident blocks of that kernel on the device
@@ -123,7 +119,7 @@ template <class T> hipError_t launch_get_hist(Fields& F, hipStream_t s, double* 
 template <class T> hipError_t launch_get_geo(Fields& F, hipStream_t s, double* out);
 constexpr int STEP_KERNELS = 2;  // at most this many kernels per step (timed separately by lbm_step_profiled)
 template <class T> hipError_t launch_step(Fields& F, hipStream_t s, T tau, hipEvent_t* ev = nullptr);
-template <class T> hipError_t launch_step_fused(Fields& F, hipStream_t s, T tau, int zc, int ty);
+template <class T> hipError_t launch_step_fused(Fields& F, hipStream_t s, T tau, int zc);
 // Fused step (64x4 tiles, no staging) that also writes rho and rho u of the
 // state it steps from to mout [4][N]; periodic grids without a plate only.
 template <class T> hipError_t launch_step_fused_moments(Fields& F, hipStream_t s, T tau, T* mout);

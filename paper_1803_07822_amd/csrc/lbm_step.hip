@@ -646,7 +646,7 @@ template <class T> hipError_t launch_step(Fields& F, hipStream_t s, T tau, hipEv
   T* pout = (T*)F.pop[cur ^ 1];
   if (step_is_fused(F)) {
     mark(0);
-    if (e == hipSuccess) e = launch_step_fused<T>(F, s, tau, F.zc, F.tile);
+    if (e == hipSuccess) e = launch_step_fused<T>(F, s, tau, F.zc);
     mark(1);
     if (e == hipSuccess && g.open) {
       // The fused kernel treats x as periodic.  With open ends, the end

@@ -523,18 +523,11 @@ template <class T, int TX, int TY, bool PL = false> hipError_t chunk_tile(Fields
   return fused_chunk<T, TX, TY, STAGE_NONE, PL>(F, F.zc, zc);
 }
 
-// Tile shapes (x by y nodes per block): 64x4 (default), 64x2, 64x1, 128x2,
-// 256x1.  A grid with an interior plate runs the plate-aware kernel on 64x4
-// tiles whatever the shape asked for.
-template <class T> hipError_t launch_step_fused(Fields& F, hipStream_t s, T tau, int zc, int tile) {
+// The fused step runs on 64x4 tiles (x by y nodes per block); a grid with an
+// interior plate runs the plate-aware instantiation.
+template <class T> hipError_t launch_step_fused(Fields& F, hipStream_t s, T tau, int zc) {
   if (F.g.pj) return launch_fused_tile<T, 64, 4, true>(F, s, tau, zc);
-  switch (tile) {
-    case TILE_64x2: return launch_fused_tile<T, 64, 2>(F, s, tau, zc);
-    case TILE_64x1: return launch_fused_tile<T, 64, 1>(F, s, tau, zc);
-    case TILE_128x2: return launch_fused_tile<T, 128, 2>(F, s, tau, zc);
-    case TILE_256x1: return launch_fused_tile<T, 256, 1>(F, s, tau, zc);
-    default: return launch_fused_tile<T, 64, 4>(F, s, tau, zc);
-  }
+  return launch_fused_tile<T, 64, 4>(F, s, tau, zc);
 }
 
 // The fused step on 64x4 tiles without register staging that also writes
@@ -548,19 +541,13 @@ template <class T> hipError_t launch_step_fused_moments(Fields& F, hipStream_t s
 
 template <class T> hipError_t fused_step_chunk(Fields& F, int* zc) {
   if (F.g.pj) return chunk_tile<T, 64, 4, true>(F, zc);
-  switch (F.tile) {
-    case TILE_64x2: return chunk_tile<T, 64, 2>(F, zc);
-    case TILE_64x1: return chunk_tile<T, 64, 1>(F, zc);
-    case TILE_128x2: return chunk_tile<T, 128, 2>(F, zc);
-    case TILE_256x1: return chunk_tile<T, 256, 1>(F, zc);
-    default: return chunk_tile<T, 64, 4>(F, zc);
-  }
+  return chunk_tile<T, 64, 4>(F, zc);
 }
 
 template hipError_t fused_step_chunk<double>(Fields&, int*);
 template hipError_t fused_step_chunk<float>(Fields&, int*);
-template hipError_t launch_step_fused<double>(Fields&, hipStream_t, double, int, int);
-template hipError_t launch_step_fused<float>(Fields&, hipStream_t, float, int, int);
+template hipError_t launch_step_fused<double>(Fields&, hipStream_t, double, int);
+template hipError_t launch_step_fused<float>(Fields&, hipStream_t, float, int);
 template hipError_t launch_step_fused_moments<double>(Fields&, hipStream_t, double, double*);
 
 }  // namespace lbm

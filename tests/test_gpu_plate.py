@@ -67,15 +67,14 @@ def _setup(nx, ny, nz, tau, plate, precision="fp64", variant=0):
 
 @pytest.mark.parametrize("shape,plate,variant", [((70, 12, 9), (5, 10, 40), 0), ((70, 12, 9), (5, 10, 40), 1),
                                                  ((70, 12, 9), (4, 0, 69), 0), ((33, 9, 5), (1, 3, 3), 0),
-                                                 ((33, 9, 5), (6, 0, 32), 1), ((70, 12, 9), (9, 60, 69), 4)])
+                                                 ((33, 9, 5), (6, 0, 32), 1), ((70, 12, 9), (9, 60, 69), 0)])
 def test_plate_step_parity_fp64(shape, plate, variant):
     """Curved chart (top bump plus the plate's spline), moving top wall and
     moving plate, body force, non-equilibrium start: populations, history,
     moments, wall and plate forces match the oracle after 1 and 12 steps, in
     the fused step and the two-pass step.  Plates next to a wall layer
     (jp = 1, jp = H - 1), one column long, over every column, and ending at
-    the last column; variant 4 (128x2 tiles) runs the plate-aware 64x4
-    kernel."""
+    the last column."""
     nx, ny, nz = shape
     S, O, f0 = _setup(nx, ny, nz, 0.7, plate, variant=variant)
     assert dev_err(_np(S.populations()), O.populations(), f0) < 1e-13

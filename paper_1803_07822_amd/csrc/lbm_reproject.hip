@@ -81,6 +81,10 @@ __device__ __forceinline__ double trilin_corners(const double F[8], const double
   return v;
 }
 
+// Newton step size at which psi counts as found, relative to the position:
+// far below the interpolation's own rounding in each storage precision.
+template <class T> constexpr double NEWTON_TOL = sizeof(T) == 4 ? 1e-10 : 1e-13;
+
 constexpr int NMF = 20;  // 0 rho, 1-3 j, 4-9 Pi, 10 A, 11-13 B, 14-19 C (Cartesian)
 
 // The moment fields are stored node by node ([node][20]): the 20 values of a
@@ -313,7 +317,7 @@ __global__ __launch_bounds__(BX * BY) void k_rp_new(Grid g, const double* __rest
       xi[a] -= d;
       dmax = fmax(dmax, fabs(d));
     }
-    if (dmax <= 1e-13 * (1.0 + fabs(xi[0]) + fabs(xi[1]) + fabs(xi[2]))) break;
+    if (dmax <= NEWTON_TOL<T> * (1.0 + fabs(xi[0]) + fabs(xi[1]) + fabs(xi[2]))) break;
   }
   // trilinear interpolation of the moment fields, y inside layers 0..ny-1
   double q1 = xi[1];

@@ -19,6 +19,7 @@
 // move with a fixed Cartesian velocity v: its chart components u_w = J^{-1} v
 // at the wall row enter the bounce-back and the gradient ghost, and their
 // dependence on J is carried back to the chart; v itself is a constant.
+#include <type_traits>
 #include <vector>
 
 #include "lbm_adjoint.h"
@@ -102,28 +103,28 @@ __device__ __forceinline__ void gradient_at(const Grid& g, const double* __restr
   for (int a = 0; a < 3; ++a)
 #pragma unroll
     for (int b = 0; b < 3; ++b) dj[a][b] = 0.0;
+  // Branch-free: every neighbour's loads are issued unconditionally (the
+  // solid neighbour's address is that of its ghost source), so that they
+  // overlap instead of each waiting for its own round trip.
   for_q([&](auto L) {
     constexpr int l = decltype(L)::value;
     if (l == 0) return;
     constexpr int x = cx(l), y = cy(l), z = cz(l);
     const int in = wrapa(p.i + x, g.nx), kn = wrapa(p.k + z, g.nz), jn = p.jf + y;
+    const bool fluid = y == 0 || (jn >= 0 && jn < g.H);
+    const unsigned m = nidx(g, in, fluid ? jn : p.jf, kn);
+    const double sgn = fluid ? 1.0 : -1.0;
     double jb[3];
-    if (jn >= 0 && jn < g.H) {
-      const unsigned m = nidx(g, in, jn, kn);
 #pragma unroll
-      for (int b = 0; b < 3; ++b) jb[b] = E(mom, (1 + b), g, m);
-    } else {
-      const unsigned m = nidx(g, in, p.jf, kn);
-#pragma unroll
-      for (int b = 0; b < 3; ++b) jb[b] = -E(mom, (1 + b), g, m);
+    for (int b = 0; b < 3; ++b) jb[b] = sgn * E(mom, (1 + b), g, m);
+    if (y != 0 && (mv0 || mv1)) {
       // a moving wall's ghost is 2 rho u_w - j, with the column's u_w
       const int w = jn < 0 ? 0 : 1;
-      if (w == 0 ? mv0 : mv1) {
-        const double r2 = 2.0 * E(mom, 0, g, m);
-        const size_t c = (((size_t)w * g.nz + kn) * g.nx + in) * 3;
+      const double rm = E(mom, 0, g, m);
+      const double r2 = (!fluid && (w == 0 ? mv0 : mv1)) ? 2.0 * rm : 0.0;
+      const size_t c = (((size_t)w * g.nz + kn) * g.nx + in) * 3;
 #pragma unroll
-        for (int b = 0; b < 3; ++b) jb[b] += r2 * uw[c + b];
-      }
+      for (int b = 0; b < 3; ++b) jb[b] += r2 * uw[c + b];
     }
     constexpr double fct = 3.0 * wgt(l);
 #pragma unroll
@@ -323,8 +324,14 @@ __global__ __launch_bounds__(BX) void k_adj_node(Grid g, int mode, const double*
   for (int a = 0; a < 3; ++a)
 #pragma unroll
     for (int b = 0; b < 3; ++b) E(ldj, (a * 3 + b), g, p.n) = djb[a][b];
+  // all 28 loads before the first store: the planes of lg may not be
+  // proven apart, so an interleaved read-modify-write would wait for each
+  // load in turn
+  double lgv[G_N];
 #pragma unroll
-  for (int q = 0; q < G_N; ++q) E(lg, q, g, p.n) += gbs[q][threadIdx.x];
+  for (int q = 0; q < G_N; ++q) lgv[q] = E(lg, q, g, p.n);
+#pragma unroll
+  for (int q = 0; q < G_N; ++q) E(lg, q, g, p.n) = lgv[q] + gbs[q][threadIdx.x];
 }
 
 // Transposed lattice gradient and the moment VJP:
@@ -351,12 +358,16 @@ __global__ __launch_bounds__(BX * BY) void k_adj_gather(Grid g, const double* __
     if (l == 0) return;
     constexpr int x = cx(l), y = cy(l), z = cz(l);
     constexpr double fct = 3.0 * wgt(l);
-    // x_src = p - c_l used this node as its neighbour in direction l
+    // x_src = p - c_l used this node as its neighbour in direction l (no
+    // branch: a solid x_src reads a fluid node of this layer and adds zero,
+    // so the loads of all directions overlap)
     const int js = p.jf - y;
-    if (js >= 0 && js < g.H) {
-      const unsigned m = nidx(g, wrapa(p.i - x, g.nx), js, wrapa(p.k - z, g.nz));
+    {
+      const bool fluid = y == 0 || (js >= 0 && js < g.H);
+      const unsigned m = nidx(g, wrapa(p.i - x, g.nx), fluid ? js : p.jf, wrapa(p.k - z, g.nz));
+      const double fm = fluid ? fct : 0.0;
       for (int b = 0; b < 3; ++b)
-        jb[b] += fct * (x * E(ldj, (0 * 3 + b), g, m) + y * E(ldj, (1 * 3 + b), g, m) + z * E(ldj, (2 * 3 + b), g, m));
+        jb[b] += fm * (x * E(ldj, (0 * 3 + b), g, m) + y * E(ldj, (1 * 3 + b), g, m) + z * E(ldj, (2 * 3 + b), g, m));
     }
     // wall ghost: node m' = p - (c_x, 0, c_z) in this layer, whose neighbour in
     // direction l is solid, used -j(p)
@@ -386,13 +397,30 @@ __global__ __launch_bounds__(BX * BY) void k_adj_gather(Grid g, const double* __
   for (int q = 0; q < 6; ++q) Pb[q] = E(lpb, q, g, p.n);
   const double keep = 1.0 - 1.0 / tau;
   double fb[Q];
-  for_q([&](auto L) {
-    constexpr int l = decltype(L)::value;
-    double v = pb_term<l>(Pb);
-    if (lfn) v += keep * streamed_adjoint<l>(g, lfn, p);
-    if (lf_add) v += E(lf_add, l, g, p.n);
-    fb[l] = v;
-  });
+  // the two optional inputs are tested once, outside the unrolled loop, so
+  // that the loads of all directions are issued together
+  auto fill = [&](auto has_s, auto has_a) {
+    for_q([&](auto L) {
+      constexpr int l = decltype(L)::value;
+      double v = pb_term<l>(Pb);
+      if constexpr (decltype(has_s)::value) v += keep * streamed_adjoint<l>(g, lfn, p);
+      if constexpr (decltype(has_a)::value) v += E(lf_add, l, g, p.n);
+      fb[l] = v;
+    });
+  };
+  using yes = std::true_type;
+  using no = std::false_type;
+  if (lfn) {
+    if (lf_add)
+      fill(yes{}, yes{});
+    else
+      fill(yes{}, no{});
+  } else {
+    if (lf_add)
+      fill(no{}, yes{});
+    else
+      fill(no{}, no{});
+  }
   double sgb = 0;
   moments_vjp(sg, S0, S1, rb, jb, fb, sgb);
   for_q([&](auto L) {

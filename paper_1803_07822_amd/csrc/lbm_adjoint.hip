@@ -136,11 +136,28 @@ __device__ __forceinline__ void gradient_at(const Grid& g, const double* __restr
   });
 }
 
+// a[q0 + q][n] += v[q] for q < NQ, every load before the first store (the
+// planes of a may not be proven apart, so an interleaved read-modify-write
+// would wait for each load in turn).
+template <int NQ>
+__device__ __forceinline__ void add_planes(double* __restrict__ a, int q0, const Grid& g, unsigned n, const double (&v)[NQ]) {
+  double o[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) o[q] = E(a, q0 + q, g, n);
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) E(a, q0 + q, g, n) = o[q] + v[q];
+}
+
 __device__ inline void add_geo_bar(const Grid& g, double* __restrict__ lg, unsigned n, const AGeoBar& gb) {
-  E(lg, G_SG, g, n) += gb.sg;
-  for (int q = 0; q < 6; ++q) E(lg, (G_GI + q), g, n) += gb.gi[q];
-  for (int q = 0; q < 18; ++q) E(lg, (G_GAM + q), g, n) += gb.gam[q];
-  for (int q = 0; q < 3; ++q) E(lg, (G_F + q), g, n) += gb.F[q];
+  double v[G_N];
+  v[G_SG] = gb.sg;
+#pragma unroll
+  for (int q = 0; q < 6; ++q) v[G_GI + q] = gb.gi[q];
+#pragma unroll
+  for (int q = 0; q < 18; ++q) v[G_GAM + q] = gb.gam[q];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) v[G_F + q] = gb.F[q];
+  add_planes<G_N>(lg, 0, g, n, v);
 }
 
 __device__ inline void zero_bar(AGeoBar& gb) {
@@ -486,14 +503,15 @@ __global__ __launch_bounds__(BX * BY) void k_adj_force(Grid g, int wall, const d
     for (int b = 0; b < 3; ++b) J[a][b] = E(jac, (a * 3 + b), g, p.n);
   // T^{i y} with y = 1: packed indices sym(i, 1)
   double Tb[6] = {0, 0, 0, 0, 0, 0};
-  double sgb = 0;
+  double sgb = 0, ljv[9];
   for (int i = 0; i < 3; ++i) {
     double wj = 0;
     for (int a = 0; a < 3; ++a) wj += W[a] * J[a][i];
     Tb[sym(i, 1)] += sgn * G.sg * wj;
     sgb += sgn * wj * o.T[sym(i, 1)];
-    for (int a = 0; a < 3; ++a) E(lj, (a * 3 + i), g, p.n) += sgn * G.sg * W[a] * o.T[sym(i, 1)];
+    for (int a = 0; a < 3; ++a) ljv[a * 3 + i] = sgn * G.sg * W[a] * o.T[sym(i, 1)];
   }
+  add_planes<9>(lj, 0, g, p.n, ljv);
   HSum h0;
   hsum_zero(h0);
   double cb[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
@@ -508,10 +526,7 @@ __global__ __launch_bounds__(BX * BY) void k_adj_force(Grid g, int wall, const d
     fb[l] = pb_term<l>(Pb);
   });
   moments_vjp(G.sg, o.S0, o.S1, rb, jb, fb, gb.sg);
-  for_q([&](auto L) {
-    constexpr int l = decltype(L)::value;
-    E(lf, l, g, p.n) += fb[l];
-  });
+  add_planes<Q>(lf, 0, g, p.n, fb);
   add_geo_bar(g, lg, p.n, gb);
 }
 

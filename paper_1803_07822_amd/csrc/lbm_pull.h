@@ -31,16 +31,18 @@ __device__ __forceinline__ Pos pos_at(const Grid& g, int i, int jf, int k) {
   return p;
 }
 
-// Regular pull: walls, plate and periodic x.
+// Regular pull: walls, plate and periodic x.  The cut test selects the
+// address, not a branch, so that the pulls of all directions are issued
+// together instead of each waiting for its own round trip.
 template <class T, int l>
 __device__ __forceinline__ T pull(const T* __restrict__ pop, const Grid& g, const Pos& p) {
   constexpr int x = cx(l), y = cy(l), z = cz(l);
-  if ((y > 0 && p.jf == 0) || (y < 0 && p.jf == g.H - 1) || plate_cut(g, p.i, p.jf, -x, -y))
-    return pop[(long long)opp(l) * g.N + p.n];
+  const bool cut = (y > 0 && p.jf == 0) || (y < 0 && p.jf == g.H - 1) || plate_cut(g, p.i, p.jf, -x, -y);
   const int is = x ? wrapd(p.i - x, g.nx) : p.i;
   const int ks = z ? wrapd(p.k - z, g.nz) : p.k;
   const int js = p.jf - y;
-  return pop[(long long)l * g.N + ((long long)ks * g.H + js) * g.nx + is];
+  const long long e = cut ? (long long)opp(l) * g.N + p.n : (long long)l * g.N + ((long long)ks * g.H + js) * g.nx + is;
+  return pop[e];
 }
 
 // rho and rho u of the streamed state at an interior node p (regular pulls):

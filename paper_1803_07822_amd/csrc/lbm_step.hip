@@ -111,10 +111,13 @@ __device__ __forceinline__ void streamed_moments(const T* __restrict__ pop, cons
 // j = 2 rho_m u_w - j_m of the fluid node m in the same column next to the wall;
 // a neighbour across the plate is replaced in the same way by the ghost of the
 // node m on this side in the neighbour's column, with the plate velocity.
-template <class T>
-__device__ __forceinline__ void lattice_gradient(const T* __restrict__ mom, const T* __restrict__ uw, const int mv0,
-                                                 const int mv1, const T* __restrict__ up, const Grid& g,
-                                                 const Pos& p, T dj[3][3]) {
+// PL: the grid has a plate; MV: a wall moves.  Each combination has its own
+// unrolled loop, so the common one (neither) has no branch between the
+// neighbours' loads.
+template <class T, bool PL, bool MV>
+__device__ __forceinline__ void lattice_gradient_t(const T* __restrict__ mom, const T* __restrict__ uw, const int mv0,
+                                                   const int mv1, const T* __restrict__ up, const Grid& g,
+                                                   const Pos& p, T dj[3][3]) {
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
@@ -127,30 +130,32 @@ __device__ __forceinline__ void lattice_gradient(const T* __restrict__ mom, cons
     const int in = !x ? p.i : (g.open ? min(max(p.i + x, 0), g.nx - 1) : wrapd(p.i + x, g.nx));
     const int kn = z ? wrapd(p.k + z, g.nz) : p.k;
     const int jn = p.jf + y;
+    // No branch around the loads: a cut link (plate) or a solid neighbour
+    // (wall) reads this layer's node for its mirror ghost 2 rho u - j, a
+    // fluid neighbour its own j; the choice is of address and sign.
+    const bool cutp = PL && plate_cut(g, p.i, p.jf, x, y);
+    const bool fluid = y == 0 || (jn >= 0 && jn < g.H);
+    const bool ghost = cutp || !fluid;
+    const long long m = ((long long)kn * g.H + (ghost ? p.jf : jn)) * g.nx + in;
+    const T sgn = ghost ? T(-1) : T(1);
     T jb[3];
-    if (plate_cut(g, p.i, p.jf, x, y)) {
-      const long long m = ((long long)kn * g.H + p.jf) * g.nx + in;
-      const T r2 = T(2) * (T(1) + mom[m]);
-      const long long c = (((long long)(p.jf == g.pj ? 1 : 0) * g.nz + kn) * g.nx + in) * 3;
 #pragma unroll
-      for (int b = 0; b < 3; ++b) jb[b] = r2 * up[c + b] - mom[(1 + b) * g.N + m];
-    } else if (jn >= 0 && jn < g.H) {
-      const long long m = ((long long)kn * g.H + jn) * g.nx + in;
-      jb[0] = mom[1 * g.N + m];
-      jb[1] = mom[2 * g.N + m];
-      jb[2] = mom[3 * g.N + m];
-    } else {
-      const int w = jn < 0 ? 0 : 1;
-      const long long m = ((long long)kn * g.H + p.jf) * g.nx + in;
-      jb[0] = -mom[1 * g.N + m];
-      jb[1] = -mom[2 * g.N + m];
-      jb[2] = -mom[3 * g.N + m];
-      if (w == 0 ? mv0 : mv1) {
-        const T r2 = T(2) * (T(1) + mom[m]);
+    for (int b = 0; b < 3; ++b) jb[b] = sgn * mom[(1 + b) * g.N + m];
+    if constexpr (y != 0 && (PL || MV)) {
+      const T r2 = T(2) * (T(1) + mom[m]);
+      if constexpr (PL) {
+        const long long c = (((long long)(p.jf == g.pj ? 1 : 0) * g.nz + kn) * g.nx + in) * 3;
+        const T rc = cutp ? r2 : T(0);
+#pragma unroll
+        for (int b = 0; b < 3; ++b) jb[b] += rc * up[c + b];
+      }
+      if constexpr (MV) {
+        const int w = jn < 0 ? 0 : 1;
+        const bool mvw = !fluid && (w == 0 ? mv0 : mv1);
         const long long c = (((long long)w * g.nz + kn) * g.nx + in) * 3;
-        jb[0] += r2 * uw[c];
-        jb[1] += r2 * uw[c + 1];
-        jb[2] += r2 * uw[c + 2];
+        const T rw = mvw ? r2 : T(0);
+#pragma unroll
+        for (int b = 0; b < 3; ++b) jb[b] += rw * uw[c + b];
       }
     }
     constexpr T f = T(3.0 * wgt(l));
@@ -161,6 +166,24 @@ __device__ __forceinline__ void lattice_gradient(const T* __restrict__ mom, cons
       if (z) dj[2][b] += T(z) * f * jb[b];
     }
   });
+}
+
+template <class T>
+__device__ __forceinline__ void lattice_gradient(const T* __restrict__ mom, const T* __restrict__ uw, const int mv0,
+                                                 const int mv1, const T* __restrict__ up, const Grid& g,
+                                                 const Pos& p, T dj[3][3]) {
+  const bool mv = mv0 || mv1;
+  if (g.pj) {
+    if (mv)
+      lattice_gradient_t<T, true, true>(mom, uw, mv0, mv1, up, g, p, dj);
+    else
+      lattice_gradient_t<T, true, false>(mom, uw, mv0, mv1, up, g, p, dj);
+  } else {
+    if (mv)
+      lattice_gradient_t<T, false, true>(mom, uw, mv0, mv1, up, g, p, dj);
+    else
+      lattice_gradient_t<T, false, false>(mom, uw, mv0, mv1, up, g, p, dj);
+  }
 }
 
 // ---------------------------------------------------------------- pass 1

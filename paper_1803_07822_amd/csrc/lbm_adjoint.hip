@@ -58,6 +58,28 @@ __device__ __forceinline__ unsigned nidx(const Grid& g, int i, int jf, int k) {
   return ((unsigned)k * g.H + jf) * g.nx + i;
 }
 
+// Row order of the node kernel (one 64-node row per workgroup): the hardware
+// deals workgroups round-robin over the 8 XCDs, so the launch gives each XCD
+// groups of ROW_GROUP consecutive rows in turn; a row's y-neighbours then sit
+// in the same L2 (512x256x256: 10.19 -> 9.74 ms per launch).
+constexpr int ROW_GROUP = 64;
+inline unsigned row_group_blocks(const Grid& g) {
+  const long long rows = (long long)((g.nx + BX - 1) / BX) * g.H * g.nz, per = 8LL * ROW_GROUP;
+  return (unsigned)((rows + per - 1) / per * per);
+}
+__device__ __forceinline__ bool row_group_node(const Grid& g, Node& p) {
+  const int ntx = (g.nx + BX - 1) / BX;
+  const int xcd = (int)(blockIdx.x % 8), slot = (int)(blockIdx.x / 8);
+  const int t = ((slot / ROW_GROUP) * 8 + xcd) * ROW_GROUP + slot % ROW_GROUP;
+  if (t >= ntx * g.H * g.nz) return false;
+  p.i = (t % ntx) * BX + threadIdx.x;
+  p.jf = (t / ntx) % g.H;
+  p.k = t / (ntx * g.H);
+  if (p.i >= g.nx) return false;
+  p.n = nidx(g, p.i, p.jf, p.k);
+  return true;
+}
+
 // Full populations f(t) = w + pulled deviation + F(t-1)/2 of a stored state.
 __device__ __forceinline__ void load_state(const Grid& g, const double* __restrict__ pop,
                                            const double* __restrict__ hist, const AGeo& G, const Node& p, double f[Q],
@@ -215,7 +237,7 @@ __global__ __launch_bounds__(BX) void k_adj_node(Grid g, int mode, const double*
                            double* __restrict__ lg, const double* __restrict__ uw, int mv0, int mv1,
                            double* __restrict__ ub) {
   Node p;
-  if (!fluid_node(g, p)) return;
+  if (!row_group_node(g, p)) return;
   const double th = 1.0 / 3.0;
   const bool with_old = mode == 0;
   // the geometry adjoint of the node is summed in LDS (one column of slots
@@ -836,7 +858,7 @@ hipError_t adjoint_backward(Fields& F, AdjointBuffers& A, hipStream_t s, int K, 
   const dim3 b(BX, BY), fg = fluid_grid(g), cg = col_grid(g), eg = ext_grid(g);
   // the node kernel runs one wave per SIMD: one-wave workgroups let each
   // SIMD take the next one as soon as its own wave ends
-  const dim3 nb(BX, 1), ng(fg.x, g.H, g.nz);
+  const dim3 nb(BX, 1), ng(row_group_blocks(g));
   double* mom = (double*)F.mom;
   const double* geo = (const double*)F.geo;
   int cur = 0;

@@ -45,6 +45,14 @@ __device__ __forceinline__ double& E(double* __restrict__ a, long long q, const 
   return *(double*)((char*)(a + (size_t)q * g.N) + e * 8u);
 }
 
+// Streaming (nontemporal) load and store of element e of plane q, for data a
+// kernel touches once: they leave L2 to the planes that are read again.
+__device__ __forceinline__ double EN(const double* __restrict__ a, long long q, const Grid& g, unsigned e) {
+  return __builtin_nontemporal_load((const double*)((const char*)(a + (size_t)q * g.N) + e * 8u));
+}
+__device__ __forceinline__ void ESN(double* __restrict__ a, long long q, const Grid& g, unsigned e, double v) {
+  __builtin_nontemporal_store(v, (double*)((char*)(a + (size_t)q * g.N) + e * 8u));
+}
 __device__ __forceinline__ bool fluid_node(const Grid& g, Node& p) {
   p.i = blockIdx.x * BX + threadIdx.x;
   p.jf = blockIdx.y * blockDim.y + threadIdx.y;
@@ -222,6 +230,16 @@ __device__ __forceinline__ double streamed_adjoint(const Grid& g, const double* 
   return E(lfn, lo, g,
            (jd >= 0 && jd < g.H) ? (unsigned)(l - lo) * (unsigned)g.N + ed : (unsigned)(opp(l) - lo) * (unsigned)g.N + p.n);
 }
+// The same, as a streaming load (the gather reads each value once).
+template <int l>
+__device__ __forceinline__ double streamed_adjoint_nt(const Grid& g, const double* __restrict__ lfn, const Node& p) {
+  constexpr int x = cx(l), y = cy(l), z = cz(l);
+  constexpr int lo = l < opp(l) ? l : opp(l);
+  const int jd = p.jf + y;
+  const unsigned ed = nidx(g, wrapa(p.i + x, g.nx), jd, wrapa(p.k + z, g.nz));
+  return EN(lfn, lo, g,
+           (jd >= 0 && jd < g.H) ? (unsigned)(l - lo) * (unsigned)g.N + ed : (unsigned)(opp(l) - lo) * (unsigned)g.N + p.n);
+}
 
 // Reverse of one step at each node (mode 0), or of the history of an initial
 // state (mode 1: only the new coefficients carry an adjoint).  The adjoints
@@ -246,8 +264,18 @@ __global__ __launch_bounds__(BX) void k_adj_node(Grid g, int mode, const double*
 #pragma unroll
   for (int q = 0; q < G_N; ++q) gbs[q][threadIdx.x] = 0.0;
   LdsGeoBar gb{&gbs[0][threadIdx.x], BX};
+  // streaming loads and stores for what this kernel touches once (the
+  // geometry, history, pulled populations and incoming coefficient adjoints;
+  // the adjoints it hands on): L2 keeps the momentum and the next state's
+  // adjoint, which neighbouring nodes read again
   AGeo G;
-  load_geo_full(g, geo, p.n, G);
+  G.sg = 1.0 + EN(geo, G_SG, g, p.n);
+#pragma unroll
+  for (int q = 0; q < 6; ++q) G.gi[q] = EN(geo, (G_GI + q), g, p.n) + ((q == 0 || q == 3 || q == 5) ? 1.0 : 0.0);
+#pragma unroll
+  for (int q = 0; q < 18; ++q) G.gam[q] = EN(geo, (G_GAM + q), g, p.n);
+#pragma unroll
+  for (int q = 0; q < 3; ++q) G.F[q] = EN(geo, (G_F + q), g, p.n);
   // forward: the moments of the state come from mom; the populations are
   // read once, for the non-equilibrium flux P, and not kept
   NodeFwd o;
@@ -268,7 +296,7 @@ __global__ __launch_bounds__(BX) void k_adj_node(Grid g, int mode, const double*
   }
   double Fp[10];
 #pragma unroll
-  for (int q = 0; q < 10; ++q) Fp[q] = E(hist, q, g, p.n);
+  for (int q = 0; q < 10; ++q) Fp[q] = EN(hist, q, g, p.n);
 #pragma unroll
   for (int q = 0; q < 6; ++q) o.bp[q] = Fp[4 + q];
   o.bp[0] -= th * Fp[0];
@@ -282,7 +310,7 @@ __global__ __launch_bounds__(BX) void k_adj_node(Grid g, int mode, const double*
     constexpr int lo = l < opp(l) ? l : opp(l);
     const bool wall = (y > 0 && p.jf == 0) || (y < 0 && p.jf == g.H - 1);
     const unsigned es = nidx(g, wrapa(p.i - x, g.nx), p.jf - y, wrapa(p.k - z, g.nz));
-    const double v = E(pop, lo, g, wall ? (unsigned)(opp(l) - lo) * (unsigned)g.N + p.n : (unsigned)(l - lo) * (unsigned)g.N + es);
+    const double v = EN(pop, lo, g, wall ? (unsigned)(opp(l) - lo) * (unsigned)g.N + p.n : (unsigned)(l - lo) * (unsigned)g.N + es);
     const double ne = wgt(l) + v + 0.5 * hermite_val<l>(o.isg, Fp[0], Fp + 1, o.bp) - hermite_val<l>(o.isg, o.rho, o.j, o.a2);
     if (x) o.P[0] += ne;
     if (y) o.P[3] += ne;
@@ -317,14 +345,14 @@ __global__ __launch_bounds__(BX) void k_adj_node(Grid g, int mode, const double*
     old_forcing_vjp(hFo, o.isg, Fp, o.bp, Fpb, sgo);
     gb.add_sg(sgo);
 #pragma unroll
-    for (int q = 0; q < 10; ++q) E(lpo, q, g, p.n) = Fpb[q];
+    for (int q = 0; q < 10; ++q) ESN(lpo, q, g, p.n, Fpb[q]);
   }
   double dj[3][3];
   gradient_at(g, mom, p, uw, MW && mv0, MW && mv1, dj);
   node_fwd_rest(Fp, G, dj, tau, false, o);
   double cb[10];
 #pragma unroll
-  for (int q = 0; q < 10; ++q) cb[q] = E(lpn, q, g, p.n);
+  for (int q = 0; q < 10; ++q) cb[q] = EN(lpn, q, g, p.n);
   double rb = 0, jb[3] = {0, 0, 0}, djb[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, Pb[6];
   node_vjp(nullptr, G, tau, with_old, o, hs, hb, cb, nullptr, Pb, rb, jb, djb, nullptr, gb);
   // moving walls: the bounce-back of a link into wall w loses
@@ -355,14 +383,14 @@ __global__ __launch_bounds__(BX) void k_adj_node(Grid g, int mode, const double*
     }
   }
 #pragma unroll
-  for (int q = 0; q < 6; ++q) E(lpb, q, g, p.n) = Pb[q];
-  E(lml, 0, g, p.n) = rb;
+  for (int q = 0; q < 6; ++q) ESN(lpb, q, g, p.n, Pb[q]);
+  ESN(lml, 0, g, p.n, rb);
 #pragma unroll
-  for (int a = 0; a < 3; ++a) E(lml, (1 + a), g, p.n) = jb[a];
+  for (int a = 0; a < 3; ++a) ESN(lml, (1 + a), g, p.n, jb[a]);
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int b = 0; b < 3; ++b) E(ldj, (a * 3 + b), g, p.n) = djb[a][b];
+    for (int b = 0; b < 3; ++b) ESN(ldj, (a * 3 + b), g, p.n, djb[a][b]);
   // all 28 loads before the first store: the planes of lg may not be
   // proven apart, so an interleaved read-modify-write would wait for each
   // load in turn
@@ -386,8 +414,8 @@ __global__ __launch_bounds__(BX * BY) void k_adj_gather(Grid g, const double* __
                              const double* __restrict__ uw, int mv0, int mv1, double* __restrict__ ub) {
   Node p;
   if (!fluid_node(g, p)) return;
-  double rb = E(lml, 0, g, p.n), jb[3] = {E(lml, 1, g, p.n), E(lml, 2, g, p.n), E(lml, 3, g, p.n)};
-  const double rho = E(mom, 0, g, p.n);
+  double rb = EN(lml, 0, g, p.n), jb[3] = {EN(lml, 1, g, p.n), EN(lml, 2, g, p.n), EN(lml, 3, g, p.n)};
+  const double rho = EN(mom, 0, g, p.n);
   // the ghost of a moving wall, 2 rho u_w - j, also carries rho and u_w
   const bool mw0 = MW && p.jf == 0 && mv0, mw1 = MW && p.jf == g.H - 1 && mv1;
   const size_t c0 = ((size_t)p.k * g.nx + p.i) * 3, c1 = (((size_t)g.nz + p.k) * g.nx + p.i) * 3;
@@ -429,11 +457,11 @@ __global__ __launch_bounds__(BX * BY) void k_adj_gather(Grid g, const double* __
     for (int b = 0; b < 3; ++b) ub[c0 + b] += ub0[b];
   if (mw1)
     for (int b = 0; b < 3; ++b) ub[c1 + b] += ub1[b];
-  const double sg = 1.0 + E(geo, G_SG, g, p.n);
-  const double S0 = rho / sg, S1[3] = {E(mom, 1, g, p.n) / sg, E(mom, 2, g, p.n) / sg, E(mom, 3, g, p.n) / sg};
+  const double sg = 1.0 + EN(geo, G_SG, g, p.n);
+  const double S0 = rho / sg, S1[3] = {EN(mom, 1, g, p.n) / sg, EN(mom, 2, g, p.n) / sg, EN(mom, 3, g, p.n) / sg};
   double Pb[6];
 #pragma unroll
-  for (int q = 0; q < 6; ++q) Pb[q] = E(lpb, q, g, p.n);
+  for (int q = 0; q < 6; ++q) Pb[q] = EN(lpb, q, g, p.n);
   const double keep = 1.0 - 1.0 / tau;
   double fb[Q];
   // the two optional inputs are tested once, outside the unrolled loop, so
@@ -442,7 +470,7 @@ __global__ __launch_bounds__(BX * BY) void k_adj_gather(Grid g, const double* __
     for_q([&](auto L) {
       constexpr int l = decltype(L)::value;
       double v = pb_term<l>(Pb);
-      if constexpr (decltype(has_s)::value) v += keep * streamed_adjoint<l>(g, lfn, p);
+      if constexpr (decltype(has_s)::value) v += keep * streamed_adjoint_nt<l>(g, lfn, p);
       if constexpr (decltype(has_a)::value) v += E(lf_add, l, g, p.n);
       fb[l] = v;
     });
@@ -464,7 +492,7 @@ __global__ __launch_bounds__(BX * BY) void k_adj_gather(Grid g, const double* __
   moments_vjp(sg, S0, S1, rb, jb, fb, sgb);
   for_q([&](auto L) {
     constexpr int l = decltype(L)::value;
-    E(lf_out, l, g, p.n) = fb[l];
+    ESN(lf_out, l, g, p.n, fb[l]);
   });
   E(lg, G_SG, g, p.n) += sgb;
 }

@@ -127,21 +127,41 @@ __device__ __forceinline__ bool march_setup(const Grid& g, int jlo, int jhi, Mar
 }
 
 // Plane k (wrapped) of NC components into one ring slot; layers outside the
-// extended grid are never read by an output inside [jlo, jhi].
+// extended grid are never read by an output inside [jlo, jhi].  Each thread
+// loads its (at most MPT) entries before writing any of them, and an entry
+// outside the grid reads a valid dummy address instead of branching, so the
+// loads of a plane are all in flight together.
+constexpr int MPT = (MN + BX * BY - 1) / (BX * BY);
 template <int NC>
 __device__ __forceinline__ void march_load(const Grid& g, const March& m, int k, const double* __restrict__ in,
                                            double (*slot)[MN]) {
   k = wrap(k, g.nz);
   const long long NE = (long long)g.nz * (g.ny + 6) * g.nx;
-  for (int e = m.ty * BX + m.tx; e < MN; e += BX * BY) {
+  double v[MPT][NC];
+  bool ok[MPT];
+#pragma unroll
+  for (int r = 0; r < MPT; ++r) {
+    const int e = m.ty * BX + m.tx + r * BX * BY;
     const int hx = e % MX, hy = e / MX;
     const int i = wrap(m.i0 - 1 + hx, g.nx), j = m.j0 - 1 + hy;
-    if (m.i0 - 1 + hx > g.nx || j < -3 || j > g.ny + 2) continue;
-    const long long p = eidx(g, i, j, k);
+    ok[r] = e < MN && !(m.i0 - 1 + hx > g.nx || j < -3 || j > g.ny + 2);
+    const long long p = ok[r] ? eidx(g, i, j, k) : 0;
 #pragma unroll
-    for (int c = 0; c < NC; ++c) slot[c][e] = in[c * NE + p];
+    for (int c = 0; c < NC; ++c) v[r][c] = in[c * NE + p];
   }
+#pragma unroll
+  for (int r = 0; r < MPT; ++r)
+    if (ok[r]) {
+      const int e = m.ty * BX + m.tx + r * BX * BY;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) slot[c][e] = v[r][c];
+    }
 }
+
+// Ring of four plane slots: the load of plane k+1 overwrites plane k-3, whose
+// last reader (the stencil of plane k-2) every thread has finished before
+// the barrier of the previous plane, so one barrier per plane suffices.
+__device__ __forceinline__ int rs(int k) { return (k + 4) & 3; }
 
 // G_i f = 3 sum_l w_l c_l^i f(x + c_l) of component c at the tile node, from
 // the ring (planes k-1, k, k+1 in slots sm, s0, sp).
@@ -168,22 +188,22 @@ __device__ __forceinline__ void march_grad(const double (*sm)[MN], const double 
 template <int NC>
 __global__ __launch_bounds__(BX * BY) void k_smooth(Grid g, int jlo, int jhi, const double* __restrict__ in,
                                                     double* __restrict__ out) {
-  __shared__ double ring[3][NC][MN];
+  __shared__ double ring[4][NC][MN];
   March m;
   if (!march_setup(g, jlo, jhi, m)) return;
   const long long NE = (long long)g.nz * (g.ny + 6) * g.nx;
   const int i = m.i0 + m.tx, j = m.j0 + m.ty;
   const bool act = i < g.nx && j <= jhi;
   const int e0 = (m.ty + 1) * MX + (m.tx + 1);
-  march_load<NC>(g, m, m.z0 - 1, in, ring[(m.z0 + 2) % 3]);
-  march_load<NC>(g, m, m.z0, in, ring[m.z0 % 3]);
+  march_load<NC>(g, m, m.z0 - 1, in, ring[rs(m.z0 - 1)]);
+  march_load<NC>(g, m, m.z0, in, ring[rs(m.z0)]);
   for (int k = m.z0; k < m.z1; ++k) {
-    march_load<NC>(g, m, k + 1, in, ring[(k + 1) % 3]);
+    march_load<NC>(g, m, k + 1, in, ring[rs(k + 1)]);
     __syncthreads();
     if (act) {
-      const double(*sm)[MN] = ring[(k + 2) % 3];
-      const double(*s0)[MN] = ring[k % 3];
-      const double(*sp)[MN] = ring[(k + 1) % 3];
+      const double(*sm)[MN] = ring[rs(k - 1)];
+      const double(*s0)[MN] = ring[rs(k)];
+      const double(*sp)[MN] = ring[rs(k + 1)];
       const long long p = eidx(g, i, j, k);
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
@@ -199,14 +219,13 @@ __global__ __launch_bounds__(BX * BY) void k_smooth(Grid g, int jlo, int jhi, co
         out[c * NE + p] = f0 - s;
       }
     }
-    __syncthreads();
   }
 }
 
 // J = I + G v and g = J^T J on layers [-1, ny]; J also stored at fluid nodes.
 __global__ __launch_bounds__(BX * BY) void k_jac_metric(Grid g, const double* __restrict__ v,
                                                         double* __restrict__ gext, double* __restrict__ jac) {
-  __shared__ double ring[3][3][MN];
+  __shared__ double ring[4][3][MN];
   const int jlo = -1, jhi = g.ny;
   March m;
   if (!march_setup(g, jlo, jhi, m)) return;
@@ -214,17 +233,17 @@ __global__ __launch_bounds__(BX * BY) void k_jac_metric(Grid g, const double* __
   const int i = m.i0 + m.tx, j = m.j0 + m.ty;
   const bool act = i < g.nx && j <= jhi;
   const int e0 = (m.ty + 1) * MX + (m.tx + 1);
-  march_load<3>(g, m, m.z0 - 1, v, ring[(m.z0 + 2) % 3]);
-  march_load<3>(g, m, m.z0, v, ring[m.z0 % 3]);
+  march_load<3>(g, m, m.z0 - 1, v, ring[rs(m.z0 - 1)]);
+  march_load<3>(g, m, m.z0, v, ring[rs(m.z0)]);
   for (int k = m.z0; k < m.z1; ++k) {
-    march_load<3>(g, m, k + 1, v, ring[(k + 1) % 3]);
+    march_load<3>(g, m, k + 1, v, ring[rs(k + 1)]);
     __syncthreads();
     if (act) {
       double J[3][3];
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         double d[3];
-        march_grad<3>(ring[(k + 2) % 3], ring[k % 3], ring[(k + 1) % 3], e0, a, d);
+        march_grad<3>(ring[rs(k - 1)], ring[rs(k)], ring[rs(k + 1)], e0, a, d);
 #pragma unroll
         for (int b = 0; b < 3; ++b) J[a][b] = (a == b ? 1.0 : 0.0) + d[b];
       }
@@ -242,7 +261,6 @@ __global__ __launch_bounds__(BX * BY) void k_jac_metric(Grid g, const double* __
           for (int b = 0; b < 3; ++b) jac[(a * 3 + b) * g.N + n] = J[a][b];
       }
     }
-    __syncthreads();
   }
 }
 
@@ -252,7 +270,7 @@ template <class T>
 __global__ __launch_bounds__(BX * BY) void k_geo(Grid g, const double* __restrict__ w, const double* __restrict__ gext,
                                                  const double* __restrict__ jac, double F0, double F1, double F2,
                                                  T* __restrict__ geo) {
-  __shared__ double ring[3][6][MN];
+  __shared__ double ring[4][6][MN];
   const int jlo = 1, jhi = g.ny - 2;
   March m;
   if (!march_setup(g, jlo, jhi, m)) return;
@@ -260,10 +278,10 @@ __global__ __launch_bounds__(BX * BY) void k_geo(Grid g, const double* __restric
   const int i = m.i0 + m.tx, j = m.j0 + m.ty;
   const bool act = i < g.nx && j <= jhi;
   const int e0 = (m.ty + 1) * MX + (m.tx + 1);
-  march_load<6>(g, m, m.z0 - 1, w, ring[(m.z0 + 2) % 3]);
-  march_load<6>(g, m, m.z0, w, ring[m.z0 % 3]);
+  march_load<6>(g, m, m.z0 - 1, w, ring[rs(m.z0 - 1)]);
+  march_load<6>(g, m, m.z0, w, ring[rs(m.z0)]);
   for (int k = m.z0; k < m.z1; ++k) {
-    march_load<6>(g, m, k + 1, w, ring[(k + 1) % 3]);
+    march_load<6>(g, m, k + 1, w, ring[rs(k + 1)]);
     __syncthreads();
     if (act) {
       const long long n = ((long long)k * g.H + (j - 1)) * g.nx + i;
@@ -283,7 +301,7 @@ __global__ __launch_bounds__(BX * BY) void k_geo(Grid g, const double* __restric
 #pragma unroll
       for (int q = 0; q < 6; ++q) {
         double d[3];
-        march_grad<6>(ring[(k + 2) % 3], ring[k % 3], ring[(k + 1) % 3], e0, q, d);
+        march_grad<6>(ring[rs(k - 1)], ring[rs(k)], ring[rs(k + 1)], e0, q, d);
         dg[0][q] = d[0];
         dg[1][q] = d[1];
         dg[2][q] = d[2];
@@ -310,7 +328,6 @@ __global__ __launch_bounds__(BX * BY) void k_geo(Grid g, const double* __restric
       for (int a = 0; a < 3; ++a)
         geo[(G_F + a) * g.N + n] = (T)(Ji[a][0] * Fc[0] + Ji[a][1] * Fc[1] + Ji[a][2] * Fc[2]);
     }
-    __syncthreads();
   }
 }
 

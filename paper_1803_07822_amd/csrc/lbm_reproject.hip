@@ -268,6 +268,8 @@ __global__ __launch_bounds__(BX * BY) void k_rp_new(Grid g, const double* __rest
   const long long NC = (long long)g.nz * g.ny * g.nx, NE = (long long)g.nz * (g.ny + 6) * g.nx;
   const long long pc = ((long long)k * g.ny + (jf + 1)) * g.nx + i;
   const double p[3] = {chart[pc], chart[NC + pc], chart[2 * NC + pc]};
+  // read before the search, so that its latency is not a phase of its own
+  const T sgd = geo[G_SG * g.N + n];
   // psi: xi + u_old(xi) = p.  Start from one fixed-point step off the node,
   // xi = p - u_old(node), which lands in the cell of the solution unless the
   // chart moved by most of a cell; the eight corners of the old displacement
@@ -393,7 +395,6 @@ __global__ __launch_bounds__(BX * BY) void k_rp_new(Grid g, const double* __rest
   for (int a = 0; a < 3; ++a) hist[(H_B + a) * g.N + n] = c.B[a];
 #pragma unroll
   for (int q = 0; q < 6; ++q) hist[(H_C + q) * g.N + n] = c.C[q];
-  const T sgd = geo[G_SG * g.N + n];
   const T isg = T(1) / (T(1) + sgd);
   T Fp[Q];
   forcing_pops(c, isg, Fp);

@@ -81,18 +81,22 @@ inline dim3 col_grid(const Grid& g) { return dim3((g.nx + BX - 1) / BX, (g.nz + 
 
 // XCD-aware numbering of the fluid-grid blocks (64 x 4 tiles, one z-plane
 // each).  The hardware deals blocks round-robin over the 8 XCDs; with a 1D
-// launch padded to a multiple of 8 blocks, each XCD takes a contiguous range
-// of tiles in x-fastest order (a slab of z-planes), so the neighbour rows and
-// planes a node reads sit in the same L2.
+// launch padded to a multiple of 8 * XCD_TILES blocks, each XCD takes groups
+// of XCD_TILES consecutive tiles in x-fastest order, the XCDs taking
+// consecutive groups in turn: the neighbour rows a node reads mostly sit in
+// its own L2, and all XCDs stream neighbouring memory (one contiguous range
+// per XCD was 2.6 % slower for the re-projection at 512x256x256).
+constexpr int XCD_TILES = 32;
 inline dim3 xcd_fluid_grid(const Grid& g) {
-  const long long nb = (long long)((g.nx + BX - 1) / BX) * ((g.H + BY - 1) / BY) * g.nz;
-  return dim3((unsigned)((nb + 7) / 8 * 8));
+  const long long nb = (long long)((g.nx + BX - 1) / BX) * ((g.H + BY - 1) / BY) * g.nz, sweep = 8LL * XCD_TILES;
+  return dim3((unsigned)((nb + sweep - 1) / sweep * sweep));
 }
 
 __device__ __forceinline__ bool xcd_fluid_node(const Grid& g, int& i, int& jf, int& k) {
   const int ntx = (g.nx + BX - 1) / BX, nty = (g.H + BY - 1) / BY;
-  const int nb = ntx * nty * g.nz, per = (nb + 7) / 8;
-  const int t = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+  const int nb = ntx * nty * g.nz;
+  const int xs = (int)(blockIdx.x % 8), sl = (int)(blockIdx.x / 8);
+  const int t = ((sl / XCD_TILES) * 8 + xs) * XCD_TILES + sl % XCD_TILES;
   if (t >= nb) return false;
   i = (t % ntx) * BX + threadIdx.x;
   jf = ((t / ntx) % nty) * BY + threadIdx.y;

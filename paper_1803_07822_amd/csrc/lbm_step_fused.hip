@@ -461,12 +461,14 @@ template <class T> constexpr int reg_stage() { return sizeof(T) == 4 ? STAGE_REG
 // `slots` (resident blocks on the whole device); a chunk of zc planes costs
 // about zc + 1 plane-times (its two halo planes get moments only).  Take the
 // zc with the least rounds * (zc + 1); ties go to the smaller zc.  Chunks are
-// capped at ZC_MAX planes: longer ones spread each block's 86 streams over
-// more of every array at once, which costs more than the model's saved halo
-// planes (512x256x256: 32 planes 2.79 ms per step against 2.88 with 256).
-constexpr int ZC_MAX = 32;
-inline int choose_zc(long long tiles, int nz, long long slots) {
-  const int top = nz < ZC_MAX ? nz : ZC_MAX;
+// capped at zc_max<T>() planes: longer ones spread each block's 86 streams
+// over more of every array at once, which costs more than the model's saved
+// halo planes (512x256x256 FP32: 256 planes 2.88 ms per step, 32 planes 2.59,
+// 16 planes 2.57; 256x128x128 FP32: 32 planes 0.298 ms, 16 planes 0.295).  In
+// FP64 32 planes stay (256x128x128: 0.599 ms against 0.610 with 16).
+template <class T> constexpr int zc_max() { return sizeof(T) == 4 ? 16 : 32; }
+inline int choose_zc(long long tiles, int nz, long long slots, int zc_cap) {
+  const int top = nz < zc_cap ? nz : zc_cap;
   int best = top;
   long long best_cost = -1;
   for (int zc = 1; zc <= top; ++zc) {
@@ -499,7 +501,7 @@ hipError_t fused_chunk(Fields& F, int zc, int* out) {
       F.slots_key = key;
     }
     const long long tiles = (long long)((g.nx + TX - 1) / TX) * ((g.H + TY - 1) / TY);
-    zc = choose_zc(tiles, g.nz, F.slots);
+    zc = choose_zc(tiles, g.nz, F.slots, zc_max<T>());
   }
   *out = zc < g.nz ? zc : g.nz;
   return hipSuccess;

@@ -161,7 +161,8 @@ def moving_wall_loop(w, wall_at, every, steps, keep_state=False):
     """FP32 run of workload `w` under a moving top wall: `steps` steps, the
     wall shape and velocity (wall_at(t) -> d [nz, nx], dd/dt [nz, nx]) updated
     with re-projection every `every` steps, the top-wall force recorded every
-    step into device memory.  GPU time per phase from events on the library's
+    step into device memory (lbm_step_force: the force of each state a step
+    starts from, states 0 .. steps-1, formed by the fused step itself).  GPU time per phase from events on the library's
     stream, and the host wall time of the whole loop.  keep_state: also
     return the final populations (FP64, on the host)."""
     import numpy as np
@@ -192,9 +193,7 @@ def moving_wall_loop(w, wall_at, every, steps, keep_state=False):
     for u in range(nup):
         e = ev[u]
         e[0].record(S.stream)
-        for t in range(u * every, (u + 1) * every):
-            lbm.lbm_step(S.ctx, 1)
-            lbm.lbm_wall_force(S.ctx, lbm.LBM_WALL_YMAX, forces[t])
+        lbm.lbm_step_force(S.ctx, every, lbm.LBM_WALL_YMAX, forces[u * every:(u + 1) * every])
         e[1].record(S.stream)
         d, vc = walls[u]
         lbm.lbm_set_wall_displacement(S.ctx, lbm.LBM_WALL_YMAX, d, 1)

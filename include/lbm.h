@@ -43,10 +43,11 @@
  * the sync points (lbm_sync, lbm_moments, lbm_backward) and calls documented
  * as synchronising.
  *
- * Graph capture: lbm_step, lbm_couple, lbm_wall_force, lbm_plate_force and
- * the setters a time loop repeats (lbm_set_metric, lbm_set_wall_displacement,
- * lbm_set_wall_velocity, lbm_set_plate_displacement, lbm_set_plate_velocity,
- * lbm_set_body_force) enqueue kernels and device-to-device copies only (no
+ * Graph capture: lbm_step, lbm_step_force, lbm_couple, lbm_wall_force,
+ * lbm_plate_force and the setters a time loop repeats (lbm_set_metric,
+ * lbm_set_wall_displacement, lbm_set_wall_velocity,
+ * lbm_set_plate_displacement, lbm_set_plate_velocity, lbm_set_body_force)
+ * enqueue kernels and device-to-device copies only (no
  * memsets, no host waits), so a sequence of them may be captured on a
  * non-null context stream into a HIP graph and replayed.  The captured work
  * reads the argument pointers of the calls captured.
@@ -164,6 +165,19 @@ int lbm_get_geometry(lbm_ctx* ctx, double* d_geo28, double* d_jac9);
  * instability guard is reported at the next sync point).  EINVAL for n < 0,
  * ESTATE before a state exists. */
 int lbm_step(lbm_ctx* ctx, int n);
+
+/* n >= 0 steps as lbm_step, each also giving the force of the fluid on `wall`
+ * (LBM_FORCE_STRESS, as lbm_wall_force: the traction of Sec. IV.A.2 with T
+ * from Eq. (fields3)) at the state it steps from: d_forces ([n][3] doubles,
+ * device) receives the forces of the states t0 .. t0+n-1, t0 being the state
+ * on entry; the force of the state left after the call comes from the next
+ * call or from lbm_wall_force.  The fused step forms the traction from the
+ * stress its collision computes, so the force costs no launch of its own;
+ * grids with a plate or open ends, or with the two-pass step selected, run
+ * lbm_wall_force and then the step, with the same result up to rounding.
+ * EINVAL for n < 0, a bad wall or a NULL output (n > 0); ESTATE before a
+ * state exists.  Capture-safe as lbm_step. */
+int lbm_step_force(lbm_ctx* ctx, int n, int wall, double* d_forces);
 
 /* rho = sqrt g sum f, u = (sqrt g sum f c)/rho (Eqs. fields1-2); u in chart
  * components, or Cartesian (J u) if cartesian != 0.  Either output may be

@@ -36,6 +36,7 @@ struct Fields {
   void* mf;       // [NC][20] T: Cartesian moment fields for re-projection, deviations from rest
   double* part;   // wall-force reduction: 3 doubles per block
   unsigned* count;// wall-force reduction: blocks done (zero between launches)
+  double* fpart;  // wall force of the fused step: 3 doubles per (tile column, z chunk), nx/64 * nz of them
   int* flag;      // instability guard
   int cur;        // index of the current population and history buffers
   int uext_cur;   // index of the current extended displacement
@@ -43,8 +44,11 @@ struct Fields {
   int zc = 0;        // planes per block of the fused step (0 = automatic)
   int variant = -1;  // -1: automatic (step_is_fused); 0: fused step; 1: two-pass step (moments pass + collision pass)
   int stage = 1;     // FP32 fused step keeps pulled populations in registers
-  int slots_key = -1;     // fused kernel whose resident-block count is cached
-  long long slots = 0;    // resident blocks of that kernel on the device
+  // resident blocks on the device of the fused-step instances used so far
+  // (key of the instance, count), so that alternating lbm_step and
+  // lbm_step_force query the device once per instance
+  int slots_key[4] = {-1, -1, -1, -1};
+  long long slots[4] = {0, 0, 0, 0};
 };
 
 constexpr int BX = 64, BY = 4;
@@ -124,6 +128,19 @@ template <class T> hipError_t launch_get_geo(Fields& F, hipStream_t s, double* o
 constexpr int STEP_KERNELS = 2;  // at most this many kernels per step (timed separately by lbm_step_profiled)
 template <class T> hipError_t launch_step(Fields& F, hipStream_t s, T tau, hipEvent_t* ev = nullptr);
 template <class T> hipError_t launch_step_fused(Fields& F, hipStream_t s, T tau, int zc);
+// Output of the fused step's wall force (WF instantiation): the wall, J at
+// the fluid nodes, the partial sums, the completion counter and the total.
+struct WallOut {
+  int wall;
+  const double* jac;
+  double* part;
+  unsigned* count;
+  double* out;
+};
+// Fused step (automatic z chunk) that also writes the stress-method force on
+// `wall` of the state it steps from to out[3]; hipErrorNotSupported for grids
+// with a plate or open ends or with the two-pass step selected.
+template <class T> hipError_t launch_step_fused_force(Fields& F, hipStream_t s, T tau, int wall, double* out);
 // Fused step (64x4 tiles, no staging) that also writes rho and rho u of the
 // state it steps from to mout [4][N]; periodic grids without a plate only.
 template <class T> hipError_t launch_step_fused_moments(Fields& F, hipStream_t s, T tau, T* mout);

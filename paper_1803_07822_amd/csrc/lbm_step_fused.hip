@@ -231,16 +231,31 @@ enum Stage {
   STAGE_REG = 1,   // registers (two planes live across the collision)
 };
 
+// Sum of v over the 64 lanes of a wave by a butterfly of lane exchanges
+// (every lane ends with the same value).
+__device__ __forceinline__ double wave_sum64(double v) {
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+
 // MO: also write each node's rho and rho u (the streamed moments the step
 // collides with) to mout [4][N], for the adjoint's recompute steps.
-template <class T, int TX, int TY, int STAGE, bool PL, bool MO = false>
+// WF: also the force of the fluid on wall wo.wall at the state the step
+// collides (the traction sqrt g T^{iy} J[.][i] at the fluid layer next to the
+// wall, Sec. IV.A.2, from the T the collision forms anyway): each block whose
+// tile holds that layer sums its columns over its planes, stores the sum in
+// wo.part[tile column, z chunk] and counts itself done in wo.count; the last
+// of them adds the partial sums in index order into wo.out[3] and clears the
+// counter.
+template <class T, int TX, int TY, int STAGE, bool PL, bool MO = false, bool WF = false>
 __global__ __launch_bounds__(TX * TY) void k_step_fused(Grid g, int ntx, int nty, int nzc, int zc,
                                                    const T* __restrict__ pin, T* __restrict__ pout,
                                                    const T* __restrict__ hist, T* __restrict__ hout,
                                                    const T* __restrict__ geo,
                                                    const T* __restrict__ uw, int mv0, int mv1,
                                                    const T* __restrict__ up, T tau,
-                                                   int* __restrict__ flag, T* __restrict__ mout) {
+                                                   int* __restrict__ flag, T* __restrict__ mout, WallOut wo) {
   constexpr int HN = Tile<TX, TY>::HN, HX = Tile<TX, TY>::HX;
   // Four ring slots: the fill of plane k+1 overwrites plane k-3, whose last
   // reader (the collision of plane k-2) every thread has finished before
@@ -266,6 +281,11 @@ __global__ __launch_bounds__(TX * TY) void k_step_fused(Grid g, int ntx, int nty
   const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
   const int i = i0 + tx, jf = j0 + ty;
   const bool active = i < g.nx && jf < g.H;
+
+  // wall force: the fluid layer next to the wall and its sign
+  [[maybe_unused]] const int wrow = wo.wall == 0 ? 0 : g.H - 1;
+  [[maybe_unused]] const double wsgn = wo.wall == 0 ? -1.0 : 1.0;
+  [[maybe_unused]] double tw[3] = {0.0, 0.0, 0.0};
 
   T cur[Q], nxt[Q];
   bool own = active;  // this thread's node is collided later in the chunk
@@ -365,6 +385,15 @@ __global__ __launch_bounds__(TX * TY) void k_step_fused(Grid g, int ntx, int nty
       for (int a = 0; a < 3; ++a) cp.B[a] = fld(hist, H_B + a, g, n);
 #pragma unroll
       for (int q = 0; q < 6; ++q) cp.C[q] = fldnt(hist, H_C + q, g, n);
+      // J at a wall-force node, loaded with the geometry so that its latency
+      // is not a round trip of its own (FP32; FP64 has no register room for
+      // it there and reads J after the node's stores)
+      [[maybe_unused]] double Jw[9];
+      if constexpr (WF && sizeof(T) == 4) {
+        if (jf == wrow)
+#pragma unroll
+          for (int q = 0; q < 9; ++q) Jw[q] = __builtin_nontemporal_load(wo.jac + (size_t)q * g.N + n);
+      }
       const T sg = T(1) + G.sgd, isg = T(1) / sg;
       const T rho = T(1) + dr, irho = T(1) / rho;
       // equilibrium coefficients (deviation form): a0 = rho - sqrt g,
@@ -387,6 +416,12 @@ __global__ __launch_bounds__(TX * TY) void k_step_fused(Grid g, int ntx, int nty
           const T pn = sgc[q] + isg * (T(0.5) * cp.C[q] - ae[q] - (a == bb ? a0e * T(1.0 / 3.0) : T(0)));
           Tm[q] = rho * T(1.0 / 3.0) * ((a == bb ? T(1) : T(0)) + G.gid[q]) + j[a] * j[bb] * irho + kneq * pn;
         }
+      // T^{iy} for the wall force, applied after this node's stores
+      [[maybe_unused]] T tiy[3];
+      if constexpr (WF) {
+#pragma unroll
+        for (int i2 = 0; i2 < 3; ++i2) tiy[i2] = Tm[sym(i2, 1)];
+      }
       Coef<T> c;
       forcing_coef(G, j, Tm, dj, c);
       // f*_l - w_l = (1 - 1/tau) g~_l + (w_l/sqrt g) h_l(a_eq/tau + a_F - a_Fprev/(2 tau))
@@ -441,6 +476,25 @@ __global__ __launch_bounds__(TX * TY) void k_step_fused(Grid g, int ntx, int nty
       for (int q = 0; q < 6; ++q) stw(hout + (size_t)(H_C + q) * g.N, n, c.C[q]);
       const T uu = j[0] * j[0] + j[1] * j[1] + j[2] * j[2];
       if (!(rho > T(0)) || !(uu < T(0.1) * rho * rho) || !isfinite(chk)) atomicOr(flag, 1);
+      if constexpr (WF) {
+        if (jf == wrow) {
+          const double sgw = 1.0 + (double)G.sgd;
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            double sa = 0.0;
+#pragma unroll
+            for (int i2 = 0; i2 < 3; ++i2) {
+              double ja;
+              if constexpr (sizeof(T) == 4)
+                ja = Jw[a * 3 + i2];
+              else
+                ja = wo.jac[(size_t)(a * 3 + i2) * g.N + n];
+              sa += (double)tiy[i2] * ja;
+            }
+            tw[a] += wsgn * sgw * sa;
+          }
+        }
+      }
     }
     if constexpr (STAGE == STAGE_REG)
       if (own)
@@ -448,6 +502,46 @@ __global__ __launch_bounds__(TX * TY) void k_step_fused(Grid g, int ntx, int nty
           constexpr int l = decltype(L)::value;
           cur[l] = nxt[l];
         });
+  }
+  if constexpr (WF) {
+    if (ty0 != wrow / TY) return;  // uniform per block: the tile holds no wall column
+    __shared__ double red[TX * TY / 64][3];
+    __shared__ unsigned last;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) tw[a] = wave_sum64(tw[a]);
+    if (lane == 0)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) red[wave][a] = tw[a];
+    __syncthreads();
+    const unsigned nwb = (unsigned)(ntx * nzc);  // blocks that take part
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        double sa = red[0][a];
+#pragma unroll
+        for (int w = 1; w < TX * TY / 64; ++w) sa += red[w][a];
+        wo.part[(size_t)(tzc * ntx + tx0) * 3 + a] = sa;
+      }
+      // publish the partial, then count this block as done
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      last = atomicAdd(wo.count, 1u) == nwb - 1;
+    }
+    __syncthreads();
+    if (!last || wave != 0) return;
+    // every other partial is visible past this point
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    double sp[3] = {0.0, 0.0, 0.0};
+    for (unsigned q = lane; q < nwb; q += 64)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) sp[a] += wo.part[(size_t)q * 3 + a];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) sp[a] = wave_sum64(sp[a]);
+    if (lane == 0) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) wo.out[a] = sp[a];
+      *wo.count = 0u;
+    }
   }
 }
 
@@ -484,42 +578,47 @@ inline int choose_zc(long long tiles, int nz, long long slots, int zc_cap) {
 
 // Planes per block for kernel k_step_fused<T, TX, TY, ST, PL>: zc if
 // positive, else the choice above for this device.
-template <class T, int TX, int TY, int ST, bool PL, bool MO = false>
+template <class T, int TX, int TY, int ST, bool PL, bool MO = false, bool WF = false>
 hipError_t fused_chunk(Fields& F, int zc, int* out) {
   const Grid g = F.g;
   if (zc <= 0) {
-    const int key = ((((int)sizeof(T) * 1000 + TX) * 100 + TY * 10 + ST) * 4) + (PL ? 1 : 0) + (MO ? 2 : 0);
-    if (F.slots_key != key) {
+    const int key = ((((int)sizeof(T) * 1000 + TX) * 100 + TY * 10 + ST) * 8) + (PL ? 1 : 0) + (MO ? 2 : 0) + (WF ? 4 : 0);
+    int hit = -1;
+    for (int q = 0; q < 4; ++q)
+      if (F.slots_key[q] == key) hit = q;
+    if (hit < 0) {
       int dev = 0, cus = 0, per_cu = 0;
       hipError_t e = hipGetDevice(&dev);
       if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
       if (e == hipSuccess)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_fused<T, TX, TY, ST, PL, MO>,
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_fused<T, TX, TY, ST, PL, MO, WF>,
                                                          Tile<TX, TY>::NT, 0);
       if (e != hipSuccess) return e;
-      F.slots = (long long)cus * (per_cu > 0 ? per_cu : 1);
-      F.slots_key = key;
+      hit = 0;
+      while (hit < 3 && F.slots_key[hit] >= 0) ++hit;  // a free entry, else the last
+      F.slots[hit] = (long long)cus * (per_cu > 0 ? per_cu : 1);
+      F.slots_key[hit] = key;
     }
     const long long tiles = (long long)((g.nx + TX - 1) / TX) * ((g.H + TY - 1) / TY);
-    zc = choose_zc(tiles, g.nz, F.slots, zc_max<T>());
+    zc = choose_zc(tiles, g.nz, F.slots[hit], zc_max<T>());
   }
   *out = zc < g.nz ? zc : g.nz;
   return hipSuccess;
 }
 
-template <class T, int TX, int TY, int ST, bool PL, bool MO = false>
-hipError_t fused_launch(Fields& F, hipStream_t s, T tau, int zc, T* mout = nullptr) {
+template <class T, int TX, int TY, int ST, bool PL, bool MO = false, bool WF = false>
+hipError_t fused_launch(Fields& F, hipStream_t s, T tau, int zc, T* mout = nullptr, WallOut wo = WallOut{}) {
   const Grid g = F.g;
-  const hipError_t e = fused_chunk<T, TX, TY, ST, PL, MO>(F, zc, &zc);
+  const hipError_t e = fused_chunk<T, TX, TY, ST, PL, MO, WF>(F, zc, &zc);
   if (e != hipSuccess) return e;
   const int ntx = (g.nx + TX - 1) / TX, nty = (g.H + TY - 1) / TY;
   const int nzc = (g.nz + zc - 1) / zc;
   const long long sweep = 8LL * XCD_GROUP;
   const unsigned nblk = (unsigned)(((long long)ntx * nty * nzc + sweep - 1) / sweep * sweep);
-  hipLaunchKernelGGL((k_step_fused<T, TX, TY, ST, PL, MO>), dim3(nblk), dim3(Tile<TX, TY>::NT), 0, s, g, ntx,
+  hipLaunchKernelGGL((k_step_fused<T, TX, TY, ST, PL, MO, WF>), dim3(nblk), dim3(Tile<TX, TY>::NT), 0, s, g, ntx,
                      nty, nzc, zc, (const T*)F.pop[F.cur], (T*)F.pop[F.cur ^ 1], (const T*)F.hist[F.cur],
                      (T*)F.hist[F.cur ^ 1], (const T*)F.geo, (const T*)F.uw, F.moving[0], F.moving[1],
-                     (const T*)F.up, tau, F.flag, mout);
+                     (const T*)F.up, tau, F.flag, mout, wo);
   F.cur ^= 1;
   return hipGetLastError();
 }
@@ -550,6 +649,17 @@ template <class T> hipError_t launch_step_fused_moments(Fields& F, hipStream_t s
   return fused_launch<T, 64, 4, STAGE_NONE, false, true>(F, s, tau, F.zc, mout);
 }
 
+// The fused step that also gives the force on a wall of the state it steps
+// from (stress method) into out[3]: grids without a plate or open ends, with
+// the fused step selected (hipErrorNotSupported otherwise; the caller then
+// takes lbm_wall_force and a plain step).
+template <class T> hipError_t launch_step_fused_force(Fields& F, hipStream_t s, T tau, int wall, double* out) {
+  if (F.g.pj || F.g.open || !step_is_fused(F) || !out) return hipErrorNotSupported;
+  const WallOut wo{wall, F.jac, F.fpart, F.count, out};
+  if (F.stage == STAGE_REG) return fused_launch<T, 64, 4, reg_stage<T>(), false, false, true>(F, s, tau, F.zc, nullptr, wo);
+  return fused_launch<T, 64, 4, STAGE_NONE, false, false, true>(F, s, tau, F.zc, nullptr, wo);
+}
+
 template <class T> hipError_t fused_step_chunk(Fields& F, int* zc) {
   if (F.g.pj) return chunk_tile<T, 64, 4, true>(F, zc);
   return chunk_tile<T, 64, 4>(F, zc);
@@ -558,6 +668,8 @@ template <class T> hipError_t fused_step_chunk(Fields& F, int* zc) {
 template hipError_t fused_step_chunk<double>(Fields&, int*);
 template hipError_t fused_step_chunk<float>(Fields&, int*);
 template hipError_t launch_step_fused<double>(Fields&, hipStream_t, double, int);
+template hipError_t launch_step_fused_force<double>(Fields&, hipStream_t, double, int, double*);
+template hipError_t launch_step_fused_force<float>(Fields&, hipStream_t, float, int, double*);
 template hipError_t launch_step_fused<float>(Fields&, hipStream_t, float, int);
 template hipError_t launch_step_fused_moments<double>(Fields&, hipStream_t, double, double*);
 

@@ -36,7 +36,7 @@ ERRORS = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EHIP", -4: "
 SYMBOLS = [
     "lbm_workspace_bytes", "lbm_create", "lbm_reserve_adjoint", "lbm_destroy", "lbm_set_body_force",
     "lbm_set_metric", "lbm_set_wall_displacement", "lbm_set_wall_velocity", "lbm_init_equilibrium",
-    "lbm_set_populations", "lbm_get_populations", "lbm_get_history", "lbm_get_geometry", "lbm_step",
+    "lbm_set_populations", "lbm_get_populations", "lbm_get_history", "lbm_get_geometry", "lbm_step", "lbm_step_force",
     "lbm_step_profiled", "lbm_set_tuning", "lbm_get_tuning", "lbm_stream_probe", "lbm_moments", "lbm_wall_force",
     "lbm_wall_force_noalloc", "lbm_couple", "lbm_set_plate", "lbm_set_plate_displacement", "lbm_set_plate_velocity", "lbm_plate_force",
     "lbm_set_open_x", "lbm_forward_record", "lbm_backward", "lbm_sync", "lbm_last_error",
@@ -65,6 +65,7 @@ _lib.lbm_get_populations.argtypes = [_P, _P]
 _lib.lbm_get_history.argtypes = [_P, _P]
 _lib.lbm_get_geometry.argtypes = [_P, _P, _P]
 _lib.lbm_step.argtypes = [_P, _I]
+_lib.lbm_step_force.argtypes = [_P, _I, _I, _P]
 _lib.lbm_step_profiled.argtypes = [_P, _I, ctypes.POINTER(ctypes.c_double), _I]
 _lib.lbm_set_tuning.argtypes = [_P, _I, _I, _I]
 _lib.lbm_stream_probe.argtypes = [_I, ctypes.c_longlong, _P, _P, _P]
@@ -199,6 +200,12 @@ def lbm_get_geometry(ctx, geo, jac=None):
 
 def lbm_step(ctx, n=1):
     return _check(ctx, _lib.lbm_step(ctx, int(n)))
+
+
+def lbm_step_force(ctx, n, wall, forces):
+    """n steps; forces [n, 3] (device, FP64) receives the force on `wall` of
+    each state stepped from."""
+    return _check(ctx, _lib.lbm_step_force(ctx, int(n), int(wall), _ptr(forces)))
 
 
 def lbm_step_profiled(ctx, n, nslots=4):

@@ -34,7 +34,7 @@ def step_kernel_name(variant, stage):
     """The FP32 step kernel a launch shape runs (lbm_get_tuning's variant and stage)."""
     if variant == 1:
         return "k_moments<float> + k_collide<float> (two-pass step; time of both)"
-    return f"k_step_fused<float, 64, 4, {stage}, false, false> (whole step, one launch)"
+    return f"k_step_fused<float, 64, 4, {stage}, false, false, false> (whole step, one launch)"
 METRIC = "MLUPS + HBM GB/s (% peak) FP32 vs FP64 step; adjoint/forward time ratio"
 
 

@@ -96,7 +96,7 @@ void carve_core(Carver& c, const Grid& g, int precision, Fields& F) {
   F.mf = c.take(sz * 20 * NC);
   F.part = (double*)c.take(sizeof(double) * 3 * (size_t)lbm::wall_force_blocks(g));
   F.count = (unsigned*)c.take(ALIGN);
-  F.fpart = (double*)c.take(sizeof(double) * 3 * (size_t)((g.nx + lbm::BX - 1) / lbm::BX) * g.nz);
+  F.fpart = (double*)c.take(sizeof(double) * 2 * 3 * (size_t)((g.nx + lbm::BX - 1) / lbm::BX) * g.nz);
   F.flag = (int*)c.take(ALIGN);
   F.cur = 0;
   F.uext_cur = 0;
@@ -486,14 +486,13 @@ int lbm_step_force(lbm_ctx* c, int n, int wall, double* d_forces) {
   if (wall != LBM_WALL_YMIN && wall != LBM_WALL_YMAX) return fail(c, LBM_EINVAL, "bad wall");
   if (n > 0 && !d_forces) return fail(c, LBM_EINVAL, "forces output is NULL");
   if (!c->have_state) return fail(c, LBM_ESTATE, "no state");
-  for (int t = 0; t < n; ++t) {
-    double* out = d_forces + 3 * (size_t)t;
-    hipError_t e = c->precision == LBM_FP64
-                       ? lbm::launch_step_fused_force<double>(c->F, c->stream, c->tau, wall, out)
-                       : lbm::launch_step_fused_force<float>(c->F, c->stream, (float)c->tau, wall, out);
-    if (e == hipErrorNotSupported) {
-      // plate, open ends or the two-pass step: the force kernel, then the step
-      (void)hipGetLastError();
+  hipError_t e = c->precision == LBM_FP64
+                     ? lbm::launch_steps_fused_force<double>(c->F, c->stream, c->tau, wall, n, d_forces)
+                     : lbm::launch_steps_fused_force<float>(c->F, c->stream, (float)c->tau, wall, n, d_forces);
+  if (e == hipErrorNotSupported) {
+    // plate, open ends or the two-pass step: the force kernel, then the step
+    for (int t = 0; t < n; ++t) {
+      double* out = d_forces + 3 * (size_t)t;
       if (c->precision == LBM_FP64) {
         LBM_HIP(c, lbm::launch_wall_force<double>(c->F, c->stream, wall, c->tau, out, nullptr, 0));
         LBM_HIP(c, lbm::launch_step<double>(c->F, c->stream, c->tau));
@@ -501,9 +500,9 @@ int lbm_step_force(lbm_ctx* c, int n, int wall, double* d_forces) {
         LBM_HIP(c, lbm::launch_wall_force<float>(c->F, c->stream, wall, (float)c->tau, out, nullptr, 0));
         LBM_HIP(c, lbm::launch_step<float>(c->F, c->stream, (float)c->tau));
       }
-    } else {
-      LBM_HIP(c, e);
     }
+  } else {
+    LBM_HIP(c, e);
   }
   if (n > 0) c->recorded = 0;
   return LBM_OK;

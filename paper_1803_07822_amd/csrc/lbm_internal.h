@@ -36,7 +36,7 @@ struct Fields {
   void* mf;       // [NC][20] T: Cartesian moment fields for re-projection, deviations from rest
   double* part;   // wall-force reduction: 3 doubles per block
   unsigned* count;// wall-force reduction: blocks done (zero between launches)
-  double* fpart;  // wall force of the fused step: 3 doubles per (tile column, z chunk), nx/64 * nz of them
+  double* fpart;  // wall force of the fused step: two halves of 3 doubles per (tile column, z chunk), nx/64 * nz each
   int* flag;      // instability guard
   int cur;        // index of the current population and history buffers
   int uext_cur;   // index of the current extended displacement
@@ -129,18 +129,21 @@ constexpr int STEP_KERNELS = 2;  // at most this many kernels per step (timed se
 template <class T> hipError_t launch_step(Fields& F, hipStream_t s, T tau, hipEvent_t* ev = nullptr);
 template <class T> hipError_t launch_step_fused(Fields& F, hipStream_t s, T tau, int zc);
 // Output of the fused step's wall force (WF instantiation): the wall, J at
-// the fluid nodes, the partial sums, the completion counter and the total.
+// the fluid nodes, this step's partial sums, and the previous step's partial
+// sums (count and destination of their total; prev_part null for none).
 struct WallOut {
   int wall;
   const double* jac;
   double* part;
-  unsigned* count;
-  double* out;
+  const double* prev_part;
+  int prev_n;
+  double* prev_out;
 };
-// Fused step (automatic z chunk) that also writes the stress-method force on
-// `wall` of the state it steps from to out[3]; hipErrorNotSupported for grids
-// with a plate or open ends or with the two-pass step selected.
-template <class T> hipError_t launch_step_fused_force(Fields& F, hipStream_t s, T tau, int wall, double* out);
+// n fused steps (automatic z chunk) that also write the stress-method force on
+// `wall` of each state stepped from to out[3 t]; hipErrorNotSupported (before
+// any launch) for grids with a plate or open ends or with the two-pass step
+// selected.
+template <class T> hipError_t launch_steps_fused_force(Fields& F, hipStream_t s, T tau, int wall, int n, double* out);
 // Fused step (64x4 tiles, no staging) that also writes rho and rho u of the
 // state it steps from to mout [4][N]; periodic grids without a plate only.
 template <class T> hipError_t launch_step_fused_moments(Fields& F, hipStream_t s, T tau, T* mout);

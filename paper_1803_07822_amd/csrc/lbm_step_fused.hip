@@ -244,10 +244,29 @@ __device__ __forceinline__ double wave_sum64(double v) {
 // WF: also the force of the fluid on wall wo.wall at the state the step
 // collides (the traction sqrt g T^{iy} J[.][i] at the fluid layer next to the
 // wall, Sec. IV.A.2, from the T the collision forms anyway): each block whose
-// tile holds that layer sums its columns over its planes, stores the sum in
-// wo.part[tile column, z chunk] and counts itself done in wo.count; the last
-// of them adds the partial sums in index order into wo.out[3] and clears the
-// counter.
+// tile holds that layer sums its columns over its planes into
+// wo.part[tile column, z chunk].  No block waits for another: block 0 of the
+// next step (or k_sum_force after the last one) adds the previous step's
+// partial sums, wo.prev_part[0 .. wo.prev_n), in index order into
+// wo.prev_out[3]; the kernel boundary orders them.
+__device__ __forceinline__ void sum_force_partials(const double* __restrict__ part, int np, double* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  double sp[3] = {0.0, 0.0, 0.0};
+  for (int q = lane; q < np; q += 64)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) sp[a] += part[(size_t)q * 3 + a];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) sp[a] = wave_sum64(sp[a]);
+  if (lane == 0)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) out[a] = sp[a];
+}
+
+// The last step's force of an lbm_step_force call: one wave.
+__global__ __launch_bounds__(64) void k_sum_force(const double* __restrict__ part, int np, double* __restrict__ out) {
+  sum_force_partials(part, np, out);
+}
+
 template <class T, int TX, int TY, int STAGE, bool PL, bool MO = false, bool WF = false>
 __global__ __launch_bounds__(TX * TY) void k_step_fused(Grid g, int ntx, int nty, int nzc, int zc,
                                                    const T* __restrict__ pin, T* __restrict__ pout,
@@ -267,6 +286,9 @@ __global__ __launch_bounds__(TX * TY) void k_step_fused(Grid g, int ntx, int nty
   // each XCD takes groups of XCD_GROUP consecutive tiles (x fastest, then y,
   // then z chunk), the XCDs taking consecutive groups in turn, so a tile's
   // neighbours mostly share its L2 while all XCDs stream neighbouring memory.
+  if constexpr (WF) {
+    if (blockIdx.x == 0 && wo.prev_part && threadIdx.x < 64) sum_force_partials(wo.prev_part, wo.prev_n, wo.prev_out);
+  }
   const int nb = ntx * nty * nzc;
   const int b = blockIdx.x;
   const int xcd = b % 8, slot = b / 8;
@@ -506,7 +528,6 @@ __global__ __launch_bounds__(TX * TY) void k_step_fused(Grid g, int ntx, int nty
   if constexpr (WF) {
     if (ty0 != wrow / TY) return;  // uniform per block: the tile holds no wall column
     __shared__ double red[TX * TY / 64][3];
-    __shared__ unsigned last;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int a = 0; a < 3; ++a) tw[a] = wave_sum64(tw[a]);
@@ -514,8 +535,7 @@ __global__ __launch_bounds__(TX * TY) void k_step_fused(Grid g, int ntx, int nty
 #pragma unroll
       for (int a = 0; a < 3; ++a) red[wave][a] = tw[a];
     __syncthreads();
-    const unsigned nwb = (unsigned)(ntx * nzc);  // blocks that take part
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0)
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         double sa = red[0][a];
@@ -523,25 +543,6 @@ __global__ __launch_bounds__(TX * TY) void k_step_fused(Grid g, int ntx, int nty
         for (int w = 1; w < TX * TY / 64; ++w) sa += red[w][a];
         wo.part[(size_t)(tzc * ntx + tx0) * 3 + a] = sa;
       }
-      // publish the partial, then count this block as done
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-      last = atomicAdd(wo.count, 1u) == nwb - 1;
-    }
-    __syncthreads();
-    if (!last || wave != 0) return;
-    // every other partial is visible past this point
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    double sp[3] = {0.0, 0.0, 0.0};
-    for (unsigned q = lane; q < nwb; q += 64)
-#pragma unroll
-      for (int a = 0; a < 3; ++a) sp[a] += wo.part[(size_t)q * 3 + a];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) sp[a] = wave_sum64(sp[a]);
-    if (lane == 0) {
-#pragma unroll
-      for (int a = 0; a < 3; ++a) wo.out[a] = sp[a];
-      *wo.count = 0u;
-    }
   }
 }
 
@@ -649,15 +650,36 @@ template <class T> hipError_t launch_step_fused_moments(Fields& F, hipStream_t s
   return fused_launch<T, 64, 4, STAGE_NONE, false, true>(F, s, tau, F.zc, mout);
 }
 
-// The fused step that also gives the force on a wall of the state it steps
-// from (stress method) into out[3]: grids without a plate or open ends, with
-// the fused step selected (hipErrorNotSupported otherwise; the caller then
-// takes lbm_wall_force and a plain step).
-template <class T> hipError_t launch_step_fused_force(Fields& F, hipStream_t s, T tau, int wall, double* out) {
+// n fused steps, each also giving the force on a wall of the state it steps
+// from (stress method) into out[3 t]: grids without a plate or open ends, with
+// the fused step selected (hipErrorNotSupported otherwise, before any launch;
+// the caller then takes lbm_wall_force and a plain step).  Step t writes its
+// partial sums into one half of F.fpart, step t+1 (or k_sum_force after the
+// last step) adds them up.
+template <class T> hipError_t launch_steps_fused_force(Fields& F, hipStream_t s, T tau, int wall, int n, double* out) {
   if (F.g.pj || F.g.open || !step_is_fused(F) || !out) return hipErrorNotSupported;
-  const WallOut wo{wall, F.jac, F.fpart, F.count, out};
-  if (F.stage == STAGE_REG) return fused_launch<T, 64, 4, reg_stage<T>(), false, false, true>(F, s, tau, F.zc, nullptr, wo);
-  return fused_launch<T, 64, 4, STAGE_NONE, false, false, true>(F, s, tau, F.zc, nullptr, wo);
+  if (n <= 0) return hipSuccess;
+  constexpr int ST = reg_stage<T>();
+  const bool staged = F.stage == STAGE_REG;
+  int zc = 0;
+  hipError_t e = staged ? fused_chunk<T, 64, 4, ST, false, false, true>(F, F.zc, &zc)
+                        : fused_chunk<T, 64, 4, STAGE_NONE, false, false, true>(F, F.zc, &zc);
+  if (e != hipSuccess) return e;
+  const int np = ((F.g.nx + 63) / 64) * ((F.g.nz + zc - 1) / zc);  // blocks holding the wall layer
+  const size_t half = 3 * (size_t)((F.g.nx + 63) / 64) * F.g.nz;
+  for (int t = 0; t < n; ++t) {
+    WallOut wo{wall, F.jac, F.fpart + half * (t & 1), nullptr, np, nullptr};
+    if (t > 0) {
+      wo.prev_part = F.fpart + half * ((t - 1) & 1);
+      wo.prev_out = out + 3 * (size_t)(t - 1);
+    }
+    e = staged ? fused_launch<T, 64, 4, ST, false, false, true>(F, s, tau, F.zc, nullptr, wo)
+               : fused_launch<T, 64, 4, STAGE_NONE, false, false, true>(F, s, tau, F.zc, nullptr, wo);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_sum_force, dim3(1), dim3(64), 0, s, (const double*)(F.fpart + half * ((n - 1) & 1)), np,
+                     out + 3 * (size_t)(n - 1));
+  return hipGetLastError();
 }
 
 template <class T> hipError_t fused_step_chunk(Fields& F, int* zc) {
@@ -668,8 +690,8 @@ template <class T> hipError_t fused_step_chunk(Fields& F, int* zc) {
 template hipError_t fused_step_chunk<double>(Fields&, int*);
 template hipError_t fused_step_chunk<float>(Fields&, int*);
 template hipError_t launch_step_fused<double>(Fields&, hipStream_t, double, int);
-template hipError_t launch_step_fused_force<double>(Fields&, hipStream_t, double, int, double*);
-template hipError_t launch_step_fused_force<float>(Fields&, hipStream_t, float, int, double*);
+template hipError_t launch_steps_fused_force<double>(Fields&, hipStream_t, double, int, int, double*);
+template hipError_t launch_steps_fused_force<float>(Fields&, hipStream_t, float, int, int, double*);
 template hipError_t launch_step_fused<float>(Fields&, hipStream_t, float, int);
 template hipError_t launch_step_fused_moments<double>(Fields&, hipStream_t, double, double*);
 

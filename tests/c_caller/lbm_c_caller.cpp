@@ -2,7 +2,8 @@
 // memory from the HIP runtime: no Python and no torch.  It runs the sheared
 // 32x16x16 channel (tau 0.8, body force 1e-6 along x, the top wall's
 // displacement read from a file) in FP64, and writes rho [fluid], the
-// Cartesian u [3][fluid] and the top-wall force [3] to an output file, so a
+// Cartesian u [3][fluid], the top-wall force [3] and then the top-wall forces
+// of 4 more steps taken with lbm_step_force [4][3] to an output file, so a
 // test can compare them with the same calls made through the Python binding.
 //
 // Usage: lbm_c_caller DISP.bin STEPS OUT.bin   (DISP.bin: nz*nx doubles)
@@ -56,12 +57,14 @@ int main(int argc, char** argv) {
 
   const size_t bytes = lbm_workspace_bytes(&grid, LBM_D3Q19, LBM_FP64, 0, 0);
   void* ws = nullptr;
-  double *d_disp = nullptr, *d_rho = nullptr, *d_u = nullptr, *d_force = nullptr;
+  double *d_disp = nullptr, *d_rho = nullptr, *d_u = nullptr, *d_force = nullptr, *d_forces = nullptr;
+  const int nsf = 4;  // steps of lbm_step_force
   if (!hip_ok(hipMalloc(&ws, bytes), "hipMalloc workspace") ||
       !hip_ok(hipMalloc((void**)&d_disp, sizeof(double) * ncol), "hipMalloc disp") ||
       !hip_ok(hipMalloc((void**)&d_rho, sizeof(double) * nf), "hipMalloc rho") ||
       !hip_ok(hipMalloc((void**)&d_u, sizeof(double) * 3 * nf), "hipMalloc u") ||
       !hip_ok(hipMalloc((void**)&d_force, sizeof(double) * 3), "hipMalloc force") ||
+      !hip_ok(hipMalloc((void**)&d_forces, sizeof(double) * 3 * nsf), "hipMalloc forces") ||
       !hip_ok(hipMemcpy(d_disp, disp.data(), sizeof(double) * ncol, hipMemcpyHostToDevice), "hipMemcpy disp"))
     return 1;
 
@@ -83,12 +86,15 @@ int main(int argc, char** argv) {
   check(lbm_step(ctx, steps), "lbm_step");
   check(lbm_moments(ctx, d_rho, d_u, 1), "lbm_moments");
   check(lbm_wall_force(ctx, LBM_WALL_YMAX, LBM_FORCE_STRESS, d_force, nullptr), "lbm_wall_force");
+  check(lbm_step_force(ctx, nsf, LBM_WALL_YMAX, d_forces), "lbm_step_force");
   check(lbm_sync(ctx), "lbm_sync");
 
-  std::vector<double> out(nf + 3 * nf + 3);
+  std::vector<double> out(nf + 3 * nf + 3 + 3 * nsf);
   if (!hip_ok(hipMemcpy(out.data(), d_rho, sizeof(double) * nf, hipMemcpyDeviceToHost), "hipMemcpy rho") ||
       !hip_ok(hipMemcpy(out.data() + nf, d_u, sizeof(double) * 3 * nf, hipMemcpyDeviceToHost), "hipMemcpy u") ||
-      !hip_ok(hipMemcpy(out.data() + 4 * nf, d_force, sizeof(double) * 3, hipMemcpyDeviceToHost), "hipMemcpy force"))
+      !hip_ok(hipMemcpy(out.data() + 4 * nf, d_force, sizeof(double) * 3, hipMemcpyDeviceToHost), "hipMemcpy force") ||
+      !hip_ok(hipMemcpy(out.data() + 4 * nf + 3, d_forces, sizeof(double) * 3 * nsf, hipMemcpyDeviceToHost),
+              "hipMemcpy forces"))
     return 1;
   FILE* fout = std::fopen(argv[3], "wb");
   if (!fout || std::fwrite(out.data(), sizeof(double), out.size(), fout) != out.size()) {
@@ -103,6 +109,7 @@ int main(int argc, char** argv) {
               "\"force\": [%.17g, %.17g, %.17g]}\n",
               first_error, first_call, early, steps, mass, out[4 * nf], out[4 * nf + 1], out[4 * nf + 2]);
   check(lbm_destroy(ctx), "lbm_destroy");
+  hipFree(d_forces);
   hipFree(d_force);
   hipFree(d_u);
   hipFree(d_rho);

@@ -35,10 +35,11 @@ def test_plain_caller_matches_python_binding(tmp_path):
     assert info["status"] == 0 and info["early_step"] == -4  # LBM_OK; the early step: LBM_ESTATE
     nf = nx * H * nz
     out = np.fromfile(tmp_path / "out.bin", dtype=np.float64)
-    assert out.size == 4 * nf + 3
+    assert out.size == 4 * nf + 3 + 12
     rho_c = out[:nf].reshape(nz, H, nx)
     u_c = out[nf:4 * nf].reshape(3, nz, H, nx)
-    f_c = out[4 * nf:]
+    f_c = out[4 * nf:4 * nf + 3]
+    fs_c = out[4 * nf + 3:].reshape(4, 3)
 
     S = lbm.Solver(nx, ny, nz, w.tau, "fp64")
     S.set_body_force(w.force)
@@ -51,3 +52,10 @@ def test_plain_caller_matches_python_binding(tmp_path):
     assert np.array_equal(u_c, u.cpu().numpy())
     assert np.array_equal(f_c, force.cpu().numpy())
     assert np.abs(u_c).max() > 0  # the drive has set up a flow
+    # four more steps, each with the top-wall force of the state it starts from
+    fs = torch.empty((4, 3), dtype=torch.float64, device=S.device)
+    lbm.lbm_step_force(S.ctx, 4, lbm.LBM_WALL_YMAX, fs)
+    S.sync()
+    assert np.array_equal(fs_c, fs.cpu().numpy())
+    # the first of them is the state the force above was taken from
+    assert np.abs(fs_c[0] - f_c).max() <= 1e-13 * np.abs(f_c).max()

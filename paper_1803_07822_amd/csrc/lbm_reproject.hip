@@ -336,14 +336,25 @@ __global__ __launch_bounds__(BX * BY) void k_rp_new(Grid g, const double* __rest
   double m[NMF];
 #pragma unroll
   for (int q = 0; q < NMF; ++q) m[q] = 0.0;
-#pragma unroll
-  for (int c = 0; c < 8; ++c) {
-    const int ox = c & 1, oy = (c >> 1) & 1, oz = (c >> 2) & 1;
+  auto corner = [&](auto C) {
+    constexpr int c = decltype(C)::value;
+    constexpr int ox = c & 1, oy = (c >> 1) & 1, oz = (c >> 2) & 1;
     const double w = (ox ? fr[0] : 1.0 - fr[0]) * (oy ? fr[1] : 1.0 - fr[1]) * (oz ? fr[2] : 1.0 - fr[2]);
     double mc[NMF];
     mf_load(mf, cl.e[c], mc);
 #pragma unroll
     for (int q = 0; q < NMF; ++q) m[q] += w * mc[q];
+  };
+  // A chart that moves the nodes along y only (a wall displaced along its
+  // normal) leaves psi on the node's own x and z, so the corners at x + 1 and
+  // z + 1 weigh exactly zero and adding them changes no bit of the sum.  The
+  // choice is made per wave (no lane diverges): the four-corner-pairs gather
+  // runs only when some lane of the wave needs it.
+  if (__any(fr[0] != 0.0 || fr[2] != 0.0)) {
+    Unroll<int, 8>::run(corner);
+  } else {
+    corner(std::integral_constant<int, 0>());
+    corner(std::integral_constant<int, 2>());
   }
 #pragma unroll
   for (int q = 0; q < NMF; ++q) m[q] += mf_rest(q);

@@ -266,6 +266,7 @@ int lbm_set_metric(lbm_ctx* c, const double* d_chart, int reproject) {
   if (!d_chart) return fail(c, LBM_EINVAL, "chart is NULL");
   if (reproject && !c->have_state) return fail(c, LBM_ESTATE, "re-projection needs a state");
   LBM_HIP(c, hipMemcpyAsync(c->F.chart, d_chart, sizeof(double) * 3 * c->F.NC, hipMemcpyDeviceToDevice, c->stream));
+  c->F.chart_yonly = 0;
   return geometry_dispatch(c, reproject);
 }
 

@@ -416,6 +416,7 @@ __global__ __launch_bounds__(BX * BY) void k_inlet_velocity(Grid g, const double
 hipError_t launch_chart_from_disp(Fields& F, hipStream_t s) {
   dim3 b(BX, BY), gr((F.g.nx + BX - 1) / BX, (F.g.ny + BY - 1) / BY, F.g.nz);
   hipLaunchKernelGGL(k_chart_from_disp, gr, b, 0, s, F.g, F.disp, F.dplate, F.chart);
+  F.chart_yonly = 1;
   return hipGetLastError();
 }
 
@@ -430,6 +431,7 @@ template <class T> hipError_t launch_geometry(Fields& F, hipStream_t s, const do
   const Grid g = F.g;
   dim3 b(BX, BY);
   double* u = F.uext[F.uext_cur];
+  F.uext_yonly[F.uext_cur] = F.chart_yonly;
   // marching grid: x tiles, layer tiles of [jlo, jhi], z chunks
   auto mg = [&](int jlo, int jhi) {
     return dim3((g.nx + BX - 1) / BX, (jhi - jlo + BY) / BY, (g.nz + MZC - 1) / MZC);

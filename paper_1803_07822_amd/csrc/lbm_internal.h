@@ -40,6 +40,12 @@ struct Fields {
   int* flag;      // instability guard
   int cur;        // index of the current population and history buffers
   int uext_cur;   // index of the current extended displacement
+  // The chart, and the chart each extended displacement was built from, moves
+  // the nodes along y only (it was built from wall and plate displacements):
+  // their x and z displacements are exactly zero.  A chart given whole counts
+  // as general.
+  int chart_yonly = 0;
+  int uext_yonly[2] = {0, 0};
   int moving[2];
   int zc = 0;        // planes per block of the fused step (0 = automatic)
   int variant = -1;  // -1: automatic (step_is_fused); 0: fused step; 1: two-pass step (moments pass + collision pass)

@@ -258,7 +258,9 @@ __global__ __launch_bounds__(BX * BY) void k_rp_ghost(Grid g, const double* __re
 
 // New state at the new fluid nodes: the streamed deviations g~ written
 // straight into the pull layout, and the new history (storage precision).
-template <class T>
+// Y: the old and the new chart both move the nodes along y only, so psi keeps
+// the node's x and z and its search is one-dimensional.
+template <class T, bool Y>
 __global__ __launch_bounds__(BX * BY) void k_rp_new(Grid g, const double* __restrict__ chart, const double* __restrict__ uold,
                          const T* __restrict__ mf, const double* __restrict__ jac, const T* __restrict__ geo,
                          T* __restrict__ pop, T* __restrict__ hist) {
@@ -267,59 +269,86 @@ __global__ __launch_bounds__(BX * BY) void k_rp_new(Grid g, const double* __rest
   const long long n = ((long long)k * g.H + jf) * g.nx + i;
   const long long NC = (long long)g.nz * g.ny * g.nx, NE = (long long)g.nz * (g.ny + 6) * g.nx;
   const long long pc = ((long long)k * g.ny + (jf + 1)) * g.nx + i;
-  const double p[3] = {chart[pc], chart[NC + pc], chart[2 * NC + pc]};
   // read before the search, so that its latency is not a phase of its own
   const T sgd = geo[G_SG * g.N + n];
   // psi: xi + u_old(xi) = p.  Start from one fixed-point step off the node,
   // xi = p - u_old(node), which lands in the cell of the solution unless the
-  // chart moved by most of a cell; the eight corners of the old displacement
-  // are gathered once per cell and reused by the Newton iterations in it.
+  // chart moved by most of a cell; the corners of the old displacement are
+  // gathered once per cell and reused by the Newton iterations in it.
   const int side = jf >= g.pj ? 1 : 0;
+  const long long e0 = ((long long)k * (g.ny + 6) + (jf + 1 + 3)) * g.nx + i;
   double xi[3];
-  {
-    const long long e0 = ((long long)k * (g.ny + 6) + (jf + 1 + 3)) * g.nx + i;
+  if constexpr (Y) {
+    // x and z displacements are zero in both charts: xi = (i, y, k) with
+    // y + u_old,y(i, y, k) = p_y, linear between the two layers around y
+    const double py = chart[NC + pc];
+    const double* uy = uold + NE;
+    const long long col = (long long)k * (g.ny + 6) * g.nx + i;
+    xi[0] = (double)i;
+    xi[2] = (double)k;
+    xi[1] = py - uy[e0];
+    int cby = INT_MIN;
+    double U0 = 0.0, U1 = 0.0;
+    for (int it = 0; it < 50; ++it) {
+      int by = (int)floor(xi[1]);
+      if (by < -3) by = -3;
+      if (by > g.ny + 1) by = g.ny + 1;
+      by = plate_side_layer(g, side, i, by);
+      if (by != cby) {
+        U0 = uy[col + (long long)(by + 3) * g.nx];
+        U1 = uy[col + (long long)(by + 4) * g.nx];
+        cby = by;
+      }
+      const double fr = xi[1] - by;
+      const double r = xi[1] + ((1.0 - fr) * U0 + fr * U1) - py;
+      const double d = r / (1.0 + (U1 - U0));
+      xi[1] -= d;
+      if (fabs(d) <= NEWTON_TOL<T> * (1.0 + xi[0] + fabs(xi[1]) + xi[2])) break;
+    }
+  } else {
+    const double p[3] = {chart[pc], chart[NC + pc], chart[2 * NC + pc]};
 #pragma unroll
     for (int a = 0; a < 3; ++a) xi[a] = p[a] - uold[a * NE + e0];
-  }
-  int cbx = INT_MIN, cby = INT_MIN, cbz = INT_MIN;
-  double U[3][8];
-  for (int it = 0; it < 50; ++it) {
-    double r[3], Jm[3][3], Ji[3][3];
-    // cell of the extended grid (layers -3 .. ny+2) holding xi
-    const int bx = (int)floor(xi[0]), bz = (int)floor(xi[2]);
-    int by = (int)floor(xi[1]);
-    if (by < -3) by = -3;
-    if (by > g.ny + 1) by = g.ny + 1;
-    by = plate_side_layer(g, side, bx, by);
-    if (bx != cbx || by != cby || bz != cbz) {
-      Cell c;
-      const double fr0[3] = {0.0, 0.0, 0.0};
-      cell_setup(g, g.ny + 6, 3, bx, by, bz, fr0, c);
+    int cbx = INT_MIN, cby = INT_MIN, cbz = INT_MIN;
+    double U[3][8];
+    for (int it = 0; it < 50; ++it) {
+      double r[3], Jm[3][3], Ji[3][3];
+      // cell of the extended grid (layers -3 .. ny+2) holding xi
+      const int bx = (int)floor(xi[0]), bz = (int)floor(xi[2]);
+      int by = (int)floor(xi[1]);
+      if (by < -3) by = -3;
+      if (by > g.ny + 1) by = g.ny + 1;
+      by = plate_side_layer(g, side, bx, by);
+      if (bx != cbx || by != cby || bz != cbz) {
+        Cell c;
+        const double fr0[3] = {0.0, 0.0, 0.0};
+        cell_setup(g, g.ny + 6, 3, bx, by, bz, fr0, c);
 #pragma unroll
-      for (int a = 0; a < 3; ++a)
+        for (int a = 0; a < 3; ++a)
 #pragma unroll
-        for (int q = 0; q < 8; ++q) U[a][q] = uold[a * NE + c.e[q]];
-      cbx = bx;
-      cby = by;
-      cbz = bz;
+          for (int q = 0; q < 8; ++q) U[a][q] = uold[a * NE + c.e[q]];
+        cbx = bx;
+        cby = by;
+        cbz = bz;
+      }
+      const double fr[3] = {xi[0] - bx, xi[1] - by, xi[2] - bz};
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        double gr[3];
+        r[a] = xi[a] + trilin_corners(U[a], fr, gr) - p[a];
+#pragma unroll
+        for (int b = 0; b < 3; ++b) Jm[a][b] = (a == b ? 1.0 : 0.0) + gr[b];
+      }
+      inv3d(Jm, Ji);
+      double dmax = 0.0;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const double d = Ji[a][0] * r[0] + Ji[a][1] * r[1] + Ji[a][2] * r[2];
+        xi[a] -= d;
+        dmax = fmax(dmax, fabs(d));
+      }
+      if (dmax <= NEWTON_TOL<T> * (1.0 + fabs(xi[0]) + fabs(xi[1]) + fabs(xi[2]))) break;
     }
-    const double fr[3] = {xi[0] - bx, xi[1] - by, xi[2] - bz};
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      double gr[3];
-      r[a] = xi[a] + trilin_corners(U[a], fr, gr) - p[a];
-#pragma unroll
-      for (int b = 0; b < 3; ++b) Jm[a][b] = (a == b ? 1.0 : 0.0) + gr[b];
-    }
-    inv3d(Jm, Ji);
-    double dmax = 0.0;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const double d = Ji[a][0] * r[0] + Ji[a][1] * r[1] + Ji[a][2] * r[2];
-      xi[a] -= d;
-      dmax = fmax(dmax, fabs(d));
-    }
-    if (dmax <= NEWTON_TOL<T> * (1.0 + fabs(xi[0]) + fabs(xi[1]) + fabs(xi[2]))) break;
   }
   // trilinear interpolation of the moment fields, y inside layers 0..ny-1
   double q1 = xi[1];
@@ -447,7 +476,8 @@ template <class T> hipError_t launch_reproject(Fields& F, hipStream_t s, const d
   F.uext_cur ^= 1;
   hipError_t e = launch_geometry<T>(F, s, Fc);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_rp_new<T>, xcd_fluid_grid(g), b, 0, s, g, (const double*)F.chart, (const double*)F.uext[old],
+  auto* kn = F.chart_yonly && F.uext_yonly[old] ? k_rp_new<T, true> : k_rp_new<T, false>;
+  hipLaunchKernelGGL(kn, xcd_fluid_grid(g), b, 0, s, g, (const double*)F.chart, (const double*)F.uext[old],
                      (const T*)F.mf, (const double*)F.jac, (const T*)F.geo, (T*)F.pop[F.cur],
                      (T*)F.hist[F.cur]);
   return hipGetLastError();

@@ -172,6 +172,18 @@ def test_reprojection_parity_fp64():
     S.set_metric(ch, reproject=True)
     fo = O.populations()
     assert dev_err(_np(S.populations()), fo, fo) < 1e-12
+    # back to a wall-displacement chart: the old chart moves x and z, so the
+    # search for psi must be the three-dimensional one
+    O.set_wall_displacement(1, d1, reproject=True)
+    S.set_wall_displacement(1, d1, reproject=True)
+    fo = O.populations()
+    assert dev_err(_np(S.populations()), fo, fo) < 1e-12
+    assert np.abs(_np(S.history()) - O.history()).max() < 1e-13
+    # and on from there between two wall charts (one-dimensional search)
+    O.set_wall_displacement(1, d2, reproject=True)
+    S.set_wall_displacement(1, d2, reproject=True)
+    fo = O.populations()
+    assert dev_err(_np(S.populations()), fo, fo) < 1e-12
 
 
 def test_reprojection_parity_fp32():
@@ -215,6 +227,9 @@ def test_reprojection_parity_fp32():
     O.step(4)
     S.step(4)
     check("chart + 4 steps")
+    O.set_wall_displacement(1, d1, reproject=True)
+    S.set_wall_displacement(1, d1, reproject=True)
+    check("chart to wall")
     r, u = S.moments(cartesian=True)
     ro, uo = O.moments(cartesian=True)
     assert np.abs(_np(r) - ro).max() < 2e-6

@@ -50,6 +50,17 @@ struct Grid {
   int open;
 };
 
+// J = dh/dxi at fluid node n from its [9][N] planes.  A chart that moves the
+// nodes along y only (Y) has the rows (1, 0, 0) and (0, 0, 1), which are then
+// not read.
+template <bool Y>
+__device__ __forceinline__ void jac_at(const double* __restrict__ jac, long long N, long long n, double J[3][3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) J[a][b] = (!Y || a == 1) ? jac[(a * 3 + b) * N + n] : (a == b ? 1.0 : 0.0);
+}
+
 // The link from fluid node (i, jf) along (x, y) crosses the plate: it joins
 // rows pj - 1 and pj and crosses the half row at i + x/2 within
 // [pi0 - 1/2, pi1 + 1/2] on the periodic x axis, where the seam point

@@ -223,9 +223,13 @@ __global__ __launch_bounds__(BX * BY) void k_smooth(Grid g, int jlo, int jhi, co
 }
 
 // J = I + G v and g = J^T J on layers [-1, ny]; J also stored at fluid nodes.
+// Y: v moves the nodes along y only; its y component alone is read (v points
+// at it) and the rows (1, 0, 0), (0, 0, 1) of J are exact.
+template <bool Y>
 __global__ __launch_bounds__(BX * BY) void k_jac_metric(Grid g, const double* __restrict__ v,
                                                         double* __restrict__ gext, double* __restrict__ jac) {
-  __shared__ double ring[4][3][MN];
+  constexpr int NV = Y ? 1 : 3;
+  __shared__ double ring[4][NV][MN];
   const int jlo = -1, jhi = g.ny;
   March m;
   if (!march_setup(g, jlo, jhi, m)) return;
@@ -233,17 +237,17 @@ __global__ __launch_bounds__(BX * BY) void k_jac_metric(Grid g, const double* __
   const int i = m.i0 + m.tx, j = m.j0 + m.ty;
   const bool act = i < g.nx && j <= jhi;
   const int e0 = (m.ty + 1) * MX + (m.tx + 1);
-  march_load<3>(g, m, m.z0 - 1, v, ring[rs(m.z0 - 1)]);
-  march_load<3>(g, m, m.z0, v, ring[rs(m.z0)]);
+  march_load<NV>(g, m, m.z0 - 1, v, ring[rs(m.z0 - 1)]);
+  march_load<NV>(g, m, m.z0, v, ring[rs(m.z0)]);
   for (int k = m.z0; k < m.z1; ++k) {
-    march_load<3>(g, m, k + 1, v, ring[rs(k + 1)]);
+    march_load<NV>(g, m, k + 1, v, ring[rs(k + 1)]);
     __syncthreads();
     if (act) {
       double J[3][3];
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
-        double d[3];
-        march_grad<3>(ring[rs(k - 1)], ring[rs(k)], ring[rs(k + 1)], e0, a, d);
+        double d[3] = {0.0, 0.0, 0.0};
+        if (!Y || a == 1) march_grad<NV>(ring[rs(k - 1)], ring[rs(k)], ring[rs(k + 1)], e0, Y ? 0 : a, d);
 #pragma unroll
         for (int b = 0; b < 3; ++b) J[a][b] = (a == b ? 1.0 : 0.0) + d[b];
       }
@@ -266,7 +270,7 @@ __global__ __launch_bounds__(BX * BY) void k_jac_metric(Grid g, const double* __
 
 // Fluid-node geometry: g^{-1}, sqrt g = det J, Gamma^i_jk = 1/2 g^il (D_j g_kl
 // + D_k g_jl - D_l g_jk) with D_l g = G_l w, and F^i = (J^{-1} F_cart)^i.
-template <class T>
+template <class T, bool Y>
 __global__ __launch_bounds__(BX * BY) void k_geo(Grid g, const double* __restrict__ w, const double* __restrict__ gext,
                                                  const double* __restrict__ jac, double F0, double F1, double F2,
                                                  T* __restrict__ geo) {
@@ -290,10 +294,8 @@ __global__ __launch_bounds__(BX * BY) void k_geo(Grid g, const double* __restric
 #pragma unroll
       for (int a = 0; a < 3; ++a)
 #pragma unroll
-        for (int b = 0; b < 3; ++b) {
-          gm[a][b] = gext[sym(a, b) * NE + e];
-          J[a][b] = jac[(a * 3 + b) * g.N + n];
-        }
+        for (int b = 0; b < 3; ++b) gm[a][b] = gext[sym(a, b) * NE + e];
+      jac_at<Y>(jac, g.N, n, J);
       inv3(gm, gi, det);
       inv3(J, Ji, detJ);
       // dg[l][q] = D_l g_q
@@ -437,10 +439,23 @@ template <class T> hipError_t launch_geometry(Fields& F, hipStream_t s, const do
     return dim3((g.nx + BX - 1) / BX, (jhi - jlo + BY) / BY, (g.nz + MZC - 1) / MZC);
   };
   hipLaunchKernelGGL(k_uext, ext_grid(g), b, 0, s, g, F.chart, u);
-  hipLaunchKernelGGL(k_smooth<3>, mg(-2, g.ny + 1), b, 0, s, g, -2, g.ny + 1, u, F.vtmp);
-  hipLaunchKernelGGL(k_jac_metric, mg(-1, g.ny), b, 0, s, g, F.vtmp, F.gext, F.jac);
+  // A chart that moves the nodes along y only has x and z displacements of
+  // exactly zero, and so smoothed x and z components of exactly zero: once
+  // the three-component pass has written those, the y component alone is
+  // smoothed (the adjoint's chart gradient reads all three).
+  const bool y = F.chart_yonly;
+  if (y && F.vtmp_xz_zero)
+    hipLaunchKernelGGL(k_smooth<1>, mg(-2, g.ny + 1), b, 0, s, g, -2, g.ny + 1, u + F.NE, F.vtmp + F.NE);
+  else
+    hipLaunchKernelGGL(k_smooth<3>, mg(-2, g.ny + 1), b, 0, s, g, -2, g.ny + 1, u, F.vtmp);
+  F.vtmp_xz_zero = y;
+  if (y)
+    hipLaunchKernelGGL(k_jac_metric<true>, mg(-1, g.ny), b, 0, s, g, F.vtmp + F.NE, F.gext, F.jac);
+  else
+    hipLaunchKernelGGL(k_jac_metric<false>, mg(-1, g.ny), b, 0, s, g, F.vtmp, F.gext, F.jac);
   hipLaunchKernelGGL(k_smooth<6>, mg(0, g.ny - 1), b, 0, s, g, 0, g.ny - 1, F.gext, F.wext);
-  hipLaunchKernelGGL(k_geo<T>, mg(1, g.ny - 2), b, 0, s, g, F.wext, F.gext, F.jac, Fc[0], Fc[1], Fc[2], (T*)F.geo);
+  auto* kg = y ? k_geo<T, true> : k_geo<T, false>;
+  hipLaunchKernelGGL(kg, mg(1, g.ny - 2), b, 0, s, g, F.wext, F.gext, F.jac, Fc[0], Fc[1], Fc[2], (T*)F.geo);
   return hipGetLastError();
 }
 

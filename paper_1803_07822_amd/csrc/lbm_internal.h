@@ -46,6 +46,8 @@ struct Fields {
   // as general.
   int chart_yonly = 0;
   int uext_yonly[2] = {0, 0};
+  // the x and z components of the smoothed displacement (vtmp) are zero
+  int vtmp_xz_zero = 0;
   int moving[2];
   int zc = 0;        // planes per block of the fused step (0 = automatic)
   int variant = -1;  // -1: automatic (step_is_fused); 0: fused step; 1: two-pass step (moments pass + collision pass)

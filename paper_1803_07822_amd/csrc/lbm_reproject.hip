@@ -150,8 +150,9 @@ __device__ __forceinline__ void inv3d(const double m[3][3], double r[3][3]) {
   r[2][2] = (m[0][0] * m[1][1] - m[0][1] * m[1][0]) * idet;
 }
 
-// Cartesian moment fields at the old fluid nodes.
-template <class T>
+// Cartesian moment fields at the old fluid nodes (Y: the old chart moves the
+// nodes along y only).
+template <class T, bool Y>
 __global__ __launch_bounds__(BX * BY) void k_rp_moments(Grid g, const T* __restrict__ pop, const T* __restrict__ hist, const T* __restrict__ geo,
                              const T* __restrict__ vin, const double* __restrict__ jac, T* __restrict__ mf) {
   int i, jf, k;
@@ -187,10 +188,7 @@ __global__ __launch_bounds__(BX * BY) void k_rp_moments(Grid g, const T* __restr
   });
   const double sg = 1.0 + (double)sgd;
   double J[3][3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int b = 0; b < 3; ++b) J[a][b] = jac[(a * 3 + b) * g.N + n];
+  jac_at<Y>(jac, g.N, n, J);
   // f = w + f~: sum w = 1, sum w c c = I/3
   const double rho = sg * (1.0 + s);
   double j[3], Pm[3][3], Bv[3], Cm[3][3];
@@ -259,7 +257,8 @@ __global__ __launch_bounds__(BX * BY) void k_rp_ghost(Grid g, const double* __re
 // New state at the new fluid nodes: the streamed deviations g~ written
 // straight into the pull layout, and the new history (storage precision).
 // Y: the old and the new chart both move the nodes along y only, so psi keeps
-// the node's x and z and its search is one-dimensional.
+// the node's x and z, its search is one-dimensional, and two rows of the new J
+// are exact.
 template <class T, bool Y>
 __global__ __launch_bounds__(BX * BY) void k_rp_new(Grid g, const double* __restrict__ chart, const double* __restrict__ uold,
                          const T* __restrict__ mf, const double* __restrict__ jac, const T* __restrict__ geo,
@@ -389,10 +388,7 @@ __global__ __launch_bounds__(BX * BY) void k_rp_new(Grid g, const double* __rest
   for (int q = 0; q < NMF; ++q) m[q] += mf_rest(q);
   // pull back with the new J^{-1}
   double J[3][3], Ji[3][3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int b = 0; b < 3; ++b) J[a][b] = jac[(a * 3 + b) * g.N + n];
+  jac_at<Y>(jac, g.N, n, J);
   inv3d(J, Ji);
   double Pc[3][3], Cc[3][3];
 #pragma unroll
@@ -469,7 +465,9 @@ template <class T> hipError_t launch_reproject(Fields& F, hipStream_t s, const d
   (void)tau;
   const Grid g = F.g;
   dim3 b(BX, BY);
-  hipLaunchKernelGGL(k_rp_moments<T>, xcd_fluid_grid(g), b, 0, s, g, (const T*)F.pop[F.cur], (const T*)F.hist[F.cur],
+  // the moments are pushed to Cartesian components with the old chart's J
+  auto* km = F.uext_yonly[F.uext_cur] ? k_rp_moments<T, true> : k_rp_moments<T, false>;
+  hipLaunchKernelGGL(km, xcd_fluid_grid(g), b, 0, s, g, (const T*)F.pop[F.cur], (const T*)F.hist[F.cur],
                      (const T*)F.geo, (const T*)F.vin, (const double*)F.jac, (T*)F.mf);
   hipLaunchKernelGGL(k_rp_ghost<T>, col_grid(g), b, 0, s, g, (const double*)F.vwall, (T*)F.mf);
   const int old = F.uext_cur;

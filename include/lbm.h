@@ -50,7 +50,15 @@
  * enqueue kernels and device-to-device copies only (no
  * memsets, no host waits), so a sequence of them may be captured on a
  * non-null context stream into a HIP graph and replayed.  The captured work
- * reads the argument pointers of the calls captured.
+ * reads the argument pointers of the calls captured, and keeps the choices the
+ * context made on the host while it was captured: which of two buffers each
+ * call reads and writes (the populations alternate at every step, the chart
+ * displacement at every re-projection), and which kernels serve the charts in
+ * place (a chart built from wall and plate displacements moves the nodes along
+ * y only and takes a cheaper path than a chart given whole).  Replay a
+ * sequence that leaves the buffers as it found them (an even number of steps
+ * and of re-projections), and do not switch between lbm_set_metric and the
+ * displacement setters between its capture and its replays.
  *
  * Errors: every call returns LBM_OK or a negative code; lbm_last_error gives a
  * message.  LBM_EHIP and LBM_EUNSTABLE are sticky: once raised, every later

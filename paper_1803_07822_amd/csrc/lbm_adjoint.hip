@@ -601,8 +601,9 @@ __device__ inline void inv3a(const double m[3][3], double r[3][3], double& det) 
 }
 
 // Fluid-node part: adjoints of Gamma, g^{-1}, det J and J^{-1} F back to
-// D_l g (ldg), g (lge, packed) and J (lJe) on the extended grid.
-__global__ __launch_bounds__(BX * BY) void k_adjg_fluid(Grid g, const double* __restrict__ wext, const double* __restrict__ gext,
+// D_l g (ldg), g (lge, packed) and J (lJe) on the extended grid.  g = J^T J
+// at the node is formed from J, as the forward pass forms it.
+__global__ __launch_bounds__(BX * BY) void k_adjg_fluid(Grid g, const double* __restrict__ wext,
                              const double* __restrict__ jac, double F0, double F1, double F2,
                              const double* __restrict__ lgv, const double* __restrict__ lj, double* __restrict__ ldg,
                              double* __restrict__ lge, double* __restrict__ lJe) {
@@ -613,10 +614,13 @@ __global__ __launch_bounds__(BX * BY) void k_adjg_fluid(Grid g, const double* __
   const long long e = eix(g, p.i, j, p.k);
   double gm[3][3], gi[3][3], J[3][3], Ji[3][3], det, detJ;
   for (int a = 0; a < 3; ++a)
-    for (int b = 0; b < 3; ++b) {
-      gm[a][b] = gext[sym(a, b) * NE + e];
-      J[a][b] = jac[(a * 3 + b) * g.N + p.n];
-    }
+    for (int b = 0; b < 3; ++b) J[a][b] = jac[(a * 3 + b) * g.N + p.n];
+  {
+    double gq[6];
+    metric_of(J, gq);
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) gm[a][b] = gq[sym(a, b)];
+  }
   inv3a(gm, gi, det);
   inv3a(J, Ji, detJ);
   double dg[3][6];
@@ -967,7 +971,7 @@ hipError_t adjoint_backward(Fields& F, AdjointBuffers& A, hipStream_t s, int K, 
     HCHK(hipMemsetAsync(A.lJe, 0, sizeof(double) * 9 * NE, s));
     HCHK(hipMemsetAsync(A.lve, 0, sizeof(double) * 3 * NE, s));
     HCHK(hipMemsetAsync(A.lue, 0, sizeof(double) * 3 * NE, s));
-    hipLaunchKernelGGL(k_adjg_fluid, fg, b, 0, s, g, (const double*)F.wext, (const double*)F.gext,
+    hipLaunchKernelGGL(k_adjg_fluid, fg, b, 0, s, g, (const double*)F.wext,
                        (const double*)F.jac, Fc[0], Fc[1], Fc[2], (const double*)A.lg, (const double*)A.lj, A.ldg,
                        A.lge, A.lJe);
     hipLaunchKernelGGL(k_adjg_w, eg, b, 0, s, g, (const double*)A.ldg, A.lwe);

@@ -61,6 +61,21 @@ __device__ __forceinline__ void jac_at(const double* __restrict__ jac, long long
     for (int b = 0; b < 3; ++b) J[a][b] = (!Y || a == 1) ? jac[(a * 3 + b) * N + n] : (a == b ? 1.0 : 0.0);
 }
 
+// g = J^T J, packed (xx, xy, xz, yy, yz, zz).
+__device__ __forceinline__ void metric_of(const double J[3][3], double gq[6]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = a; b < 3; ++b) gq[sym(a, b)] = J[0][a] * J[0][b] + J[1][a] * J[1][b] + J[2][a] * J[2][b];
+}
+
+// J of a chart that moves the nodes along y only, from its varying row.
+__device__ __forceinline__ void jac_of_row(double r0, double r1, double r2, double J[3][3]) {
+  J[0][0] = 1.0, J[0][1] = 0.0, J[0][2] = 0.0;
+  J[1][0] = r0, J[1][1] = r1, J[1][2] = r2;
+  J[2][0] = 0.0, J[2][1] = 0.0, J[2][2] = 1.0;
+}
+
 // The link from fluid node (i, jf) along (x, y) crosses the plate: it joins
 // rows pj - 1 and pj and crosses the half row at i + x/2 within
 // [pi0 - 1/2, pi1 + 1/2] on the periodic x axis, where the seam point

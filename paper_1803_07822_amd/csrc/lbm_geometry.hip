@@ -54,6 +54,9 @@ __device__ __forceinline__ double plate_spline(double eta, int eta_p, int H) {
 // across the channel (Sec. IV.A.1 (i)) plus the plate's cross-section
 // displacement carried by plate_spline; eta = xi_y - 1/2 puts the halfway
 // walls at 0 and H and the plate (between fluid rows pj - 1 and pj) at pj.
+// XZ: write the x and z components (i, k); they are left in place when the
+// chart already holds them from an earlier call.
+template <bool XZ>
 __global__ __launch_bounds__(BX * BY) void k_chart_from_disp(Grid g, const double* __restrict__ disp,
                                                              const double* __restrict__ dplate,
                                                              double* __restrict__ chart) {
@@ -65,12 +68,17 @@ __global__ __launch_bounds__(BX * BY) void k_chart_from_disp(Grid g, const doubl
   const double eta = j - 0.5, s = eta / g.H;
   double y = (double)j + (1.0 - s) * disp[q] + s * disp[(long long)g.nz * g.nx + q];
   if (g.pj) y += dplate[q] * plate_spline(eta, g.pj, g.H);
-  chart[p] = (double)i;
   chart[NC + p] = y;
-  chart[2 * NC + p] = (double)k;
+  if (XZ) {
+    chart[p] = (double)i;
+    chart[2 * NC + p] = (double)k;
+  }
 }
 
 // u = chart - xi on layers 0..ny-1, cubic continuation on -3..-1 and ny..ny+2.
+// Y: the chart moves the nodes along y only, so u_x = u_z = 0 exactly; XZ:
+// write those two components (Y: zeros), else they are already in place.
+template <bool Y, bool XZ>
 __global__ __launch_bounds__(BX * BY) void k_uext(Grid g, const double* __restrict__ chart, double* __restrict__ u) {
   const int i = blockIdx.x * BX + threadIdx.x, je = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
   if (i >= g.nx || je >= g.ny + 6) return;
@@ -82,6 +90,11 @@ __global__ __launch_bounds__(BX * BY) void k_uext(Grid g, const double* __restri
   };
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
+    if (a != 1 && !XZ) continue;
+    if (Y && a != 1) {
+      u[a * NE + eidx(g, i, j, k)] = 0.0;
+      continue;
+    }
     double v;
     if (j >= 0 && j < g.ny) {
       v = uat(a, j);
@@ -222,9 +235,55 @@ __global__ __launch_bounds__(BX * BY) void k_smooth(Grid g, int jlo, int jhi, co
   }
 }
 
+// The smoothing above applied to g = J^T J of a chart that moves the nodes
+// along y only, g formed at every stencil point from the varying row of J
+// (three components read instead of six, same arithmetic per component).
+__global__ __launch_bounds__(BX * BY) void k_smooth_gy(Grid g, int jlo, int jhi, const double* __restrict__ row,
+                                                       double* __restrict__ out) {
+  __shared__ double ring[4][3][MN];
+  March m;
+  if (!march_setup(g, jlo, jhi, m)) return;
+  const long long NE = (long long)g.nz * (g.ny + 6) * g.nx;
+  const int i = m.i0 + m.tx, j = m.j0 + m.ty;
+  const bool act = i < g.nx && j <= jhi;
+  const int e0 = (m.ty + 1) * MX + (m.tx + 1);
+  march_load<3>(g, m, m.z0 - 1, row, ring[rs(m.z0 - 1)]);
+  march_load<3>(g, m, m.z0, row, ring[rs(m.z0)]);
+  for (int k = m.z0; k < m.z1; ++k) {
+    march_load<3>(g, m, k + 1, row, ring[rs(k + 1)]);
+    __syncthreads();
+    if (act) {
+      const double(*sm)[MN] = ring[rs(k - 1)];
+      const double(*s0)[MN] = ring[rs(k)];
+      const double(*sp)[MN] = ring[rs(k + 1)];
+      auto metric_at = [&](const double(*sl)[MN], int o, double gq[6]) {
+        double J[3][3];
+        jac_of_row(sl[0][o], sl[1][o], sl[2][o], J);
+        metric_of(J, gq);
+      };
+      double g0[6], s[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      metric_at(s0, e0, g0);
+      for_q([&](auto L) {
+        constexpr int l = decltype(L)::value;
+        if (l == 0) return;
+        constexpr int x = cx(l), y = cy(l), z = cz(l);
+        double gl[6];
+        metric_at(z < 0 ? sm : (z > 0 ? sp : s0), e0 + y * MX + x, gl);
+#pragma unroll
+        for (int q = 0; q < 6; ++q) s[q] += wgt(l) * (gl[q] - g0[q]);
+      });
+      const long long p = eidx(g, i, j, k);
+#pragma unroll
+      for (int q = 0; q < 6; ++q) out[q * NE + p] = g0[q] - s[q];
+    }
+  }
+}
+
 // J = I + G v and g = J^T J on layers [-1, ny]; J also stored at fluid nodes.
 // Y: v moves the nodes along y only; its y component alone is read (v points
-// at it) and the rows (1, 0, 0), (0, 0, 1) of J are exact.
+// at it), the rows (1, 0, 0), (0, 0, 1) of J are exact, and the varying row
+// (J_yx, J_yy, J_yz) is stored in the first three components of gext in place
+// of g, which its readers form from it.
 template <bool Y>
 __global__ __launch_bounds__(BX * BY) void k_jac_metric(Grid g, const double* __restrict__ v,
                                                         double* __restrict__ gext, double* __restrict__ jac) {
@@ -252,11 +311,15 @@ __global__ __launch_bounds__(BX * BY) void k_jac_metric(Grid g, const double* __
         for (int b = 0; b < 3; ++b) J[a][b] = (a == b ? 1.0 : 0.0) + d[b];
       }
       const long long e = eidx(g, i, j, k);
+      if constexpr (Y) {
 #pragma unroll
-      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) gext[b * NE + e] = J[1][b];
+      } else {
+        double gq[6];
+        metric_of(J, gq);
 #pragma unroll
-        for (int b = a; b < 3; ++b)
-          gext[sym(a, b) * NE + e] = J[0][a] * J[0][b] + J[1][a] * J[1][b] + J[2][a] * J[2][b];
+        for (int q = 0; q < 6; ++q) gext[q * NE + e] = gq[q];
+      }
       if (j >= 1 && j <= g.ny - 2) {
         const long long n = ((long long)k * g.H + (j - 1)) * g.nx + i;
 #pragma unroll
@@ -291,11 +354,20 @@ __global__ __launch_bounds__(BX * BY) void k_geo(Grid g, const double* __restric
       const long long n = ((long long)k * g.H + (j - 1)) * g.nx + i;
       const long long e = eidx(g, i, j, k);
       double gm[3][3], gi[3][3], J[3][3], Ji[3][3], det, detJ;
-#pragma unroll
-      for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int b = 0; b < 3; ++b) gm[a][b] = gext[sym(a, b) * NE + e];
       jac_at<Y>(jac, g.N, n, J);
+      if constexpr (Y) {
+        double gq[6];
+        metric_of(J, gq);
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+          for (int b = 0; b < 3; ++b) gm[a][b] = gq[sym(a, b)];
+      } else {
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+          for (int b = 0; b < 3; ++b) gm[a][b] = gext[sym(a, b) * NE + e];
+      }
       inv3(gm, gi, det);
       inv3(J, Ji, detJ);
       // dg[l][q] = D_l g_q
@@ -417,7 +489,10 @@ __global__ __launch_bounds__(BX * BY) void k_inlet_velocity(Grid g, const double
 
 hipError_t launch_chart_from_disp(Fields& F, hipStream_t s) {
   dim3 b(BX, BY), gr((F.g.nx + BX - 1) / BX, (F.g.ny + BY - 1) / BY, F.g.nz);
-  hipLaunchKernelGGL(k_chart_from_disp, gr, b, 0, s, F.g, F.disp, F.dplate, F.chart);
+  if (F.chart_yonly)
+    hipLaunchKernelGGL(k_chart_from_disp<false>, gr, b, 0, s, F.g, F.disp, F.dplate, F.chart);
+  else
+    hipLaunchKernelGGL(k_chart_from_disp<true>, gr, b, 0, s, F.g, F.disp, F.dplate, F.chart);
   F.chart_yonly = 1;
   return hipGetLastError();
 }
@@ -433,17 +508,22 @@ template <class T> hipError_t launch_geometry(Fields& F, hipStream_t s, const do
   const Grid g = F.g;
   dim3 b(BX, BY);
   double* u = F.uext[F.uext_cur];
-  F.uext_yonly[F.uext_cur] = F.chart_yonly;
   // marching grid: x tiles, layer tiles of [jlo, jhi], z chunks
   auto mg = [&](int jlo, int jhi) {
     return dim3((g.nx + BX - 1) / BX, (jhi - jlo + BY) / BY, (g.nz + MZC - 1) / MZC);
   };
-  hipLaunchKernelGGL(k_uext, ext_grid(g), b, 0, s, g, F.chart, u);
   // A chart that moves the nodes along y only has x and z displacements of
-  // exactly zero, and so smoothed x and z components of exactly zero: once
-  // the three-component pass has written those, the y component alone is
-  // smoothed (the adjoint's chart gradient reads all three).
+  // exactly zero, and so smoothed x and z components of exactly zero: once a
+  // buffer holds those zeros, only its y component is written again (the
+  // adjoint's chart gradient reads all three components of the smoothed one).
   const bool y = F.chart_yonly;
+  if (!y)
+    hipLaunchKernelGGL((k_uext<false, true>), ext_grid(g), b, 0, s, g, F.chart, u);
+  else if (F.uext_yonly[F.uext_cur])
+    hipLaunchKernelGGL((k_uext<true, false>), ext_grid(g), b, 0, s, g, F.chart, u);
+  else
+    hipLaunchKernelGGL((k_uext<true, true>), ext_grid(g), b, 0, s, g, F.chart, u);
+  F.uext_yonly[F.uext_cur] = y;
   if (y && F.vtmp_xz_zero)
     hipLaunchKernelGGL(k_smooth<1>, mg(-2, g.ny + 1), b, 0, s, g, -2, g.ny + 1, u + F.NE, F.vtmp + F.NE);
   else
@@ -453,7 +533,10 @@ template <class T> hipError_t launch_geometry(Fields& F, hipStream_t s, const do
     hipLaunchKernelGGL(k_jac_metric<true>, mg(-1, g.ny), b, 0, s, g, F.vtmp + F.NE, F.gext, F.jac);
   else
     hipLaunchKernelGGL(k_jac_metric<false>, mg(-1, g.ny), b, 0, s, g, F.vtmp, F.gext, F.jac);
-  hipLaunchKernelGGL(k_smooth<6>, mg(0, g.ny - 1), b, 0, s, g, 0, g.ny - 1, F.gext, F.wext);
+  if (y)
+    hipLaunchKernelGGL(k_smooth_gy, mg(0, g.ny - 1), b, 0, s, g, 0, g.ny - 1, F.gext, F.wext);
+  else
+    hipLaunchKernelGGL(k_smooth<6>, mg(0, g.ny - 1), b, 0, s, g, 0, g.ny - 1, F.gext, F.wext);
   auto* kg = y ? k_geo<T, true> : k_geo<T, false>;
   hipLaunchKernelGGL(kg, mg(1, g.ny - 2), b, 0, s, g, F.wext, F.gext, F.jac, Fc[0], Fc[1], Fc[2], (T*)F.geo);
   return hipGetLastError();

@@ -283,8 +283,9 @@ __global__ __launch_bounds__(BX * BY) void k_smooth_gy(Grid g, int jlo, int jhi,
 // Y: v moves the nodes along y only; its y component alone is read (v points
 // at it), the rows (1, 0, 0), (0, 0, 1) of J are exact, and the varying row
 // (J_yx, J_yy, J_yz) is stored in the first three components of gext in place
-// of g, which its readers form from it.
-template <bool Y>
+// of g, which its readers form from it.  RW (Y only): write the exact rows of
+// J at the fluid nodes, else they are already in place.
+template <bool Y, bool RW>
 __global__ __launch_bounds__(BX * BY) void k_jac_metric(Grid g, const double* __restrict__ v,
                                                         double* __restrict__ gext, double* __restrict__ jac) {
   constexpr int NV = Y ? 1 : 3;
@@ -325,7 +326,8 @@ __global__ __launch_bounds__(BX * BY) void k_jac_metric(Grid g, const double* __
 #pragma unroll
         for (int a = 0; a < 3; ++a)
 #pragma unroll
-          for (int b = 0; b < 3; ++b) jac[(a * 3 + b) * g.N + n] = J[a][b];
+          for (int b = 0; b < 3; ++b)
+            if (!Y || RW || a == 1) jac[(a * 3 + b) * g.N + n] = J[a][b];
       }
     }
   }
@@ -529,10 +531,14 @@ template <class T> hipError_t launch_geometry(Fields& F, hipStream_t s, const do
   else
     hipLaunchKernelGGL(k_smooth<3>, mg(-2, g.ny + 1), b, 0, s, g, -2, g.ny + 1, u, F.vtmp);
   F.vtmp_xz_zero = y;
-  if (y)
-    hipLaunchKernelGGL(k_jac_metric<true>, mg(-1, g.ny), b, 0, s, g, F.vtmp + F.NE, F.gext, F.jac);
+  // likewise the rows (1, 0, 0) and (0, 0, 1) of J at the fluid nodes
+  if (!y)
+    hipLaunchKernelGGL((k_jac_metric<false, true>), mg(-1, g.ny), b, 0, s, g, F.vtmp, F.gext, F.jac);
+  else if (F.jac_rows_exact)
+    hipLaunchKernelGGL((k_jac_metric<true, false>), mg(-1, g.ny), b, 0, s, g, F.vtmp + F.NE, F.gext, F.jac);
   else
-    hipLaunchKernelGGL(k_jac_metric<false>, mg(-1, g.ny), b, 0, s, g, F.vtmp, F.gext, F.jac);
+    hipLaunchKernelGGL((k_jac_metric<true, true>), mg(-1, g.ny), b, 0, s, g, F.vtmp + F.NE, F.gext, F.jac);
+  F.jac_rows_exact = y;
   if (y)
     hipLaunchKernelGGL(k_smooth_gy, mg(0, g.ny - 1), b, 0, s, g, 0, g.ny - 1, F.gext, F.wext);
   else

@@ -48,6 +48,8 @@ struct Fields {
   int uext_yonly[2] = {0, 0};
   // the x and z components of the smoothed displacement (vtmp) are zero
   int vtmp_xz_zero = 0;
+  // jac holds the rows (1, 0, 0) and (0, 0, 1) of such a chart
+  int jac_rows_exact = 0;
   int moving[2];
   int zc = 0;        // planes per block of the fused step (0 = automatic)
   int variant = -1;  // -1: automatic (step_is_fused); 0: fused step; 1: two-pass step (moments pass + collision pass)

@@ -1,0 +1,83 @@
+"""Charts built from wall displacements move the nodes along y only, and the
+library gives them an update path of its own: a one-dimensional search for
+the inverse-chart point, the moment interpolation from two corners, J's
+varying row stored in place of g, and only the y components of the chart and
+its displacement rewritten once the rest is in place.  The same charts given
+whole through lbm_set_metric take the general path.  Both paths must give the
+same geometry and the same re-projected and stepped states, to rounding (the
+two differ in the order of floating-point operations only), through a
+sequence that visits both displacement buffers of the re-projection twice."""
+import numpy as np
+import pytest
+
+from paper_1803_07822_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+W = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
+
+
+def _lbm():
+    from paper_1803_07822_amd import lbm
+
+    return lbm
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _dev_err(a, b):
+    """max |a - b| relative to the largest deviation of b from the weights."""
+    return np.abs(a - b).max() / np.abs(b - W.reshape((19, 1, 1, 1))).max()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_wall_chart_path_matches_general_path(precision):
+    lbm = _lbm()
+    nx, ny, nz = 70, 12, 9  # a ragged 64-wide tile in x, three 4-row tiles in y
+    H = ny - 2
+    d1 = synth.gaussian_bump(nx, nz, A=1.0, x0=35, z0=4, sigma=5)
+    d2 = 0.6 * d1 + 0.25 * np.sin(2 * np.pi * np.arange(nx) / nx)[None, :]
+    rho = 1 + synth.random_perturbation((nz, H, nx), 2e-3, 11)
+    uc = synth.random_perturbation((3, nz, H, nx), 1e-2, 12)
+
+    def set_chart(S, d, general, reproject):
+        if general:
+            S.set_metric(synth.chart_from_displacement(nx, ny, nz, d), reproject=reproject)
+        else:
+            S.set_wall_displacement(lbm.LBM_WALL_YMAX, d, reproject=reproject)
+
+    S = {}
+    for general in (False, True):
+        X = lbm.Solver(nx, ny, nz, 0.7, precision)
+        X.set_body_force((1e-5, 0.0, 2e-6))
+        set_chart(X, d1, general, False)
+        X.init_equilibrium(rho, uc)
+        X.step(3)
+        S[general] = X
+
+    (ga, ja), (gb, jb) = (tuple(_np(t) for t in S[g].geometry()) for g in (False, True))
+    geo_tol = 1e-13 if precision == "fp64" else 2e-7
+    assert np.abs(ja - jb).max() <= 1e-13 * np.abs(jb).max()
+    assert np.abs(ga - gb).max() <= geo_tol * max(1.0, np.abs(gb).max())
+    # J of a chart that moves the nodes along y only: rows (1, 0, 0), (0, 0, 1)
+    J = ja.reshape(3, 3, -1)
+    assert np.all(J[0, 0] == 1) and np.all(J[0, 1:] == 0) and np.all(J[2, :2] == 0) and np.all(J[2, 2] == 1)
+
+    tol = 1e-12 if precision == "fp64" else 1e-5
+    for tag, d, steps in (("d2", d2, 2), ("d1", d1, 2), ("d2 again", d2, 1), ("d1 again", d1, 0)):
+        for general in (False, True):
+            set_chart(S[general], d, general, True)
+            S[general].step(steps)
+        pa, pb = _np(S[False].populations()), _np(S[True].populations())
+        ha, hb = _np(S[False].history()), _np(S[True].history())
+        ep = _dev_err(pa, pb)
+        eh = np.abs(ha - hb).max() / np.abs(hb).max()
+        print(f"{precision} {tag}: populations {ep:.2e}, history {eh:.2e}", flush=True)
+        assert ep < tol, (tag, ep)
+        assert eh < tol, (tag, eh)
+    for X in S.values():
+        X.sync()

@@ -277,15 +277,23 @@ __global__ __launch_bounds__(BX * BY) void k_rp_new(Grid g, const double* __rest
   const int side = jf >= g.pj ? 1 : 0;
   const long long e0 = ((long long)k * (g.ny + 6) + (jf + 1 + 3)) * g.nx + i;
   double xi[3];
+  // Y: J's varying row, read before the search for the same reason
+  double J[3][3];
+  if constexpr (Y) jac_at<true>(jac, g.N, n, J);
   if constexpr (Y) {
     // x and z displacements are zero in both charts: xi = (i, y, k) with
-    // y + u_old,y(i, y, k) = p_y, linear between the two layers around y
+    // y + u_old,y(i, y, k) = p_y, linear between the two layers around y.
+    // The node's own layer and the two beside it are loaded together: the
+    // walls move much less than a layer per update, so the first cell is
+    // one of the two they span and its corners need no second round trip.
     const double py = chart[NC + pc];
     const double* uy = uold + NE;
     const long long col = (long long)k * (g.ny + 6) * g.nx + i;
+    const int jn = jf + 1;  // the node's layer
+    const double Um = uy[e0 - g.nx], Uc = uy[e0], Up = uy[e0 + g.nx];
     xi[0] = (double)i;
     xi[2] = (double)k;
-    xi[1] = py - uy[e0];
+    xi[1] = py - Uc;
     int cby = INT_MIN;
     double U0 = 0.0, U1 = 0.0;
     for (int it = 0; it < 50; ++it) {
@@ -294,8 +302,16 @@ __global__ __launch_bounds__(BX * BY) void k_rp_new(Grid g, const double* __rest
       if (by > g.ny + 1) by = g.ny + 1;
       by = plate_side_layer(g, side, i, by);
       if (by != cby) {
-        U0 = uy[col + (long long)(by + 3) * g.nx];
-        U1 = uy[col + (long long)(by + 4) * g.nx];
+        if (by == jn - 1) {
+          U0 = Um;
+          U1 = Uc;
+        } else if (by == jn) {
+          U0 = Uc;
+          U1 = Up;
+        } else {
+          U0 = uy[col + (long long)(by + 3) * g.nx];
+          U1 = uy[col + (long long)(by + 4) * g.nx];
+        }
         cby = by;
       }
       const double fr = xi[1] - by;
@@ -378,7 +394,7 @@ __global__ __launch_bounds__(BX * BY) void k_rp_new(Grid g, const double* __rest
   // z + 1 weigh exactly zero and adding them changes no bit of the sum.  The
   // choice is made per wave (no lane diverges): the four-corner-pairs gather
   // runs only when some lane of the wave needs it.
-  if (__any(fr[0] != 0.0 || fr[2] != 0.0)) {
+  if (!Y && __any(fr[0] != 0.0 || fr[2] != 0.0)) {
     Unroll<int, 8>::run(corner);
   } else {
     corner(std::integral_constant<int, 0>());
@@ -387,8 +403,8 @@ __global__ __launch_bounds__(BX * BY) void k_rp_new(Grid g, const double* __rest
 #pragma unroll
   for (int q = 0; q < NMF; ++q) m[q] += mf_rest(q);
   // pull back with the new J^{-1}
-  double J[3][3], Ji[3][3];
-  jac_at<Y>(jac, g.N, n, J);
+  double Ji[3][3];
+  if constexpr (!Y) jac_at<false>(jac, g.N, n, J);
   inv3d(J, Ji);
   double Pc[3][3], Cc[3][3];
 #pragma unroll
@@ -440,20 +456,19 @@ __global__ __launch_bounds__(BX * BY) void k_rp_new(Grid g, const double* __rest
   // Store g~_l = f~_l - F_l/2 in the pull layout: at x - c_l when the link
   // from there is open, else (a link through a wall or the plate) in the
   // bounce-back slot opp(l) of this node.  Every slot of the layout has
-  // exactly one writer.
+  // exactly one writer.  The store takes a selected address, not a branch.
   for_q([&](auto L) {
     constexpr int l = decltype(L)::value;
     constexpr int x = cx(l), y = cy(l), z = cz(l);
     const double fdev = wgt(l) / sg * hermite_term<double, l>(a0, jt, a2);
     const T v = (T)(fdev - 0.5 * (double)Fp[l]);
     const int js = jf - y;
-    if (js < 0 || js >= g.H || plate_cut(g, i, jf, -x, -y)) {
-      pop[(long long)opp(l) * g.N + n] = v;
-    } else {
-      const int is = x ? wrapr(i - x, g.nx) : i;
-      const int ks = z ? wrapr(k - z, g.nz) : k;
-      pop[(long long)l * g.N + ((long long)ks * g.H + js) * g.nx + is] = v;
-    }
+    const bool cut = js < 0 || js >= g.H || plate_cut(g, i, jf, -x, -y);
+    const int is = x ? wrapr(i - x, g.nx) : i;
+    const int ks = z ? wrapr(k - z, g.nz) : k;
+    const long long dst =
+        cut ? (long long)opp(l) * g.N + n : (long long)l * g.N + ((long long)ks * g.H + js) * g.nx + is;
+    pop[dst] = v;
   });
 }
 

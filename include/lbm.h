@@ -130,7 +130,8 @@ int lbm_set_body_force(lbm_ctx* ctx, const double h_F_cart[3]);
  * geometry of App. A with the fourth-order derivative of App. D (FP64).  The
  * chart is continued three layers beyond each wall layer by the cubic through
  * the four nearest layers.  reproject != 0 carries the current state onto the
- * new chart (Sec. IV.B); it needs a state.  Synchronising. */
+ * new chart (Sec. IV.B); it needs a state.  Enqueued on the context's stream
+ * like the other setters (capture-safe, see above). */
 int lbm_set_metric(lbm_ctx* ctx, const double* d_chart, int reproject);
 
 /* Set the y-displacement d of one wall and rebuild the chart by the linear

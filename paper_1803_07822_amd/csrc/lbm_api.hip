@@ -275,13 +275,8 @@ int lbm_set_wall_displacement(lbm_ctx* c, int wall, const double* d_disp, int re
   c->recorded = 0;  // a recorded trajectory no longer matches the fields
   if (wall != LBM_WALL_YMIN && wall != LBM_WALL_YMAX) return fail(c, LBM_EINVAL, "bad wall");
   if (reproject && !c->have_state) return fail(c, LBM_ESTATE, "re-projection needs a state");
-  const size_t ncol = (size_t)c->F.g.nz * c->F.g.nx;
-  double* dst = c->F.disp + (size_t)wall * ncol;
-  if (d_disp)
-    LBM_HIP(c, hipMemcpyAsync(dst, d_disp, sizeof(double) * ncol, hipMemcpyDeviceToDevice, c->stream));
-  else
-    LBM_HIP(c, zero_async(dst, ncol, c->stream));
-  LBM_HIP(c, lbm::launch_chart_from_disp(c->F, c->stream));
+  // the chart kernel takes the displacement from d_disp and stores it
+  LBM_HIP(c, lbm::launch_chart_from_disp(c->F, c->stream, wall, d_disp));
   return geometry_dispatch(c, reproject);
 }
 
@@ -289,19 +284,22 @@ int lbm_set_wall_velocity(lbm_ctx* c, int wall, const double* d_vcart) {
   LBM_GUARD(c);
   c->recorded = 0;  // a recorded trajectory no longer matches the fields
   if (wall != LBM_WALL_YMIN && wall != LBM_WALL_YMAX) return fail(c, LBM_EINVAL, "bad wall");
+  c->F.moving[wall] = d_vcart != nullptr;
+  if (c->have_geo) {
+    // the kernel takes the velocity from d_vcart, stores it and forms its
+    // chart components
+    if (c->precision == LBM_FP64)
+      LBM_HIP(c, lbm::launch_wall_velocity<double>(c->F, c->stream, wall, d_vcart));
+    else
+      LBM_HIP(c, lbm::launch_wall_velocity<float>(c->F, c->stream, wall, d_vcart));
+    return LBM_OK;
+  }
   const size_t n = (size_t)c->F.g.nz * c->F.g.nx * 3;
   double* dst = c->F.vwall + (size_t)wall * n;
   if (d_vcart)
     LBM_HIP(c, hipMemcpyAsync(dst, d_vcart, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
   else
     LBM_HIP(c, zero_async(dst, n, c->stream));
-  c->F.moving[wall] = d_vcart != nullptr;
-  if (c->have_geo) {
-    if (c->precision == LBM_FP64)
-      LBM_HIP(c, lbm::launch_wall_velocity<double>(c->F, c->stream));
-    else
-      LBM_HIP(c, lbm::launch_wall_velocity<float>(c->F, c->stream));
-  }
   return LBM_OK;
 }
 
@@ -340,12 +338,8 @@ int lbm_set_plate_displacement(lbm_ctx* c, const double* d_disp, int reproject) 
   c->recorded = 0;  // a recorded trajectory no longer matches the fields
   if (!c->F.g.pj) return fail(c, LBM_ESTATE, "no plate");
   if (reproject && !c->have_state) return fail(c, LBM_ESTATE, "re-projection needs a state");
-  const size_t ncol = (size_t)c->F.g.nz * c->F.g.nx;
-  if (d_disp)
-    LBM_HIP(c, hipMemcpyAsync(c->F.dplate, d_disp, sizeof(double) * ncol, hipMemcpyDeviceToDevice, c->stream));
-  else
-    LBM_HIP(c, zero_async(c->F.dplate, ncol, c->stream));
-  LBM_HIP(c, lbm::launch_chart_from_disp(c->F, c->stream));
+  // the chart kernel takes the plate displacement from d_disp and stores it
+  LBM_HIP(c, lbm::launch_chart_from_disp(c->F, c->stream, 2, d_disp));
   return geometry_dispatch(c, reproject);
 }
 
@@ -353,17 +347,20 @@ int lbm_set_plate_velocity(lbm_ctx* c, const double* d_vcart) {
   LBM_GUARD(c);
   c->recorded = 0;  // a recorded trajectory no longer matches the fields
   if (!c->F.g.pj) return fail(c, LBM_ESTATE, "no plate");
+  if (c->have_geo) {
+    // the kernel takes the velocity from d_vcart, stores it and forms its
+    // chart components
+    if (c->precision == LBM_FP64)
+      LBM_HIP(c, lbm::launch_plate_velocity<double>(c->F, c->stream, 1, d_vcart));
+    else
+      LBM_HIP(c, lbm::launch_plate_velocity<float>(c->F, c->stream, 1, d_vcart));
+    return LBM_OK;
+  }
   const size_t n = (size_t)c->F.g.nz * c->F.g.nx * 3;
   if (d_vcart)
     LBM_HIP(c, hipMemcpyAsync(c->F.vplate, d_vcart, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
   else
     LBM_HIP(c, zero_async(c->F.vplate, n, c->stream));
-  if (c->have_geo) {
-    if (c->precision == LBM_FP64)
-      LBM_HIP(c, lbm::launch_plate_velocity<double>(c->F, c->stream));
-    else
-      LBM_HIP(c, lbm::launch_plate_velocity<float>(c->F, c->stream));
-  }
   return LBM_OK;
 }
 

@@ -55,19 +55,26 @@ __device__ __forceinline__ double plate_spline(double eta, int eta_p, int H) {
 // displacement carried by plate_spline; eta = xi_y - 1/2 puts the halfway
 // walls at 0 and H and the plate (between fluid rows pj - 1 and pj) at pj.
 // XZ: write the x and z components (i, k); they are left in place when the
-// chart already holds them from an earlier call.
+// chart already holds them from an earlier call.  A new displacement of one
+// field (which: 0 bottom wall, 1 top wall, 2 plate; -1 none) comes from src
+// (NULL: zero) and is stored into the context's copy by the layer-0 thread of
+// each column, in place of a separate copy.
 template <bool XZ>
-__global__ __launch_bounds__(BX * BY) void k_chart_from_disp(Grid g, const double* __restrict__ disp,
-                                                             const double* __restrict__ dplate,
-                                                             double* __restrict__ chart) {
+__global__ __launch_bounds__(BX * BY) void k_chart_from_disp(Grid g, double* __restrict__ disp,
+                                                             double* __restrict__ dplate,
+                                                             double* __restrict__ chart, int which,
+                                                             const double* __restrict__ src) {
   const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
   if (i >= g.nx || j >= g.ny) return;
-  const long long NC = (long long)g.nz * g.ny * g.nx;
+  const long long NC = (long long)g.nz * g.ny * g.nx, ncol = (long long)g.nz * g.nx;
   const long long p = ((long long)k * g.ny + j) * g.nx + i;
   const long long q = (long long)k * g.nx + i;
+  const double vin = which >= 0 && src ? src[q] : 0.0;
+  const double d0 = which == 0 ? vin : disp[q], d1 = which == 1 ? vin : disp[ncol + q];
+  if (which >= 0 && j == 0) (which == 2 ? dplate : disp + which * ncol)[q] = vin;
   const double eta = j - 0.5, s = eta / g.H;
-  double y = (double)j + (1.0 - s) * disp[q] + s * disp[(long long)g.nz * g.nx + q];
-  if (g.pj) y += dplate[q] * plate_spline(eta, g.pj, g.H);
+  double y = (double)j + (1.0 - s) * d0 + s * d1;
+  if (g.pj) y += (which == 2 ? vin : dplate[q]) * plate_spline(eta, g.pj, g.H);
   chart[NC + p] = y;
   if (XZ) {
     chart[p] = (double)i;
@@ -426,9 +433,17 @@ __global__ __launch_bounds__(BX * BY) void k_body_force(Grid g, const double* __
 // Chart components J^{-1} v of the Cartesian wall velocity at the fluid node
 // next to each wall.
 template <class T>
-__global__ __launch_bounds__(BX * BY) void k_wall_velocity(Grid g, const double* __restrict__ jac, const double* __restrict__ vwall, T* __restrict__ uw) {
+__global__ __launch_bounds__(BX * BY) void k_wall_velocity(Grid g, const double* __restrict__ jac, double* __restrict__ vwall,
+                                                           T* __restrict__ uw, int which, const double* __restrict__ src) {
   const int i = blockIdx.x * BX + threadIdx.x, k = blockIdx.y * BY + threadIdx.y;
   if (i >= g.nx || k >= g.nz) return;
+  // a new Cartesian velocity of wall `which` (-1: none) comes from src (NULL:
+  // zero) and is stored into the context's copy, in place of a separate copy
+  if (which >= 0) {
+    const long long c = (((long long)which * g.nz + k) * g.nx + i) * 3, q = ((long long)k * g.nx + i) * 3;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) vwall[c + a] = src ? src[q + a] : 0.0;
+  }
   for (int w = 0; w < 2; ++w) {
     const int jf = w == 0 ? 0 : g.H - 1;
     const long long n = ((long long)k * g.H + jf) * g.nx + i;
@@ -450,11 +465,23 @@ __global__ __launch_bounds__(BX * BY) void k_wall_velocity(Grid g, const double*
 // column off the plate takes the velocity of the nearest plate column (the
 // diagonal links at the plate's ends).
 template <class T>
-__global__ __launch_bounds__(BX * BY) void k_plate_velocity(Grid g, const double* __restrict__ jac, const double* __restrict__ vplate, T* __restrict__ up) {
+__global__ __launch_bounds__(BX * BY) void k_plate_velocity(Grid g, const double* __restrict__ jac, double* __restrict__ vplate,
+                                                            T* __restrict__ up, int in, const double* __restrict__ src) {
   const int i = blockIdx.x * BX + threadIdx.x, k = blockIdx.y * BY + threadIdx.y;
   if (i >= g.nx || k >= g.nz) return;
   const int ic = i < g.pi0 ? g.pi0 : (i > g.pi1 ? g.pi1 : i);
-  const double* v = vplate + ((long long)k * g.nx + ic) * 3;
+  // in: a new plate velocity comes from src (NULL: zero); each column stores
+  // its own into the context's copy and reads the nearest plate column's from
+  // src, so no thread reads what another writes
+  const long long qc = ((long long)k * g.nx + ic) * 3;
+  double v[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) v[a] = in ? (src ? src[qc + a] : 0.0) : vplate[qc + a];
+  if (in) {
+    const long long q = ((long long)k * g.nx + i) * 3;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) vplate[q + a] = src ? src[q + a] : 0.0;
+  }
   for (int side = 0; side < 2; ++side) {
     const long long n = ((long long)k * g.H + (g.pj - 1 + side)) * g.nx + i;
     double J[3][3], Ji[3][3], det;
@@ -489,20 +516,20 @@ __global__ __launch_bounds__(BX * BY) void k_inlet_velocity(Grid g, const double
 
 }  // namespace
 
-hipError_t launch_chart_from_disp(Fields& F, hipStream_t s) {
+hipError_t launch_chart_from_disp(Fields& F, hipStream_t s, int which, const double* src) {
   dim3 b(BX, BY), gr((F.g.nx + BX - 1) / BX, (F.g.ny + BY - 1) / BY, F.g.nz);
   if (F.chart_yonly)
-    hipLaunchKernelGGL(k_chart_from_disp<false>, gr, b, 0, s, F.g, F.disp, F.dplate, F.chart);
+    hipLaunchKernelGGL(k_chart_from_disp<false>, gr, b, 0, s, F.g, F.disp, F.dplate, F.chart, which, src);
   else
-    hipLaunchKernelGGL(k_chart_from_disp<true>, gr, b, 0, s, F.g, F.disp, F.dplate, F.chart);
+    hipLaunchKernelGGL(k_chart_from_disp<true>, gr, b, 0, s, F.g, F.disp, F.dplate, F.chart, which, src);
   F.chart_yonly = 1;
   return hipGetLastError();
 }
 
-template <class T> hipError_t launch_plate_velocity(Fields& F, hipStream_t s) {
+template <class T> hipError_t launch_plate_velocity(Fields& F, hipStream_t s, int in, const double* src) {
   if (!F.g.pj) return hipSuccess;
   dim3 b(BX, BY);
-  hipLaunchKernelGGL(k_plate_velocity<T>, col_grid(F.g), b, 0, s, F.g, F.jac, F.vplate, (T*)F.up);
+  hipLaunchKernelGGL(k_plate_velocity<T>, col_grid(F.g), b, 0, s, F.g, F.jac, F.vplate, (T*)F.up, in, src);
   return hipGetLastError();
 }
 
@@ -554,9 +581,9 @@ template <class T> hipError_t launch_body_force(Fields& F, hipStream_t s, const 
   return hipGetLastError();
 }
 
-template <class T> hipError_t launch_wall_velocity(Fields& F, hipStream_t s) {
+template <class T> hipError_t launch_wall_velocity(Fields& F, hipStream_t s, int which, const double* src) {
   dim3 b(BX, BY);
-  hipLaunchKernelGGL(k_wall_velocity<T>, col_grid(F.g), b, 0, s, F.g, F.jac, F.vwall, (T*)F.uw);
+  hipLaunchKernelGGL(k_wall_velocity<T>, col_grid(F.g), b, 0, s, F.g, F.jac, F.vwall, (T*)F.uw, which, src);
   return hipGetLastError();
 }
 
@@ -564,8 +591,8 @@ template hipError_t launch_geometry<double>(Fields&, hipStream_t, const double*)
 template hipError_t launch_geometry<float>(Fields&, hipStream_t, const double*);
 template hipError_t launch_body_force<double>(Fields&, hipStream_t, const double*);
 template hipError_t launch_body_force<float>(Fields&, hipStream_t, const double*);
-template hipError_t launch_wall_velocity<double>(Fields&, hipStream_t);
-template hipError_t launch_wall_velocity<float>(Fields&, hipStream_t);
+template hipError_t launch_wall_velocity<double>(Fields&, hipStream_t, int, const double*);
+template hipError_t launch_wall_velocity<float>(Fields&, hipStream_t, int, const double*);
 template <class T> hipError_t launch_inlet_velocity(Fields& F, hipStream_t s) {
   if (!F.g.open) return hipSuccess;
   dim3 b(BX, BY), gr((F.g.H + BX - 1) / BX, (F.g.nz + BY - 1) / BY, 1);
@@ -575,7 +602,7 @@ template <class T> hipError_t launch_inlet_velocity(Fields& F, hipStream_t s) {
 
 template hipError_t launch_inlet_velocity<double>(Fields&, hipStream_t);
 template hipError_t launch_inlet_velocity<float>(Fields&, hipStream_t);
-template hipError_t launch_plate_velocity<double>(Fields&, hipStream_t);
-template hipError_t launch_plate_velocity<float>(Fields&, hipStream_t);
+template hipError_t launch_plate_velocity<double>(Fields&, hipStream_t, int, const double*);
+template hipError_t launch_plate_velocity<float>(Fields&, hipStream_t, int, const double*);
 
 }  // namespace lbm

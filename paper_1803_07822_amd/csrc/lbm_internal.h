@@ -124,10 +124,14 @@ hipError_t launch_stream_probe(int precision, long long n, const void* in, void*
 // geometry (FP64 precompute; writes geo in precision T)
 template <class T> hipError_t launch_geometry(Fields& F, hipStream_t s, const double Fc[3]);
 template <class T> hipError_t launch_body_force(Fields& F, hipStream_t s, const double Fc[3]);
-template <class T> hipError_t launch_wall_velocity(Fields& F, hipStream_t s);
-template <class T> hipError_t launch_plate_velocity(Fields& F, hipStream_t s);
+// The velocity and chart launchers can also take a new input for one field
+// (which: wall 0 or 1, for the chart 2 = plate; -1 none) straight from the
+// caller's device array (NULL: zero): the kernel stores it into the context's
+// copy, in place of a separate copy launch.
+template <class T> hipError_t launch_wall_velocity(Fields& F, hipStream_t s, int which = -1, const double* src = nullptr);
+template <class T> hipError_t launch_plate_velocity(Fields& F, hipStream_t s, int in = 0, const double* src = nullptr);
 template <class T> hipError_t launch_inlet_velocity(Fields& F, hipStream_t s);
-hipError_t launch_chart_from_disp(Fields& F, hipStream_t s);
+hipError_t launch_chart_from_disp(Fields& F, hipStream_t s, int which = -1, const double* src = nullptr);
 
 // state
 template <class T> hipError_t launch_feq_full(Fields& F, hipStream_t s, const double* rho, const double* uc);

@@ -357,13 +357,24 @@ __global__ __launch_bounds__(BX * BY) void k_geo(Grid g, const double* __restric
   march_load<6>(g, m, m.z0 - 1, w, ring[rs(m.z0 - 1)]);
   march_load<6>(g, m, m.z0, w, ring[rs(m.z0)]);
   for (int k = m.z0; k < m.z1; ++k) {
+    // this plane's J (and g) are loaded ahead of the ring's next plane and
+    // the barrier, so that their round trip overlaps those
+    const long long n = ((long long)k * g.H + (j - 1)) * g.nx + i;
+    double gm[3][3], J[3][3];
+    if (act) {
+      jac_at<Y>(jac, g.N, n, J);
+      if constexpr (!Y) {
+        const long long e = eidx(g, i, j, k);
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+          for (int b = 0; b < 3; ++b) gm[a][b] = gext[sym(a, b) * NE + e];
+      }
+    }
     march_load<6>(g, m, k + 1, w, ring[rs(k + 1)]);
     __syncthreads();
     if (act) {
-      const long long n = ((long long)k * g.H + (j - 1)) * g.nx + i;
-      const long long e = eidx(g, i, j, k);
-      double gm[3][3], gi[3][3], J[3][3], Ji[3][3], det, detJ;
-      jac_at<Y>(jac, g.N, n, J);
+      double gi[3][3], Ji[3][3], det, detJ;
       if constexpr (Y) {
         double gq[6];
         metric_of(J, gq);
@@ -371,11 +382,6 @@ __global__ __launch_bounds__(BX * BY) void k_geo(Grid g, const double* __restric
         for (int a = 0; a < 3; ++a)
 #pragma unroll
           for (int b = 0; b < 3; ++b) gm[a][b] = gq[sym(a, b)];
-      } else {
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-          for (int b = 0; b < 3; ++b) gm[a][b] = gext[sym(a, b) * NE + e];
       }
       inv3(gm, gi, det);
       inv3(J, Ji, detJ);

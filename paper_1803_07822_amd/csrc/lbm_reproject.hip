@@ -159,6 +159,9 @@ __global__ __launch_bounds__(BX * BY) void k_rp_moments(Grid g, const T* __restr
   if (!xcd_fluid_node(g, i, jf, k)) return;
   const long long n = ((long long)k * g.H + jf) * g.nx + i;
   const long long e = ((long long)k * g.ny + (jf + 1)) * g.nx + i;
+  // J is loaded first, so that its round trip overlaps the pulls'
+  double J[3][3];
+  jac_at<Y>(jac, g.N, n, J);
   Coef<T> c;
   c.A = hist[H_A * g.N + n];
 #pragma unroll
@@ -187,8 +190,6 @@ __global__ __launch_bounds__(BX * BY) void k_rp_moments(Grid g, const T* __restr
     if (y && z) P[4] += y * z * v;
   });
   const double sg = 1.0 + (double)sgd;
-  double J[3][3];
-  jac_at<Y>(jac, g.N, n, J);
   // f = w + f~: sum w = 1, sum w c c = I/3
   const double rho = sg * (1.0 + s);
   double j[3], Pm[3][3], Bv[3], Cm[3][3];

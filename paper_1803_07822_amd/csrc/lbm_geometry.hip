@@ -264,9 +264,7 @@ __global__ __launch_bounds__(BX * BY) void k_smooth_gy(Grid g, int jlo, int jhi,
       const double(*s0)[MN] = ring[rs(k)];
       const double(*sp)[MN] = ring[rs(k + 1)];
       auto metric_at = [&](const double(*sl)[MN], int o, double gq[6]) {
-        double J[3][3];
-        jac_of_row(sl[0][o], sl[1][o], sl[2][o], J);
-        metric_of(J, gq);
+        metric_of_row(sl[0][o], sl[1][o], sl[2][o], gq);
       };
       double g0[6], s[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
       metric_at(s0, e0, g0);
@@ -377,7 +375,7 @@ __global__ __launch_bounds__(BX * BY) void k_geo(Grid g, const double* __restric
       double gi[3][3], Ji[3][3], det, detJ;
       if constexpr (Y) {
         double gq[6];
-        metric_of(J, gq);
+        metric_of_row(J[1][0], J[1][1], J[1][2], gq);
 #pragma unroll
         for (int a = 0; a < 3; ++a)
 #pragma unroll

@@ -244,7 +244,7 @@ __global__ __launch_bounds__(BX * BY) void k_smooth(Grid g, int jlo, int jhi, co
 
 // The smoothing above applied to g = J^T J of a chart that moves the nodes
 // along y only, g formed at every stencil point from the varying row of J
-// (three components read instead of six, same arithmetic per component).
+// (three components read instead of six).
 __global__ __launch_bounds__(BX * BY) void k_smooth_gy(Grid g, int jlo, int jhi, const double* __restrict__ row,
                                                        double* __restrict__ out) {
   __shared__ double ring[4][3][MN];

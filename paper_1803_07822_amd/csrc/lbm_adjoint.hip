@@ -253,7 +253,8 @@ __global__ __launch_bounds__(BX) void k_adj_node(Grid g, int mode, const double*
                            const double* __restrict__ lfn, const double* __restrict__ lpn, double* __restrict__ lpb,
                            double* __restrict__ lml, double* __restrict__ ldj, double* __restrict__ lpo,
                            double* __restrict__ lg, const double* __restrict__ uw, int mv0, int mv1,
-                           double* __restrict__ ub) {
+                           double* __restrict__ ub, int fwall, const double* __restrict__ W,
+                           const double* __restrict__ jac, double* __restrict__ lj) {
   Node p;
   if (!row_group_node(g, p)) return;
   const double th = 1.0 / 3.0;
@@ -354,7 +355,32 @@ __global__ __launch_bounds__(BX) void k_adj_node(Grid g, int mode, const double*
 #pragma unroll
   for (int q = 0; q < 10; ++q) cb[q] = EN(lpn, q, g, p.n);
   double rb = 0, jb[3] = {0, 0, 0}, djb[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, Pb[6];
-  node_vjp(nullptr, G, tau, with_old, o, hs, hb, cb, nullptr, Pb, rb, jb, djb, nullptr, gb);
+  // The wall force of this state, when the loss holds it (W = dL/dF of the
+  // state, Sec. IV.A.2 traction sqrt g T^{iy} J): its adjoint of T joins the
+  // step's in node_vjp, which is linear in it, and its adjoints of sqrt g and
+  // J are added here, at the wall row only.
+  double Tbf[6] = {0, 0, 0, 0, 0, 0};
+  if (W && p.jf == (fwall == 0 ? 0 : g.H - 1)) {
+    const double sgn = fwall == 0 ? -1.0 : 1.0;
+    double J[3][3], ljv[9], sgb = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) J[a][b] = E(jac, (a * 3 + b), g, p.n);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      double wj = 0;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) wj += W[a] * J[a][i];
+      Tbf[sym(i, 1)] += sgn * G.sg * wj;
+      sgb += sgn * wj * o.T[sym(i, 1)];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) ljv[a * 3 + i] = sgn * G.sg * W[a] * o.T[sym(i, 1)];
+    }
+    add_planes<9>(lj, 0, g, p.n, ljv);
+    gb.add_sg(sgb);
+  }
+  node_vjp(nullptr, G, tau, with_old, o, hs, hb, cb, Tbf, Pb, rb, jb, djb, nullptr, gb);
   // moving walls: the bounce-back of a link into wall w loses
   // 6 (w_l / sqrt g) rho c_l . u_w (chart components u_w of the column)
   if (MW && with_old) {
@@ -930,16 +956,15 @@ hipError_t adjoint_backward(Fields& F, AdjointBuffers& A, hipStream_t s, int K, 
         mt = A.tmom + 4 * Nn * (t - t0);
       else
         hipLaunchKernelGGL(k_adj_moments, fg, b, 0, s, g, pop, hist, geo, mom);
+      // the force of state t (t >= 1, in the loss) is reversed inside its node kernel
+      const double* W = t >= 1 ? dLdF + 3 * (t - 1) : nullptr;
       hipLaunchKernelGGL(mw ? k_adj_node<true> : k_adj_node<false>, ng, nb, 0, s, g, 0, pop, hist, geo, mt, tau,
                          (const double*)A.lf[cur], (const double*)A.lp[cur], A.lpb, A.lml, A.ldj, A.lp[cur ^ 1],
-                         A.lg, uwd, mv0, mv1, A.ub);
+                         A.lg, uwd, mv0, mv1, A.ub, wall, W, (const double*)F.jac, A.lj);
       hipLaunchKernelGGL(mw ? k_adj_gather<true> : k_adj_gather<false>, fg, b, 0, s, g, geo, mt,
                          (const double*)A.lf[cur], tau, (const double*)A.lpb, (const double*)A.lml,
                          (const double*)A.ldj, (const double*)nullptr, A.lf[cur ^ 1], A.lg, uwd, mv0, mv1, A.ub);
       cur ^= 1;
-      if (t >= 1)
-        hipLaunchKernelGGL(k_adj_force, cg, b, 0, s, g, wall, pop, hist, geo, (const double*)F.jac, tau,
-                           dLdF + 3 * (t - 1), A.lf[cur], A.lg, A.lj);
     }
   }
   // history of the initial state: F(x,-1) := F(state 0)
@@ -954,7 +979,7 @@ hipError_t adjoint_backward(Fields& F, AdjointBuffers& A, hipStream_t s, int K, 
       hipLaunchKernelGGL(k_adj_moments, fg, b, 0, s, g, pop, hist, geo, mom);
     hipLaunchKernelGGL(mw ? k_adj_node<true> : k_adj_node<false>, ng, nb, 0, s, g, 1, pop, hist, geo, mt, tau,
                        (const double*)A.lf[cur], (const double*)A.lp[cur], A.lpb, A.lml, A.ldj, (double*)nullptr,
-                       A.lg, uwd, mv0, mv1, A.ub);
+                       A.lg, uwd, mv0, mv1, A.ub, wall, (const double*)nullptr, (const double*)F.jac, A.lj);
     hipLaunchKernelGGL(mw ? k_adj_gather<true> : k_adj_gather<false>, fg, b, 0, s, g, geo, mt,
                        (const double*)nullptr, tau, (const double*)A.lpb, (const double*)A.lml,
                        (const double*)A.ldj, (const double*)A.lf[cur], A.lf[cur ^ 1], A.lg, uwd, mv0, mv1, A.ub);

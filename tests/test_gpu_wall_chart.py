@@ -6,7 +6,8 @@ its displacement rewritten once the rest is in place.  The same charts given
 whole through lbm_set_metric take the general path.  Both paths must give the
 same geometry and the same re-projected and stepped states, to rounding (the
 two differ in the order of floating-point operations only), through a
-sequence that visits both displacement buffers of the re-projection twice."""
+sequence that visits both displacement buffers of the re-projection twice and
+ends with a wall lifted by 2.5 layers in one update."""
 import numpy as np
 import pytest
 
@@ -68,7 +69,11 @@ def test_wall_chart_path_matches_general_path(precision):
     assert np.all(J[0, 0] == 1) and np.all(J[0, 1:] == 0) and np.all(J[2, :2] == 0) and np.all(J[2, 2] == 1)
 
     tol = 1e-12 if precision == "fp64" else 1e-5
-    for tag, d, steps in (("d2", d2, 2), ("d1", d1, 2), ("d2 again", d2, 1), ("d1 again", d1, 0)):
+    # the last change lifts the wall by 2.5 layers at once: the search for psi
+    # then leaves the layers beside the node and loads its cells on the way
+    lift = d1 + 2.5
+    for tag, d, steps in (("d2", d2, 2), ("d1", d1, 2), ("d2 again", d2, 1), ("d1 again", d1, 0),
+                          ("lifted 2.5 layers", lift, 1)):
         for general in (False, True):
             set_chart(S[general], d, general, True)
             S[general].step(steps)

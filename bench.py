@@ -157,18 +157,23 @@ def adjoint_ratio(repeats=3):
             "ratio": round(b / f, 3), "forward_mlups": round(w.fluid_nodes * K / (f * 1e-3) / 1e6, 1)}
 
 
-def moving_wall_loop(w, wall_at, every, steps, keep_state=False):
+def moving_wall_loop(w, wall_at, every, steps, keep_state=False, general_updates=0):
     """FP32 run of workload `w` under a moving top wall: `steps` steps, the
     wall shape and velocity (wall_at(t) -> d [nz, nx], dd/dt [nz, nx]) updated
     with re-projection every `every` steps, the top-wall force recorded every
     step into device memory (lbm_step_force: the force of each state a step
     starts from, states 0 .. steps-1, formed by the fused step itself).  GPU time per phase from events on the library's
     stream, and the host wall time of the whole loop.  keep_state: also
-    return the final populations (FP64, on the host)."""
+    return the final populations (FP64, on the host).
+
+    Charts built from a wall displacement move the nodes along y only and the
+    library updates them on a path of its own; general_updates > 0 then also
+    times that many updates with the loop's last two wall charts given whole
+    (lbm_set_metric, the general path) on the final state, for comparison."""
     import numpy as np
     import torch
 
-    from paper_1803_07822_amd import lbm
+    from paper_1803_07822_amd import lbm, synth
 
     S = lbm.Solver(w.nx, w.ny, w.nz, w.tau, "fp32")
     S.set_body_force(w.force)
@@ -208,12 +213,26 @@ def moving_wall_loop(w, wall_at, every, steps, keep_state=False):
     vel_ms = sum(e[2].elapsed_time(e[3]) for e in ev)
     total_ms = ev[0][0].elapsed_time(ev[-1][3])
     f = forces.cpu().numpy()
+    gen_ms = None
+    if general_updates > 0:
+        charts = [torch.as_tensor(synth.chart_from_displacement(w.nx, w.ny, w.nz, np.asarray(walls[u][0].cpu())),
+                                  device=S.device) for u in (nup - 2, nup - 1)]
+        g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        lbm.lbm_set_metric(S.ctx, charts[0], 1)
+        g0.record(S.stream)
+        for r in range(general_updates):
+            lbm.lbm_set_metric(S.ctx, charts[(r + 1) % 2], 1)
+        g1.record(S.stream)
+        S.sync()
+        torch.cuda.synchronize()
+        gen_ms = round(g0.elapsed_time(g1) / general_updates, 4)
     res = {"workload": w.name, "precision": "fp32", "steps": steps, "updates": nup,
            "gpu_ms": round(total_ms, 2), "wall_s": round(wall_s, 3),
            "mlups_with_updates": round(w.fluid_nodes * steps / (total_ms * 1e-3) / 1e6, 1),
            "step_and_force_ms_per_step": round(step_ms / steps, 5),
            "metric_update_and_reprojection_ms": round(rp_ms / nup, 4),
            "wall_velocity_ms": round(vel_ms / nup, 4),
+           "general_chart_update_ms": gen_ms,
            "force_finite": bool(np.isfinite(f).all()), "final_force": [float(x) for x in f[-1]]}
     state = S.populations().cpu() if keep_state else None
     del S, walls, forces
@@ -227,7 +246,8 @@ def c3_loop():
     from paper_1803_07822_amd import synth
 
     w = synth.workload("c3_oscillating_256x128x128")
-    return moving_wall_loop(w, lambda t: synth.oscillating_wall(w.nx, w.nz, t=t), w.extra["update_every"], w.steps)
+    return moving_wall_loop(w, lambda t: synth.oscillating_wall(w.nx, w.nz, t=t), w.extra["update_every"], w.steps,
+                            general_updates=10)
 
 
 def open_channel(steps=50, repeats=2):

@@ -278,9 +278,9 @@ __global__ __launch_bounds__(BX * BY) void k_rp_new(Grid g, const double* __rest
   const int side = jf >= g.pj ? 1 : 0;
   const long long e0 = ((long long)k * (g.ny + 6) + (jf + 1 + 3)) * g.nx + i;
   double xi[3];
-  // Y: J's varying row, read before the search for the same reason
+  // the new J (Y: its varying row), read before the search for the same reason
   double J[3][3];
-  if constexpr (Y) jac_at<true>(jac, g.N, n, J);
+  jac_at<Y>(jac, g.N, n, J);
   if constexpr (Y) {
     // x and z displacements are zero in both charts: xi = (i, y, k) with
     // y + u_old,y(i, y, k) = p_y, linear between the two layers around y.
@@ -405,7 +405,6 @@ __global__ __launch_bounds__(BX * BY) void k_rp_new(Grid g, const double* __rest
   for (int q = 0; q < NMF; ++q) m[q] += mf_rest(q);
   // pull back with the new J^{-1}
   double Ji[3][3];
-  if constexpr (!Y) jac_at<false>(jac, g.N, n, J);
   inv3d(J, Ji);
   double Pc[3][3], Cc[3][3];
 #pragma unroll
